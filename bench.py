@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark: approximate fPEPS contraction on a random 3-regular graph.
+
+Workload (one GPU): a Z2 fermionic PEPS on a seeded random 3-regular graph
+with 40 sites, physical dim 4 (2 even / 2 odd), bond D = 4 (2 / 2), entries
+N(0, 1/32); approximate contraction with bond compression to chi = 64 along
+a seeded greedy path, FP64 throughout. One step = the norm <psi|psi> plus
+the hopping term <psi|h|psi> on the first edge: two network contractions
+(metric unit: contractions per second).
+
+Prints one JSON line with the throughput, a roofline entry for the dominant
+kernel class (timed with HIP events on the library's stream inside the
+timed region), and the CPU oracle timed on a bounded sample on rank 0.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"gemm_f64": (78.6, "TFLOP/s", "mfma"), "gemm_f32": (157.3, "TFLOP/s", "mfma"),
+        "gemm_bf16x3": (2500.0, "TFLOP/s", "mfma"), "permute": (8000.0, "GB/s", "hbm")}
+
+
+def load_paths():
+    with open(os.path.join(ROOT, "synth", "data", "paths.json")) as f:
+        return json.load(f)
+
+
+def gpu_setup(cfg, paths):
+    import torch
+    from paper_2410_02215_amd import peps as GP
+    from synth import workloads as W
+    from synth.operators import operator_dense
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"])
+    kets = GP.ket_tensors(spec, vals)
+    op = GP.operator_tensor(spec, operator_dense("hop", "Z2"))
+    nn = GP.norm_network(spec, kets)
+    nh = GP.norm_network(spec, kets, op=op, op_sites=cfg["op_sites"])
+    torch.cuda.synchronize()
+    return dict(nn=nn, nh=nh, kets=kets, op=op, pn=paths["c2_norm"]["path"], ph=paths["c2_hop"]["path"])
+
+
+def gpu_step(g, chi):
+    m1, e1, s1 = g["nn"].contract(g["pn"], chi=chi)
+    m2, e2, s2 = g["nh"].contract(g["ph"], chi=chi)
+    return (m1, e1, m2, e2), (s1, s2)
+
+
+def cpu_baseline(cfg, paths, budget_s):
+    """Oracle on a bounded sample: the first steps of one norm contraction.
+
+    Runs the oracle step by step until the time budget is spent, then scales
+    the elapsed time by the fraction of the path's planner-estimated flops
+    those steps cover.
+    """
+    import torch
+    from oracle import physics as OP
+    from oracle.network import Network, contract_network
+    from synth import workloads as W
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"])
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    kets = OP.ket_tensors(spec, vals)
+    net = OP.norm_network(spec, kets, conv="local")
+    path = paths["c2_norm"]["path"]
+    lf = paths["c2_norm"]["log2_flops"]
+    tot = sum(2.0 ** x for x in lf)
+    t0 = time.time()
+    done = 0
+    # the oracle contracts a growing prefix of the path; stop at the budget
+    for k in range(1, len(path) + 1):
+        prefix = path[:k]
+        # contract only the prefix: the remaining tensors stay untouched
+        try:
+            _partial_contract(net, prefix, cfg["chi"])
+        except MemoryError:
+            break
+        done = k
+        if time.time() - t0 > budget_s:
+            break
+    el = time.time() - t0
+    frac = sum(2.0 ** x for x in lf[:done]) / tot
+    return dict(value=(frac / el) if el > 0 and frac > 0 else None, unit="contractions/s", cores=cores,
+                kind="oracle",
+                sample="first %d of %d steps of one <psi|psi> contraction (%.3g%% of the planner-estimated "
+                       "GEMM flops), %.1f s, extrapolated linearly in flops" % (done, len(path), 100 * frac, el))
+
+
+_PC = {}
+
+
+def _partial_contract(net, prefix, chi):
+    """Advance a cached oracle contraction by one step (prefix grows by one)."""
+    from oracle import network as N
+    st = _PC.get("st")
+    if st is None:
+        st = N._State(net)
+        _PC["st"] = st
+        _PC["ssa"] = {i: t for i, t in enumerate(sorted(st.T))}
+        _PC["nid"] = max(st.T) + 1
+        _PC["k"] = 0
+        _PC["order"] = sorted(st.T)
+    k = _PC["k"]
+    i, j = prefix[k]
+    ssa = _PC["ssa"]
+    x, y = ssa[i], ssa[j]
+    lx, ly = N._shared(st, x, y)
+    Z = N.ftensordot(st.T[x], st.T[y], lx, ly, conv="local")
+    z = _PC["nid"]
+    _PC["nid"] += 1
+    st.T[z] = Z
+    st.lab[z] = ([l for q, l in enumerate(st.lab[x]) if q not in lx] +
+                 [l for q, l in enumerate(st.lab[y]) if q not in ly])
+    for t in (x, y):
+        del st.T[t]
+        del st.lab[t]
+    ssa[len(ssa)] = z
+    N._fuse_and_compress(st, z, chi, "local", _PC["order"])
+    N._renorm(st, z)
+    _PC["k"] = k + 1
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: a single approximate contraction does not shard "
+              "(see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2410_02215_amd as P
+    from synth import workloads as W
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    P.load_library()
+    cfg = W.c2()
+    chi = cfg["chi"]
+    paths = load_paths()
+    g = gpu_setup(cfg, paths)
+    print("[bench] workload %s: warmup %d" % (cfg["name"], args.warmup), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        res, st = gpu_step(g, chi)
+        print("[bench] warmup step done: norm mantissa %.6g exp %d" % (res[0], res[1]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    P.ftn.profile_collect()
+    P.ftn.profile_enable(True)
+    t0 = time.perf_counter()
+    flops = 0.0
+    for k in range(args.steps):
+        res, st = gpu_step(g, chi)
+        flops += st[0]["flops"] + st[1]["flops"]
+        print("[bench] step %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.ftn.profile_enable(False)
+    prof = P.ftn.profile_collect()
+    el = t1 - t0
+    ms_step = 1000.0 * el / args.steps
+    value = 2.0 * args.steps / el
+    norm = res[0] * 2.0 ** res[1]
+    hop = (res[2] / res[0]) * 2.0 ** (res[3] - res[1])
+    # dominant kernel class by time
+    dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
+    ms, cnt, work = prof[dom]
+    peak, unit, bound = PEAK[dom]
+    if unit == "TFLOP/s":
+        achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    else:
+        achieved = work / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": None, "kernel": dom, "launches": cnt, "avg_launch_ms": ms / max(cnt, 1)}
+    out = {
+        "metric": "ftensordot useful TFLOP/s + fPEPS contractions/sec on 1 GPU at stated err vs FP64",
+        "value": value, "unit": "contractions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": chi,
+                   "contractions_per_step": 2, "terms": ["norm", "hopping(first edge)"]},
+        "ftensordot_useful_tflops": flops / el / 1e12,
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, %.0f s budget)" % args.cpu_budget, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, paths, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,326 @@
+// Internal declarations of the fermionic tensor library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ftn.h"
+
+namespace ftn {
+
+constexpr int MAXD = 16;  // maximum number of legs of one tensor
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws Error; the C ABI catches it and returns code.
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPC(x) ::ftn::hip_check((x), #x)
+void set_last_error(const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// charges: (q0, q1); Z2 keeps q0 in {0,1}, q1 = 0.
+struct Q {
+  int32_t a, b;
+};
+__host__ __device__ inline Q q_canon(int sym, Q q) {
+  if (sym == FTN_Z2) return Q{q.a & 1, 0};
+  if (sym == FTN_U1) return Q{q.a, 0};
+  return q;
+}
+__host__ __device__ inline Q q_add(int sym, Q x, Q y) { return q_canon(sym, Q{x.a + y.a, x.b + y.b}); }
+__host__ __device__ inline Q q_neg(int sym, Q x) { return q_canon(sym, Q{-x.a, -x.b}); }
+__host__ __device__ inline Q q_signed(int sym, int dual, Q x) { return dual ? q_neg(sym, x) : q_canon(sym, x); }
+__host__ __device__ inline bool q_eq(Q x, Q y) { return x.a == y.a && x.b == y.b; }
+__host__ __device__ inline bool q_lt(Q x, Q y) { return x.a < y.a || (x.a == y.a && x.b < y.b); }
+__host__ __device__ inline int q_par(Q x) { return (x.a + x.b) & 1; }
+
+// ---------------------------------------------------------------------------
+struct Leg {
+  std::vector<Q> q;        // sector charges, strictly ascending
+  std::vector<int64_t> d;  // sector dims (> 0)
+  int dual = 0;            // 0 '+', 1 '-'
+  int nsect() const { return (int)q.size(); }
+  int64_t size() const {
+    int64_t s = 0;
+    for (auto x : d) s += x;
+    return s;
+  }
+  int find(Q c) const {
+    for (int i = 0; i < nsect(); ++i)
+      if (q_eq(q[i], c)) return i;
+    return -1;
+  }
+  bool operator==(const Leg& o) const {
+    if (dual != o.dual || q.size() != o.q.size()) return false;
+    for (size_t i = 0; i < q.size(); ++i)
+      if (!q_eq(q[i], o.q[i]) || d[i] != o.d[i]) return false;
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// device memory
+void* dmalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+template <typename T>
+struct DBuf {  // owning device buffer, released stream-ordered
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(size_t n_, hipStream_t s_) : n(n_), s(s_) { p = n ? (T*)dmalloc(n * sizeof(T), s) : nullptr; }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    reset();
+    p = o.p; n = o.n; s = o.s;
+    o.p = nullptr; o.n = 0;
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) dfree(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const T* h, size_t cnt) {
+    if (cnt) HIPC(hipMemcpyAsync(p, h, cnt * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// upload a host vector into a new device buffer (async on s; the host
+// vector must stay alive until the copy completes, so callers keep it or
+// synchronise)
+template <typename T>
+DBuf<T> to_device(const std::vector<T>& v, hipStream_t s) {
+  DBuf<T> b(v.size(), s);
+  b.upload(v.data(), v.size());
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// tensors: immutable block structure (shared, cached) + data
+struct Structure {
+  int sym = FTN_Z2;
+  int ndim = 0;
+  std::vector<Leg> legs;
+  Q total{0, 0};
+  int64_t nblocks = 0;
+  int64_t size = 0;
+  std::vector<int32_t> keys;     // nblocks * ndim sector indices, lexicographic
+  std::vector<int64_t> offsets;  // nblocks + 1
+  std::vector<int64_t> shapes;   // nblocks * ndim
+  std::vector<uint32_t> parmask; // nblocks, bit i = parity of leg i's sector
+  DBuf<int32_t> d_keys;
+  DBuf<int64_t> d_offsets;
+  DBuf<int32_t> d_shapes;
+  DBuf<uint32_t> d_parmask;
+  std::string skey;
+};
+
+// structure of (sym, legs, total): enumerated on the device the first time,
+// then served from a process-wide cache
+std::shared_ptr<const Structure> get_structure(int sym, const std::vector<Leg>& legs, Q total,
+                                               hipStream_t s);
+std::string structure_key(int sym, const std::vector<Leg>& legs, Q total);
+
+struct Tensor {
+  std::shared_ptr<const Structure> st;
+  int dtype = FTN_F64;
+  std::shared_ptr<void> buf;  // owns the device data (shared by views)
+  void* data = nullptr;
+  const Structure& S() const { return *st; }
+  int sym() const { return st->sym; }
+  int ndim() const { return st->ndim; }
+  const std::vector<Leg>& legs() const { return st->legs; }
+  Q total() const { return st->total; }
+  int64_t size() const { return st->size; }
+  int64_t nblocks() const { return st->nblocks; }
+  size_t esize() const { return dtype == FTN_F64 ? 8 : 4; }
+  int parity() const { return q_par(st->total); }
+};
+
+// new tensor with the given structure; data zeroed if zero = true
+std::unique_ptr<Tensor> make_tensor(int sym, int dtype, const std::vector<Leg>& legs, Q total,
+                                    hipStream_t s, bool zero = true);
+std::unique_ptr<Tensor> make_tensor(std::shared_ptr<const Structure> st, int dtype, hipStream_t s,
+                                    bool zero = true);
+int64_t block_index(const Structure& t, const int32_t* key);  // -1 if absent (host)
+// a tensor sharing t's data under another structure of the same layout
+std::unique_ptr<Tensor> share_tensor(const Tensor& t, std::shared_ptr<const Structure> st);
+void scale_inplace(Tensor& t, double alpha, hipStream_t s);
+
+// leg tables passed by value to kernels
+struct LegTab {
+  int ndim;
+  int sym;
+  int nsect[MAXD];
+  int base[MAXD];
+  int dual[MAXD];
+  Q total;
+};
+
+// flattened sector arrays of a tensor's legs, resident on the device
+struct DevLegs {
+  LegTab tab;
+  DBuf<Q> q;
+  DBuf<int64_t> d;
+};
+void make_devlegs(const std::vector<Leg>& legs, int sym, Q total, hipStream_t s, DevLegs& out);
+
+// exclusive scan of n int64 values in place on the device; writes the total
+// to total_out (device pointer, may be null)
+void scan_exclusive(int64_t* v, int64_t n, int64_t* total_out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// signed block <-> matrix permute (sign computation fused into the copy)
+//
+// A block of tensor t (legs in t's order, row-major) is mapped to a strided
+// region: the destination order is perm (position p holds leg perm[p]) and is
+// cut into three segments A = [0, nA), G = [nA, nA+nG), B = [nA+nG, ndim).
+// Address = moff + idx_B + bext * (idx_G + gext * idx_A) where idx_X is the
+// row-major index inside segment X (gext = 0 means the natural size of G).
+struct SignOp {
+  uint32_t kmask[MAXD];  // Koszul mask per destination position
+  int perm[MAXD];
+  int ndim;
+  int nA, nG;
+  uint32_t rev_mask;     // legs whose pairwise parity products add to the sign
+  uint32_t flip_mask;    // legs whose parities add to the sign
+  int phase;             // constant sign bit
+};
+SignOp make_signop(int ndim, const int* perm, int nA, int nG);
+
+struct PermTask {
+  int64_t block;  // block index in the tensor whose structure is given
+  int64_t moff;   // strided-side element offset
+  int64_t gext;   // extent of segment G when forming segment A's strides
+  int64_t bext;   // extent of segment B (row length of the strided side)
+  int32_t skip;   // 1: nothing to do
+  int32_t extra;  // extra sign bit of this task
+};
+
+std::vector<int64_t> block_sizes(const Structure& s);
+
+// a ready-to-launch permute: tasks and tile map resident on the device
+struct PermPlan {
+  SignOp op;
+  DBuf<PermTask> tasks;
+  DBuf<int64_t> tile_start;
+  int64_t ntasks = 0, ntiles = 0;
+  int64_t nelem = 0;  // elements moved per run (for the profile)
+};
+// builds the tile map from per-task element counts (synchronises s)
+void perm_plan_tiles(PermPlan& p, const std::vector<int64_t>& task_elems, hipStream_t s);
+// dir = 0: block -> strided region; dir = 1: strided region -> block.
+// `st` gives the block structure, dtype the element type. No host sync.
+void run_perm(int dir, const Structure& st, int dtype, const PermPlan& p, const void* src, void* dst,
+              hipStream_t s, double alpha = 1.0);
+
+// device key matching for unary ops: source block b maps to the output block
+// whose key is (remap[leg][key[perm[p]]])_p; fills tasks (moff = offset of the
+// output block, single segment)
+void unary_tasks(const Structure& src, const Structure& dst, const SignOp& op,
+                 const std::vector<int32_t>& remap, const std::vector<int>& remap_base,
+                 DBuf<PermTask>& tasks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// grouped GEMM
+struct GemmGroup {
+  int64_t M, N, K;
+  int64_t a_off, b_off;  // element offsets into the A / B matrix buffers
+  int64_t lda, ldb;
+  int32_t transA, transB;
+  // output: either a plain matrix (c_off, ldc) or a block scatter
+  int64_t c_off, ldc;
+  // scatter tables (when scatter != 0): row combos / col combos of the group
+  int32_t scatter;
+  int32_t nrc, ncc;         // number of row / col combos
+  int64_t rc_base, cc_base; // offsets into the combo start arrays
+  int64_t boff_base;        // offset into block offset table (nrc * ncc)
+  int64_t tile0;            // first tile index of this group
+  int64_t ntm, ntn;         // tiles along M and N
+};
+struct GemmScatter {
+  const int64_t* rc_start;  // per row combo: first row; terminated per group by M
+  const int64_t* cc_start;  // per col combo: first col
+  const int64_t* cc_dim;    // per col combo: its dim (row length in the block)
+  const int64_t* boff;      // block offsets into C
+};
+// a ready-to-launch grouped GEMM (group table resident on the device)
+struct GemmPlan {
+  std::vector<GemmGroup> host;
+  DBuf<GemmGroup> groups;
+  int64_t ntiles = 0;
+  int kind = FTN_GEMM_F64;
+};
+void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s);
+// C[g] = alpha * op(A[g]) op(B[g]) (+ beta C for plain outputs). No host sync.
+void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
+              const GemmScatter* sc, hipStream_t s, double alpha = 1.0, double beta = 0.0);
+// one-off convenience: plan + run + synchronise
+void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,
+                      const void* B, void* C, const GemmScatter* sc, hipStream_t s,
+                      double alpha = 1.0, double beta = 0.0);
+double gemm_flops(const std::vector<GemmGroup>& groups);
+
+// ---------------------------------------------------------------------------
+// operations
+std::unique_ptr<Tensor> op_ftranspose(const Tensor& a, const std::vector<int>& perm, hipStream_t s);
+std::unique_ptr<Tensor> op_flip_dual(const Tensor& a, int leg, int with_sign, hipStream_t s);
+std::unique_ptr<Tensor> op_dagger(const Tensor& a, hipStream_t s);
+std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& legs, int conv, int rev,
+                                hipStream_t s);
+std::unique_ptr<Tensor> op_scale(const Tensor& a, double alpha, hipStream_t s);
+std::unique_ptr<Tensor> op_cast(const Tensor& a, int dtype, hipStream_t s);
+std::unique_ptr<Tensor> op_leg_sign(const Tensor& a, int leg, hipStream_t s);
+std::unique_ptr<Tensor> op_ftensordot(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                                      const std::vector<int>& axb, int conv, int gemm, hipStream_t s,
+                                      double* flops = nullptr);
+struct CompressResult {
+  std::unique_ptr<Tensor> a, b;
+  double discarded = 0.0;
+  std::vector<double> svals;
+  bool near_tie = false;
+};
+CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi,
+                                double cutoff, int conv, hipStream_t s);
+double op_max_abs(const Tensor& a, hipStream_t s);  // synchronises
+
+// contraction plans (shared with the compression code)
+struct DotPlan;
+struct DotPlanView {
+  std::vector<GemmGroup> groups;
+  std::vector<Q> gq;  // contracted charge of each group
+  const PermPlan* pa;
+  const PermPlan* pb;
+  int64_t asz, bsz;
+};
+std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                                  const std::vector<int>& axb, int conv, int gemm, hipStream_t s);
+DotPlanView dot_plan_view(const DotPlan& p);
+
+// block copies between dense and block layouts
+void gather_dense(Tensor& t, const void* dense, hipStream_t s);
+void scatter_dense(const Tensor& t, void* dense, hipStream_t s);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// event timing of instrumented launches (profile.hip)
+bool prof_on();
+void* prof_begin(hipStream_t s);
+void prof_end(void* tok, hipStream_t s, int cls, double work);
+
+}  // namespace ftn

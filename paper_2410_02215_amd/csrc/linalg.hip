@@ -1,0 +1,919 @@
+// Bond compression (Sec. II.A truncated SVD over all symmetry blocks; used
+// by approximate contraction, Fig. 1b and Sec. III), FP64 throughout.
+//
+// For the bond between A (leg la) and B (leg lb), per bond charge q:
+//   A~_q (M x d) and B~_q (d x N) are the fused matrices of the contraction
+//   plan (signed permutes). G_A = A~^T A~ and G_B = B~ B~^T (split-K MFMA
+//   GEMMs) are factored by pivoted Cholesky, G_A = R_A^T R_A, G_B = R_B^T
+//   R_B, so A~ = Q_A R_A and B~ = R_B^T Q_B with orthonormal Q's. The SVD of
+//   X = R_A R_B^T = U S V^T gives the best rank-chi approximation of A~ B~,
+//   with the chi largest values kept over all charges. The projectors
+//   P_A = R_B^T V S^-1/2 and P_B = S^-1/2 U^T R_A give A' = A~ P_A and
+//   B' = P_B B~, computed as ordinary fermionic contractions of A and B with
+//   2-leg block-diagonal tensors followed by transpositions that put the new
+//   bond back in place. A per-sector sign (the bond parity of the local
+//   convention) commutes with the block-diagonal projectors, so the same
+//   A', B' serve both conventions.
+// The SVD of X: the smaller Gram matrix H of X is diagonalised with a cyclic
+// Jacobi method in LDS when its order is <= 128, otherwise its leading
+// eigenspace is found by subspace iteration (Cholesky-QR orthonormalisation)
+// followed by a Rayleigh-Ritz step on a 128-dimensional subspace.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace ftn {
+
+constexpr int LT = 1024;     // threads of the factorisation kernels
+constexpr int JMAX = 128;    // largest order diagonalised in LDS
+constexpr int CHOL_MAX = 4096;
+
+// ---------------------------------------------------------------------------
+// pivoted Cholesky of a symmetric PSD K x K matrix (one workgroup per
+// matrix). R (K x K, zeroed) receives R[l][c] with R^T R = G; rows beyond
+// the numerical rank stay zero. Stops when the largest remaining pivot is
+// not above tol * (largest diagonal of G).
+struct CholJob {
+  const double* G;
+  double* R;
+  int K;
+  int pad;
+};
+
+__global__ void __launch_bounds__(LT) k_chol_pivot(const CholJob* jobs, double tol, int* rank_out) {
+  const CholJob J = jobs[blockIdx.x];
+  const int K = J.K;
+  __shared__ double dp[CHOL_MAX];
+  __shared__ int piv[CHOL_MAX];
+  __shared__ double red_v[LT / 64];
+  __shared__ int red_i[LT / 64];
+  __shared__ double s_dmax;
+  __shared__ int s_p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < K; i += LT) {
+    dp[i] = J.G[(int64_t)i * K + i];
+    piv[i] = i;
+  }
+  __syncthreads();
+  // largest diagonal
+  {
+    double m = 0;
+    for (int i = tid; i < K; i += LT) m = fmax(m, dp[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) red_v[w] = m;
+    __syncthreads();
+    if (tid == 0) {
+      double mm = 0;
+      for (int i = 0; i < LT / 64; ++i) mm = fmax(mm, red_v[i]);
+      s_dmax = mm;
+    }
+    __syncthreads();
+  }
+  const double thr = tol * s_dmax;
+  int rank = 0;
+  for (int j = 0; j < K; ++j) {
+    // argmax of remaining pivots (ties: lowest position)
+    double bv = -1.0;
+    int bi = K;
+    for (int i = j + tid; i < K; i += LT) {
+      double v = dp[i];
+      if (v > bv) {
+        bv = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o);
+      int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[w] = bv;
+      red_i[w] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = -1.0;
+      int p = K;
+      for (int i = 0; i < LT / 64; ++i)
+        if (red_v[i] > v || (red_v[i] == v && red_i[i] < p)) {
+          v = red_v[i];
+          p = red_i[i];
+        }
+      s_p = (v > thr && v > 0.0) ? p : -1;
+      if (s_p >= 0 && s_p != j) {
+        double td = dp[j];
+        dp[j] = dp[s_p];
+        dp[s_p] = td;
+        int ti = piv[j];
+        piv[j] = piv[s_p];
+        piv[s_p] = ti;
+      }
+    }
+    __syncthreads();
+    if (s_p < 0) break;
+    const int cj = piv[j];
+    const double rjj = sqrt(dp[j]);
+    if (tid == 0) J.R[(int64_t)j * K + cj] = rjj;
+    for (int i = j + 1 + tid; i < K; i += LT) {
+      const int ci = piv[i];
+      double sacc = J.G[(int64_t)cj * K + ci];
+      for (int l = 0; l < j; ++l) sacc -= J.R[(int64_t)l * K + cj] * J.R[(int64_t)l * K + ci];
+      double r = sacc / rjj;
+      J.R[(int64_t)j * K + ci] = r;
+      dp[i] = fmax(dp[i] - r * r, 0.0);
+    }
+    rank = j + 1;
+    __syncthreads();
+  }
+  if (tid == 0) rank_out[blockIdx.x] = rank;
+}
+
+// ---------------------------------------------------------------------------
+// cyclic Jacobi eigensolver for symmetric n x n (n <= 128) held in LDS;
+// eigenvectors accumulated in global memory. Outputs eigenvalues in
+// descending order and the matching eigenvector columns (row-major n x n).
+struct EigJob {
+  const double* H;  // n x n input
+  double* V;        // n x n eigenvectors (columns), output
+  double* W;        // n eigenvalues, output (descending)
+  double* Vtmp;     // n x n scratch
+  int n;
+  int pad;
+};
+
+__device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
+  // round-robin tournament on n2 (even) players: fixed player n2-1
+  if (i == 0) {
+    p = r;
+    q = n2 - 1;
+  } else {
+    p = (r + i) % (n2 - 1);
+    q = (r - i + (n2 - 1)) % (n2 - 1);
+  }
+  if (p > q) {
+    int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+__global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs, int max_sweeps) {
+  const EigJob J = jobs[blockIdx.x];
+  const int n = J.n;
+  if (n <= 0) return;
+  __shared__ double A[JMAX][JMAX + 1];
+  __shared__ double cs[JMAX / 2][2];
+  __shared__ int pq[JMAX / 2][2];
+  __shared__ double red[LT / 64];
+  __shared__ double s_off, s_tot;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n2 = n + (n & 1);  // pad with a dummy index when n is odd
+  for (int e = tid; e < n * n; e += LT) {
+    int i = e / n, j = e % n;
+    A[i][j] = J.H[e];
+    J.Vtmp[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // convergence: off-diagonal relative to diagonal scale
+    double off = 0, tot = 0;
+    for (int e = tid; e < n * n; e += LT) {
+      int i = e / n, j = e % n;
+      double v = A[i][j] * A[i][j];
+      if (i != j)
+        off += v;
+      else
+        tot += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
+    if (lane == 0) red[w] = off;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0;
+      for (int i = 0; i < LT / 64; ++i) s += red[i];
+      s_off = s;
+    }
+    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (lane == 0) red[w] = tot;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0;
+      for (int i = 0; i < LT / 64; ++i) s += red[i];
+      s_tot = s;
+    }
+    __syncthreads();
+    if (s_off <= 1e-30 * s_tot || s_off == 0.0) break;
+    for (int r = 0; r < n2 - 1; ++r) {
+      const int npairs = n2 / 2;
+      if (tid < npairs) {
+        int p, q;
+        rr_pair(n2, r, tid, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          double apq = A[p][q];
+          if (apq != 0.0) {
+            double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pq[tid][0] = p;
+        pq[tid][1] = q;
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = tid; e < npairs * n; e += LT) {
+        int k = e / n, j = e % n;
+        int p = pq[k][0], q = pq[k][1];
+        if (q >= n) continue;
+        double c = cs[k][0], s = cs[k][1];
+        double ap = A[p][j], aq = A[q][j];
+        A[p][j] = c * ap - s * aq;
+        A[q][j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J ; V <- V J
+      for (int e = tid; e < npairs * n; e += LT) {
+        int k = e / n, i = e % n;
+        int p = pq[k][0], q = pq[k][1];
+        if (q >= n) continue;
+        double c = cs[k][0], s = cs[k][1];
+        double ap = A[i][p], aq = A[i][q];
+        A[i][p] = c * ap - s * aq;
+        A[i][q] = s * ap + c * aq;
+        double vp = J.Vtmp[(int64_t)i * n + p], vq = J.Vtmp[(int64_t)i * n + q];
+        J.Vtmp[(int64_t)i * n + p] = c * vp - s * vq;
+        J.Vtmp[(int64_t)i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // sort eigenvalues descending (ties: lower index first)
+  for (int i = tid; i < n; i += LT) {
+    double v = A[i][i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double u = A[j][j];
+      rank += (u > v) || (u == v && j < i);
+    }
+    J.W[rank] = v;
+    for (int r = 0; r < n; ++r) J.V[(int64_t)r * n + rank] = J.Vtmp[(int64_t)r * n + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of a small SPD p x p matrix in LDS, then the inverse of the upper
+// triangular factor: Rinv with (G = R^T R, Y Rinv orthonormal). One WG each.
+struct OrthJob {
+  const double* G;
+  double* Rinv;
+  int p;
+  int pad;
+};
+
+__global__ void __launch_bounds__(LT) k_chol_inv(const OrthJob* jobs) {
+  const OrthJob J = jobs[blockIdx.x];
+  const int p = J.p;
+  __shared__ double R[JMAX][JMAX + 1];
+  double* X = J.Rinv;  // p x p, column `col` owned by one thread below
+  const int tid = threadIdx.x;
+  for (int e = tid; e < p * p; e += LT) {
+    int i = e / p, j = e % p;
+    R[i][j] = J.G[e];
+  }
+  __syncthreads();
+  // right-looking Cholesky, upper factor in place (R[j][j..])
+  for (int j = 0; j < p; ++j) {
+    if (tid == 0) {
+      double d = R[j][j];
+      R[j][j] = d > 0 ? sqrt(d) : 1e-300;
+    }
+    __syncthreads();
+    const double rjj = R[j][j];
+    for (int i = j + 1 + tid; i < p; i += LT) R[j][i] /= rjj;
+    __syncthreads();
+    for (int e = tid; e < (p - j - 1) * (p - j - 1); e += LT) {
+      int a = j + 1 + e / (p - j - 1), b = j + 1 + e % (p - j - 1);
+      if (b >= a) R[a][b] -= R[j][a] * R[j][b];
+    }
+    __syncthreads();
+  }
+  // inverse of upper triangular R: solve R X = I column by column (parallel
+  // over columns), back substitution
+  for (int col = tid; col < p; col += LT) {
+    for (int i = p - 1; i >= 0; --i) {
+      double sacc = (i == col) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= col; ++k) sacc -= R[i][k] * X[(int64_t)k * p + col];
+      X[(int64_t)i * p + col] = (i <= col) ? sacc / R[i][i] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// global top-chi selection over all groups (one workgroup). Order: larger
+// value, then lower charge rank of the group, then lower index.
+__global__ void __launch_bounds__(LT) k_select(const double* vals, const int* grp, const int* idx,
+                                               const int* crank, int n, int ngroups, int64_t chi,
+                                               double cutoff, int* kept, double* stats) {
+  __shared__ int cnt[1024];
+  __shared__ double red[LT / 64];
+  __shared__ double s_max;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int g = tid; g < ngroups; g += LT) cnt[g] = 0;
+  double m = 0;
+  for (int i = tid; i < n; i += LT) m = fmax(m, vals[i]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) red[w] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double mm = 0;
+    for (int i = 0; i < LT / 64; ++i) mm = fmax(mm, red[i]);
+    s_max = mm;
+  }
+  __syncthreads();
+  double disc = 0;
+  for (int i = tid; i < n; i += LT) {
+    const double v = vals[i];
+    const int cg = crank[grp[i]];
+    int64_t rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double u = vals[j];
+      const int cu = crank[grp[j]];
+      rank += (u > v) || (u == v && (cu < cg || (cu == cg && idx[j] < idx[i])));
+    }
+    bool keep = rank < chi && v > cutoff * s_max && v > 0.0;
+    if (keep)
+      atomicAdd(&cnt[grp[i]], 1);
+    else
+      disc += v * v;
+    if (rank == chi - 1) stats[1] = v;  // chi-th value
+    if (rank == chi) stats[2] = v;      // (chi+1)-th value
+  }
+  for (int o = 32; o > 0; o >>= 1) disc += __shfl_xor(disc, o);
+  if (lane == 0) red[w] = disc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0;
+    for (int i = 0; i < LT / 64; ++i) s += red[i];
+    stats[0] = s;
+  }
+  for (int g = tid; g < ngroups; g += LT) kept[g] = cnt[g];
+}
+
+// ---------------------------------------------------------------------------
+// small elementwise helpers
+__global__ void k_sum_partials(const double* P, int64_t n, int nparts, double* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0;
+  for (int k = 0; k < nparts; ++k) s += P[(int64_t)k * n + i];
+  out[i] = s;
+}
+
+// deterministic pseudo-random start block (splitmix64 of the index)
+__global__ void k_fill_random(double* X, int64_t n, uint64_t seed) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// column scaling: X[:, j] *= f(w[j]) for j < k (row-major rows x ld)
+// mode 0: 1/sqrt(w); mode 1: sqrt(w); mode 2: 1/w
+__global__ void k_scale_cols(double* X, int64_t rows, int64_t ld, int k, const double* w, int mode) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= rows * k) return;
+  int64_t r = e / k;
+  int j = (int)(e % k);
+  double v = w[j];
+  double f = mode == 0 ? 1.0 / sqrt(v) : (mode == 1 ? sqrt(v) : 1.0 / v);
+  X[r * ld + j] *= f;
+}
+
+__global__ void k_sqrt_inplace(double* w, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = sqrt(fmax(w[i], 0.0));
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* x, D* y, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (D)x[i];
+}
+
+static void launch_1d(int64_t n, hipStream_t s, void (*k)(double*, int), double* a, int b) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, a, b);
+  HIPC(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int64_t lda, int ta,
+                             int64_t b_off, int64_t ldb, int tb, int64_t c_off, int64_t ldc) {
+  GemmGroup g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.a_off = a_off;
+  g.lda = lda;
+  g.transA = ta;
+  g.b_off = b_off;
+  g.ldb = ldb;
+  g.transB = tb;
+  g.c_off = c_off;
+  g.ldc = ldc;
+  return g;
+}
+
+// per bond sector q
+struct Sect {
+  int64_t M, N, d;       // rows of A~, cols of B~, bond dim
+  int64_t a_off, b_off;  // into A~ / B~
+  int rA = 0, rB = 0;    // Cholesky ranks
+  int ns = 0;            // order of H
+  int p = 0;             // subspace size (<= JMAX) or ns
+  bool iterate = false;
+  int kept = 0;
+  Q charge;
+  int crank = 0;
+};
+
+// top-p eigenpairs of symmetric H (ns x ns, per sector) -> W (desc), V (ns x p)
+static void eig_top(std::vector<Sect>& S, double* H, const std::vector<int64_t>& hoff, double* V,
+                    const std::vector<int64_t>& voff, double* W, const std::vector<int64_t>& woff, hipStream_t s) {
+  const int ng = (int)S.size();
+  // direct Jacobi for small orders
+  std::vector<EigJob> ej;
+  std::vector<int64_t> tmp_off;
+  int64_t tmp_n = 0;
+  for (int g = 0; g < ng; ++g)
+    if (!S[g].iterate && S[g].ns > 0) {
+      tmp_off.push_back(tmp_n);
+      tmp_n += (int64_t)S[g].ns * S[g].ns;
+    }
+  DBuf<double> tmp(std::max<int64_t>(tmp_n, 1), s);
+  {
+    int t = 0;
+    for (int g = 0; g < ng; ++g)
+      if (!S[g].iterate && S[g].ns > 0) {
+        EigJob j;
+        j.H = H + hoff[g];
+        j.V = V + voff[g];
+        j.W = W + woff[g];
+        j.Vtmp = tmp.p + tmp_off[t++];
+        j.n = S[g].ns;
+        j.pad = 0;
+        ej.push_back(j);
+      }
+  }
+  if (!ej.empty()) {
+    DBuf<EigJob> dj = to_device(ej, s);
+    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p, 40);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+  }
+  // subspace iteration for large orders
+  std::vector<int> it;
+  for (int g = 0; g < ng; ++g)
+    if (S[g].iterate) it.push_back(g);
+  if (it.empty()) return;
+  int64_t qn = 0, gn = 0;
+  std::vector<int64_t> qoff, goff;
+  for (int g : it) {
+    qoff.push_back(qn);
+    qn += (int64_t)S[g].ns * S[g].p;
+    goff.push_back(gn);
+    gn += (int64_t)S[g].p * S[g].p;
+  }
+  DBuf<double> Qb(qn, s), Yb(qn, s), Gb(gn, s), Rb(gn, s), Tb(gn, s), Wv(gn, s), Ww(qn, s), Vt(gn, s);
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)cdiv(qn, 256)), dim3(256), 0, s, Qb.p, qn,
+                     (uint64_t)0x5eedf00dull);
+  HIPC(hipGetLastError());
+  const int iters = 24;
+  auto multiply = [&](const double* Qin, double* Yout) {
+    std::vector<GemmGroup> gs;
+    for (size_t t = 0; t < it.size(); ++t) {
+      const Sect& x = S[it[t]];
+      gs.push_back(plain_group(x.ns, x.p, x.ns, hoff[it[t]], x.ns, 0, qoff[t], x.p, 0, qoff[t], x.p));
+    }
+    // H is stored at H (absolute); Q / Y offsets relative to their buffers
+    std::vector<GemmGroup> g2 = gs;
+    for (size_t t = 0; t < it.size(); ++t) g2[t].a_off = hoff[it[t]];
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g2, H, Qin, Yout, nullptr, s);
+  };
+  auto orthonormalize = [&](double* Y, double* Qout) {
+    std::vector<GemmGroup> gs;
+    for (size_t t = 0; t < it.size(); ++t) {
+      const Sect& x = S[it[t]];
+      gs.push_back(plain_group(x.p, x.p, x.ns, qoff[t], x.p, 1, qoff[t], x.p, 0, goff[t], x.p));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, Y, Y, Gb.p, nullptr, s);
+    std::vector<OrthJob> oj;
+    for (size_t t = 0; t < it.size(); ++t) {
+      OrthJob o;
+      o.G = Gb.p + goff[t];
+      o.Rinv = Rb.p + goff[t];
+      o.p = S[it[t]].p;
+      o.pad = 0;
+      oj.push_back(o);
+    }
+    DBuf<OrthJob> doj = to_device(oj, s);
+    hipLaunchKernelGGL(k_chol_inv, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p);
+    HIPC(hipGetLastError());
+    std::vector<GemmGroup> g3;
+    for (size_t t = 0; t < it.size(); ++t) {
+      const Sect& x = S[it[t]];
+      g3.push_back(plain_group(x.ns, x.p, x.p, qoff[t], x.p, 0, goff[t], x.p, 0, qoff[t], x.p));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g3, Y, Rb.p, Qout, nullptr, s);
+  };
+  // two CholQR passes per orthonormalisation keep Q orthonormal to rounding
+  orthonormalize(Qb.p, Yb.p);
+  orthonormalize(Yb.p, Qb.p);
+  for (int k = 0; k < iters; ++k) {
+    multiply(Qb.p, Yb.p);
+    orthonormalize(Yb.p, Qb.p);
+    orthonormalize(Qb.p, Yb.p);
+    std::swap(Qb.p, Yb.p);
+  }
+  // Rayleigh-Ritz: T = Q^T H Q
+  multiply(Qb.p, Yb.p);
+  {
+    std::vector<GemmGroup> gs;
+    for (size_t t = 0; t < it.size(); ++t) {
+      const Sect& x = S[it[t]];
+      gs.push_back(plain_group(x.p, x.p, x.ns, qoff[t], x.p, 1, qoff[t], x.p, 0, goff[t], x.p));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, Qb.p, Yb.p, Tb.p, nullptr, s);
+  }
+  std::vector<EigJob> ej2;
+  for (size_t t = 0; t < it.size(); ++t) {
+    EigJob j;
+    j.H = Tb.p + goff[t];
+    j.V = Wv.p + goff[t];
+    j.W = W + woff[it[t]];
+    j.Vtmp = Vt.p + goff[t];
+    j.n = S[it[t]].p;
+    j.pad = 0;
+    ej2.push_back(j);
+  }
+  DBuf<EigJob> dj2 = to_device(ej2, s);
+  hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)ej2.size()), dim3(LT), 0, s, dj2.p, 40);
+  HIPC(hipGetLastError());
+  // V = Q Wv  (ns x p)
+  std::vector<GemmGroup> g4;
+  for (size_t t = 0; t < it.size(); ++t) {
+    const Sect& x = S[it[t]];
+    g4.push_back(plain_group(x.ns, x.p, x.p, qoff[t], x.p, 0, goff[t], x.p, 0, voff[it[t]], x.p));
+  }
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g4, Qb.p, Wv.p, V, nullptr, s);
+}
+
+CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff,
+                                int conv, hipStream_t s) {
+  CompressResult res;
+  if (a.sym() != b.sym()) fail(FTN_EINVAL, "symmetry mismatch");
+  if (a.dtype != b.dtype) fail(FTN_ENOTSUP, "operands must have the same dtype");
+  if (conv != FTN_LOCAL && conv != FTN_GLOBAL) fail(FTN_EINVAL, "unknown convention");
+  const Leg& LA = a.legs()[la];
+  const Leg& LB = b.legs()[lb];
+  if (LA.dual == LB.dual) fail(FTN_ECHARGE, "bond legs must have opposite duals");
+  const int sym = a.sym();
+  const int gk = a.dtype == FTN_F64 ? FTN_GEMM_F64 : FTN_GEMM_F32;
+  auto P = dot_plan(a, b, {la}, {lb}, FTN_GLOBAL, gk, s);
+  DotPlanView pv = dot_plan_view(*P);
+  // fused matrices (FP64)
+  DBuf<double> At(pv.asz, s), Bt(pv.bsz, s);
+  if (a.dtype == FTN_F64) {
+    run_perm(0, a.S(), a.dtype, *pv.pa, a.data, At.p, s);
+    run_perm(0, b.S(), b.dtype, *pv.pb, b.data, Bt.p, s);
+  } else {
+    DBuf<float> a32(pv.asz, s), b32(pv.bsz, s);
+    run_perm(0, a.S(), a.dtype, *pv.pa, a.data, a32.p, s);
+    run_perm(0, b.S(), b.dtype, *pv.pb, b.data, b32.p, s);
+    if (pv.asz)
+      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)cdiv(pv.asz, 256)), dim3(256), 0, s, a32.p,
+                         At.p, pv.asz);
+    if (pv.bsz)
+      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)cdiv(pv.bsz, 256)), dim3(256), 0, s, b32.p,
+                         Bt.p, pv.bsz);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+  }
+  // sectors: one GEMM group per bond charge present on both legs
+  std::vector<Sect> S;
+  for (size_t gi = 0; gi < pv.groups.size(); ++gi) {
+    const GemmGroup& g = pv.groups[gi];
+    if (g.K == 0) continue;  // charge absent on one side: contributes nothing
+    Sect x;
+    x.M = g.M;
+    x.N = g.N;
+    x.d = g.K;
+    x.a_off = g.a_off;
+    x.b_off = g.b_off;
+    x.charge = q_signed(sym, LA.dual, pv.gq[gi]);  // Q = sigma(la) q
+    S.push_back(x);
+  }
+  const int ng = (int)S.size();
+  {
+    std::vector<int> order(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return q_lt(S[x].charge, S[y].charge); });
+    for (int r = 0; r < ng; ++r) S[order[r]].crank = r;
+  }
+  // Gram matrices with split-K
+  std::vector<int64_t> goffA(ng), goffB(ng);
+  int64_t gsz = 0;
+  for (int g = 0; g < ng; ++g) {
+    goffA[g] = gsz;
+    gsz += S[g].d * S[g].d;
+    goffB[g] = gsz;
+    gsz += S[g].d * S[g].d;
+  }
+  DBuf<double> Gm(std::max<int64_t>(gsz, 1), s);
+  {
+    int64_t tiles = 0;
+    for (auto& x : S) tiles += 2 * cdiv(x.d, 64) * cdiv(x.d, 64);
+    int64_t maxk = 1;
+    for (auto& x : S) maxk = std::max(maxk, std::max(x.M, x.N));
+    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, std::max<int64_t>(tiles, 1)), cdiv(maxk, 256)));
+    DBuf<double> part((int64_t)nsplit * std::max<int64_t>(gsz, 1), s);
+    std::vector<GemmGroup> gA, gB;
+    for (int k = 0; k < nsplit; ++k)
+      for (int g = 0; g < ng; ++g) {
+        const Sect& x = S[g];
+        int64_t ca = cdiv(x.M, nsplit), k0 = std::min<int64_t>(k * ca, x.M), k1 = std::min<int64_t>(k0 + ca, x.M);
+        // G_A = A~^T A~ : op(A) = A~^T (transA, lda = d), op(B) = A~ (ldb = d)
+        gA.push_back(plain_group(x.d, x.d, k1 - k0, x.a_off + k0 * x.d, x.d, 1, x.a_off + k0 * x.d, x.d, 0,
+                                 (int64_t)k * gsz + goffA[g], x.d));
+        int64_t cb = cdiv(x.N, nsplit), j0 = std::min<int64_t>(k * cb, x.N), j1 = std::min<int64_t>(j0 + cb, x.N);
+        // G_B = B~ B~^T : op(A) = B~ (lda = N), op(B) = B~^T (transB, ldb = N)
+        gB.push_back(plain_group(x.d, x.d, j1 - j0, x.b_off + j0, x.N, 0, x.b_off + j0, x.N, 1,
+                                 (int64_t)k * gsz + goffB[g], x.d));
+      }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gA, At.p, At.p, part.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gB, Bt.p, Bt.p, part.p, nullptr, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
+    HIPC(hipGetLastError());
+  }
+  // pivoted Cholesky of both Gram matrices
+  DBuf<double> Rm(std::max<int64_t>(gsz, 1), s);
+  HIPC(hipMemsetAsync(Rm.p, 0, std::max<int64_t>(gsz, 1) * 8, s));
+  {
+    std::vector<CholJob> cj;
+    for (int g = 0; g < ng; ++g) {
+      if (S[g].d > CHOL_MAX) fail(FTN_ENOTSUP, "bond sector larger than 4096");
+      cj.push_back(CholJob{Gm.p + goffA[g], Rm.p + goffA[g], (int)S[g].d, 0});
+      cj.push_back(CholJob{Gm.p + goffB[g], Rm.p + goffB[g], (int)S[g].d, 0});
+    }
+    DBuf<CholJob> dcj = to_device(cj, s);
+    DBuf<int> drank(2 * ng, s);
+    if (ng) {
+      hipLaunchKernelGGL(k_chol_pivot, dim3(2 * ng), dim3(LT), 0, s, dcj.p, 1e-13, drank.p);
+      HIPC(hipGetLastError());
+    }
+    std::vector<int> rk(2 * ng);
+    if (ng) HIPC(hipMemcpyAsync(rk.data(), drank.p, 2 * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    for (int g = 0; g < ng; ++g) {
+      S[g].rA = rk[2 * g];
+      S[g].rB = rk[2 * g + 1];
+    }
+  }
+  // X = R_A R_B^T (rA x rB); H = X^T X (rB <= rA) or X X^T
+  std::vector<int64_t> xoff(ng), hoff(ng), voff(ng), woff(ng), uoff(ng);
+  int64_t xs = 0, hs = 0, vs = 0, ws = 0, us = 0;
+  for (int g = 0; g < ng; ++g) {
+    Sect& x = S[g];
+    x.ns = std::min(x.rA, x.rB);
+    x.iterate = x.ns > JMAX;
+    x.p = x.iterate ? JMAX : x.ns;
+    xoff[g] = xs;
+    xs += (int64_t)x.rA * x.rB;
+    hoff[g] = hs;
+    hs += (int64_t)x.ns * x.ns;
+    voff[g] = vs;
+    vs += (int64_t)x.ns * x.p;
+    woff[g] = ws;
+    ws += std::max(x.p, 1);
+    uoff[g] = us;
+    us += (int64_t)std::max(x.rA, x.rB) * std::max(x.p, 1);
+  }
+  DBuf<double> Xm(std::max<int64_t>(xs, 1), s), Hm(std::max<int64_t>(hs, 1), s), Vm(std::max<int64_t>(vs, 1), s),
+      Wm(std::max<int64_t>(ws, 1), s), Um(std::max<int64_t>(us, 1), s);
+  {
+    std::vector<GemmGroup> gx, gh;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      // R_A rows are rA x d (row-major, ld d); X = R_A R_B^T
+      gx.push_back(plain_group(x.rA, x.rB, x.d, goffA[g], x.d, 0, goffB[g], x.d, 1, xoff[g], x.rB));
+      if (x.rB <= x.rA)  // H = X^T X (rB x rB)
+        gh.push_back(plain_group(x.rB, x.rB, x.rA, xoff[g], x.rB, 1, xoff[g], x.rB, 0, hoff[g], x.rB));
+      else  // H = X X^T (rA x rA)
+        gh.push_back(plain_group(x.rA, x.rA, x.rB, xoff[g], x.rB, 0, xoff[g], x.rB, 1, hoff[g], x.rA));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rm.p, Rm.p, Xm.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Xm.p, Xm.p, Hm.p, nullptr, s);
+  }
+  eig_top(S, Hm.p, hoff, Vm.p, voff, Wm.p, woff, s);
+  // singular values = sqrt(eigenvalues); selection
+  launch_1d(std::max<int64_t>(ws, 1), s, k_sqrt_inplace, Wm.p, (int)std::max<int64_t>(ws, 1));
+  {
+    std::vector<int> grp, idx, crank(ng);
+    std::vector<int64_t> pos;
+    for (int g = 0; g < ng; ++g) {
+      crank[g] = S[g].crank;
+      for (int i = 0; i < S[g].p; ++i) {
+        grp.push_back(g);
+        idx.push_back(i);
+        pos.push_back(woff[g] + i);
+      }
+    }
+    const int n = (int)grp.size();
+    std::vector<double> hw(std::max<int64_t>(ws, 1));
+    HIPC(hipMemcpyAsync(hw.data(), Wm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::vector<double> vals(n);
+    for (int i = 0; i < n; ++i) vals[i] = hw[pos[i]];
+    DBuf<double> dv = to_device(vals, s);
+    DBuf<int> dg = to_device(grp, s), di = to_device(idx, s), dc = to_device(crank, s);
+    DBuf<int> dk(std::max(ng, 1), s);
+    DBuf<double> dst(4, s);
+    std::vector<double> st(4, 0.0);
+    HIPC(hipMemsetAsync(dst.p, 0, 32, s));
+    if (ng > 1024) fail(FTN_ENOTSUP, "more than 1024 bond sectors");
+    if (n)
+      hipLaunchKernelGGL(k_select, dim3(1), dim3(LT), 0, s, dv.p, dg.p, di.p, dc.p, n, ng, chi, cutoff, dk.p, dst.p);
+    HIPC(hipGetLastError());
+    std::vector<int> kept(std::max(ng, 1), 0);
+    if (n) HIPC(hipMemcpyAsync(kept.data(), dk.p, ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(st.data(), dst.p, 32, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    res.discarded = st[0];
+    // values dropped because a side's Gram rank was below the sector dim are
+    // exactly zero and add nothing
+    double a1 = st[1], a2 = st[2];
+    res.near_tie = (a2 > 0 && std::fabs(a1 - a2) <= 1e3 * 2.220446049250313e-16 * std::fabs(a1));
+    for (int g = 0; g < ng; ++g) S[g].kept = kept[g];
+    for (int g = 0; g < ng; ++g)
+      for (int i = 0; i < S[g].kept; ++i) res.svals.push_back(hw[woff[g] + i]);
+    std::sort(res.svals.begin(), res.svals.end(), std::greater<double>());
+  }
+  // projectors. With H = X^T X: V (rB x k) from H, U = X V S^-1.
+  // With H = X X^T: U (rA x k) from H, V = X^T U S^-1.
+  // P_A = R_B^T V S^-1/2 (d x k); P_B = S^-1/2 U^T R_A (k x d)
+  std::vector<int64_t> pa_off(ng), pb_off(ng);
+  int64_t pas = 0;
+  for (int g = 0; g < ng; ++g) {
+    pa_off[g] = pas;
+    pas += S[g].d * S[g].kept;
+    pb_off[g] = pas;
+    pas += S[g].kept * S[g].d;
+  }
+  DBuf<double> PAB(std::max<int64_t>(pas, 1), s);
+  {
+    // the other singular vectors: O = X V or X^T U (then scaled by 1/s)
+    std::vector<GemmGroup> go;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.kept) continue;
+      if (x.rB <= x.rA)  // U = X V : (rA x rB)(rB x k)
+        go.push_back(plain_group(x.rA, x.kept, x.rB, xoff[g], x.rB, 0, voff[g], x.p, 0, uoff[g], x.kept));
+      else  // V = X^T U : (rB x rA)(rA x k)
+        go.push_back(plain_group(x.rB, x.kept, x.rA, xoff[g], x.rB, 1, voff[g], x.p, 0, uoff[g], x.kept));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, go, Xm.p, Vm.p, Um.p, nullptr, s);
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.kept) continue;
+      // O = X V (rows rA) or X^T U (rows rB); O / s are the other singular
+      // vectors, and both sides are then scaled by s^-1/2
+      const int64_t rows = x.rB <= x.rA ? x.rA : x.rB;
+      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
+                         rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 2);
+      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv((int64_t)x.ns * x.kept, 256)), dim3(256), 0, s,
+                         Vm.p + voff[g], (int64_t)x.ns, (int64_t)x.p, x.kept, Wm.p + woff[g], 0);
+      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
+                         rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 0);
+      HIPC(hipGetLastError());
+    }
+    // now: Vs = V S^-1/2 and Us = U S^-1/2 (for whichever side)
+    std::vector<GemmGroup> gpa, gpb;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.kept) continue;
+      if (x.rB <= x.rA) {
+        // eigen side = V (rB x k, ld p) in Vm; other = U (rA x k, ld k) in Um
+        // P_A = R_B^T V : (d x rB)(rB x k)
+        gpa.push_back(plain_group(x.d, x.kept, x.rB, goffB[g], x.d, 1, voff[g], x.p, 0, pa_off[g], x.kept));
+        // P_B = U^T R_A : (k x rA)(rA x d)
+        gpb.push_back(plain_group(x.kept, x.d, x.rA, uoff[g], x.kept, 1, goffA[g], x.d, 0, pb_off[g], x.d));
+      } else {
+        // eigen side = U (rA x k, ld p) in Vm; other = V (rB x k, ld k) in Um
+        gpa.push_back(plain_group(x.d, x.kept, x.rB, goffB[g], x.d, 1, uoff[g], x.kept, 0, pa_off[g], x.kept));
+        gpb.push_back(plain_group(x.kept, x.d, x.rA, voff[g], x.p, 1, goffA[g], x.d, 0, pb_off[g], x.d));
+      }
+    }
+    // operand buffers differ per case; run each case separately
+    std::vector<GemmGroup> pa1, pa2, pb1, pb2;
+    {
+      int t = 0;
+      for (int g = 0; g < ng; ++g) {
+        const Sect& x = S[g];
+        if (!x.kept) continue;
+        if (x.rB <= x.rA) {
+          pa1.push_back(gpa[t]);
+          pb1.push_back(gpb[t]);
+        } else {
+          pa2.push_back(gpa[t]);
+          pb2.push_back(gpb[t]);
+        }
+        ++t;
+      }
+    }
+    if (!pa1.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pa1, Rm.p, Vm.p, PAB.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pb1, Um.p, Rm.p, PAB.p, nullptr, s);
+    }
+    if (!pa2.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pa2, Rm.p, Um.p, PAB.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pb2, Vm.p, Rm.p, PAB.p, nullptr, s);
+    }
+  }
+  // projector tensors: P_A legs (conj of la, new) and P_B legs (new', conj of lb)
+  std::vector<int> order(ng);
+  for (int g = 0; g < ng; ++g) order[g] = g;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return q_lt(S[x].charge, S[y].charge); });
+  Leg nla, nlb;  // new bond legs
+  nla.dual = LA.dual;
+  nlb.dual = LB.dual;
+  for (int g : order)
+    if (S[g].kept) {
+      nla.q.push_back(S[g].charge);
+      nla.d.push_back(S[g].kept);
+      nlb.q.push_back(S[g].charge);
+      nlb.d.push_back(S[g].kept);
+    }
+  Leg cla = LA, clb = LB;  // partners of la / lb
+  cla.dual = 1 - LA.dual;
+  clb.dual = 1 - LB.dual;
+  Q zero{0, 0};
+  auto PA = make_tensor(sym, FTN_F64, {cla, nla}, zero, s, true);
+  auto PB = make_tensor(sym, FTN_F64, {nlb, clb}, zero, s, true);
+  {
+    // block (q, q) of P_A has shape d_q x k_q; of P_B k_q x d_q
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.kept) continue;
+      int32_t ka[2] = {LA.find(x.charge), nla.find(x.charge)};
+      int32_t kb[2] = {nlb.find(x.charge), LB.find(x.charge)};
+      int64_t ba = block_index(PA->S(), ka), bb = block_index(PB->S(), kb);
+      if (ba < 0 || bb < 0) fail(FTN_EINVAL, "internal: projector block missing");
+      HIPC(hipMemcpyAsync((double*)PA->data + PA->S().offsets[ba], PAB.p + pa_off[g], x.d * x.kept * 8,
+                          hipMemcpyDeviceToDevice, s));
+      HIPC(hipMemcpyAsync((double*)PB->data + PB->S().offsets[bb], PAB.p + pb_off[g], x.kept * x.d * 8,
+                          hipMemcpyDeviceToDevice, s));
+    }
+  }
+  std::unique_ptr<Tensor> PAc, PBc;
+  const Tensor* pa_t = PA.get();
+  const Tensor* pb_t = PB.get();
+  if (a.dtype != FTN_F64) {
+    PAc = op_cast(*PA, a.dtype, s);
+    PBc = op_cast(*PB, a.dtype, s);
+    pa_t = PAc.get();
+    pb_t = PBc.get();
+  }
+  // A' = F(A P_A) with the new leg moved back to la; B' = F(P_B B) likewise
+  auto A1 = op_ftensordot(a, *pa_t, {la}, {0}, FTN_GLOBAL, gk, s);
+  auto B1 = op_ftensordot(*pb_t, b, {1}, {lb}, FTN_GLOBAL, gk, s);
+  const int na = a.ndim(), nb = b.ndim();
+  std::vector<int> perm_a(na), perm_b(nb);
+  {
+    // A1 legs: rest(A) ++ [new]; want new at position la
+    int t = 0;
+    for (int i = 0; i < na; ++i) perm_a[i] = (i == la) ? (na - 1) : t++;
+    // B1 legs: [new] ++ rest(B); want new at position lb
+    t = 1;
+    for (int i = 0; i < nb; ++i) perm_b[i] = (i == lb) ? 0 : t++;
+  }
+  res.a = op_ftranspose(*A1, perm_a, s);
+  res.b = op_ftranspose(*B1, perm_b, s);
+  (void)conv;
+  return res;
+}
+
+}  // namespace ftn

@@ -1,0 +1,455 @@
+// Signed permutes: fermionic transposition (Eq. transposition), arrow
+// reversal (Sec. II.E), fusion (Sec. IV.A) and the block <-> fused-matrix
+// copies around the grouped GEMM. The sign of every block is computed on the
+// device from the parity bits of its sectors (integer, bit-exact).
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+#include "common.h"
+
+namespace ftn {
+
+SignOp make_signop(int ndim, const int* perm, int nA, int nG) {
+  SignOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.ndim = ndim;
+  op.nA = nA;
+  op.nG = nG;
+  for (int p = 0; p < ndim; ++p) op.perm[p] = perm[p];
+  // inverted pairs (p < u, perm[p] > perm[u]) contribute p_{perm[p]} p_{perm[u]}
+  for (int p = 0; p < ndim; ++p) {
+    uint32_t m = 0;
+    for (int u = p + 1; u < ndim; ++u)
+      if (perm[u] < perm[p]) m |= 1u << perm[u];
+    op.kmask[p] = m;
+  }
+  return op;
+}
+
+__device__ inline int sign_bit(const SignOp& op, uint32_t P, int extra) {
+  int e = op.phase ^ extra;
+  for (int p = 0; p < op.ndim; ++p)
+    if ((P >> op.perm[p]) & 1u) e ^= __popc(P & op.kmask[p]) & 1;
+  int n = __popc(P & op.rev_mask);
+  e ^= ((n * (n - 1)) >> 1) & 1;
+  e ^= __popc(P & op.flip_mask) & 1;
+  return e & 1;
+}
+
+constexpr int PM_THREADS = 256;
+constexpr int PM_TILE = 2048;  // elements of one block handled by one workgroup
+
+template <typename T, int DIR>
+__global__ void __launch_bounds__(PM_THREADS)
+    k_block_matrix(SignOp op, const PermTask* __restrict__ tasks, const int64_t* __restrict__ tile_start,
+                   int64_t ntasks, const int32_t* __restrict__ shapes, const int64_t* __restrict__ offsets,
+                   const uint32_t* __restrict__ parmask, const T* __restrict__ src, T* __restrict__ dst,
+                   T alpha) {
+  __shared__ int64_t s_str[MAXD];
+  __shared__ int32_t s_dim[MAXD];
+  __shared__ int64_t s_info[4];  // task, block offset, nelem, moff
+  __shared__ T s_val;
+  const int64_t tile = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int64_t lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= tile)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const PermTask tk = tasks[lo];
+    s_info[0] = tk.skip ? -1 : lo;
+    if (!tk.skip) {
+      const int64_t b = tk.block;
+      const int n = op.ndim;
+      for (int j = 0; j < n; ++j) s_dim[j] = shapes[b * n + j];
+      // strides of the strided side, per destination position, then per leg
+      const int nA = op.nA, nAG = op.nA + op.nG;
+      int64_t st = 1;
+      for (int p = n - 1; p >= nAG; --p) {
+        s_str[op.perm[p]] = st;
+        st *= s_dim[op.perm[p]];
+      }
+      st = tk.bext;
+      int64_t g = 1;
+      for (int p = nAG - 1; p >= nA; --p) {
+        s_str[op.perm[p]] = st * g;
+        g *= s_dim[op.perm[p]];
+      }
+      int64_t gx = tk.gext ? tk.gext : g;
+      st = tk.bext * gx;
+      for (int p = nA - 1; p >= 0; --p) {
+        s_str[op.perm[p]] = st;
+        st *= s_dim[op.perm[p]];
+      }
+      s_info[1] = offsets[b];
+      s_info[2] = offsets[b + 1] - offsets[b];
+      s_info[3] = tk.moff;
+      int e = sign_bit(op, parmask[b], tk.extra);
+      s_val = e ? -alpha : alpha;
+    }
+  }
+  __syncthreads();
+  if (s_info[0] < 0) return;
+  const int n = op.ndim;
+  const int64_t first = (tile - tile_start[s_info[0]]) * PM_TILE;
+  const int64_t nel = s_info[2];
+  const int64_t boff = s_info[1], moff = s_info[3];
+  const T v = s_val;
+  for (int j = threadIdx.x; j < PM_TILE; j += PM_THREADS) {
+    int64_t e = first + j;
+    if (e >= nel) break;
+    uint32_t r = (uint32_t)e;  // one block stays below 2^32 entries
+    int64_t addr = moff;
+    for (int d = n - 1; d >= 0; --d) {
+      uint32_t dd = (uint32_t)s_dim[d];
+      uint32_t q = r / dd;
+      addr += (int64_t)(r - q * dd) * s_str[d];
+      r = q;
+    }
+    if (DIR == 0)
+      dst[addr] = v * src[boff + e];
+    else
+      dst[boff + e] = v * src[addr];
+  }
+}
+
+void perm_plan_tiles(PermPlan& p, const std::vector<int64_t>& task_elems, hipStream_t s) {
+  p.ntasks = (int64_t)task_elems.size();
+  std::vector<int64_t> ts(p.ntasks);
+  int64_t tiles = 0;
+  p.nelem = 0;
+  for (int64_t k = 0; k < p.ntasks; ++k) {
+    ts[k] = tiles;
+    tiles += cdiv(task_elems[k], PM_TILE);
+    p.nelem += task_elems[k];
+  }
+  if (tiles > 0x7fffffffLL) fail(FTN_EINVAL, "permute too large");
+  p.ntiles = tiles;
+  p.tile_start = DBuf<int64_t>(ts.size(), s);
+  p.tile_start.upload(ts.data(), ts.size());
+  HIPC(hipStreamSynchronize(s));
+}
+
+void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const void* src, void* dst,
+              hipStream_t s, double alpha) {
+  if (p.ntiles == 0) return;
+  void* tok = prof_begin(s);
+  if (dtype == FTN_F64) {
+    auto k = dir == 0 ? k_block_matrix<double, 0> : k_block_matrix<double, 1>;
+    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
+                       p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
+                       (const double*)src, (double*)dst, alpha);
+  } else {
+    auto k = dir == 0 ? k_block_matrix<float, 0> : k_block_matrix<float, 1>;
+    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
+                       p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
+                       (const float*)src, (float*)dst, (float)alpha);
+  }
+  HIPC(hipGetLastError());
+  prof_end(tok, s, FTN_PROF_PERMUTE, 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4));
+}
+
+// ---------------------------------------------------------------------------
+// unary key matching on the device
+__global__ void k_unary_tasks(int n, SignOp op, const int32_t* __restrict__ skeys, int64_t snb,
+                              const int32_t* __restrict__ dkeys, const int64_t* __restrict__ doff,
+                              int64_t dnb, const int32_t* __restrict__ remap,
+                              const int32_t* __restrict__ rbase, PermTask* tasks) {
+  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= snb) return;
+  int32_t nk[MAXD];
+  for (int p = 0; p < n; ++p) {
+    int leg = op.perm[p];
+    nk[p] = remap[rbase[leg] + skeys[b * n + leg]];
+  }
+  int64_t lo = 0, hi = dnb;
+  int64_t found = -1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    int c = 0;
+    for (int i = 0; i < n && !c; ++i) {
+      int32_t x = dkeys[mid * n + i];
+      c = x < nk[i] ? -1 : (x > nk[i] ? 1 : 0);
+    }
+    if (c == 0) {
+      found = mid;
+      break;
+    }
+    if (c < 0)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  PermTask t;
+  t.block = b;
+  t.moff = found >= 0 ? doff[found] : 0;
+  t.gext = 0;
+  t.bext = 1;
+  t.skip = found < 0;
+  t.extra = 0;
+  tasks[b] = t;
+}
+
+void unary_tasks(const Structure& src, const Structure& dst, const SignOp& op,
+                 const std::vector<int32_t>& remap, const std::vector<int>& remap_base,
+                 DBuf<PermTask>& tasks, hipStream_t s) {
+  tasks = DBuf<PermTask>(src.nblocks, s);
+  if (!src.nblocks) return;
+  std::vector<int32_t> rb(remap_base.begin(), remap_base.end());
+  DBuf<int32_t> drm = to_device(remap, s);
+  DBuf<int32_t> drb = to_device(rb, s);
+  hipLaunchKernelGGL(k_unary_tasks, dim3((unsigned)cdiv(src.nblocks, 128)), dim3(128), 0, s, src.ndim,
+                     op, src.d_keys.p, src.nblocks, dst.d_keys.p, dst.d_offsets.p, dst.nblocks, drm.p,
+                     drb.p, tasks.p);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
+}
+
+std::vector<int64_t> block_sizes(const Structure& s) {
+  std::vector<int64_t> v(s.nblocks);
+  for (int64_t b = 0; b < s.nblocks; ++b) v[b] = s.offsets[b + 1] - s.offsets[b];
+  return v;
+}
+
+// shared driver of the unary signed permutes
+static std::unique_ptr<Tensor> unary_signed(const Tensor& a, const std::vector<Leg>& out_legs,
+                                            const SignOp& op, const std::vector<int32_t>& remap,
+                                            const std::vector<int>& rbase, hipStream_t s,
+                                            const Q* total = nullptr) {
+  auto out = make_tensor(a.sym(), a.dtype, out_legs, total ? *total : a.total(), s, false);
+  if (a.ndim() == 0) {
+    if (a.size()) {
+      HIPC(hipMemcpyAsync(out->data, a.data, a.esize(), hipMemcpyDeviceToDevice, s));
+      if (op.phase) {
+        auto neg = op_scale(*out, -1.0, s);
+        return neg;
+      }
+    }
+    return out;
+  }
+  PermPlan pp;
+  pp.op = op;
+  unary_tasks(a.S(), out->S(), op, remap, rbase, pp.tasks, s);
+  if (out->size() != a.size()) fail(FTN_EINVAL, "internal: unary permute changed the size");
+  perm_plan_tiles(pp, block_sizes(a.S()), s);
+  run_perm(0, a.S(), a.dtype, pp, a.data, out->data, s);
+  return out;
+}
+
+static void identity_remap(const Structure& a, std::vector<int32_t>& remap, std::vector<int>& rbase) {
+  for (int i = 0; i < a.ndim; ++i) {
+    rbase.push_back((int)remap.size());
+    for (int k = 0; k < a.legs[i].nsect(); ++k) remap.push_back(k);
+  }
+}
+
+std::unique_ptr<Tensor> op_ftranspose(const Tensor& a, const std::vector<int>& perm, hipStream_t s) {
+  const int n = a.ndim();
+  if ((int)perm.size() != n) fail(FTN_EINVAL, "permutation length differs from ndim");
+  std::vector<int> chk(perm);
+  std::sort(chk.begin(), chk.end());
+  for (int i = 0; i < n; ++i)
+    if (chk[i] != i) fail(FTN_EINVAL, "not a permutation");
+  std::vector<Leg> legs(n);
+  for (int p = 0; p < n; ++p) legs[p] = a.legs()[perm[p]];
+  SignOp op = make_signop(n, perm.data(), n, 0);
+  std::vector<int32_t> remap;
+  std::vector<int> rbase;
+  identity_remap(a.S(), remap, rbase);
+  return unary_signed(a, legs, op, remap, rbase, s);
+}
+
+// conjugated leg: charges negated and re-sorted; remap old sector -> new
+static Leg conj_leg(int sym, const Leg& l, std::vector<int32_t>& remap) {
+  std::vector<std::pair<Q, int>> v;
+  for (int k = 0; k < l.nsect(); ++k) v.push_back({q_neg(sym, l.q[k]), k});
+  std::sort(v.begin(), v.end(), [](const std::pair<Q, int>& x, const std::pair<Q, int>& y) {
+    return q_lt(x.first, y.first);
+  });
+  Leg o;
+  o.dual = 1 - l.dual;
+  remap.assign(l.nsect(), 0);
+  for (int i = 0; i < (int)v.size(); ++i) {
+    o.q.push_back(v[i].first);
+    o.d.push_back(l.d[v[i].second]);
+    remap[v[i].second] = i;
+  }
+  return o;
+}
+
+std::unique_ptr<Tensor> op_flip_dual(const Tensor& a, int leg, int with_sign, hipStream_t s) {
+  const int n = a.ndim();
+  if (leg < 0 || leg >= n) fail(FTN_EINVAL, "leg out of range");
+  std::vector<Leg> legs = a.legs();
+  std::vector<int32_t> lr;
+  legs[leg] = conj_leg(a.sym(), a.legs()[leg], lr);
+  std::vector<int32_t> remap;
+  std::vector<int> rbase;
+  for (int i = 0; i < n; ++i) {
+    rbase.push_back((int)remap.size());
+    if (i == leg)
+      remap.insert(remap.end(), lr.begin(), lr.end());
+    else
+      for (int k = 0; k < a.legs()[i].nsect(); ++k) remap.push_back(k);
+  }
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  SignOp op = make_signop(n, perm.data(), n, 0);
+  bool sign = with_sign < 0 ? a.legs()[leg].dual == 1 : with_sign != 0;
+  if (sign) op.flip_mask = 1u << leg;
+  return unary_signed(a, legs, op, remap, rbase, s);
+}
+
+std::unique_ptr<Tensor> op_dagger(const Tensor& a, hipStream_t s) {
+  const int n = a.ndim();
+  std::vector<int> perm(n);
+  std::vector<Leg> legs(n);
+  for (int p = 0; p < n; ++p) {
+    perm[p] = n - 1 - p;
+    legs[p] = a.legs()[n - 1 - p];
+    legs[p].dual = 1 - legs[p].dual;
+  }
+  SignOp op = make_signop(n, perm.data(), n, 0);
+  // the Koszul sign of the full reversal equals the pairwise-product sign
+  // over all legs; adding the latter cancels it (a plain relabelling)
+  op.rev_mask = n ? (uint32_t)((1ull << n) - 1) : 0u;
+  std::vector<int32_t> remap;
+  std::vector<int> rbase;
+  identity_remap(a.S(), remap, rbase);
+  Q tot = q_neg(a.sym(), a.total());
+  return unary_signed(a, legs, op, remap, rbase, s, &tot);
+}
+
+std::unique_ptr<Tensor> op_leg_sign(const Tensor& a, int leg, hipStream_t s) {
+  const int n = a.ndim();
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  SignOp op = make_signop(n, perm.data(), n, 0);
+  op.flip_mask = 1u << leg;
+  std::vector<int32_t> remap;
+  std::vector<int> rbase;
+  identity_remap(a.S(), remap, rbase);
+  return unary_signed(a, a.legs(), op, remap, rbase, s);
+}
+
+// ---------------------------------------------------------------------------
+// fusion (Sec. IV.A)
+std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, int conv, int rev,
+                                hipStream_t s) {
+  const int n = a.ndim();
+  const int m = (int)glegs.size();
+  const int sym = a.sym();
+  if (m < 1) fail(FTN_EINVAL, "fuse needs at least one leg");
+  std::vector<int> isg(n, 0);
+  for (int l : glegs) {
+    if (l < 0 || l >= n || isg[l]) fail(FTN_EINVAL, "bad fuse legs");
+    isg[l] = 1;
+  }
+  std::vector<int> rest;
+  for (int i = 0; i < n; ++i)
+    if (!isg[i]) rest.push_back(i);
+  int pos = 0;
+  for (int i : rest)
+    if (i < glegs[0]) ++pos;
+  std::vector<int> order(rest.begin(), rest.begin() + pos);
+  order.insert(order.end(), glegs.begin(), glegs.end());
+  order.insert(order.end(), rest.begin() + pos, rest.end());
+  // components after dual alignment
+  const int d0 = a.legs()[glegs[0]].dual;
+  std::vector<Leg> comp(m);
+  std::vector<std::vector<int32_t>> cremap(m);
+  uint32_t flip = 0;
+  for (int j = 0; j < m; ++j) {
+    const Leg& l = a.legs()[glegs[j]];
+    if (l.dual != d0) {
+      comp[j] = conj_leg(sym, l, cremap[j]);
+      if (conv == FTN_LOCAL && l.dual == 1) flip |= 1u << glegs[j];
+    } else {
+      comp[j] = l;
+      cremap[j].resize(l.nsect());
+      std::iota(cremap[j].begin(), cremap[j].end(), 0);
+    }
+  }
+  bool do_rev = conv == FTN_LOCAL ? d0 == 1 : rev != 0;
+  // fused leg: combos in lexicographic order grouped by total charge
+  std::map<std::pair<int, int>, std::vector<std::pair<std::vector<int>, int64_t>>> groups;
+  std::vector<int> idx(m, 0);
+  int64_t ncomb = 1;
+  for (auto& c : comp) ncomb *= c.nsect();
+  for (int64_t c = 0; c < ncomb; ++c) {
+    int64_t r = c;
+    for (int j = m - 1; j >= 0; --j) {
+      idx[j] = (int)(r % comp[j].nsect());
+      r /= comp[j].nsect();
+    }
+    Q qq{0, 0};
+    int64_t d = 1;
+    for (int j = 0; j < m; ++j) {
+      qq = q_add(sym, qq, comp[j].q[idx[j]]);
+      d *= comp[j].d[idx[j]];
+    }
+    groups[{qq.a, qq.b}].push_back({idx, d});
+  }
+  Leg fl;
+  fl.dual = d0;
+  std::map<std::vector<int>, std::pair<int, int64_t>> table;
+  int si = 0;
+  for (auto& g : groups) {
+    int64_t off = 0;
+    for (auto& e : g.second) {
+      table[e.first] = {si, off};
+      off += e.second;
+    }
+    fl.q.push_back(Q{g.first.first, g.first.second});
+    fl.d.push_back(off);
+    ++si;
+  }
+  std::vector<Leg> out_legs;
+  for (int i = 0; i < pos; ++i) out_legs.push_back(a.legs()[rest[i]]);
+  out_legs.push_back(fl);
+  for (size_t i = pos; i < rest.size(); ++i) out_legs.push_back(a.legs()[rest[i]]);
+  auto out = make_tensor(sym, a.dtype, out_legs, a.total(), s, true);
+  const Structure& A = a.S();
+  const Structure& O = out->S();
+  SignOp op = make_signop(n, order.data(), pos, m);
+  op.flip_mask = flip;
+  if (do_rev)
+    for (int l : glegs) op.rev_mask |= 1u << l;
+  // tasks (host): each source block writes a slab of one output block
+  std::vector<PermTask> tasks(A.nblocks);
+  std::vector<int32_t> okey(O.ndim);
+  std::vector<int> ck(m);
+  for (int64_t b = 0; b < A.nblocks; ++b) {
+    const int32_t* k = &A.keys[b * n];
+    for (int j = 0; j < m; ++j) ck[j] = cremap[j][k[glegs[j]]];
+    auto te = table.at(ck);
+    int t = 0;
+    for (int i = 0; i < pos; ++i) okey[t++] = k[rest[i]];
+    okey[t++] = te.first;
+    for (size_t i = pos; i < rest.size(); ++i) okey[t++] = k[rest[i]];
+    int64_t ob = block_index(O, okey.data());
+    if (ob < 0) fail(FTN_EINVAL, "internal: fused block missing");
+    int64_t bext = 1;
+    for (size_t i = pos; i < rest.size(); ++i) bext *= A.shapes[b * n + rest[i]];
+    PermTask tk;
+    tk.block = b;
+    tk.bext = bext;
+    tk.gext = fl.d[te.first];
+    tk.moff = O.offsets[ob] + te.second * bext;
+    tk.skip = 0;
+    tk.extra = 0;
+    tasks[b] = tk;
+  }
+  PermPlan pp;
+  pp.op = op;
+  pp.tasks = to_device(tasks, s);
+  perm_plan_tiles(pp, block_sizes(A), s);
+  run_perm(0, A, a.dtype, pp, a.data, out->data, s);
+  return out;
+}
+
+}  // namespace ftn

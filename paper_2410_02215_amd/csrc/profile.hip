@@ -1,0 +1,110 @@
+// Opt-in kernel timing with HIP events on the launching stream. When
+// enabled, each instrumented launch is bracketed by two events; durations,
+// launch counts and the algorithmic work the caller attributes to the launch
+// (flops or bytes) are accumulated per kernel class until collected.
+#include <mutex>
+
+#include "common.h"
+
+namespace ftn {
+
+namespace {
+struct Rec {
+  hipEvent_t a, b;
+  int cls;
+  double work;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+double g_ms[FTN_PROF_NCLASS], g_cnt[FTN_PROF_NCLASS], g_work[FTN_PROF_NCLASS];
+
+hipEvent_t take() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPC(hipEventCreate(&e));
+  return e;
+}
+
+void drain_locked() {
+  for (auto& r : g_recs) {
+    HIPC(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, r.a, r.b));
+    g_ms[r.cls] += ms;
+    g_cnt[r.cls] += 1;
+    g_work[r.cls] += r.work;
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+}
+}  // namespace
+
+bool prof_on() { return g_on; }
+
+void* prof_begin(hipStream_t s) {
+  if (!g_on) return nullptr;
+  std::lock_guard<std::mutex> g(g_mu);
+  Rec* r = new Rec;
+  r->a = take();
+  r->b = take();
+  HIPC(hipEventRecord(r->a, s));
+  return r;
+}
+
+void prof_end(void* tok, hipStream_t s, int cls, double work) {
+  if (!tok) return;
+  Rec* r = (Rec*)tok;
+  std::lock_guard<std::mutex> g(g_mu);
+  HIPC(hipEventRecord(r->b, s));
+  r->cls = cls;
+  r->work = work;
+  g_recs.push_back(*r);
+  delete r;
+  if (g_recs.size() > 4096) drain_locked();
+}
+
+void prof_enable(int on) {
+  std::lock_guard<std::mutex> g(g_mu);
+  drain_locked();
+  g_on = on != 0;
+}
+
+void prof_collect(double* ms, double* count, double* work) {
+  std::lock_guard<std::mutex> g(g_mu);
+  drain_locked();
+  for (int c = 0; c < FTN_PROF_NCLASS; ++c) {
+    if (ms) ms[c] = g_ms[c];
+    if (count) count[c] = g_cnt[c];
+    if (work) work[c] = g_work[c];
+    g_ms[c] = g_cnt[c] = g_work[c] = 0;
+  }
+}
+
+}  // namespace ftn
+
+extern "C" int ftn_profile_enable(int on) {
+  try {
+    ftn::prof_enable(on);
+    return FTN_OK;
+  } catch (const ftn::Error& e) {
+    ftn::set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+extern "C" int ftn_profile_collect(double* ms, double* count, double* work) {
+  try {
+    ftn::prof_collect(ms, count, work);
+    return FTN_OK;
+  } catch (const ftn::Error& e) {
+    ftn::set_last_error(e.msg);
+    return e.code;
+  }
+}

@@ -1,0 +1,336 @@
+"""Thin Python binding of libftn.so (argument marshalling only).
+
+Every operation runs in the HIP library; this module converts Python
+arguments into the C ABI declared in include/ftn.h and wraps handles. Device
+buffers passed in or out are torch tensors on the current HIP device, and
+work is enqueued on torch's current stream. There is no fallback: if the
+library cannot be loaded, importing the operations raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftn.so")
+
+Z2, U1, U1xU1 = 0, 1, 2
+F64, F32 = 0, 1
+LOCAL, GLOBAL = 0, 1
+GEMM_F64, GEMM_F32, GEMM_BF16X3 = 0, 1, 2
+
+SYM_NAMES = {"Z2": Z2, "U1": U1, "U1xU1": U1xU1}
+_ERRORS = {-1: "EINVAL", -2: "ECHARGE", -3: "ENOMEM", -4: "EHIP", -5: "ENOCONV", -6: "ENOTSUP"}
+
+_lib = None
+
+# (name, restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PU8 = ctypes.POINTER(ctypes.c_uint8)
+_PD = ctypes.POINTER(ctypes.c_double)
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+SIGNATURES = [
+    ("ftn_last_error", ctypes.c_char_p, []),
+    ("ftn_version", ctypes.c_char_p, []),
+    ("ftn_set_allocator", _I, [_P, _P, _P]),
+    ("ftn_tensor_create", _I, [_I, _I, _I, _PI32, _PI32, _PI64, _PU8, _PI32, _P, _P, _PP]),
+    ("ftn_tensor_from_dense", _I, [_I, _I, _I, _PI32, _PI32, _PI64, _PU8, _PI32, _P, _P, _PP]),
+    ("ftn_tensor_to_dense", _I, [_P, _P, _P]),
+    ("ftn_tensor_info", _I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), _PI64, _PI64, _PI32]),
+    ("ftn_tensor_blocks", _I, [_P, ctypes.POINTER(_PI32), ctypes.POINTER(_PI64), ctypes.POINTER(_PI64)]),
+    ("ftn_tensor_leg", _I, [_P, _I, _PI32, ctypes.POINTER(_PI32), ctypes.POINTER(_PI64), _PU8]),
+    ("ftn_tensor_data", _I, [_P, _PP]),
+    ("ftn_tensor_copy_data", _I, [_P, _P, _P]),
+    ("ftn_tensor_cast", _I, [_P, _I, _P, _PP]),
+    ("ftn_tensor_scale", _I, [_P, _D, _P, _PP]),
+    ("ftn_tensor_free", _I, [_P]),
+    ("ftn_ftranspose", _I, [_P, _PI32, _P, _PP]),
+    ("ftn_flip_dual", _I, [_P, _I, _I, _P, _PP]),
+    ("ftn_dagger", _I, [_P, _P, _PP]),
+    ("ftn_fuse", _I, [_P, _I, _PI32, _I, _I, _P, _PP]),
+    ("ftn_ftensordot", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP]),
+    ("ftn_compress_bond", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _PP, _PP, _PD, _PD, _PI64]),
+    ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
+    ("ftn_net_free", _I, [_P]),
+    ("ftn_contract_network", _I, [_P, _I, _PI32, _I64, _I, _P, _PD, _PI64, _PP, _PI32, _PD]),
+    ("ftn_profile_enable", _I, [_I]),
+    ("ftn_profile_collect", _I, [_PD, _PD, _PD]),
+]
+
+PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_bf16x3", "permute", "factor", "other"]
+
+
+def profile_enable(on=True):
+    load_library()
+    _check(_lib.ftn_profile_enable(1 if on else 0))
+
+
+def profile_collect():
+    """{class: (ms, launches, work)} since the last collect."""
+    n = len(PROF_CLASSES)
+    ms, cnt, wk = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
+    _check(_lib.ftn_profile_collect(ms, cnt, wk))
+    return {c: (ms[i], cnt[i], wk[i]) for i, c in enumerate(PROF_CLASSES)}
+
+
+class FtnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRORS.get(code, "E?"), code, msg))
+        self.code = code
+
+
+def load_library(path=LIB_PATH):
+    """Load libftn.so and declare every entry point; raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libftn.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise FtnError(rc, _lib.ftn_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _arr(vals, ctype):
+    a = (ctype * max(len(vals), 1))(*vals)
+    return a
+
+
+def _legs_args(sym, legs):
+    nsect, charges, dims, duals = [], [], [], []
+    for (chs, ds, dual) in legs:
+        nsect.append(len(chs))
+        for q, d in zip(chs, ds):
+            q = tuple(int(x) for x in q)
+            charges += [q[0], q[1] if len(q) > 1 else 0]
+            dims.append(int(d))
+        duals.append(int(dual))
+    return (_arr(nsect, ctypes.c_int32), _arr(charges, ctypes.c_int32),
+            _arr(dims, ctypes.c_int64), _arr(duals, ctypes.c_uint8))
+
+
+def _total(total):
+    t = tuple(int(x) for x in total)
+    return _arr([t[0], t[1] if len(t) > 1 else 0], ctypes.c_int32)
+
+
+class Tensor:
+    """Owning wrapper of an ftn_tensor_t handle."""
+
+    def __init__(self, handle):
+        self.h = ctypes.c_void_p(handle) if not isinstance(handle, ctypes.c_void_p) else handle
+
+    def __del__(self):
+        try:
+            if self.h and self.h.value and _lib is not None:
+                _lib.ftn_tensor_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    # --- construction ----------------------------------------------------
+    @classmethod
+    def from_dense(cls, sym, legs, total, dense):
+        """``legs``: list of (charges, dims, dual); ``dense``: torch cuda tensor."""
+        load_library()
+        import torch
+        if not dense.is_cuda:
+            raise ValueError("dense must be a device tensor")
+        dense = dense.contiguous()
+        dt = F64 if dense.dtype == torch.float64 else F32
+        if dense.dtype not in (torch.float64, torch.float32):
+            raise ValueError("dense must be float64 or float32")
+        ns, ch, dm, du = _legs_args(sym, legs)
+        out = ctypes.c_void_p()
+        _check(_lib.ftn_tensor_from_dense(sym, dt, len(legs), ns, ch, dm, du, _total(total),
+                                          ctypes.c_void_p(dense.data_ptr()), _stream(),
+                                          ctypes.byref(out)))
+        return cls(out)
+
+    @classmethod
+    def create(cls, sym, legs, total, dtype=F64, data=None):
+        load_library()
+        ns, ch, dm, du = _legs_args(sym, legs)
+        out = ctypes.c_void_p()
+        src = ctypes.c_void_p(data.data_ptr()) if data is not None else None
+        _check(_lib.ftn_tensor_create(sym, dtype, len(legs), ns, ch, dm, du, _total(total), src,
+                                      _stream(), ctypes.byref(out)))
+        return cls(out)
+
+    # --- queries ---------------------------------------------------------
+    def info(self):
+        sym, dt, nd = _I(), _I(), _I()
+        nb, sz = _I64(), _I64()
+        tot = (ctypes.c_int32 * 2)()
+        _check(_lib.ftn_tensor_info(self.h, ctypes.byref(sym), ctypes.byref(dt), ctypes.byref(nd),
+                                    ctypes.byref(nb), ctypes.byref(sz), tot))
+        return dict(sym=sym.value, dtype=dt.value, ndim=nd.value, nblocks=nb.value,
+                    size=sz.value, total=(tot[0], tot[1]))
+
+    @property
+    def ndim(self):
+        return self.info()["ndim"]
+
+    @property
+    def size(self):
+        return self.info()["size"]
+
+    def blocks(self):
+        inf = self.info()
+        k, o, s = _PI32(), _PI64(), _PI64()
+        _check(_lib.ftn_tensor_blocks(self.h, ctypes.byref(k), ctypes.byref(o), ctypes.byref(s)))
+        nb, nd = inf["nblocks"], inf["ndim"]
+        keys = np.ctypeslib.as_array(k, shape=(nb * nd,)).copy().reshape(nb, nd) if nb * nd else np.zeros((nb, nd), np.int32)
+        offs = np.ctypeslib.as_array(o, shape=(nb + 1,)).copy()
+        shp = np.ctypeslib.as_array(s, shape=(nb * nd,)).copy().reshape(nb, nd) if nb * nd else np.zeros((nb, nd), np.int64)
+        return keys, offs, shp
+
+    def leg(self, i):
+        ns = ctypes.c_int32()
+        ch, dm = _PI32(), _PI64()
+        du = ctypes.c_uint8()
+        _check(_lib.ftn_tensor_leg(self.h, i, ctypes.byref(ns), ctypes.byref(ch), ctypes.byref(dm),
+                                   ctypes.byref(du)))
+        n = ns.value
+        c = np.ctypeslib.as_array(ch, shape=(2 * n,)).copy().reshape(n, 2) if n else np.zeros((0, 2), np.int32)
+        d = np.ctypeslib.as_array(dm, shape=(n,)).copy() if n else np.zeros(0, np.int64)
+        return [tuple(int(x) for x in r) for r in c], [int(x) for x in d], int(du.value)
+
+    def legs(self):
+        return [self.leg(i) for i in range(self.ndim)]
+
+    def data(self):
+        """Copy of the block data as a torch device tensor."""
+        import torch
+        inf = self.info()
+        dt = torch.float64 if inf["dtype"] == F64 else torch.float32
+        out = torch.empty(inf["size"], dtype=dt, device="cuda")
+        if inf["size"]:
+            _check(_lib.ftn_tensor_copy_data(self.h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def to_dense(self):
+        import torch
+        inf = self.info()
+        dt = torch.float64 if inf["dtype"] == F64 else torch.float32
+        shape = [sum(l[1]) for l in self.legs()]
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        _check(_lib.ftn_tensor_to_dense(self.h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def cast(self, dtype):
+        out = ctypes.c_void_p()
+        _check(_lib.ftn_tensor_cast(self.h, dtype, _stream(), ctypes.byref(out)))
+        return Tensor(out)
+
+    def scale(self, alpha):
+        out = ctypes.c_void_p()
+        _check(_lib.ftn_tensor_scale(self.h, float(alpha), _stream(), ctypes.byref(out)))
+        return Tensor(out)
+
+
+def ftranspose(a, perm):
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_ftranspose(a.h, _arr([int(p) for p in perm], ctypes.c_int32), _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def flip_dual(a, leg, with_sign=-1):
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_flip_dual(a.h, int(leg), int(with_sign), _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def dagger(a):
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_dagger(a.h, _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def fuse(a, legs, conv=LOCAL, rev=0):
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_fuse(a.h, len(legs), _arr([int(l) for l in legs], ctypes.c_int32), int(conv), int(rev),
+                         _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def ftensordot(a, b, axes_a, axes_b, conv=LOCAL, gemm=GEMM_F64):
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_ftensordot(a.h, b.h, len(axes_a), _arr([int(x) for x in axes_a], ctypes.c_int32),
+                               _arr([int(x) for x in axes_b], ctypes.c_int32), int(conv), int(gemm),
+                               _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def compress_bond(a, b, leg_a, leg_b, chi, cutoff=1e-12, conv=LOCAL):
+    ao, bo = ctypes.c_void_p(), ctypes.c_void_p()
+    disc = ctypes.c_double()
+    sv = (ctypes.c_double * int(chi))()
+    nk = ctypes.c_int64()
+    _check(_lib.ftn_compress_bond(a.h, b.h, int(leg_a), int(leg_b), int(chi), float(cutoff), int(conv),
+                                  _stream(), ctypes.byref(ao), ctypes.byref(bo), ctypes.byref(disc), sv,
+                                  ctypes.byref(nk)))
+    return Tensor(ao), Tensor(bo), dict(discarded=disc.value, svals=list(sv[:nk.value]))
+
+
+class Network:
+    def __init__(self, tensors, bonds, conv=LOCAL, positions=None):
+        load_library()
+        self.tensors = list(tensors)  # keep the wrappers alive
+        hs = (ctypes.c_void_p * len(tensors))(*[t.h.value for t in tensors])
+        ends = []
+        for b in bonds:
+            ends += [int(x) for x in b]
+        pos = _arr([int(p) for p in positions], ctypes.c_int32) if positions is not None else None
+        self.h = ctypes.c_void_p()
+        _check(_lib.ftn_net_create(len(tensors), hs, len(bonds), _arr(ends, ctypes.c_int32), int(conv), pos,
+                                   ctypes.byref(self.h)))
+
+    def __del__(self):
+        try:
+            if self.h and self.h.value and _lib is not None:
+                _lib.ftn_net_free(self.h)
+        except Exception:
+            pass
+
+    def contract(self, path, chi=0, gemm=GEMM_F64, open_legs=False):
+        """Returns (mantissa, exp2, stats) or (tensor, exp2, leg_src, stats)."""
+        flat = []
+        for (i, j) in path:
+            flat += [int(i), int(j)]
+        m = ctypes.c_double()
+        e = ctypes.c_int64()
+        st = (ctypes.c_double * 8)()
+        out = ctypes.c_void_p()
+        src = (ctypes.c_int32 * 64)()
+        _check(_lib.ftn_contract_network(self.h, len(path), _arr(flat, ctypes.c_int32), int(chi or 0), int(gemm),
+                                         _stream(), ctypes.byref(m), ctypes.byref(e),
+                                         ctypes.byref(out) if open_legs else None, src, st))
+        stats = dict(flops=st[0], compressions=int(st[1]), discarded=st[2], near_ties=int(st[3]),
+                     max_entries=st[4])
+        if open_legs and out.value:
+            t = Tensor(out)
+            n = t.ndim
+            return t, e.value, [(src[2 * k], src[2 * k + 1]) for k in range(n)], stats
+        return m.value, e.value, stats

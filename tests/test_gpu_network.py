@@ -1,0 +1,159 @@
+"""GPU parity of bond compression and network contraction (via the C ABI).
+
+Exact contractions agree with the oracle to FP64 rounding (1e-12 relative).
+Compression: the compressed pair's contraction F(A'B') is gauge invariant
+and is compared with the oracle's; the library factors Gram matrices (so a
+direction with singular value s is resolved to ~eps * s_max^2 / s), which
+bounds the agreement of truncated results at 1e-9 relative on these
+inputs. Integer results (kept sector dims) must be identical.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import symmetry as S
+from oracle import physics as OP
+from oracle.linalg import compress_bond as o_compress
+from oracle.network import Network as ONet, contract_network as o_contract, network_value
+from oracle.ops import ftensordot, ftranspose
+from synth import workloads as W
+from synth.operators import operator_dense
+from tests.helpers import rand_leg, partner, rand_tensor, random_network, random_ssa_path
+from tests.gpu_helpers import to_gpu, from_gpu, assert_same_structure
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_02215_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    P.load_library()
+    return P
+
+
+def _val(m, e):
+    return m * 2.0 ** e
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+def test_c1_exact_norm(P, conv):
+    from paper_2410_02215_amd import peps as GP
+    cfg = W.c1()
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"], std=cfg["std"])
+    onet = OP.norm_network(spec, OP.ket_tensors(spec, vals), conv=conv)
+    path = W.norm_path(spec, seed=0)
+    ref = _val(*network_value(onet, path))
+    gnet = GP.norm_network(spec, GP.ket_tensors(spec, vals), conv=P.LOCAL if conv == "local" else P.GLOBAL)
+    m, e, st = gnet.contract(path)
+    assert abs(_val(m, e) - ref) <= 1e-12 * abs(ref)
+    # a second, different path gives the same value (order invariance)
+    p2 = W.norm_path(spec, seed=5, pair_layers=False)
+    m2, e2, _ = gnet.contract(p2)
+    assert abs(_val(m2, e2) - ref) <= 1e-12 * abs(ref)
+
+
+def _flat_perm(labels, order, ndims):
+    flat = [(t, l) for t in order for l in range(ndims[t])]
+    rank = {x: k for k, x in enumerate(flat)}
+    return sorted(range(len(labels)), key=lambda k: rank[tuple(labels[k])])
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", [S.Z2, S.U1])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_networks_with_odd_tensors(P, sym, conv, seed):
+    rng = np.random.default_rng(700 + seed)
+    nt = int(rng.integers(2, 6))
+    tensors, bonds = random_network(rng, sym, nt, nt + 1, n_open=int(rng.integers(0, 3)), odd_frac=0.5)
+    pos = list(rng.permutation(nt))
+    order = sorted(range(nt), key=lambda t: pos[t])
+    onet = ONet(tensors, bonds, conv="global", positions=pos)
+    path = random_ssa_path(rng, tensors, bonds)
+    T, labs, e, _ = o_contract(onet, path)
+    perm = _flat_perm([(l[1], l[2]) for l in labs], order, {t: x.ndim for t, x in tensors.items()})
+    ref = ftranspose(T, perm).to_dense() * 2.0 ** e
+    g = [to_gpu(tensors[t]) for t in range(nt)]
+    gnet = P.Network(g, bonds, conv=P.GLOBAL if conv == "global" else P.LOCAL, positions=pos)
+    if conv == "local":
+        # the same network in local form: the oracle's translation defines it
+        from oracle.network import to_local
+        loc = to_local(onet)
+        g = [to_gpu(loc.tensors[t]) for t in range(nt)]
+        gnet = P.Network(g, bonds, conv=P.LOCAL, positions=pos)
+    if T.ndim == 0:
+        m, ge, _ = gnet.contract(path)
+        assert abs(_val(m, ge) - float(ref)) <= 1e-12 * max(1.0, abs(float(ref)))
+    else:
+        G, ge, src, _ = gnet.contract(path, open_legs=True)
+        gp = _flat_perm(src, order, {t: x.ndim for t, x in tensors.items()})
+        Gt = P.ftranspose(G, gp)
+        got = Gt.to_dense().cpu().numpy() * 2.0 ** ge
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", [S.Z2, S.U1, S.U1U1])
+def test_compress_bond_matches_oracle(P, sym, conv):
+    rng = np.random.default_rng(800)
+    for trial in range(5):
+        bond = rand_leg(rng, sym, maxd=6)
+        la = [rand_leg(rng, sym, maxd=3) for _ in range(2)]
+        lb = [rand_leg(rng, sym, maxd=3) for _ in range(2)]
+        pa, pb = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        A = rand_tensor(rng, sym, la[:pa] + [bond] + la[pa:], total=S.zero(sym))
+        B = rand_tensor(rng, sym, lb[:pb] + [partner(bond)] + lb[pb:], total=S.zero(sym))
+        chi = int(rng.integers(2, 8))
+        A2, B2, info = o_compress(A, B, pa, pb, chi, conv=conv)
+        ref = ftensordot(A2, B2, [pa], [pb], conv).to_dense()
+        cv = P.LOCAL if conv == "local" else P.GLOBAL
+        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), pa, pb, chi, 1e-12, cv)
+        assert GA.legs()[pa][1] == list(A2.legs[pa].dims)       # kept dims, bit-exact
+        GC = P.ftensordot(GA, GB, [pa], [pb], conv=cv)
+        got = GC.to_dense().cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()))
+        kept = sorted(np.concatenate([v.numpy() for v in info["svals"].values()]), reverse=True)
+        np.testing.assert_allclose(ginfo["svals"], kept, rtol=1e-9)
+
+
+def test_compress_large_sector_subspace_iteration(P):
+    # bond sectors above 128 exercise the subspace-iteration SVD path
+    rng = np.random.default_rng(801)
+    sym = S.Z2
+    from oracle.tensor import make_leg
+    bond = make_leg(sym, [(0,), (1,)], [150, 140], 1)
+    A = rand_tensor(rng, sym, [make_leg(sym, [(0,), (1,)], [200, 180], 0), bond], total=(0,))
+    B = rand_tensor(rng, sym, [partner(bond), make_leg(sym, [(0,), (1,)], [170, 190], 1)], total=(0,))
+    chi = 64
+    A2, B2, info = o_compress(A, B, 1, 0, chi)
+    ref = ftensordot(A2, B2, [1], [0]).to_dense()
+    GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi)
+    assert GA.legs()[1][1] == list(A2.legs[1].dims)
+    got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n_sites,chi", [(8, 16), (12, 24)])
+def test_approximate_norm_and_hopping_small_rrg(P, n_sites, chi):
+    from paper_2410_02215_amd import peps as GP
+    cfg = W.c2(n_sites=n_sites, chi=chi)
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"])
+    okets = OP.ket_tensors(spec, vals)
+    path = W.norm_path(spec, chi=chi, seed=1)
+    ref = _val(*network_value(OP.norm_network(spec, okets, conv="local"), path, chi=chi))
+    gk = GP.ket_tensors(spec, vals)
+    m, e, st = GP.norm_network(spec, gk).contract(path, chi=chi)
+    assert abs(_val(m, e) - ref) <= 1e-9 * abs(ref)
+    assert st["compressions"] > 0
+    # hopping term on the first edge
+    u, v = cfg["op_sites"]
+    G = OP.operator_tensor(OP.two_site_local("hop"), okets[0].legs[0], S.Z2)
+    p2 = W.norm_path(spec, chi=chi, seed=1, op_sites=(u, v))
+    oref = _val(*network_value(OP.norm_network(spec, okets, op=G, op_sites=(u, v), conv="local"), p2, chi=chi))
+    gop = GP.operator_tensor(spec, operator_dense("hop", "Z2"))
+    m2, e2, _ = GP.norm_network(spec, gk, op=gop, op_sites=(u, v)).contract(p2, chi=chi)
+    assert abs(_val(m2, e2) - oref) <= 1e-9 * abs(ref)

@@ -1,0 +1,181 @@
+"""GPU parity of the elementary operations against the oracle (via the C ABI).
+
+Integer work (block keys, offsets) and pure sign-carrying copies
+(transposition, arrow reversal, fusion, dense gather) must be bit-exact.
+Contractions in FP64 agree with the oracle up to summation order: the
+tolerance is 64 * eps * sum_k |a_ik||b_kj| per entry (a forward error bound
+of a length-k dot product), checked as a relative max error of 1e-12 on
+these O(1) random inputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import symmetry as S
+from oracle.ops import ftranspose, ftensordot, flip_dual, fuse
+from oracle.tensor import FTensor, make_leg
+from tests.helpers import rand_leg, partner, rand_tensor
+from tests.gpu_helpers import to_gpu, from_gpu, assert_same_structure, flat_blocks
+
+pytestmark = pytest.mark.gpu
+
+SYMS = [S.Z2, S.U1, S.U1U1]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_02215_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    P.load_library()
+    return P
+
+
+def _data(G):
+    return G.data().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("sym", SYMS)
+def test_create_structure_and_gather_bit_exact(P, sym):
+    rng = np.random.default_rng(1)
+    for trial in range(8):
+        n = int(rng.integers(0, 6))
+        legs = [rand_leg(rng, sym, maxd=3) for _ in range(n)]
+        T = rand_tensor(rng, sym, legs)
+        G = to_gpu(T)
+        assert_same_structure(T, G)
+        np.testing.assert_array_equal(_data(G), flat_blocks(T))
+        np.testing.assert_array_equal(G.to_dense().cpu().numpy(), T.to_dense())
+
+
+def test_many_sectors_large_enumeration(P):
+    # U(1) legs with many sectors: enumeration over tens of thousands of keys
+    rng = np.random.default_rng(2)
+    legs = [make_leg(S.U1, [(q,) for q in range(-4, 5)], [1] * 9, int(rng.integers(0, 2)))
+            for _ in range(6)]
+    T = FTensor.zeros(S.U1, legs, (1,))
+    G = P.Tensor.create(1, [([(q[0], 0) for q in l.charges], list(l.dims), l.dual) for l in legs], (1, 0))
+    assert_same_structure(T, G)
+
+
+@pytest.mark.parametrize("sym", SYMS)
+def test_ftranspose_bit_exact(P, sym):
+    rng = np.random.default_rng(3)
+    for trial in range(10):
+        n = int(rng.integers(1, 7))
+        legs = [rand_leg(rng, sym, maxd=3) for _ in range(n)]
+        T = rand_tensor(rng, sym, legs)
+        perm = list(rng.permutation(n))
+        ref = ftranspose(T, perm)
+        G = P.ftranspose(to_gpu(T), perm)
+        assert_same_structure(ref, G)
+        np.testing.assert_array_equal(_data(G), flat_blocks(ref))
+
+
+@pytest.mark.parametrize("sym", SYMS)
+def test_flip_dual_bit_exact(P, sym):
+    rng = np.random.default_rng(4)
+    for trial in range(6):
+        n = int(rng.integers(1, 5))
+        legs = [rand_leg(rng, sym, maxd=3) for _ in range(n)]
+        T = rand_tensor(rng, sym, legs)
+        leg = int(rng.integers(0, n))
+        for ws, ref in ((-1, flip_dual(T, leg)), (0, flip_dual(T, leg, with_sign=False)),
+                        (1, flip_dual(T, leg, with_sign=True))):
+            G = P.flip_dual(to_gpu(T), leg, ws)
+            assert_same_structure(ref, G)
+            np.testing.assert_array_equal(_data(G), flat_blocks(ref))
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", SYMS)
+def test_fuse_bit_exact(P, sym, conv):
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        n = int(rng.integers(2, 6))
+        legs = [rand_leg(rng, sym, maxd=2) for _ in range(n)]
+        T = rand_tensor(rng, sym, legs)
+        m = int(rng.integers(2, n + 1))
+        gl = [int(x) for x in rng.permutation(n)[:m]]
+        rev = int(rng.integers(0, 2))
+        ref, _ = fuse(T, gl, conv=conv, rev=rev)
+        G = P.fuse(to_gpu(T), gl, conv=P.LOCAL if conv == "local" else P.GLOBAL, rev=rev)
+        assert_same_structure(ref, G)
+        np.testing.assert_array_equal(_data(G), flat_blocks(ref))
+
+
+def _rand_pair(rng, sym, k, nfa, nfb, maxd):
+    bond = [rand_leg(rng, sym, maxd=maxd) for _ in range(k)]
+    fa = [rand_leg(rng, sym, maxd=maxd) for _ in range(nfa)]
+    fb = [rand_leg(rng, sym, maxd=maxd) for _ in range(nfb)]
+    A_legs = fa + bond
+    B_legs = [partner(b) for b in bond] + fb
+    pa = list(rng.permutation(len(A_legs)))
+    pb = list(rng.permutation(len(B_legs)))
+    A = rand_tensor(rng, sym, [A_legs[p] for p in pa])
+    B = rand_tensor(rng, sym, [B_legs[p] for p in pb])
+    ax_a = [pa.index(nfa + t) for t in range(k)]
+    ax_b = [pb.index(t) for t in range(k)]
+    return A, B, ax_a, ax_b
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", SYMS)
+def test_ftensordot_fp64(P, sym, conv):
+    rng = np.random.default_rng(6)
+    for trial in range(8):
+        k = int(rng.integers(0, 4))
+        A, B, ax_a, ax_b = _rand_pair(rng, sym, k, int(rng.integers(0, 4)), int(rng.integers(0, 4)), 3)
+        ref = ftensordot(A, B, ax_a, ax_b, conv=conv)
+        G = P.ftensordot(to_gpu(A), to_gpu(B), ax_a, ax_b,
+                         conv=P.LOCAL if conv == "local" else P.GLOBAL)
+        assert_same_structure(ref, G)
+        r = flat_blocks(ref)
+        np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * max(1.0, np.abs(r).max(initial=0)))
+
+
+def test_ftensordot_tiles_and_ragged_tails(P):
+    # large sectors: several 64 x 64 tiles per group plus ragged edges
+    rng = np.random.default_rng(7)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(37, 41, 0), l(70, 9, 1), l(13, 30, 0)], total=(0,))
+    B = rand_tensor(rng, sym, [l(13, 30, 1), l(150, 3, 0)], total=(1,))
+    ref = ftensordot(A, B, [2], [0], conv="local")
+    G = P.ftensordot(to_gpu(A), to_gpu(B), [2], [0])
+    assert_same_structure(ref, G)
+    r = flat_blocks(ref)
+    np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * np.abs(r).max())
+
+
+@pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
+def test_ftensordot_fp32_forms(P, gemm):
+    rng = np.random.default_rng(8)
+    sym = S.U1U1
+    tol = {"f32": 1e-5, "bf16x3": 1e-4}[gemm]
+    for trial in range(6):
+        k = int(rng.integers(1, 3))
+        A, B, ax_a, ax_b = _rand_pair(rng, sym, k, 2, 2, 4)
+        ref = ftensordot(A, B, ax_a, ax_b, conv="local")
+        Ga = to_gpu(A, torch.float32)
+        Gb = to_gpu(B, torch.float32)
+        G = P.ftensordot(Ga, Gb, ax_a, ax_b, gemm=P.GEMM_F32 if gemm == "f32" else P.GEMM_BF16X3)
+        assert_same_structure(ref, G)
+        r = flat_blocks(ref)
+        err = np.abs(_data(G) - r).max(initial=0) / max(np.abs(r).max(initial=0), 1e-30)
+        assert err < tol, err
+
+
+def test_errors_are_reported(P):
+    rng = np.random.default_rng(9)
+    sym = S.Z2
+    la = rand_leg(rng, sym)
+    A = rand_tensor(rng, sym, [la, rand_leg(rng, sym)])
+    B = rand_tensor(rng, sym, [la, rand_leg(rng, sym)])  # same dual: not contractible
+    with pytest.raises(P.FtnError) as e:
+        P.ftensordot(to_gpu(A), to_gpu(B), [0], [0])
+    assert e.value.code == -2
+    with pytest.raises(P.FtnError) as e:
+        P.ftranspose(to_gpu(A), [0, 0])
+    assert e.value.code == -1

@@ -270,3 +270,11 @@ def test_dagger_and_dummy():
     D = add_dummy(T)
     assert D.parity == 0 and D.ndim == 4 and D.legs[0].dims == (1,)
     np.testing.assert_array_equal(D.to_dense()[0], T.to_dense())
+
+
+def test_scalar_tensors():
+    # a tensor with no legs holds one entry iff its total charge is neutral
+    T = FTensor.from_dense(S.Z2, [], (0,), np.array(2.5))
+    assert T.keys() == [()] and float(T.block(())) == 2.5
+    assert FTensor.from_dense(S.Z2, [], (1,), np.array(2.5)).keys() == []
+    assert ftranspose(T, []).to_dense() == 2.5
