@@ -127,7 +127,7 @@ class FTensor:
             raise ValueError("dense shape mismatch")
         for k in t.keys():
             sl = tuple(slice(l.offset(i), l.offset(i) + l.dims[i]) for l, i in zip(t.legs, k))
-            t.blocks[k] = torch.from_numpy(arr[sl].copy())
+            t.blocks[k] = torch.from_numpy(np.array(arr[sl], dtype=np.float64))
         return t
 
     def to_dense(self):
