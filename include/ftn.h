@@ -205,7 +205,9 @@ int ftn_ftensordot(ftn_tensor_t a, ftn_tensor_t b, int naxes, const int32_t* axe
    is the best rank-chi approximation of F(AB) across that bond, keeping the
    chi largest singular values over all charge sectors (ties: larger value,
    then lower charge, then lower index). Values not above cutoff * s_max are
-   dropped and empty sectors removed. The bond keeps its leg positions,
+   dropped and empty sectors removed; the decomposition goes through Gram
+   matrices, which resolve singular values to about 1e-8 * s_max, so cutoffs
+   below 1e-6 are raised to 1e-6. The bond keeps its leg positions,
    duals and charge labels; only sector dims shrink. conv selects how F(AB)
    is read (as in ftn_ftensordot). FP64 arithmetic is used for the
    decomposition whatever the tensors' dtype. discarded_weight (may be NULL)
@@ -241,7 +243,7 @@ int ftn_net_free(ftn_net_t net);
    shares. With chi > 0 (approximate contraction, compression as early as
    possible, Sec. III): after each step the bonds the new tensor shares with
    one neighbour are fused into one (Sec. IV.A) and every such bond larger
-   than chi is compressed with ftn_compress_bond (cutoff 1e-12). chi <= 0
+   than chi is compressed with ftn_compress_bond (cutoff 1e-6). chi <= 0
    means exact. Every intermediate is rescaled by a power of two; the value
    is mantissa * 2^exp2. For a closed network the result is a scalar and
    open_out may be NULL; otherwise *open_out receives the final tensor (its

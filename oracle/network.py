@@ -17,7 +17,8 @@ Two conventions, each implemented as the paper describes it:
 Approximate contraction (Fig. 1b, Sec. III, compression as early as
 possible): after each pairwise contraction the bonds the new tensor shares
 with one neighbour are fused into one bond (Sec. IV.A), and every such bond
-larger than chi is compressed with ``compress_bond``. Each intermediate is
+larger than chi is compressed with ``compress_bond`` (singular values not
+above 1e-6 of the largest count as zero). Each intermediate is
 rescaled by a power of two, accumulated in an integer exponent (exact in
 binary floating point).
 """
@@ -92,7 +93,10 @@ def _neighbours(st, z):
     return out
 
 
-def _fuse_and_compress(st, z, chi, conv, order):
+CUTOFF = 1e-6  # relative singular-value cutoff of network compression
+
+
+def _fuse_and_compress(st, z, chi, conv, order, cutoff=CUTOFF):
     """Fuse parallel bonds of z to each neighbour, then compress > chi."""
     infos = []
     for w in sorted(_neighbours(st, z)):
@@ -119,14 +123,16 @@ def _fuse_and_compress(st, z, chi, conv, order):
         dim = st.T[z].legs[lz[0]].size
         if chi is not None and dim > chi:
             if conv == "local":
-                A, B, info = compress_bond(st.T[z], st.T[w], lz[0], lw[0], chi, conv="local")
+                A, B, info = compress_bond(st.T[z], st.T[w], lz[0], lw[0], chi, conv="local", cutoff=cutoff)
                 st.T[z], st.T[w] = A, B
             else:
                 if order.index(z) < order.index(w):
-                    A, B, info = compress_bond(st.T[z], st.T[w], lz[0], lw[0], chi, conv="global")
+                    A, B, info = compress_bond(st.T[z], st.T[w], lz[0], lw[0], chi, conv="global",
+                                               cutoff=cutoff)
                     st.T[z], st.T[w] = A, B
                 else:
-                    A, B, info = compress_bond(st.T[w], st.T[z], lw[0], lz[0], chi, conv="global")
+                    A, B, info = compress_bond(st.T[w], st.T[z], lw[0], lz[0], chi, conv="global",
+                                               cutoff=cutoff)
                     st.T[w], st.T[z] = A, B
             infos.append(info)
     return infos

@@ -25,6 +25,14 @@ struct Error {
 [[noreturn]] void fail(int code, const std::string& msg);
 void hip_check(hipError_t e, const char* what);
 #define HIPC(x) ::ftn::hip_check((x), #x)
+// host-side check of a launch configuration (names the kernel on failure)
+void check_launch(const char* name, dim3 grid, dim3 block);
+#define LAUNCH(kern, grid, block, shm, stream, ...)                                   \
+  do {                                                                                \
+    ::ftn::check_launch(#kern, (grid), (block));                                      \
+    hipLaunchKernelGGL(kern, (grid), (block), (shm), (stream), __VA_ARGS__);          \
+    ::ftn::hip_check(hipGetLastError(), #kern);                                       \
+  } while (0)
 void set_last_error(const std::string& msg);
 
 // ---------------------------------------------------------------------------

@@ -299,7 +299,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
     P->pa.op = make_signop(na, order.data(), (int)fa.size(), k);
     P->pa.tasks = DBuf<PermTask>(A.nblocks(), s);
     if (A.nblocks())
-      hipLaunchKernelGGL(k_dot_tasks, dim3((unsigned)cdiv(A.nblocks(), 128)), dim3(128), 0, s, da,
+      LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(A.nblocks(), 128)), dim3(128), 0, s, da,
                          A.S().d_keys.p, A.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pa.tasks.p);
     HIPC(hipGetLastError());
     perm_plan_tiles(P->pa, block_sizes(A.S()), s);  // synchronises
@@ -318,7 +318,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
     P->pb.op = op;
     P->pb.tasks = DBuf<PermTask>(B.nblocks(), s);
     if (B.nblocks())
-      hipLaunchKernelGGL(k_dot_tasks, dim3((unsigned)cdiv(B.nblocks(), 128)), dim3(128), 0, s, db,
+      LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(B.nblocks(), 128)), dim3(128), 0, s, db,
                          B.S().d_keys.p, B.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pb.tasks.p);
     HIPC(hipGetLastError());
     perm_plan_tiles(P->pb, block_sizes(B.S()), s);
@@ -390,7 +390,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
         HIPC(hipMemcpyAsync(P->boff.p, z.data(), 8, hipMemcpyHostToDevice, s));
         HIPC(hipStreamSynchronize(s));
       } else {
-        hipLaunchKernelGGL(k_dot_boff, dim3((unsigned)cdiv(CS.nblocks, 128)), dim3(128), 0, s, ba,
+        LAUNCH(k_dot_boff, dim3((unsigned)cdiv(CS.nblocks, 128)), dim3(128), 0, s, ba,
                            CS.d_keys.p, CS.d_offsets.p, CS.nblocks, drg.p, drl.p, dcl.p, dgb.p, dgn.p,
                            P->boff.p);
         HIPC(hipGetLastError());

@@ -380,15 +380,15 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   void* tok = prof_begin(s);
   if (p.kind == FTN_GEMM_F64) {
     if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
-    hipLaunchKernelGGL((k_gemm<double, TBM, TBN, 16>), grid, block, 0, s, L, (const double*)A,
+    LAUNCH((k_gemm<double, TBM, TBN, 16>), grid, block, 0, s, L, (const double*)A,
                        (const double*)B, (double*)C);
   } else if (p.kind == FTN_GEMM_F32) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 GEMM needs FP32 tensors");
-    hipLaunchKernelGGL((k_gemm<float, TBM, TBN, 16>), grid, block, 0, s, L, (const float*)A,
+    LAUNCH((k_gemm<float, TBM, TBN, 16>), grid, block, 0, s, L, (const float*)A,
                        (const float*)B, (float*)C);
   } else if (p.kind == FTN_GEMM_BF16X3) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "split-BF16 GEMM needs FP32 tensors");
-    hipLaunchKernelGGL((k_gemm_bf16x3<TBM, TBN, 32>), grid, block, 0, s, L, (const float*)A,
+    LAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, block, 0, s, L, (const float*)A,
                        (const float*)B, (float*)C);
   } else {
     fail(FTN_EINVAL, "unknown GEMM kind");

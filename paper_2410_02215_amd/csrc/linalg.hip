@@ -271,50 +271,104 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs, int max_s
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky of a small SPD p x p matrix in LDS, then the inverse of the upper
-// triangular factor: Rinv with (G = R^T R, Y Rinv orthonormal). One WG each.
+// Rank-revealing orthonormalisation factor (one workgroup per matrix): for
+// the Gram matrix G = Y^T Y (p x p, p <= 128) in LDS, symmetric-pivoted
+// Cholesky G = P^T R^T R P stops at the numerical rank r (pivot not above
+// tol * largest diagonal). The output M (p x p) has M[piv[i]][c] = R11^-1[i][c]
+// for i, c < r and zeros elsewhere, so Y M has r orthonormal columns followed
+// by zero columns: dependent directions are dropped instead of amplified.
 struct OrthJob {
   const double* G;
-  double* Rinv;
+  double* Rinv;  // p x p scratch
+  double* M;     // p x p output
   int p;
   int pad;
 };
 
-__global__ void __launch_bounds__(LT) k_chol_inv(const OrthJob* jobs) {
+__global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double tol) {
   const OrthJob J = jobs[blockIdx.x];
   const int p = J.p;
-  __shared__ double R[JMAX][JMAX + 1];
-  double* X = J.Rinv;  // p x p, column `col` owned by one thread below
+  __shared__ double A[JMAX][JMAX + 1];
+  __shared__ int piv[JMAX];
+  __shared__ int s_k, s_rank;
+  __shared__ double s_thr;
   const int tid = threadIdx.x;
   for (int e = tid; e < p * p; e += LT) {
     int i = e / p, j = e % p;
-    R[i][j] = J.G[e];
+    A[i][j] = J.G[e];
+    J.M[e] = 0.0;
+  }
+  for (int i = tid; i < p; i += LT) piv[i] = i;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < p; ++i) m = fmax(m, A[i][i]);
+    s_thr = tol * m;
+    s_rank = m > 0.0 ? p : 0;
   }
   __syncthreads();
-  // right-looking Cholesky, upper factor in place (R[j][j..])
-  for (int j = 0; j < p; ++j) {
+  for (int j = 0; j < s_rank; ++j) {
     if (tid == 0) {
-      double d = R[j][j];
-      R[j][j] = d > 0 ? sqrt(d) : 1e-300;
+      int k = j;
+      double v = A[j][j];
+      for (int i = j + 1; i < p; ++i)
+        if (A[i][i] > v) {
+          v = A[i][i];
+          k = i;
+        }
+      if (!(v > s_thr)) {
+        s_rank = j;
+        s_k = -1;
+      } else {
+        s_k = k;
+        int t = piv[j];
+        piv[j] = piv[k];
+        piv[k] = t;
+      }
     }
     __syncthreads();
-    const double rjj = R[j][j];
-    for (int i = j + 1 + tid; i < p; i += LT) R[j][i] /= rjj;
+    const int k = s_k;
+    if (k < 0) break;
+    if (k != j) {  // symmetric swap of rows and columns j, k
+      for (int c = tid; c < p; c += LT) {
+        double t = A[j][c];
+        A[j][c] = A[k][c];
+        A[k][c] = t;
+      }
+      __syncthreads();
+      for (int r = tid; r < p; r += LT) {
+        double t = A[r][j];
+        A[r][j] = A[r][k];
+        A[r][k] = t;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) A[j][j] = sqrt(A[j][j]);
     __syncthreads();
-    for (int e = tid; e < (p - j - 1) * (p - j - 1); e += LT) {
-      int a = j + 1 + e / (p - j - 1), b = j + 1 + e % (p - j - 1);
-      if (b >= a) R[a][b] -= R[j][a] * R[j][b];
+    const double rjj = A[j][j];
+    for (int c = j + 1 + tid; c < p; c += LT) A[j][c] /= rjj;
+    __syncthreads();
+    const int m = p - j - 1;
+    for (int e = tid; e < m * m; e += LT) {
+      int a = j + 1 + e / m, b = j + 1 + e % m;
+      A[a][b] -= A[j][a] * A[j][b];
     }
     __syncthreads();
   }
-  // inverse of upper triangular R: solve R X = I column by column (parallel
-  // over columns), back substitution
-  for (int col = tid; col < p; col += LT) {
-    for (int i = p - 1; i >= 0; --i) {
+  const int r = s_rank;
+  // R11^-1 by back substitution, one column per thread
+  double* X = J.Rinv;
+  for (int col = tid; col < r; col += LT) {
+    for (int i = col; i >= 0; --i) {
       double sacc = (i == col) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= col; ++k) sacc -= R[i][k] * X[(int64_t)k * p + col];
-      X[(int64_t)i * p + col] = (i <= col) ? sacc / R[i][i] : 0.0;
+      for (int q = i + 1; q <= col; ++q) sacc -= A[i][q] * X[(int64_t)q * p + col];
+      X[(int64_t)i * p + col] = sacc / A[i][i];
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += LT) {
+    int i = e / r, c = e % r;
+    J.M[(int64_t)piv[i] * p + c] = (i <= c) ? X[(int64_t)i * p + c] : 0.0;
   }
 }
 
@@ -415,7 +469,7 @@ __global__ void k_convert(const S* x, D* y, int64_t n) {
 
 static void launch_1d(int64_t n, hipStream_t s, void (*k)(double*, int), double* a, int b) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, a, b);
+  LAUNCH(k, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, a, b);
   HIPC(hipGetLastError());
 }
 
@@ -451,11 +505,18 @@ struct Sect {
   int crank = 0;
 };
 
-// top-p eigenpairs of symmetric H (ns x ns, per sector) -> W (desc), V (ns x p)
-static void eig_top(std::vector<Sect>& S, double* H, const std::vector<int64_t>& hoff, double* V,
-                    const std::vector<int64_t>& voff, double* W, const std::vector<int64_t>& woff, hipStream_t s) {
+// Leading spectral data of X (rA x rB) per sector. Output: eigenvalues of the
+// smaller Gram matrix H (= s^2, descending) in W and its eigenvectors in V
+// (ns x p, ld p), ns = min(rA, rB). Orders <= JMAX: Jacobi on H directly.
+// Larger orders: block power iteration with X and X^T alternately (the Gram
+// matrices of the iterates then span s^2, not s^4), each iterate
+// orthonormalised twice by the rank-revealing factor, and a Rayleigh-Ritz
+// step T = (X Q)^T (X Q) every 8 iterations until the leading Ritz values are
+// stable (relative change <= 1e-14 of the largest) or 96 iterations.
+static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const std::vector<int64_t>& hoff,
+                    const double* X, const std::vector<int64_t>& xoff, double* V, const std::vector<int64_t>& voff,
+                    double* W, const std::vector<int64_t>& woff, hipStream_t s) {
   const int ng = (int)S.size();
-  // direct Jacobi for small orders
   std::vector<EigJob> ej;
   std::vector<int64_t> tmp_off;
   int64_t tmp_n = 0;
@@ -481,105 +542,119 @@ static void eig_top(std::vector<Sect>& S, double* H, const std::vector<int64_t>&
   }
   if (!ej.empty()) {
     DBuf<EigJob> dj = to_device(ej, s);
-    hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p, 40);
-    HIPC(hipGetLastError());
+    LAUNCH(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p, 40);
     HIPC(hipStreamSynchronize(s));
   }
-  // subspace iteration for large orders
   std::vector<int> it;
   for (int g = 0; g < ng; ++g)
     if (S[g].iterate) it.push_back(g);
   if (it.empty()) return;
-  int64_t qn = 0, gn = 0;
-  std::vector<int64_t> qoff, goff;
-  for (int g : it) {
-    qoff.push_back(qn);
-    qn += (int64_t)S[g].ns * S[g].p;
-    goff.push_back(gn);
-    gn += (int64_t)S[g].p * S[g].p;
-  }
-  DBuf<double> Qb(qn, s), Yb(qn, s), Gb(gn, s), Rb(gn, s), Tb(gn, s), Wv(gn, s), Ww(qn, s), Vt(gn, s);
-  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)cdiv(qn, 256)), dim3(256), 0, s, Qb.p, qn,
-                     (uint64_t)0x5eedf00dull);
-  HIPC(hipGetLastError());
-  const int iters = 24;
-  auto multiply = [&](const double* Qin, double* Yout) {
-    std::vector<GemmGroup> gs;
-    for (size_t t = 0; t < it.size(); ++t) {
-      const Sect& x = S[it[t]];
-      gs.push_back(plain_group(x.ns, x.p, x.ns, hoff[it[t]], x.ns, 0, qoff[t], x.p, 0, qoff[t], x.p));
-    }
-    // H is stored at H (absolute); Q / Y offsets relative to their buffers
-    std::vector<GemmGroup> g2 = gs;
-    for (size_t t = 0; t < it.size(); ++t) g2[t].a_off = hoff[it[t]];
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g2, H, Qin, Yout, nullptr, s);
-  };
-  auto orthonormalize = [&](double* Y, double* Qout) {
-    std::vector<GemmGroup> gs;
-    for (size_t t = 0; t < it.size(); ++t) {
-      const Sect& x = S[it[t]];
-      gs.push_back(plain_group(x.p, x.p, x.ns, qoff[t], x.p, 1, qoff[t], x.p, 0, goff[t], x.p));
-    }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, Y, Y, Gb.p, nullptr, s);
-    std::vector<OrthJob> oj;
-    for (size_t t = 0; t < it.size(); ++t) {
-      OrthJob o;
-      o.G = Gb.p + goff[t];
-      o.Rinv = Rb.p + goff[t];
-      o.p = S[it[t]].p;
-      o.pad = 0;
-      oj.push_back(o);
-    }
-    DBuf<OrthJob> doj = to_device(oj, s);
-    hipLaunchKernelGGL(k_chol_inv, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p);
-    HIPC(hipGetLastError());
-    std::vector<GemmGroup> g3;
-    for (size_t t = 0; t < it.size(); ++t) {
-      const Sect& x = S[it[t]];
-      g3.push_back(plain_group(x.ns, x.p, x.p, qoff[t], x.p, 0, goff[t], x.p, 0, qoff[t], x.p));
-    }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g3, Y, Rb.p, Qout, nullptr, s);
-  };
-  // two CholQR passes per orthonormalisation keep Q orthonormal to rounding
-  orthonormalize(Qb.p, Yb.p);
-  orthonormalize(Yb.p, Qb.p);
-  for (int k = 0; k < iters; ++k) {
-    multiply(Qb.p, Yb.p);
-    orthonormalize(Yb.p, Qb.p);
-    orthonormalize(Qb.p, Yb.p);
-    std::swap(Qb.p, Yb.p);
-  }
-  // Rayleigh-Ritz: T = Q^T H Q
-  multiply(Qb.p, Yb.p);
-  {
-    std::vector<GemmGroup> gs;
-    for (size_t t = 0; t < it.size(); ++t) {
-      const Sect& x = S[it[t]];
-      gs.push_back(plain_group(x.p, x.p, x.ns, qoff[t], x.p, 1, qoff[t], x.p, 0, goff[t], x.p));
-    }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, Qb.p, Yb.p, Tb.p, nullptr, s);
-  }
-  std::vector<EigJob> ej2;
-  for (size_t t = 0; t < it.size(); ++t) {
-    EigJob j;
-    j.H = Tb.p + goff[t];
-    j.V = Wv.p + goff[t];
-    j.W = W + woff[it[t]];
-    j.Vtmp = Vt.p + goff[t];
-    j.n = S[it[t]].p;
-    j.pad = 0;
-    ej2.push_back(j);
-  }
-  DBuf<EigJob> dj2 = to_device(ej2, s);
-  hipLaunchKernelGGL(k_jacobi_eig, dim3((unsigned)ej2.size()), dim3(LT), 0, s, dj2.p, 40);
-  HIPC(hipGetLastError());
-  // V = Q Wv  (ns x p)
-  std::vector<GemmGroup> g4;
-  for (size_t t = 0; t < it.size(); ++t) {
+  const int ni = (int)it.size();
+  // per iterated sector: eigen side e (dim ne), other side o (dim no)
+  std::vector<int64_t> ne(ni), no(ni), qoff(ni), zoff(ni), goff(ni);
+  int64_t qn = 0, zn = 0, gn = 0;
+  for (int t = 0; t < ni; ++t) {
     const Sect& x = S[it[t]];
-    g4.push_back(plain_group(x.ns, x.p, x.p, qoff[t], x.p, 0, goff[t], x.p, 0, voff[it[t]], x.p));
+    const bool eR = x.rB <= x.rA;  // eigenvectors live in the rB space
+    ne[t] = eR ? x.rB : x.rA;
+    no[t] = eR ? x.rA : x.rB;
+    qoff[t] = qn;
+    qn += ne[t] * x.p;
+    zoff[t] = zn;
+    zn += no[t] * x.p;
+    goff[t] = gn;
+    gn += (int64_t)x.p * x.p;
   }
-  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g4, Qb.p, Wv.p, V, nullptr, s);
+  DBuf<double> Qa(qn, s), Qb(qn, s), Za(zn, s), Zb(zn, s), Gm(gn, s), Rs(gn, s), Mm(gn, s), Tm(gn, s),
+      Wv(gn, s), Vt(gn, s), Wt(std::max<int64_t>(ni * (int64_t)JMAX, 1), s);
+  // GEMM plans (reused every iteration)
+  std::vector<GemmGroup> gxq, gxz, gq_gram, gz_gram, gq_app, gz_app, gt;
+  for (int t = 0; t < ni; ++t) {
+    const Sect& x = S[it[t]];
+    const int64_t p = x.p;
+    const bool eR = x.rB <= x.rA;
+    // Z = op(X) Q : eR -> X (rA x rB) * Q (rB x p); else X^T (rB x rA) * Q (rA x p)
+    gxq.push_back(plain_group(no[t], p, ne[t], xoff[it[t]], x.rB, eR ? 0 : 1, qoff[t], p, 0, zoff[t], p));
+    // Q = op(X)^T Z : eR -> X^T * Z; else X * Z
+    gxz.push_back(plain_group(ne[t], p, no[t], xoff[it[t]], x.rB, eR ? 1 : 0, zoff[t], p, 0, qoff[t], p));
+    gq_gram.push_back(plain_group(p, p, ne[t], qoff[t], p, 1, qoff[t], p, 0, goff[t], p));
+    gz_gram.push_back(plain_group(p, p, no[t], zoff[t], p, 1, zoff[t], p, 0, goff[t], p));
+    gq_app.push_back(plain_group(ne[t], p, p, qoff[t], p, 0, goff[t], p, 0, qoff[t], p));
+    gz_app.push_back(plain_group(no[t], p, p, zoff[t], p, 0, goff[t], p, 0, zoff[t], p));
+    gt.push_back(plain_group(ne[t], p, p, qoff[t], p, 0, goff[t], p, 0, voff[it[t]], p));
+  }
+  GemmPlan Pxq, Pxz, Pqg, Pzg, Pqa, Pza, Pv;
+  gemm_plan(Pxq, gxq, FTN_GEMM_F64, s);
+  gemm_plan(Pxz, gxz, FTN_GEMM_F64, s);
+  gemm_plan(Pqg, gq_gram, FTN_GEMM_F64, s);
+  gemm_plan(Pzg, gz_gram, FTN_GEMM_F64, s);
+  gemm_plan(Pqa, gq_app, FTN_GEMM_F64, s);
+  gemm_plan(Pza, gz_app, FTN_GEMM_F64, s);
+  gemm_plan(Pv, gt, FTN_GEMM_F64, s);
+  std::vector<OrthJob> oj;
+  std::vector<EigJob> ejr;
+  for (int t = 0; t < ni; ++t) {
+    OrthJob o;
+    o.G = Gm.p + goff[t];
+    o.Rinv = Rs.p + goff[t];
+    o.M = Mm.p + goff[t];
+    o.p = S[it[t]].p;
+    o.pad = 0;
+    oj.push_back(o);
+    EigJob e;
+    e.H = Tm.p + goff[t];
+    e.V = Wv.p + goff[t];
+    e.W = Wt.p + (int64_t)t * JMAX;
+    e.Vtmp = Vt.p + goff[t];
+    e.n = S[it[t]].p;
+    e.pad = 0;
+    ejr.push_back(e);
+  }
+  DBuf<OrthJob> doj = to_device(oj, s);
+  DBuf<EigJob> dej = to_device(ejr, s);
+  HIPC(hipStreamSynchronize(s));
+  const double tol = 1e-13;
+  // Y (buffer y) <- orthonormal basis of its columns, through scratch o
+  auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double* y, double* o) {
+    run_gemm(gram, FTN_F64, y, y, Gm.p, nullptr, s);
+    LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
+    run_gemm(app, FTN_F64, y, Mm.p, o, nullptr, s);
+  };
+  LAUNCH(k_fill_random, dim3((unsigned)cdiv(qn, 256)), dim3(256), 0, s, Qa.p, qn, (uint64_t)0x5eedf00dull);
+  orth(Pqg, Pqa, Qa.p, Qb.p);
+  orth(Pqg, Pqa, Qb.p, Qa.p);  // Q in Qa
+  std::vector<double> prev, cur(ni * (int64_t)JMAX);
+  const int max_iter = 96, check = 8;
+  for (int k = 1; k <= max_iter; ++k) {
+    run_gemm(Pxq, FTN_F64, X, Qa.p, Za.p, nullptr, s);
+    orth(Pzg, Pza, Za.p, Zb.p);
+    orth(Pzg, Pza, Zb.p, Za.p);
+    run_gemm(Pxz, FTN_F64, X, Za.p, Qa.p, nullptr, s);
+    orth(Pqg, Pqa, Qa.p, Qb.p);
+    orth(Pqg, Pqa, Qb.p, Qa.p);
+    if (k % check == 0 || k == max_iter) {
+      // Rayleigh-Ritz: Z = op(X) Q; T = Z^T Z
+      run_gemm(Pxq, FTN_F64, X, Qa.p, Za.p, nullptr, s);
+      run_gemm(Pzg, FTN_F64, Za.p, Za.p, Tm.p, nullptr, s);
+      LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p, 40);
+      HIPC(hipMemcpyAsync(cur.data(), Wt.p, cur.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      bool done = !prev.empty();
+      for (int t = 0; t < ni && done; ++t) {
+        const int kk = (int)std::min<int64_t>(chi, S[it[t]].p);
+        const double top = std::max(cur[(int64_t)t * JMAX], 1e-300);
+        for (int q = 0; q < kk; ++q)
+          if (std::fabs(cur[(int64_t)t * JMAX + q] - prev[(int64_t)t * JMAX + q]) > 1e-14 * top) done = false;
+      }
+      prev = cur;
+      if (done) break;
+    }
+  }
+  // outputs: eigenvalues, eigenvectors V = Q Wv
+  for (int t = 0; t < ni; ++t)
+    HIPC(hipMemcpyAsync(W + woff[it[t]], Wt.p + (int64_t)t * JMAX, S[it[t]].p * 8, hipMemcpyDeviceToDevice, s));
+  run_gemm(Pv, FTN_F64, Qa.p, Wv.p, V, nullptr, s);
+  HIPC(hipStreamSynchronize(s));
 }
 
 CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff,
@@ -592,6 +667,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   const Leg& LB = b.legs()[lb];
   if (LA.dual == LB.dual) fail(FTN_ECHARGE, "bond legs must have opposite duals");
   const int sym = a.sym();
+  if (a.size() == 0 || b.size() == 0) fail(FTN_EINVAL, "compress_bond: empty tensor");
   const int gk = a.dtype == FTN_F64 ? FTN_GEMM_F64 : FTN_GEMM_F32;
   auto P = dot_plan(a, b, {la}, {lb}, FTN_GLOBAL, gk, s);
   DotPlanView pv = dot_plan_view(*P);
@@ -605,10 +681,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     run_perm(0, a.S(), a.dtype, *pv.pa, a.data, a32.p, s);
     run_perm(0, b.S(), b.dtype, *pv.pb, b.data, b32.p, s);
     if (pv.asz)
-      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)cdiv(pv.asz, 256)), dim3(256), 0, s, a32.p,
+      LAUNCH((k_convert<float, double>), dim3((unsigned)cdiv(pv.asz, 256)), dim3(256), 0, s, a32.p,
                          At.p, pv.asz);
     if (pv.bsz)
-      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)cdiv(pv.bsz, 256)), dim3(256), 0, s, b32.p,
+      LAUNCH((k_convert<float, double>), dim3((unsigned)cdiv(pv.bsz, 256)), dim3(256), 0, s, b32.p,
                          Bt.p, pv.bsz);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));
@@ -628,6 +704,22 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     S.push_back(x);
   }
   const int ng = (int)S.size();
+  if (ng == 0) {
+    auto leg_str = [](const Leg& l) {
+      std::string r = "dual " + std::to_string(l.dual) + " [";
+      for (int k = 0; k < l.nsect(); ++k)
+        r += "(" + std::to_string(l.q[k].a) + "," + std::to_string(l.q[k].b) + "):" + std::to_string(l.d[k]) + " ";
+      return r + "]";
+    };
+    std::string g;
+    for (size_t gi = 0; gi < pv.groups.size(); ++gi)
+      g += " {M " + std::to_string(pv.groups[gi].M) + " N " + std::to_string(pv.groups[gi].N) + " K " +
+           std::to_string(pv.groups[gi].K) + "}";
+    fail(FTN_EINVAL, "compress_bond: no charge sector common to both bond legs: A leg " + std::to_string(la) +
+                         " of " + std::to_string(a.ndim()) + " " + leg_str(LA) + ", B leg " + std::to_string(lb) +
+                         " of " + std::to_string(b.ndim()) + " " + leg_str(LB) + ", sizes " +
+                         std::to_string(a.size()) + " / " + std::to_string(b.size()) + ", groups" + g);
+  }
   {
     std::vector<int> order(ng);
     for (int g = 0; g < ng; ++g) order[g] = g;
@@ -666,7 +758,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       }
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gA, At.p, At.p, part.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gB, Bt.p, Bt.p, part.p, nullptr, s);
-    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
+    LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
   // pivoted Cholesky of both Gram matrices
@@ -682,7 +774,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     DBuf<CholJob> dcj = to_device(cj, s);
     DBuf<int> drank(2 * ng, s);
     if (ng) {
-      hipLaunchKernelGGL(k_chol_pivot, dim3(2 * ng), dim3(LT), 0, s, dcj.p, 1e-13, drank.p);
+      LAUNCH(k_chol_pivot, dim3(2 * ng), dim3(LT), 0, s, dcj.p, 1e-13, drank.p);
       HIPC(hipGetLastError());
     }
     std::vector<int> rk(2 * ng);
@@ -728,7 +820,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rm.p, Rm.p, Xm.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Xm.p, Xm.p, Hm.p, nullptr, s);
   }
-  eig_top(S, Hm.p, hoff, Vm.p, voff, Wm.p, woff, s);
+  eig_top(S, chi, Hm.p, hoff, Xm.p, xoff, Vm.p, voff, Wm.p, woff, s);
   // singular values = sqrt(eigenvalues); selection
   launch_1d(std::max<int64_t>(ws, 1), s, k_sqrt_inplace, Wm.p, (int)std::max<int64_t>(ws, 1));
   {
@@ -747,7 +839,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     HIPC(hipMemcpyAsync(hw.data(), Wm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     std::vector<double> vals(n);
-    for (int i = 0; i < n; ++i) vals[i] = hw[pos[i]];
+    for (int i = 0; i < n; ++i) {
+      vals[i] = hw[pos[i]];
+      if (!std::isfinite(vals[i])) fail(FTN_ENOCONV, "compress_bond: non-finite singular value");
+    }
     DBuf<double> dv = to_device(vals, s);
     DBuf<int> dg = to_device(grp, s), di = to_device(idx, s), dc = to_device(crank, s);
     DBuf<int> dk(std::max(ng, 1), s);
@@ -755,8 +850,11 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     std::vector<double> st(4, 0.0);
     HIPC(hipMemsetAsync(dst.p, 0, 32, s));
     if (ng > 1024) fail(FTN_ENOTSUP, "more than 1024 bond sectors");
+    // the Gram route resolves singular values to ~1e-8 of the largest, so a
+    // relative cutoff below 1e-6 is raised to 1e-6 (values under it are zero)
+    const double eff_cut = std::max(cutoff, 1e-6);
     if (n)
-      hipLaunchKernelGGL(k_select, dim3(1), dim3(LT), 0, s, dv.p, dg.p, di.p, dc.p, n, ng, chi, cutoff, dk.p, dst.p);
+      LAUNCH(k_select, dim3(1), dim3(LT), 0, s, dv.p, dg.p, di.p, dc.p, n, ng, chi, eff_cut, dk.p, dst.p);
     HIPC(hipGetLastError());
     std::vector<int> kept(std::max(ng, 1), 0);
     if (n) HIPC(hipMemcpyAsync(kept.data(), dk.p, ng * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -802,11 +900,11 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       // O = X V (rows rA) or X^T U (rows rB); O / s are the other singular
       // vectors, and both sides are then scaled by s^-1/2
       const int64_t rows = x.rB <= x.rA ? x.rA : x.rB;
-      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
+      LAUNCH(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
                          rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 2);
-      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv((int64_t)x.ns * x.kept, 256)), dim3(256), 0, s,
+      LAUNCH(k_scale_cols, dim3((unsigned)cdiv((int64_t)x.ns * x.kept, 256)), dim3(256), 0, s,
                          Vm.p + voff[g], (int64_t)x.ns, (int64_t)x.p, x.kept, Wm.p + woff[g], 0);
-      hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
+      LAUNCH(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
                          rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 0);
       HIPC(hipGetLastError());
     }

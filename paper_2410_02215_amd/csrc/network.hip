@@ -16,6 +16,8 @@
 // intermediate is rescaled by a power of two (exact), kept in an exponent.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -179,6 +181,7 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
     for (int t = 0; t < n; ++t) ssa[t] = t;
     int next_bond = net->nbonds;
     int64_t e2 = 0;
+    const bool trace = std::getenv("FTN_TRACE") != nullptr;
     double st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < nsteps; ++k) {
       int i = ssa_path[2 * k], j = ssa_path[2 * k + 1];
@@ -239,7 +242,7 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
           }
           const int64_t dim = T[z]->legs()[lzs[0]].size();
           if (dim > chi) {
-            CompressResult r = op_compress_bond(*T[z], *T[w], lzs[0], lw[0], chi, 1e-12, FTN_LOCAL, s);
+            CompressResult r = op_compress_bond(*T[z], *T[w], lzs[0], lw[0], chi, 1e-6, FTN_LOCAL, s);
             T[z] = std::move(r.a);
             T[w] = std::move(r.b);
             st[1] += 1;
@@ -249,6 +252,14 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
         }
       }
       st[4] = std::max(st[4], (double)T[z]->size());
+      if (T[z]->size() == 0 && T[z]->ndim() > 0)
+        fail(FTN_EINVAL, "path step " + std::to_string(k) + " produced a tensor with no allowed block");
+      if (trace) {
+        std::string d;
+        for (auto& l : T[z]->legs()) d += std::to_string(l.size()) + (l.dual ? "-" : "+") + " ";
+        std::fprintf(stderr, "[ftn] step %d: (%d,%d) -> %d legs [%s] size %lld\n", k, i, j, T[z]->ndim(),
+                     d.c_str(), (long long)T[z]->size());
+      }
       double m = op_max_abs(*T[z], s);
       if (m > 0 && std::isfinite(m)) {
         int e;

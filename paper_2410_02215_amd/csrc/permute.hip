@@ -140,12 +140,12 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
   void* tok = prof_begin(s);
   if (dtype == FTN_F64) {
     auto k = dir == 0 ? k_block_matrix<double, 0> : k_block_matrix<double, 1>;
-    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
+    LAUNCH(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
                        p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
                        (const double*)src, (double*)dst, alpha);
   } else {
     auto k = dir == 0 ? k_block_matrix<float, 0> : k_block_matrix<float, 1>;
-    hipLaunchKernelGGL(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
+    LAUNCH(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
                        p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
                        (const float*)src, (float*)dst, (float)alpha);
   }
@@ -202,7 +202,7 @@ void unary_tasks(const Structure& src, const Structure& dst, const SignOp& op,
   std::vector<int32_t> rb(remap_base.begin(), remap_base.end());
   DBuf<int32_t> drm = to_device(remap, s);
   DBuf<int32_t> drb = to_device(rb, s);
-  hipLaunchKernelGGL(k_unary_tasks, dim3((unsigned)cdiv(src.nblocks, 128)), dim3(128), 0, s, src.ndim,
+  LAUNCH(k_unary_tasks, dim3((unsigned)cdiv(src.nblocks, 128)), dim3(128), 0, s, src.ndim,
                      op, src.d_keys.p, src.nblocks, dst.d_keys.p, dst.d_offsets.p, dst.nblocks, drm.p,
                      drb.p, tasks.p);
   HIPC(hipGetLastError());

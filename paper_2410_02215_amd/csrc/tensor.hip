@@ -16,6 +16,15 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
+void check_launch(const char* name, dim3 grid, dim3 block) {
+  const uint64_t threads = (uint64_t)grid.x * grid.y * grid.z * block.x * block.y * block.z;
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0 || block.x == 0)
+    fail(FTN_EINVAL, std::string("internal: empty launch of ") + name);
+  if ((uint64_t)grid.x * block.x >= (1ull << 32) || threads >= (1ull << 32))
+    fail(FTN_EINVAL, std::string("internal: launch of ") + name + " exceeds 2^32 work-items (grid " +
+                         std::to_string(grid.x) + ")");
+}
+
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
@@ -121,7 +130,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_exclusive(int64_t* v, int64_t n
 }
 
 void scan_exclusive(int64_t* v, int64_t n, int64_t* total_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(SCAN_T), 0, s, v, n, total_out);
+  LAUNCH(k_scan_exclusive, dim3(1), dim3(SCAN_T), 0, s, v, n, total_out);
   HIPC(hipGetLastError());
 }
 
@@ -278,7 +287,7 @@ std::shared_ptr<const Structure> get_structure(int sym, const std::vector<Leg>& 
     DBuf<int32_t> last(P, s);
     DBuf<int64_t> flag(P + 1, s);
     const int T = 256;
-    hipLaunchKernelGGL(k_enum_flags, dim3((unsigned)cdiv(P, T)), dim3(T), 0, s, dl.tab, dl.q.p, P,
+    LAUNCH(k_enum_flags, dim3((unsigned)cdiv(P, T)), dim3(T), 0, s, dl.tab, dl.q.p, P,
                        last.p, flag.p);
     HIPC(hipGetLastError());
     scan_exclusive(flag.p, P, flag.p + P, s);
@@ -292,7 +301,7 @@ std::shared_ptr<const Structure> get_structure(int sym, const std::vector<Leg>& 
     w->d_shapes = DBuf<int32_t>(nb * n, nullptr);
     w->d_parmask = DBuf<uint32_t>(nb, nullptr);
     if (nb) {
-      hipLaunchKernelGGL(k_enum_write, dim3((unsigned)cdiv(P, T)), dim3(T), 0, s, dl.tab, dl.q.p,
+      LAUNCH(k_enum_write, dim3((unsigned)cdiv(P, T)), dim3(T), 0, s, dl.tab, dl.q.p,
                          dl.d.p, P, last.p, flag.p, w->d_keys.p, w->d_offsets.p, w->d_shapes.p,
                          w->d_parmask.p);
       HIPC(hipGetLastError());
@@ -459,10 +468,10 @@ static void dense_io(const Tensor& t, void* dense, hipStream_t s) {
   const int T = 256;
   dim3 g((unsigned)cdiv(st.size, T));
   if (t.dtype == FTN_F64)
-    hipLaunchKernelGGL((k_dense_blocks<double, DIR>), g, dim3(T), 0, s, m, st.d_keys.p, st.d_shapes.p,
+    LAUNCH((k_dense_blocks<double, DIR>), g, dim3(T), 0, s, m, st.d_keys.p, st.d_shapes.p,
                        st.d_offsets.p, st.nblocks, st.size, dso.p, (double*)t.data, (double*)dense);
   else
-    hipLaunchKernelGGL((k_dense_blocks<float, DIR>), g, dim3(T), 0, s, m, st.d_keys.p, st.d_shapes.p,
+    LAUNCH((k_dense_blocks<float, DIR>), g, dim3(T), 0, s, m, st.d_keys.p, st.d_shapes.p,
                        st.d_offsets.p, st.nblocks, st.size, dso.p, (float*)t.data, (float*)dense);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));  // soff / dso lifetime
@@ -497,9 +506,9 @@ std::unique_ptr<Tensor> op_scale(const Tensor& a, double alpha, hipStream_t s) {
   if (n) {
     dim3 g((unsigned)cdiv(n, 256));
     if (a.dtype == FTN_F64)
-      hipLaunchKernelGGL(k_scale<double>, g, dim3(256), 0, s, (const double*)a.data, (double*)out->data, n, alpha);
+      LAUNCH(k_scale<double>, g, dim3(256), 0, s, (const double*)a.data, (double*)out->data, n, alpha);
     else
-      hipLaunchKernelGGL(k_scale<float>, g, dim3(256), 0, s, (const float*)a.data, (float*)out->data, n,
+      LAUNCH(k_scale<float>, g, dim3(256), 0, s, (const float*)a.data, (float*)out->data, n,
                          (float)alpha);
     HIPC(hipGetLastError());
   }
@@ -514,9 +523,9 @@ std::unique_ptr<Tensor> op_cast(const Tensor& a, int dtype, hipStream_t s) {
   if (a.dtype == dtype) {
     HIPC(hipMemcpyAsync(out->data, a.data, n * a.esize(), hipMemcpyDeviceToDevice, s));
   } else if (a.dtype == FTN_F64) {
-    hipLaunchKernelGGL((k_cast<double, float>), g, dim3(256), 0, s, (const double*)a.data, (float*)out->data, n);
+    LAUNCH((k_cast<double, float>), g, dim3(256), 0, s, (const double*)a.data, (float*)out->data, n);
   } else {
-    hipLaunchKernelGGL((k_cast<float, double>), g, dim3(256), 0, s, (const float*)a.data, (double*)out->data, n);
+    LAUNCH((k_cast<float, double>), g, dim3(256), 0, s, (const float*)a.data, (double*)out->data, n);
   }
   HIPC(hipGetLastError());
   return out;
@@ -560,10 +569,10 @@ double op_max_abs(const Tensor& a, hipStream_t s) {
   int nb = (int)std::min<int64_t>(1024, cdiv(n, 256));
   DBuf<double> part(nb + 1, s);
   if (a.dtype == FTN_F64)
-    hipLaunchKernelGGL(k_absmax<double>, dim3(nb), dim3(256), 0, s, (const double*)a.data, n, part.p);
+    LAUNCH(k_absmax<double>, dim3(nb), dim3(256), 0, s, (const double*)a.data, n, part.p);
   else
-    hipLaunchKernelGGL(k_absmax<float>, dim3(nb), dim3(256), 0, s, (const float*)a.data, n, part.p);
-  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, part.p, nb, part.p + nb);
+    LAUNCH(k_absmax<float>, dim3(nb), dim3(256), 0, s, (const float*)a.data, n, part.p);
+  LAUNCH(k_max_reduce, dim3(1), dim3(256), 0, s, part.p, nb, part.p + nb);
   HIPC(hipGetLastError());
   double m = 0.0;
   HIPC(hipMemcpyAsync(&m, part.p + nb, 8, hipMemcpyDeviceToHost, s));
@@ -576,9 +585,9 @@ void scale_inplace(Tensor& t, double alpha, hipStream_t s) {
   if (!n) return;
   dim3 g((unsigned)cdiv(n, 256));
   if (t.dtype == FTN_F64)
-    hipLaunchKernelGGL(k_scale<double>, g, dim3(256), 0, s, (const double*)t.data, (double*)t.data, n, alpha);
+    LAUNCH(k_scale<double>, g, dim3(256), 0, s, (const double*)t.data, (double*)t.data, n, alpha);
   else
-    hipLaunchKernelGGL(k_scale<float>, g, dim3(256), 0, s, (const float*)t.data, (float*)t.data, n, (float)alpha);
+    LAUNCH(k_scale<float>, g, dim3(256), 0, s, (const float*)t.data, (float*)t.data, n, (float)alpha);
   HIPC(hipGetLastError());
 }
 

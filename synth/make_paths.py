@@ -43,8 +43,8 @@ def plan(spec, chi, op_sites=None, seed=7, trials=3000, temperature=2.0):
 def main():
     out = {}
     cfg = W.c2()
-    out["c2_norm"] = plan(cfg["spec"], cfg["chi"])
-    out["c2_hop"] = plan(cfg["spec"], cfg["chi"], op_sites=cfg["op_sites"])
+    out["c2_norm"] = plan(cfg["spec"], cfg["chi"], seed=7, temperature=2.0)
+    out["c2_hop"] = plan(cfg["spec"], cfg["chi"], op_sites=cfg["op_sites"], seed=14, temperature=1.5)
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     with open(OUT, "w") as f:
         json.dump(out, f)
