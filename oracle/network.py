@@ -121,7 +121,10 @@ def _fuse_and_compress(st, z, chi, conv, order, cutoff=CUTOFF):
             lz = [st.lab[z].index(("b", bid))]
             lw = [st.lab[w].index(("b", bid))]
         dim = st.T[z].legs[lz[0]].size
-        if chi is not None and dim > chi:
+        # a tensor with no allowed block is exactly zero: every later product
+        # vanishes and there is no spectrum to truncate, so the bond is kept
+        empty = st.T[z].nnz() == 0 or st.T[w].nnz() == 0
+        if chi is not None and dim > chi and not empty:
             if conv == "local":
                 A, B, info = compress_bond(st.T[z], st.T[w], lz[0], lw[0], chi, conv="local", cutoff=cutoff)
                 st.T[z], st.T[w] = A, B

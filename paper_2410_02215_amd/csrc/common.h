@@ -108,13 +108,26 @@ struct DBuf {  // owning device buffer, released stream-ordered
   }
 };
 
-// upload a host vector into a new device buffer (async on s; the host
-// vector must stay alive until the copy completes, so callers keep it or
-// synchronise)
+// upload a host vector into a new device buffer, ordered on s. Copies from
+// pageable host memory are staged before hipMemcpyAsync returns, so the
+// vector may be released right after the call.
 template <typename T>
 DBuf<T> to_device(const std::vector<T>& v, hipStream_t s) {
   DBuf<T> b(v.size(), s);
   b.upload(v.data(), v.size());
+  return b;
+}
+
+// buffers of cached plans live for the whole process: allocated with
+// hipMalloc (no stream), filled on the stream that builds the plan
+template <typename T>
+DBuf<T> persist(size_t n) {
+  return DBuf<T>(n, nullptr);
+}
+template <typename T>
+DBuf<T> persist_upload(const std::vector<T>& v, hipStream_t s) {
+  DBuf<T> b(v.size(), nullptr);
+  if (v.size()) HIPC(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return b;
 }
 
@@ -274,11 +287,12 @@ struct GemmPlan {
   int64_t ntiles = 0;
   int kind = FTN_GEMM_F64;
 };
-void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s);
+void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
+               bool persistent = false);
 // C[g] = alpha * op(A[g]) op(B[g]) (+ beta C for plain outputs). No host sync.
 void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
               const GemmScatter* sc, hipStream_t s, double alpha = 1.0, double beta = 0.0);
-// one-off convenience: plan + run + synchronise
+// one-off convenience: plan + run (the plan's table is freed stream-ordered)
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,
                       const void* B, void* C, const GemmScatter* sc, hipStream_t s,
                       double alpha = 1.0, double beta = 0.0);

@@ -127,7 +127,7 @@ struct DotPlan {
 };
 
 static std::mutex g_plan_mu;
-static std::unordered_map<std::string, std::shared_ptr<DotPlan>> g_plans;
+static auto& g_plans = *new std::unordered_map<std::string, std::shared_ptr<DotPlan>>();
 
 static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, const std::vector<int>& axa,
                                            const std::vector<int>& axb, int conv, int gemm, hipStream_t s) {
@@ -297,12 +297,12 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
     std::vector<int> order(fa);
     order.insert(order.end(), axa.begin(), axa.end());
     P->pa.op = make_signop(na, order.data(), (int)fa.size(), k);
-    P->pa.tasks = DBuf<PermTask>(A.nblocks(), s);
+    P->pa.tasks = persist<PermTask>(A.nblocks());
     if (A.nblocks())
       LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(A.nblocks(), 128)), dim3(128), 0, s, da,
                          A.S().d_keys.p, A.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pa.tasks.p);
     HIPC(hipGetLastError());
-    perm_plan_tiles(P->pa, block_sizes(A.S()), s);  // synchronises
+    perm_plan_tiles(P->pa, block_sizes(A.S()), s);
   }
   {
     DBuf<int32_t> dkm = to_device(kfb, s);
@@ -316,7 +316,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       for (int t = 0; t < k; ++t)
         if (A.legs()[axa[t]].dual == 0) op.flip_mask |= 1u << axb[t];
     P->pb.op = op;
-    P->pb.tasks = DBuf<PermTask>(B.nblocks(), s);
+    P->pb.tasks = persist<PermTask>(B.nblocks());
     if (B.nblocks())
       LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(B.nblocks(), 128)), dim3(128), 0, s, db,
                          B.S().d_keys.p, B.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pb.tasks.p);
@@ -358,10 +358,10 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
     boff_n += (int64_t)nrc[g] * ncc[g];
     groups.push_back(gg);
   }
-  P->rc_start = to_device(rcs, s);
-  P->cc_start = to_device(ccs, s);
-  P->cc_dim = to_device(ccd, s);
-  P->boff = DBuf<int64_t>(std::max<int64_t>(boff_n, 1), s);
+  P->rc_start = persist_upload(rcs, s);
+  P->cc_start = persist_upload(ccs, s);
+  P->cc_dim = persist_upload(ccd, s);
+  P->boff = persist<int64_t>(std::max<int64_t>(boff_n, 1));
   HIPC(hipMemsetAsync(P->boff.p, 0xff, std::max<int64_t>(boff_n, 1) * sizeof(int64_t), s));  // -1
   {
     const Structure& CS = *P->cst;
@@ -388,7 +388,6 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
         // scalar output: one block at offset 0
         std::vector<int64_t> z(1, 0);
         HIPC(hipMemcpyAsync(P->boff.p, z.data(), 8, hipMemcpyHostToDevice, s));
-        HIPC(hipStreamSynchronize(s));
       } else {
         LAUNCH(k_dot_boff, dim3((unsigned)cdiv(CS.nblocks, 128)), dim3(128), 0, s, ba,
                            CS.d_keys.p, CS.d_offsets.p, CS.nblocks, drg.p, drl.p, dcl.p, dgb.p, dgn.p,
@@ -396,13 +395,12 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
         HIPC(hipGetLastError());
       }
     }
-    HIPC(hipStreamSynchronize(s));
   }
   P->sc.rc_start = P->rc_start.p;
   P->sc.cc_start = P->cc_start.p;
   P->sc.cc_dim = P->cc_dim.p;
   P->sc.boff = P->boff.p;
-  gemm_plan(P->gp, groups, gemm, s);
+  gemm_plan(P->gp, groups, gemm, s, true);
   P->flops = gemm_flops(groups);
   return P;
 }

@@ -346,7 +346,7 @@ double gemm_flops(const std::vector<GemmGroup>& groups) {
 
 constexpr int TBM = 64, TBN = 64;
 
-void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s) {
+void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s, bool persistent) {
   p.host.clear();
   p.kind = kind;
   int64_t t = 0;
@@ -360,9 +360,9 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   }
   if (t > 0x7fffffffLL) fail(FTN_EINVAL, "GEMM too large");
   p.ntiles = t;
-  p.groups = DBuf<GemmGroup>(p.host.size(), s);
-  p.groups.upload(p.host.data(), p.host.size());
-  HIPC(hipStreamSynchronize(s));
+  p.groups = persistent ? persist<GemmGroup>(p.host.size()) : DBuf<GemmGroup>(p.host.size(), s);
+  if (!p.host.empty())
+    HIPC(hipMemcpyAsync(p.groups.p, p.host.data(), p.host.size() * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
 }
 
 void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
@@ -404,7 +404,6 @@ void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups,
   GemmPlan p;
   gemm_plan(p, groups, gemm, s);
   run_gemm(p, dtype, A, B, C, sc, s, alpha, beta);
-  HIPC(hipStreamSynchronize(s));
 }
 
 }  // namespace ftn

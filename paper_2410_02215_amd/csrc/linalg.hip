@@ -134,6 +134,130 @@ __global__ void __launch_bounds__(LT) k_chol_pivot(const CholJob* jobs, double t
 }
 
 // ---------------------------------------------------------------------------
+// Blocked pivoted Cholesky (Gram matrices up to 4096): a panel kernel factors
+// up to 64 pivoted columns per launch (one workgroup per matrix), followed by
+// an MFMA GEMM that removes the panel from the Schur complement,
+// G <- G - R_p^T R_p. R is kept in original column order (R[l][c]), so the
+// update needs no gather. Stops at the numerical rank (largest remaining
+// pivot not above tol * largest diagonal of G).
+struct CholState {
+  double* G;    // d x d, overwritten by the Schur complement
+  double* R;    // d x d, zeroed on entry
+  double* dp;   // d: remaining pivots by position
+  int* piv;     // d: original index at each position
+  double* thr;  // 1: absolute pivot threshold
+  int* rank;    // 1: -1 while running, then the rank
+  int d;
+  int pad;
+};
+
+__global__ void __launch_bounds__(LT) k_chol_init(const CholState* st, double tol) {
+  const CholState S = st[blockIdx.x];
+  const int d = S.d, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ double red[LT / 64];
+  double m = 0.0;
+  for (int i = tid; i < d; i += LT) {
+    double v = S.G[(int64_t)i * d + i];
+    S.dp[i] = v;
+    S.piv[i] = i;
+    m = fmax(m, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) red[w] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double mm = 0.0;
+    for (int i = 0; i < LT / 64; ++i) mm = fmax(mm, red[i]);
+    S.thr[0] = tol * mm;
+    S.rank[0] = (mm > 0.0 && d > 0) ? -1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(LT) k_chol_panel(const CholState* st, int j0, int nb) {
+  const CholState S = st[blockIdx.x];
+  const int d = S.d, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (j0 >= d || S.rank[0] >= 0) return;
+  __shared__ double dp[CHOL_MAX];
+  __shared__ int piv[CHOL_MAX];
+  __shared__ double red_v[LT / 64];
+  __shared__ int red_i[LT / 64];
+  __shared__ int s_stop;
+  for (int i = tid; i < d; i += LT) {
+    dp[i] = S.dp[i];
+    piv[i] = S.piv[i];
+  }
+  if (tid == 0) s_stop = -1;
+  __syncthreads();
+  const double thr = S.thr[0];
+  const int jend = min(j0 + nb, d);
+  for (int j = j0; j < jend; ++j) {
+    double bv = -1.0;
+    int bi = d;
+    for (int i = j + tid; i < d; i += LT)
+      if (dp[i] > bv) {
+        bv = dp[i];
+        bi = i;
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(bv, o);
+      int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[w] = bv;
+      red_i[w] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = -1.0;
+      int p = d;
+      for (int i = 0; i < LT / 64; ++i)
+        if (red_v[i] > v || (red_v[i] == v && red_i[i] < p)) {
+          v = red_v[i];
+          p = red_i[i];
+        }
+      if (!(v > thr)) {
+        s_stop = j;
+      } else if (p != j) {
+        double t = dp[j];
+        dp[j] = dp[p];
+        dp[p] = t;
+        int ti = piv[j];
+        piv[j] = piv[p];
+        piv[p] = ti;
+      }
+    }
+    __syncthreads();
+    if (s_stop >= 0) break;
+    const int cj = piv[j];
+    const double rjj = sqrt(dp[j]);
+    if (tid == 0) S.R[(int64_t)j * d + cj] = rjj;
+    for (int i = j + 1 + tid; i < d; i += LT) {
+      const int ci = piv[i];
+      double sacc = S.G[(int64_t)cj * d + ci];
+      for (int l = j0; l < j; ++l) sacc -= S.R[(int64_t)l * d + cj] * S.R[(int64_t)l * d + ci];
+      const double r = sacc / rjj;
+      S.R[(int64_t)j * d + ci] = r;
+      dp[i] = fmax(dp[i] - r * r, 0.0);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < d; i += LT) {
+    S.dp[i] = dp[i];
+    S.piv[i] = piv[i];
+  }
+  if (tid == 0) {
+    if (s_stop >= 0)
+      S.rank[0] = s_stop;
+    else if (jend == d)
+      S.rank[0] = d;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // cyclic Jacobi eigensolver for symmetric n x n (n <= 128) held in LDS;
 // eigenvectors accumulated in global memory. Outputs eigenvalues in
 // descending order and the matching eigenvector columns (row-major n x n).
@@ -761,28 +885,55 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
-  // pivoted Cholesky of both Gram matrices
+  // pivoted Cholesky of both Gram matrices (blocked: panel + MFMA update)
   DBuf<double> Rm(std::max<int64_t>(gsz, 1), s);
   HIPC(hipMemsetAsync(Rm.p, 0, std::max<int64_t>(gsz, 1) * 8, s));
   {
-    std::vector<CholJob> cj;
+    const int nm = 2 * ng;
+    std::vector<int64_t> moff(nm), md(nm);
+    int64_t dsum = 0, dmax = 0;
     for (int g = 0; g < ng; ++g) {
       if (S[g].d > CHOL_MAX) fail(FTN_ENOTSUP, "bond sector larger than 4096");
-      cj.push_back(CholJob{Gm.p + goffA[g], Rm.p + goffA[g], (int)S[g].d, 0});
-      cj.push_back(CholJob{Gm.p + goffB[g], Rm.p + goffB[g], (int)S[g].d, 0});
+      moff[2 * g] = goffA[g];
+      moff[2 * g + 1] = goffB[g];
+      md[2 * g] = md[2 * g + 1] = S[g].d;
+      dsum += 2 * S[g].d;
+      dmax = std::max(dmax, S[g].d);
     }
-    DBuf<CholJob> dcj = to_device(cj, s);
-    DBuf<int> drank(2 * ng, s);
-    if (ng) {
-      LAUNCH(k_chol_pivot, dim3(2 * ng), dim3(LT), 0, s, dcj.p, 1e-13, drank.p);
-      HIPC(hipGetLastError());
+    DBuf<double> dpv(std::max<int64_t>(dsum, 1), s), thr(nm, s);
+    DBuf<int> pv(std::max<int64_t>(dsum, 1), s), rk(nm, s);
+    std::vector<CholState> cs(nm);
+    int64_t o = 0;
+    for (int m = 0; m < nm; ++m) {
+      cs[m] = CholState{Gm.p + moff[m], Rm.p + moff[m], dpv.p + o, pv.p + o, thr.p + m, rk.p + m, (int)md[m], 0};
+      o += md[m];
     }
-    std::vector<int> rk(2 * ng);
-    if (ng) HIPC(hipMemcpyAsync(rk.data(), drank.p, 2 * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    DBuf<CholState> dcs = to_device(cs, s);
+    const int nb = 64;
+    LAUNCH(k_chol_init, dim3(nm), dim3(LT), 0, s, dcs.p, 1e-13);
+    std::vector<GemmPlan> upd;
+    for (int j0 = 0; j0 < dmax; j0 += nb) {
+      LAUNCH(k_chol_panel, dim3(nm), dim3(LT), 0, s, dcs.p, j0, nb);
+      std::vector<GemmGroup> gs;
+      for (int m = 0; m < nm; ++m) {
+        const int64_t d = md[m];
+        if (j0 + nb >= d) continue;  // no later panel reads this matrix
+        const int64_t kk = std::min<int64_t>(nb, d - j0);
+        gs.push_back(plain_group(d, d, kk, moff[m] + j0 * d, d, 1, moff[m] + j0 * d, d, 0, moff[m], d));
+      }
+      if (!gs.empty()) {
+        upd.emplace_back();
+        gemm_plan(upd.back(), gs, FTN_GEMM_F64, s);
+        run_gemm(upd.back(), FTN_F64, Rm.p, Rm.p, Gm.p, nullptr, s, -1.0, 1.0);
+      }
+    }
+    std::vector<int> rks(nm);
+    HIPC(hipMemcpyAsync(rks.data(), rk.p, nm * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     for (int g = 0; g < ng; ++g) {
-      S[g].rA = rk[2 * g];
-      S[g].rB = rk[2 * g + 1];
+      S[g].rA = rks[2 * g];
+      S[g].rB = rks[2 * g + 1];
+      if (S[g].rA < 0 || S[g].rB < 0) fail(FTN_EINVAL, "internal: Cholesky did not finish");
     }
   }
   // X = R_A R_B^T (rA x rB); H = X^T X (rB <= rA) or X X^T

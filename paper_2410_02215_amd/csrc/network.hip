@@ -241,7 +241,8 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
             lzs = shared_legs(L[z], L[w], lw);
           }
           const int64_t dim = T[z]->legs()[lzs[0]].size();
-          if (dim > chi) {
+          // a tensor with no allowed block is exactly zero: nothing to truncate
+          if (dim > chi && T[z]->size() > 0 && T[w]->size() > 0) {
             CompressResult r = op_compress_bond(*T[z], *T[w], lzs[0], lw[0], chi, 1e-6, FTN_LOCAL, s);
             T[z] = std::move(r.a);
             T[w] = std::move(r.b);
@@ -252,8 +253,6 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
         }
       }
       st[4] = std::max(st[4], (double)T[z]->size());
-      if (T[z]->size() == 0 && T[z]->ndim() > 0)
-        fail(FTN_EINVAL, "path step " + std::to_string(k) + " produced a tensor with no allowed block");
       if (trace) {
         std::string d;
         for (auto& l : T[z]->legs()) d += std::to_string(l.size()) + (l.dual ? "-" : "+") + " ";

@@ -4,6 +4,7 @@
 // device from the parity bits of its sectors (integer, bit-exact).
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
@@ -129,9 +130,7 @@ void perm_plan_tiles(PermPlan& p, const std::vector<int64_t>& task_elems, hipStr
   }
   if (tiles > 0x7fffffffLL) fail(FTN_EINVAL, "permute too large");
   p.ntiles = tiles;
-  p.tile_start = DBuf<int64_t>(ts.size(), s);
-  p.tile_start.upload(ts.data(), ts.size());
-  HIPC(hipStreamSynchronize(s));
+  p.tile_start = persist_upload(ts, s);
 }
 
 void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const void* src, void* dst,
@@ -197,7 +196,7 @@ __global__ void k_unary_tasks(int n, SignOp op, const int32_t* __restrict__ skey
 void unary_tasks(const Structure& src, const Structure& dst, const SignOp& op,
                  const std::vector<int32_t>& remap, const std::vector<int>& remap_base,
                  DBuf<PermTask>& tasks, hipStream_t s) {
-  tasks = DBuf<PermTask>(src.nblocks, s);
+  tasks = persist<PermTask>(src.nblocks);
   if (!src.nblocks) return;
   std::vector<int32_t> rb(remap_base.begin(), remap_base.end());
   DBuf<int32_t> drm = to_device(remap, s);
@@ -205,9 +204,18 @@ void unary_tasks(const Structure& src, const Structure& dst, const SignOp& op,
   LAUNCH(k_unary_tasks, dim3((unsigned)cdiv(src.nblocks, 128)), dim3(128), 0, s, src.ndim,
                      op, src.d_keys.p, src.nblocks, dst.d_keys.p, dst.d_offsets.p, dst.nblocks, drm.p,
                      drb.p, tasks.p);
-  HIPC(hipGetLastError());
-  HIPC(hipStreamSynchronize(s));
 }
+
+// cache of unary permutes: output structure + ready plan per (input
+// structure, operation)
+namespace {
+struct UnaryPlan {
+  std::shared_ptr<const Structure> out;
+  PermPlan pp;
+};
+std::mutex g_unary_mu;
+auto* g_unary = new std::unordered_map<std::string, std::shared_ptr<UnaryPlan>>();
+}  // namespace
 
 std::vector<int64_t> block_sizes(const Structure& s) {
   std::vector<int64_t> v(s.nblocks);
@@ -220,8 +228,8 @@ static std::unique_ptr<Tensor> unary_signed(const Tensor& a, const std::vector<L
                                             const SignOp& op, const std::vector<int32_t>& remap,
                                             const std::vector<int>& rbase, hipStream_t s,
                                             const Q* total = nullptr) {
-  auto out = make_tensor(a.sym(), a.dtype, out_legs, total ? *total : a.total(), s, false);
   if (a.ndim() == 0) {
+    auto out = make_tensor(a.sym(), a.dtype, out_legs, total ? *total : a.total(), s, false);
     if (a.size()) {
       HIPC(hipMemcpyAsync(out->data, a.data, a.esize(), hipMemcpyDeviceToDevice, s));
       if (op.phase) {
@@ -231,12 +239,29 @@ static std::unique_ptr<Tensor> unary_signed(const Tensor& a, const std::vector<L
     }
     return out;
   }
-  PermPlan pp;
-  pp.op = op;
-  unary_tasks(a.S(), out->S(), op, remap, rbase, pp.tasks, s);
-  if (out->size() != a.size()) fail(FTN_EINVAL, "internal: unary permute changed the size");
-  perm_plan_tiles(pp, block_sizes(a.S()), s);
-  run_perm(0, a.S(), a.dtype, pp, a.data, out->data, s);
+  std::string key = a.st->skey + "|u|";
+  key.append((const char*)&op, sizeof(op));
+  key.append((const char*)remap.data(), remap.size() * sizeof(int32_t));
+  key += structure_key(a.sym(), out_legs, total ? *total : a.total());
+  std::shared_ptr<UnaryPlan> U;
+  {
+    std::lock_guard<std::mutex> g(g_unary_mu);
+    auto it = g_unary->find(key);
+    if (it != g_unary->end()) U = it->second;
+  }
+  if (!U) {
+    U = std::make_shared<UnaryPlan>();
+    U->out = get_structure(a.sym(), out_legs, total ? *total : a.total(), s);
+    U->pp.op = op;
+    unary_tasks(a.S(), *U->out, op, remap, rbase, U->pp.tasks, s);
+    if (U->out->size != a.size()) fail(FTN_EINVAL, "internal: unary permute changed the size");
+    perm_plan_tiles(U->pp, block_sizes(a.S()), s);
+    std::lock_guard<std::mutex> g(g_unary_mu);
+    if (g_unary->size() > 8192) g_unary->clear();
+    g_unary->emplace(key, U);
+  }
+  auto out = make_tensor(U->out, a.dtype, s, false);
+  run_perm(0, a.S(), a.dtype, U->pp, a.data, out->data, s);
   return out;
 }
 
@@ -344,6 +369,18 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
   const int m = (int)glegs.size();
   const int sym = a.sym();
   if (m < 1) fail(FTN_EINVAL, "fuse needs at least one leg");
+  std::string key = a.st->skey + "|f|" + std::to_string(conv) + "," + std::to_string(rev) + "|";
+  for (int l : glegs) key += std::to_string(l) + ",";
+  {
+    std::lock_guard<std::mutex> g(g_unary_mu);
+    auto it = g_unary->find(key);
+    if (it != g_unary->end()) {
+      auto U = it->second;
+      auto out = make_tensor(U->out, a.dtype, s, false);
+      run_perm(0, a.S(), a.dtype, U->pp, a.data, out->data, s);
+      return out;
+    }
+  }
   std::vector<int> isg(n, 0);
   for (int l : glegs) {
     if (l < 0 || l >= n || isg[l]) fail(FTN_EINVAL, "bad fuse legs");
@@ -412,7 +449,8 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
   for (int i = 0; i < pos; ++i) out_legs.push_back(a.legs()[rest[i]]);
   out_legs.push_back(fl);
   for (size_t i = pos; i < rest.size(); ++i) out_legs.push_back(a.legs()[rest[i]]);
-  auto out = make_tensor(sym, a.dtype, out_legs, a.total(), s, true);
+  // every output entry is written by exactly one source block
+  auto out = make_tensor(sym, a.dtype, out_legs, a.total(), s, false);
   const Structure& A = a.S();
   const Structure& O = out->S();
   SignOp op = make_signop(n, order.data(), pos, m);
@@ -444,11 +482,15 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
     tk.extra = 0;
     tasks[b] = tk;
   }
-  PermPlan pp;
-  pp.op = op;
-  pp.tasks = to_device(tasks, s);
-  perm_plan_tiles(pp, block_sizes(A), s);
-  run_perm(0, A, a.dtype, pp, a.data, out->data, s);
+  auto U = std::make_shared<UnaryPlan>();
+  U->out = out->st;
+  U->pp.op = op;
+  U->pp.tasks = persist_upload(tasks, s);
+  perm_plan_tiles(U->pp, block_sizes(A), s);
+  run_perm(0, A, a.dtype, U->pp, a.data, out->data, s);
+  std::lock_guard<std::mutex> g(g_unary_mu);
+  if (g_unary->size() > 8192) g_unary->clear();
+  g_unary->emplace(key, U);
   return out;
 }
 

@@ -234,7 +234,7 @@ std::string structure_key(int sym, const std::vector<Leg>& legs, Q total) {
 }
 
 static std::mutex g_struct_mu;
-static std::unordered_map<std::string, std::shared_ptr<const Structure>> g_structs;
+static auto& g_structs = *new std::unordered_map<std::string, std::shared_ptr<const Structure>>();
 
 static void validate_legs(int sym, const std::vector<Leg>& legs) {
   if (legs.size() > (size_t)MAXD) fail(FTN_EINVAL, "too many legs (max 16)");
