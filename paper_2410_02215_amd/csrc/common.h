@@ -78,39 +78,46 @@ struct Leg {
 
 // ---------------------------------------------------------------------------
 // device memory
-void* dmalloc(size_t bytes, hipStream_t s);
-void dfree(void* p, hipStream_t s);
+// stream-ordered device memory from the pool (any stream, the null stream
+// included); persistent buffers of cached plans use hipMalloc / hipFree
+void* dmalloc(size_t bytes, hipStream_t s, bool persistent = false);
+void dfree(void* p, hipStream_t s, bool persistent = false);
+// host-to-device copy ordered on s; small copies go through a pinned staging
+// ring so that they are asynchronous, and src may be reused on return
+void h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 template <typename T>
 struct DBuf {  // owning device buffer, released stream-ordered
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  bool pers = false;
   DBuf() = default;
-  DBuf(size_t n_, hipStream_t s_) : n(n_), s(s_) { p = n ? (T*)dmalloc(n * sizeof(T), s) : nullptr; }
+  DBuf(size_t n_, hipStream_t s_, bool persistent = false) : n(n_), s(s_), pers(persistent) {
+    p = n ? (T*)dmalloc(n * sizeof(T), s, pers) : nullptr;
+  }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   DBuf(DBuf&& o) noexcept { *this = std::move(o); }
   DBuf& operator=(DBuf&& o) noexcept {
     reset();
-    p = o.p; n = o.n; s = o.s;
+    p = o.p; n = o.n; s = o.s; pers = o.pers;
     o.p = nullptr; o.n = 0;
     return *this;
   }
   ~DBuf() { reset(); }
   void reset() {
-    if (p) dfree(p, s);
+    if (p) dfree(p, s, pers);
     p = nullptr;
     n = 0;
   }
   void upload(const T* h, size_t cnt) {
-    if (cnt) HIPC(hipMemcpyAsync(p, h, cnt * sizeof(T), hipMemcpyHostToDevice, s));
+    if (cnt) h2d(p, h, cnt * sizeof(T), s);
   }
 };
 
-// upload a host vector into a new device buffer, ordered on s. Copies from
-// pageable host memory are staged before hipMemcpyAsync returns, so the
-// vector may be released right after the call.
+// upload a host vector into a new device buffer, ordered on s (the vector
+// may be released right after the call)
 template <typename T>
 DBuf<T> to_device(const std::vector<T>& v, hipStream_t s) {
   DBuf<T> b(v.size(), s);
@@ -122,12 +129,12 @@ DBuf<T> to_device(const std::vector<T>& v, hipStream_t s) {
 // hipMalloc (no stream), filled on the stream that builds the plan
 template <typename T>
 DBuf<T> persist(size_t n) {
-  return DBuf<T>(n, nullptr);
+  return DBuf<T>(n, nullptr, true);
 }
 template <typename T>
 DBuf<T> persist_upload(const std::vector<T>& v, hipStream_t s) {
-  DBuf<T> b(v.size(), nullptr);
-  if (v.size()) HIPC(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  DBuf<T> b(v.size(), nullptr, true);
+  if (v.size()) h2d(b.p, v.data(), v.size() * sizeof(T), s);
   return b;
 }
 
@@ -264,9 +271,10 @@ struct GemmGroup {
   int64_t a_off, b_off;  // element offsets into the A / B matrix buffers
   int64_t lda, ldb;
   int32_t transA, transB;
-  // output: either a plain matrix (c_off, ldc) or a block scatter
+  // output: a plain matrix (c_off, ldc), a block scatter (scatter == 1) or a
+  // split-K partial into the plan's workspace (scatter == 2, at c_off, ldc)
   int64_t c_off, ldc;
-  // scatter tables (when scatter != 0): row combos / col combos of the group
+  // scatter tables (when scatter == 1): row combos / col combos of the group
   int32_t scatter;
   int32_t nrc, ncc;         // number of row / col combos
   int64_t rc_base, cc_base; // offsets into the combo start arrays
@@ -280,12 +288,26 @@ struct GemmScatter {
   const int64_t* cc_dim;    // per col combo: its dim (row length in the block)
   const int64_t* boff;      // block offsets into C
 };
-// a ready-to-launch grouped GEMM (group table resident on the device)
+// split-K reduction of one plain output: C = alpha * sum_q W[w_off + q M N]
+// (+ beta C); e0 = first element of this output in the reduction grid
+struct SplitRed {
+  int64_t M, N, c_off, ldc, w_off, e0;
+  int S;
+  int pad;
+};
+// a ready-to-launch grouped GEMM (group table resident on the device). Groups
+// whose tiles alone cannot fill the chip are cut into K slices that write
+// partial sums (GemmGroup::scatter == 2) reduced by a second kernel.
 struct GemmPlan {
   std::vector<GemmGroup> host;
   DBuf<GemmGroup> groups;
+  std::vector<SplitRed> red_host;
+  DBuf<SplitRed> red;
   int64_t ntiles = 0;
+  int64_t ws_elems = 0, red_elems = 0;
+  double flops = 0;
   int kind = FTN_GEMM_F64;
+  int cfg = 0;
 };
 void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
                bool persistent = false);

@@ -387,7 +387,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       if (CS.ndim == 0) {
         // scalar output: one block at offset 0
         std::vector<int64_t> z(1, 0);
-        HIPC(hipMemcpyAsync(P->boff.p, z.data(), 8, hipMemcpyHostToDevice, s));
+        h2d(P->boff.p, z.data(), 8, s);
       } else {
         LAUNCH(k_dot_boff, dim3((unsigned)cdiv(CS.nblocks, 128)), dim3(128), 0, s, ba,
                            CS.d_keys.p, CS.d_offsets.p, CS.nblocks, drg.p, drl.p, dcl.p, dgb.p, dgn.p,

@@ -9,6 +9,8 @@
 // split BF16 (x = hi + lo, both BF16 rounded to nearest even; hi*hi + hi*lo +
 // lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -93,8 +95,16 @@ __device__ inline void build_epi(EpiTab<BM, BN>& e, const GemmGroup& G, const Ge
 }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32 MFMA kernel. LDS holds A as [k][m] and B as [k][n] so that the
-// 16 lanes reading one MFMA operand column touch consecutive addresses.
+// FP64 / FP32 MFMA kernel: BM x BN tile per workgroup, 4 waves in a
+// WGM x WGN grid, BK = 16. The next K slice is fetched into registers while
+// the MFMAs consume the current one, and LDS is double-buffered, so each K
+// step costs one barrier. LDS holds A as [k][m] and B as [k][n] (one padding
+// column) so that the 16 lanes reading an MFMA operand column touch
+// consecutive addresses and the global-to-LDS stores do not collide.
+// Output modes per group: plain (alpha / beta), block scatter, or raw
+// partial sums of a K slice into the split-K workspace.
+constexpr int GBK = 16;
+
 template <typename T>
 struct MfmaOp;
 // Operand layout (both types): A[lane % 16][lane / 16], B[lane / 16][lane % 16].
@@ -118,14 +128,18 @@ struct MfmaOp<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, int BM, int BN, int BK>
+
+template <typename T, int BM, int BN, int WGM, int WGN>
 __global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__ A, const T* __restrict__ B,
-                                             T* __restrict__ C) {
+                                             T* __restrict__ C, T* __restrict__ Wk) {
+  static_assert(WGM * WGN == GT / 64, "four waves");
   typedef typename MfmaOp<T>::acc_t acc_t;
-  constexpr int WM = BM / 2, WN = BN / 2;  // per-wave tile
+  constexpr int WM = BM / WGM, WN = BN / WGN;  // per-wave tile
   constexpr int TM = WM / 16, TN = WN / 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  constexpr int NA = BM * GBK / GT, NB = BN * GBK / GT;
+  static_assert(TM >= 1 && TN >= 1 && NA >= 1 && NB >= 1, "tile shape");
+  __shared__ T As[2][GBK][BM + 1];
+  __shared__ T Bs[2][GBK][BN + 1];
   __shared__ EpiTab<BM, BN> epi;
   __shared__ int s_g;
 
@@ -136,64 +150,81 @@ __global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__
   const int64_t lt = tile - G.tile0;
   const int64_t m0 = (lt / G.ntn) * BM, n0 = (lt % G.ntn) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-
-  acc_t acc[TM][TN];
-  for (int i = 0; i < TM; ++i)
-    for (int j = 0; j < TN; ++j)
-      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
-
+  const int wm = wave / WGN, wn = wave % WGN;
   const T* Ag = A + G.a_off;
   const T* Bg = B + G.b_off;
-  for (int64_t k0 = 0; k0 < G.K; k0 += BK) {
-    // A tile: element (m, k)
-    for (int e = threadIdx.x; e < BM * BK; e += GT) {
-      int mm, kk;
-      if (G.transA) {
-        kk = e / BM;
-        mm = e % BM;
-      } else {
-        mm = e / BK;
-        kk = e % BK;
-      }
-      int64_t m = m0 + mm, k = k0 + kk;
-      T v = 0;
-      if (m < G.M && k < G.K) v = G.transA ? Ag[k * G.lda + m] : Ag[m * G.lda + k];
-      As[kk][mm] = v;
-    }
-    // B tile: element (k, n)
-    for (int e = threadIdx.x; e < BK * BN; e += GT) {
-      int kk, nn;
-      if (G.transB) {
-        nn = e / BK;
-        kk = e % BK;
-      } else {
-        kk = e / BN;
-        nn = e % BN;
-      }
-      int64_t k = k0 + kk, n = n0 + nn;
-      T v = 0;
-      if (k < G.K && n < G.N) v = G.transB ? Bg[n * G.ldb + k] : Bg[k * G.ldb + n];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
+
+  T ra[NA], rb[NB];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + GT * u;
+      const int mm = G.transA ? e % BM : e / GBK, kk = G.transA ? e / BM : e % GBK;
+      const int64_t m = m0 + mm, k = k0 + kk;
+      T v = T(0);
+      if (m < G.M && k < G.K) v = G.transA ? Ag[k * G.lda + m] : Ag[m * G.lda + k];
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = threadIdx.x + GT * u;
+      const int nn = G.transB ? e / GBK : e % BN, kk = G.transB ? e % GBK : e / BN;
+      const int64_t k = k0 + kk, n = n0 + nn;
+      T v = T(0);
+      if (k < G.K && n < G.N) v = G.transB ? Bg[n * G.ldb + k] : Bg[k * G.ldb + n];
+      rb[u] = v;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = threadIdx.x + GT * u;
+      const int mm = G.transA ? e % BM : e / GBK, kk = G.transA ? e / BM : e % GBK;
+      As[buf][kk][mm] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = threadIdx.x + GT * u;
+      const int nn = G.transB ? e / GBK : e % BN, kk = G.transB ? e % GBK : e / BN;
+      Bs[buf][kk][nn] = rb[u];
+    }
+  };
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  const int64_t nk = (G.K + GBK - 1) / GBK;
+  if (nk > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) fetch((kt + 1) * GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
       T a[TM], b[TN];
       const int kr = kk + (lane >> 4), c = lane & 15;
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kr][wm * WM + 16 * i + c];
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][kr][wm * WM + 16 * i + c];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kr][wn * WN + 16 * j + c];
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][kr][wn * WN + 16 * j + c];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MfmaOp<T>::run(a[i], b[j], acc[i][j]);
     }
+    if (kt + 1 < nk) stash(cur ^ 1);
     __syncthreads();
   }
 
-  if (G.scatter) {
+  if (G.scatter == 1) {
     build_epi<BM, BN>(epi, G, L.sc, m0, n0);
     __syncthreads();
   }
@@ -208,15 +239,41 @@ __global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__
         const int cc = wn * WN + 16 * j + (lane & 15);
         const int64_t m = m0 + rr, n = n0 + cc;
         if (m >= G.M || n >= G.N) continue;
-        T v = alpha * acc[i][j][r];
-        if (G.scatter) {
+        if (G.scatter == 1) {
           const int64_t bo = L.sc.boff[G.boff_base + (int64_t)epi.rfi[rr] * G.ncc + epi.cgj[cc]];
-          if (bo >= 0) C[bo + epi.rlr[rr] * epi.cnd[cc] + epi.clc[cc]] = v;
+          if (bo >= 0) C[bo + epi.rlr[rr] * epi.cnd[cc] + epi.clc[cc]] = alpha * acc[i][j][r];
+        } else if (G.scatter == 2) {
+          Wk[G.c_off + m * G.ldc + n] = acc[i][j][r];
         } else {
+          const T v = alpha * acc[i][j][r];
           T* p = C + G.c_off + m * G.ldc + n;
           *p = beta != (T)0 ? v + beta * *p : v;
         }
       }
+}
+
+// split-K finish: C = alpha * (sum of the K-slice partials) (+ beta C)
+template <typename T>
+__global__ void k_splitk_reduce(const SplitRed* __restrict__ R, int nr, int64_t total, const T* __restrict__ Wk,
+                                T* __restrict__ C, double alpha, double beta) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (R[mid].e0 <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SplitRed r = R[lo];
+  const int64_t loc = e - r.e0, mn = r.M * r.N;
+  const int64_t m = loc / r.N, n = loc % r.N;
+  T sum = T(0);
+  for (int q = 0; q < r.S; ++q) sum += Wk[r.w_off + q * mn + loc];
+  T* p = C + r.c_off + m * r.ldc + n;
+  const T v = (T)alpha * sum;
+  *p = beta != 0.0 ? v + (T)beta * *p : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -344,25 +401,121 @@ double gemm_flops(const std::vector<GemmGroup>& groups) {
   return f;
 }
 
-constexpr int TBM = 64, TBN = 64;
+constexpr int TBM = 64, TBN = 64;  // split-BF16 tile
+
+// tile configurations of the FP64 / FP32 kernel
+enum { CFG_64 = 0, CFG_128 = 1, CFG_256x16 = 2, CFG_256x32 = 3, CFG_16x256 = 4, CFG_32x256 = 5 };
+static const int CFG_BM[] = {64, 128, 256, 256, 16, 32};
+static const int CFG_BN[] = {64, 128, 16, 32, 256, 256};
+constexpr int NCU = 256;  // compute units to fill
+
+static int choose_cfg(const std::vector<GemmGroup>& gs) {
+  int64_t maxM = 0, maxN = 0, t128 = 0;
+  for (auto& g : gs) {
+    maxM = std::max(maxM, g.M);
+    maxN = std::max(maxN, g.N);
+    t128 += cdiv(g.M, 128) * cdiv(g.N, 128);
+  }
+  if (maxN <= 16 && maxM >= 256) return CFG_256x16;
+  if (maxN <= 32 && maxM >= 256) return CFG_256x32;
+  if (maxM <= 16 && maxN >= 256) return CFG_16x256;
+  if (maxM <= 32 && maxN >= 256) return CFG_32x256;
+  if (t128 >= NCU && std::min(maxM, maxN) >= 128) return CFG_128;
+  return CFG_64;
+}
 
 void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s, bool persistent) {
   p.host.clear();
+  p.red_host.clear();
   p.kind = kind;
+  p.ws_elems = 0;
+  p.flops = 0;
+  std::vector<GemmGroup> gs;
+  for (auto& g : groups)
+    if (g.M > 0 && g.N > 0) gs.push_back(g);
+  p.flops = gemm_flops(gs);
+  p.cfg = kind == FTN_GEMM_BF16X3 ? CFG_64 : choose_cfg(gs);
+  const int bm = kind == FTN_GEMM_BF16X3 ? TBM : CFG_BM[p.cfg], bn = kind == FTN_GEMM_BF16X3 ? TBN : CFG_BN[p.cfg];
+  int64_t tiles = 0;
+  for (auto& g : gs) tiles += cdiv(g.M, bm) * cdiv(g.N, bn);
+  // split-K for plain outputs when the tiles alone cannot fill the chip
+  int64_t split = 1;
+  if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < NCU) split = std::max<int64_t>(1, cdiv(2 * NCU, tiles));
   int64_t t = 0;
-  for (auto g : groups) {
-    if (g.M <= 0 || g.N <= 0) continue;
-    g.ntm = cdiv(g.M, TBM);
-    g.ntn = cdiv(g.N, TBN);
-    g.tile0 = t;
-    t += g.ntm * g.ntn;
-    p.host.push_back(g);
+  for (auto g : gs) {
+    const int64_t S = g.scatter ? 1 : std::min<int64_t>(split, std::min<int64_t>(64, g.K / 128));
+    g.ntm = cdiv(g.M, bm);
+    g.ntn = cdiv(g.N, bn);
+    if (S <= 1) {
+      g.tile0 = t;
+      t += g.ntm * g.ntn;
+      p.host.push_back(g);
+      continue;
+    }
+    const int64_t kc = cdiv(cdiv(g.K, S), GBK) * GBK;
+    const int64_t ns = cdiv(g.K, kc);
+    SplitRed r;
+    std::memset(&r, 0, sizeof(r));
+    r.M = g.M;
+    r.N = g.N;
+    r.c_off = g.c_off;
+    r.ldc = g.ldc;
+    r.w_off = p.ws_elems;
+    r.S = (int)ns;
+    p.red_host.push_back(r);
+    for (int64_t q = 0; q < ns; ++q) {
+      GemmGroup h = g;
+      const int64_t k0 = q * kc;
+      h.K = std::min(kc, g.K - k0);
+      h.a_off = g.a_off + (g.transA ? k0 * g.lda : k0);
+      h.b_off = g.b_off + (g.transB ? k0 : k0 * g.ldb);
+      h.scatter = 2;
+      h.c_off = p.ws_elems + q * g.M * g.N;
+      h.ldc = g.N;
+      h.tile0 = t;
+      t += h.ntm * h.ntn;
+      p.host.push_back(h);
+    }
+    p.ws_elems += ns * g.M * g.N;
   }
+  int64_t e0 = 0;
+  for (auto& r : p.red_host) {
+    r.e0 = e0;
+    e0 += r.M * r.N;
+  }
+  p.red_elems = e0;
   if (t > 0x7fffffffLL) fail(FTN_EINVAL, "GEMM too large");
   p.ntiles = t;
   p.groups = persistent ? persist<GemmGroup>(p.host.size()) : DBuf<GemmGroup>(p.host.size(), s);
   if (!p.host.empty())
-    HIPC(hipMemcpyAsync(p.groups.p, p.host.data(), p.host.size() * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+    h2d(p.groups.p, p.host.data(), p.host.size() * sizeof(GemmGroup), s);
+  p.red = persistent ? persist<SplitRed>(p.red_host.size()) : DBuf<SplitRed>(p.red_host.size(), s);
+  if (!p.red_host.empty())
+    h2d(p.red.p, p.red_host.data(), p.red_host.size() * sizeof(SplitRed), s);
+}
+
+template <typename T>
+static void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmLaunch& L, const T* A, const T* B, T* C, T* W) {
+  switch (cfg) {
+    case CFG_128:
+      LAUNCH((k_gemm<T, 128, 128, 2, 2>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+    case CFG_256x16:
+      LAUNCH((k_gemm<T, 256, 16, 4, 1>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+    case CFG_256x32:
+      LAUNCH((k_gemm<T, 256, 32, 4, 1>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+    case CFG_16x256:
+      LAUNCH((k_gemm<T, 16, 256, 1, 4>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+    case CFG_32x256:
+      LAUNCH((k_gemm<T, 32, 256, 1, 4>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+    default:
+      LAUNCH((k_gemm<T, 64, 64, 2, 2>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      break;
+  }
 }
 
 void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
@@ -376,26 +529,44 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   L.beta = beta;
   std::memset(&L.sc, 0, sizeof(L.sc));
   if (sc) L.sc = *sc;
-  dim3 grid((unsigned)p.ntiles), block(GT);
+  dim3 grid((unsigned)p.ntiles);
+  static const bool trace = std::getenv("FTN_TRACE_GEMM") != nullptr;
+  if (trace) {
+    int64_t mm = 0, mn = 0, mk = 0;
+    for (auto& g : p.host) {
+      mm = std::max(mm, g.M);
+      mn = std::max(mn, g.N);
+      mk = std::max(mk, g.K);
+    }
+    std::fprintf(stderr, "[gemm] tiles %lld groups %zu flops %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sc %d cfg %d split %zu\n",
+                 (long long)p.ntiles, p.host.size(), p.flops, (long long)mm, (long long)mn, (long long)mk,
+                 p.host[0].transA, p.host[0].transB, p.host[0].scatter, p.cfg, p.red_host.size());
+  }
+  const size_t es = dtype == FTN_F64 ? 8 : 4;
+  DBuf<char> ws(p.ws_elems * es, s);
   void* tok = prof_begin(s);
   if (p.kind == FTN_GEMM_F64) {
     if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
-    LAUNCH((k_gemm<double, TBM, TBN, 16>), grid, block, 0, s, L, (const double*)A,
-                       (const double*)B, (double*)C);
+    launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)ws.p);
+    if (p.red_elems)
+      LAUNCH((k_splitk_reduce<double>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
+             (int)p.red_host.size(), p.red_elems, (const double*)ws.p, (double*)C, alpha, beta);
   } else if (p.kind == FTN_GEMM_F32) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 GEMM needs FP32 tensors");
-    LAUNCH((k_gemm<float, TBM, TBN, 16>), grid, block, 0, s, L, (const float*)A,
-                       (const float*)B, (float*)C);
+    launch_cfg<float>(p.cfg, grid, s, L, (const float*)A, (const float*)B, (float*)C, (float*)ws.p);
+    if (p.red_elems)
+      LAUNCH((k_splitk_reduce<float>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
+             (int)p.red_host.size(), p.red_elems, (const float*)ws.p, (float*)C, alpha, beta);
   } else if (p.kind == FTN_GEMM_BF16X3) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "split-BF16 GEMM needs FP32 tensors");
-    LAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, block, 0, s, L, (const float*)A,
+    LAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, dim3(GT), 0, s, L, (const float*)A,
                        (const float*)B, (float*)C);
   } else {
     fail(FTN_EINVAL, "unknown GEMM kind");
   }
   HIPC(hipGetLastError());
   prof_end(tok, s, p.kind == FTN_GEMM_F64 ? FTN_PROF_GEMM_F64 : (p.kind == FTN_GEMM_F32 ? FTN_PROF_GEMM_F32 : FTN_PROF_GEMM_BF16X3),
-           gemm_flops(p.host));
+           p.flops);
 }
 
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,

@@ -29,108 +29,12 @@ constexpr int LT = 1024;     // threads of the factorisation kernels
 constexpr int JMAX = 128;    // largest order diagonalised in LDS
 constexpr int CHOL_MAX = 4096;
 
-// ---------------------------------------------------------------------------
-// pivoted Cholesky of a symmetric PSD K x K matrix (one workgroup per
-// matrix). R (K x K, zeroed) receives R[l][c] with R^T R = G; rows beyond
-// the numerical rank stay zero. Stops when the largest remaining pivot is
-// not above tol * (largest diagonal of G).
-struct CholJob {
-  const double* G;
-  double* R;
-  int K;
-  int pad;
-};
+typedef double d4 __attribute__((ext_vector_type(4)));
+static_assert(LT == 1024 && JMAX == 128, "register staging assumes 1024 threads and order 128");
 
-__global__ void __launch_bounds__(LT) k_chol_pivot(const CholJob* jobs, double tol, int* rank_out) {
-  const CholJob J = jobs[blockIdx.x];
-  const int K = J.K;
-  __shared__ double dp[CHOL_MAX];
-  __shared__ int piv[CHOL_MAX];
-  __shared__ double red_v[LT / 64];
-  __shared__ int red_i[LT / 64];
-  __shared__ double s_dmax;
-  __shared__ int s_p;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < K; i += LT) {
-    dp[i] = J.G[(int64_t)i * K + i];
-    piv[i] = i;
-  }
-  __syncthreads();
-  // largest diagonal
-  {
-    double m = 0;
-    for (int i = tid; i < K; i += LT) m = fmax(m, dp[i]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if (lane == 0) red_v[w] = m;
-    __syncthreads();
-    if (tid == 0) {
-      double mm = 0;
-      for (int i = 0; i < LT / 64; ++i) mm = fmax(mm, red_v[i]);
-      s_dmax = mm;
-    }
-    __syncthreads();
-  }
-  const double thr = tol * s_dmax;
-  int rank = 0;
-  for (int j = 0; j < K; ++j) {
-    // argmax of remaining pivots (ties: lowest position)
-    double bv = -1.0;
-    int bi = K;
-    for (int i = j + tid; i < K; i += LT) {
-      double v = dp[i];
-      if (v > bv) {
-        bv = v;
-        bi = i;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(bv, o);
-      int oi = __shfl_xor(bi, o);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      red_v[w] = bv;
-      red_i[w] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double v = -1.0;
-      int p = K;
-      for (int i = 0; i < LT / 64; ++i)
-        if (red_v[i] > v || (red_v[i] == v && red_i[i] < p)) {
-          v = red_v[i];
-          p = red_i[i];
-        }
-      s_p = (v > thr && v > 0.0) ? p : -1;
-      if (s_p >= 0 && s_p != j) {
-        double td = dp[j];
-        dp[j] = dp[s_p];
-        dp[s_p] = td;
-        int ti = piv[j];
-        piv[j] = piv[s_p];
-        piv[s_p] = ti;
-      }
-    }
-    __syncthreads();
-    if (s_p < 0) break;
-    const int cj = piv[j];
-    const double rjj = sqrt(dp[j]);
-    if (tid == 0) J.R[(int64_t)j * K + cj] = rjj;
-    for (int i = j + 1 + tid; i < K; i += LT) {
-      const int ci = piv[i];
-      double sacc = J.G[(int64_t)cj * K + ci];
-      for (int l = 0; l < j; ++l) sacc -= J.R[(int64_t)l * K + cj] * J.R[(int64_t)l * K + ci];
-      double r = sacc / rjj;
-      J.R[(int64_t)j * K + ci] = r;
-      dp[i] = fmax(dp[i] - r * r, 0.0);
-    }
-    rank = j + 1;
-    __syncthreads();
-  }
-  if (tid == 0) rank_out[blockIdx.x] = rank;
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -258,17 +162,34 @@ __global__ void __launch_bounds__(LT) k_chol_panel(const CholState* st, int j0, 
 }
 
 // ---------------------------------------------------------------------------
-// cyclic Jacobi eigensolver for symmetric n x n (n <= 128) held in LDS;
-// eigenvectors accumulated in global memory. Outputs eigenvalues in
-// descending order and the matching eigenvector columns (row-major n x n).
+// Cyclic Jacobi eigensolver for a symmetric n x n matrix (n <= 128), one
+// workgroup per matrix, in two phases.
+// Phase 1 keeps the upper triangle in LDS and sweeps it in round-robin
+// order: per round, n/2 disjoint rotations are chosen, then every 2 x 2
+// block (pair k1, pair k2) is updated as J_k1^T A J_k2 by one thread, which
+// needs one barrier per round and no eigenvector traffic. The rotations are
+// logged to global memory. Phase 2 reuses the LDS for V = I and replays the
+// log: each wave owns a set of rows of V and applies every round to them
+// (lane k = rotation k), so rounds need no workgroup barrier. Sweeps stop
+// when the off-diagonal norm^2 is <= 1e-30 of the diagonal norm^2.
+// Outputs: eigenvalues descending (ties: lower index first) and the matching
+// eigenvector columns (row-major n x n).
+constexpr int JAC_SWEEPS = 30;
+
 struct EigJob {
   const double* H;  // n x n input
   double* V;        // n x n eigenvectors (columns), output
   double* W;        // n eigenvalues, output (descending)
-  double* Vtmp;     // n x n scratch
+  double2* rot;     // rotation log: (c, s) per rotation
+  int* rpq;         // rotation log: p | q << 16
   int n;
   int pad;
 };
+
+__host__ __device__ inline int64_t jacobi_log_len(int n) {
+  const int n2 = n + (n & 1);
+  return (int64_t)JAC_SWEEPS * (n2 - 1) * (n2 / 2);
+}
 
 __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
   // round-robin tournament on n2 (even) players: fixed player n2-1
@@ -286,125 +207,157 @@ __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
   }
 }
 
-__global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs, int max_sweeps) {
+__global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int n = J.n;
   if (n <= 0) return;
   __shared__ double A[JMAX][JMAX + 1];
-  __shared__ double cs[JMAX / 2][2];
-  __shared__ int pq[JMAX / 2][2];
-  __shared__ double red[LT / 64];
-  __shared__ double s_off, s_tot;
+  __shared__ double2 cs[JMAX / 2];
+  __shared__ int pq[JMAX / 2];
+  __shared__ double ev[JMAX];
+  __shared__ int rk[JMAX];
+  __shared__ double red[2][LT / 64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int n2 = n + (n & 1);  // pad with a dummy index when n is odd
-  for (int e = tid; e < n * n; e += LT) {
-    int i = e / n, j = e % n;
-    A[i][j] = J.H[e];
-    J.Vtmp[e] = (i == j) ? 1.0 : 0.0;
+  const int n2 = n + (n & 1);  // an odd order gets a zero row / column
+  const int np = n2 / 2;
+  for (int e = tid; e < n2 * n2; e += LT) {
+    const int i = e / n2, j = e % n2;
+    if (i <= j) A[i][j] = (j < n) ? J.H[(int64_t)i * n + j] : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal relative to diagonal scale
-    double off = 0, tot = 0;
-    for (int e = tid; e < n * n; e += LT) {
-      int i = e / n, j = e % n;
-      double v = A[i][j] * A[i][j];
-      if (i != j)
-        off += v;
-      else
-        tot += v;
+  int nr = 0;  // rounds done (the same in every thread)
+  for (int sweep = 0; sweep < JAC_SWEEPS; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n2 * n2; e += LT) {
+      const int i = e / n2, j = e % n2;
+      if (i < j)
+        off += A[i][j] * A[i][j];
+      else if (i == j)
+        tot += A[i][i] * A[i][i];
     }
-    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
-    if (lane == 0) red[w] = off;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0;
-      for (int i = 0; i < LT / 64; ++i) s += red[i];
-      s_off = s;
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
     }
-    __syncthreads();
-    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-    if (lane == 0) red[w] = tot;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0;
-      for (int i = 0; i < LT / 64; ++i) s += red[i];
-      s_tot = s;
+    if (lane == 0) {
+      red[0][w] = off;
+      red[1][w] = tot;
     }
     __syncthreads();
-    if (s_off <= 1e-30 * s_tot || s_off == 0.0) break;
-    for (int r = 0; r < n2 - 1; ++r) {
-      const int npairs = n2 / 2;
-      if (tid < npairs) {
+    off = 0.0;
+    tot = 0.0;
+    for (int i = 0; i < LT / 64; ++i) {
+      off += red[0][i];
+      tot += red[1][i];
+    }
+    __syncthreads();
+    if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
+    for (int r = 0; r < n2 - 1; ++r, ++nr) {
+      if (tid < np) {
         int p, q;
         rr_pair(n2, r, tid, p, q);
         double c = 1.0, s = 0.0;
-        if (q < n) {
-          double apq = A[p][q];
-          if (apq != 0.0) {
-            double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+        const double apq = A[p][q];
+        if (apq != 0.0) {
+          const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
         }
-        pq[tid][0] = p;
-        pq[tid][1] = q;
-        cs[tid][0] = c;
-        cs[tid][1] = s;
+        cs[tid] = make_double2(c, s);
+        pq[tid] = p | (q << 16);
+        J.rot[(int64_t)nr * np + tid] = make_double2(c, s);
+        J.rpq[(int64_t)nr * np + tid] = p | (q << 16);
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < npairs * n; e += LT) {
-        int k = e / n, j = e % n;
-        int p = pq[k][0], q = pq[k][1];
-        if (q >= n) continue;
-        double c = cs[k][0], s = cs[k][1];
-        double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns: A <- A J ; V <- V J
-      for (int e = tid; e < npairs * n; e += LT) {
-        int k = e / n, i = e % n;
-        int p = pq[k][0], q = pq[k][1];
-        if (q >= n) continue;
-        double c = cs[k][0], s = cs[k][1];
-        double ap = A[i][p], aq = A[i][q];
-        A[i][p] = c * ap - s * aq;
-        A[i][q] = s * ap + c * aq;
-        double vp = J.Vtmp[(int64_t)i * n + p], vq = J.Vtmp[(int64_t)i * n + q];
-        J.Vtmp[(int64_t)i * n + p] = c * vp - s * vq;
-        J.Vtmp[(int64_t)i * n + q] = s * vp + c * vq;
+      for (int e = tid; e < np * np; e += LT) {
+        const int k1 = e / np, k2 = e % np;
+        if (k1 > k2) continue;
+        const int v1 = pq[k1];
+        const int p1 = v1 & 0xffff, q1 = v1 >> 16;
+        const double2 r1 = cs[k1];
+        if (k1 == k2) {
+          const double apq = A[p1][q1], t = r1.y / r1.x;
+          A[p1][p1] -= t * apq;
+          A[q1][q1] += t * apq;
+          A[p1][q1] = 0.0;
+        } else {
+          const int v2 = pq[k2];
+          const int p2 = v2 & 0xffff, q2 = v2 >> 16;
+          const double2 r2 = cs[k2];
+          double* a00 = &A[min(p1, p2)][max(p1, p2)];
+          double* a01 = &A[min(p1, q2)][max(p1, q2)];
+          double* a10 = &A[min(q1, p2)][max(q1, p2)];
+          double* a11 = &A[min(q1, q2)][max(q1, q2)];
+          const double b00 = *a00, b01 = *a01, b10 = *a10, b11 = *a11;
+          const double r00 = r1.x * b00 - r1.y * b10, r01 = r1.x * b01 - r1.y * b11;
+          const double r10 = r1.y * b00 + r1.x * b10, r11 = r1.y * b01 + r1.x * b11;
+          *a00 = r2.x * r00 - r2.y * r01;
+          *a01 = r2.y * r00 + r2.x * r01;
+          *a10 = r2.x * r10 - r2.y * r11;
+          *a11 = r2.y * r10 + r2.x * r11;
+        }
       }
       __syncthreads();
     }
   }
-  // sort eigenvalues descending (ties: lower index first)
+  for (int i = tid; i < n; i += LT) ev[i] = A[i][i];
+  __syncthreads();
+  for (int e = tid; e < n2 * n2; e += LT) {
+    const int i = e / n2, j = e % n2;
+    A[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (lane < np) {
+    for (int t = 0; t < nr; ++t) {
+      const double2 r = J.rot[(int64_t)t * np + lane];
+      const int v = J.rpq[(int64_t)t * np + lane];
+      const int p = v & 0xffff, q = v >> 16;
+      for (int i = w; i < n2; i += LT / 64) {
+        const double vp = A[i][p], vq = A[i][q];
+        A[i][p] = r.x * vp - r.y * vq;
+        A[i][q] = r.y * vp + r.x * vq;
+      }
+    }
+  }
+  __syncthreads();
   for (int i = tid; i < n; i += LT) {
-    double v = A[i][i];
+    const double v = ev[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      double u = A[j][j];
+      const double u = ev[j];
       rank += (u > v) || (u == v && j < i);
     }
+    rk[i] = rank;
     J.W[rank] = v;
-    for (int r = 0; r < n; ++r) J.V[(int64_t)r * n + rank] = J.Vtmp[(int64_t)r * n + i];
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += LT) {
+    const int r = e / n, i = e % n;
+    J.V[(int64_t)r * n + rk[i]] = A[r][i];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Rank-revealing orthonormalisation factor (one workgroup per matrix): for
-// the Gram matrix G = Y^T Y (p x p, p <= 128) in LDS, symmetric-pivoted
-// Cholesky G = P^T R^T R P stops at the numerical rank r (pivot not above
-// tol * largest diagonal). The output M (p x p) has M[piv[i]][c] = R11^-1[i][c]
-// for i, c < r and zeros elsewhere, so Y M has r orthonormal columns followed
-// by zero columns: dependent directions are dropped instead of amplified.
+// the Gram matrix G = Y^T Y (p x p, p <= 128), symmetric-pivoted Cholesky
+// G = P^T R^T R P stops at the numerical rank r (largest remaining pivot not
+// above tol * largest diagonal). The output M (p x p) has
+// M[piv[i]][c] = R11^-1[i][c] for i <= c < r and zeros elsewhere, so Y M has
+// r orthonormal columns followed by zero columns: dependent directions are
+// dropped instead of amplified.
+// The factorisation is left-looking in LDS: row j of R is written over the
+// (no longer needed) row of G of the j-th pivot, eight threads per column
+// share each dot product, and every wave chooses the pivot itself from a
+// double-buffered diagonal, so a step costs one barrier. R is then
+// gathered into pivot order, padded with the identity to order 128, and
+// inverted in place: 16 x 16 diagonal blocks by back substitution, then
+// three doubling levels [U11 U12; 0 U22]^-1 = [U11^-1, -U11^-1 U12 U22^-1;
+// 0, U22^-1] with FP64 MFMA tiles (the product U11^-1 U12 is staged in the
+// free lower triangle).
 struct OrthJob {
   const double* G;
-  double* Rinv;  // p x p scratch
-  double* M;     // p x p output
+  double* M;  // p x p output
   int p;
   int pad;
 };
@@ -413,86 +366,140 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   const OrthJob J = jobs[blockIdx.x];
   const int p = J.p;
   __shared__ double A[JMAX][JMAX + 1];
-  __shared__ int piv[JMAX];
-  __shared__ int s_k, s_rank;
-  __shared__ double s_thr;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < p * p; e += LT) {
-    int i = e / p, j = e % p;
-    A[i][j] = J.G[e];
-    J.M[e] = 0.0;
-  }
-  for (int i = tid; i < p; i += LT) piv[i] = i;
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < p; ++i) m = fmax(m, A[i][i]);
-    s_thr = tol * m;
-    s_rank = m > 0.0 ? p : 0;
+  __shared__ double dpb[2][JMAX];
+  __shared__ int sel[JMAX], pos[JMAX];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < p * p; e += LT) A[e / p][e % p] = J.G[e];
+  for (int i = tid; i < JMAX; i += LT) {
+    pos[i] = -1;
+    dpb[0][i] = (i < p) ? J.G[(int64_t)i * p + i] : -1.0;
   }
   __syncthreads();
-  for (int j = 0; j < s_rank; ++j) {
-    if (tid == 0) {
-      int k = j;
-      double v = A[j][j];
-      for (int i = j + 1; i < p; ++i)
-        if (A[i][i] > v) {
-          v = A[i][i];
-          k = i;
-        }
-      if (!(v > s_thr)) {
-        s_rank = j;
-        s_k = -1;
+  double mx = 0.0;
+  for (int i = lane; i < p; i += 64) mx = fmax(mx, dpb[0][i]);
+  mx = wave_max(mx);
+  const double thr = tol * mx;
+  int r = (mx > 0.0) ? p : 0;
+  int cur = 0;
+  for (int j = 0; j < r; ++j) {
+    const double* dpc = dpb[cur];
+    double* dpn = dpb[cur ^ 1];
+    double bv = -1.0;
+    int bi = JMAX;
+    for (int i = lane; i < p; i += 64) {
+      const double v = dpc[i];
+      if (v > bv) {
+        bv = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (!(bv > thr)) {
+      r = j;
+      break;
+    }
+    const int cj = bi;
+    const double rjj = sqrt(bv), inv = 1.0 / rjj;
+    const int c = tid >> 3, sub = tid & 7;
+    const bool act = c < p && c != cj && dpc[c] >= 0.0;
+    double sacc = 0.0;
+    if (act)
+      for (int l = sub; l < j; l += 8) {
+        const int o = sel[l];
+        sacc += A[o][cj] * A[o][c];
+      }
+    sacc += __shfl_xor(sacc, 1);
+    sacc += __shfl_xor(sacc, 2);
+    sacc += __shfl_xor(sacc, 4);
+    if (sub == 0 && c < p) {
+      if (act) {
+        const double v = (A[cj][c] - sacc) * inv;
+        A[cj][c] = v;
+        dpn[c] = fmax(dpc[c] - v * v, 0.0);
       } else {
-        s_k = k;
-        int t = piv[j];
-        piv[j] = piv[k];
-        piv[k] = t;
+        dpn[c] = -1.0;
       }
     }
-    __syncthreads();
-    const int k = s_k;
-    if (k < 0) break;
-    if (k != j) {  // symmetric swap of rows and columns j, k
-      for (int c = tid; c < p; c += LT) {
-        double t = A[j][c];
-        A[j][c] = A[k][c];
-        A[k][c] = t;
-      }
-      __syncthreads();
-      for (int r = tid; r < p; r += LT) {
-        double t = A[r][j];
-        A[r][j] = A[r][k];
-        A[r][k] = t;
-      }
-      __syncthreads();
+    if (tid == 0) {
+      A[cj][cj] = rjj;
+      sel[j] = cj;
+      pos[cj] = j;
     }
-    if (tid == 0) A[j][j] = sqrt(A[j][j]);
-    __syncthreads();
-    const double rjj = A[j][j];
-    for (int c = j + 1 + tid; c < p; c += LT) A[j][c] /= rjj;
-    __syncthreads();
-    const int m = p - j - 1;
-    for (int e = tid; e < m * m; e += LT) {
-      int a = j + 1 + e / m, b = j + 1 + e % m;
-      A[a][b] -= A[j][a] * A[j][b];
-    }
+    cur ^= 1;
     __syncthreads();
   }
-  const int r = s_rank;
-  // R11^-1 by back substitution, one column per thread
-  double* X = J.Rinv;
-  for (int col = tid; col < r; col += LT) {
-    for (int i = col; i >= 0; --i) {
-      double sacc = (i == col) ? 1.0 : 0.0;
-      for (int q = i + 1; q <= col; ++q) sacc -= A[i][q] * X[(int64_t)q * p + col];
-      X[(int64_t)i * p + col] = sacc / A[i][i];
-    }
+  // R in pivot order, identity beyond the rank (through registers)
+  double v[JMAX * JMAX / LT];
+#pragma unroll
+  for (int u = 0; u < JMAX * JMAX / LT; ++u) {
+    const int e = tid + u * LT, l = e >> 7, i = e & 127;
+    double x = 0.0;
+    if (l <= i) x = (i < r) ? A[sel[l]][sel[i]] : (l == i ? 1.0 : 0.0);
+    v[u] = x;
   }
   __syncthreads();
-  for (int e = tid; e < r * r; e += LT) {
-    int i = e / r, c = e % r;
-    J.M[(int64_t)piv[i] * p + c] = (i <= c) ? X[(int64_t)i * p + c] : 0.0;
+#pragma unroll
+  for (int u = 0; u < JMAX * JMAX / LT; ++u) {
+    const int e = tid + u * LT;
+    A[e >> 7][e & 127] = v[u];
+  }
+  __syncthreads();
+  // 16 x 16 diagonal blocks: lane c of wave w solves column c of block w
+  if (w < JMAX / 16 && lane < 16) {
+    const int o = 16 * w, c = lane;
+    double x[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = i + 1; q < 16; ++q) s -= A[o + i][o + q] * x[q];
+      x[i] = (i <= c) ? s / A[o + i][o + i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i <= c) A[o + i][o + c] = x[i];
+  }
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int h = 16; h < JMAX; h *= 2) {
+    const int m = 2 * h, nt = h / 16, tiles = (JMAX / m) * nt * nt;
+    const int pr = w / (nt * nt), t = w % (nt * nt);
+    const int b = pr * m, i0 = 16 * (t / nt), j0 = 16 * (t % nt);
+    if (w < tiles) {  // T = U11^-1 U12 into the lower-left block
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = i0; k0 < h; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = (k >= i0 + li) ? A[b + i0 + li][b + k] : 0.0;
+        const double bb = A[b + k][b + h + j0 + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A[b + h + i0 + lk + 4 * q][b + j0 + li] = acc[q];
+    }
+    __syncthreads();
+    if (w < tiles) {  // U12 <- -T U22^-1
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < j0 + 16; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = A[b + h + i0 + li][b + k];
+        const double bb = (k <= j0 + li) ? A[b + h + k][b + h + j0 + li] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A[b + i0 + lk + 4 * q][b + h + j0 + li] = -acc[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < p * p; e += LT) {
+    const int o = e / p, c = e % p, i = pos[o];
+    J.M[e] = (i >= 0 && c < r && i <= c) ? A[i][c] : 0.0;
   }
 }
 
@@ -642,14 +649,15 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
                     double* W, const std::vector<int64_t>& woff, hipStream_t s) {
   const int ng = (int)S.size();
   std::vector<EigJob> ej;
-  std::vector<int64_t> tmp_off;
-  int64_t tmp_n = 0;
+  std::vector<int64_t> log_off;
+  int64_t log_n = 0;
   for (int g = 0; g < ng; ++g)
     if (!S[g].iterate && S[g].ns > 0) {
-      tmp_off.push_back(tmp_n);
-      tmp_n += (int64_t)S[g].ns * S[g].ns;
+      log_off.push_back(log_n);
+      log_n += jacobi_log_len(S[g].ns);
     }
-  DBuf<double> tmp(std::max<int64_t>(tmp_n, 1), s);
+  DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
+  DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
   {
     int t = 0;
     for (int g = 0; g < ng; ++g)
@@ -658,7 +666,8 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
         j.H = H + hoff[g];
         j.V = V + voff[g];
         j.W = W + woff[g];
-        j.Vtmp = tmp.p + tmp_off[t++];
+        j.rot = lrot.p + log_off[t];
+        j.rpq = lpq.p + log_off[t++];
         j.n = S[g].ns;
         j.pad = 0;
         ej.push_back(j);
@@ -666,7 +675,7 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
   }
   if (!ej.empty()) {
     DBuf<EigJob> dj = to_device(ej, s);
-    LAUNCH(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p, 40);
+    LAUNCH(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p);
     HIPC(hipStreamSynchronize(s));
   }
   std::vector<int> it;
@@ -689,8 +698,10 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
     goff[t] = gn;
     gn += (int64_t)x.p * x.p;
   }
-  DBuf<double> Qa(qn, s), Qb(qn, s), Za(zn, s), Zb(zn, s), Gm(gn, s), Rs(gn, s), Mm(gn, s), Tm(gn, s),
-      Wv(gn, s), Vt(gn, s), Wt(std::max<int64_t>(ni * (int64_t)JMAX, 1), s);
+  DBuf<double> Qa(qn, s), Qb(qn, s), Za(zn, s), Zb(zn, s), Gm(gn, s), Mm(gn, s), Tm(gn, s), Wv(gn, s),
+      Wt(std::max<int64_t>(ni * (int64_t)JMAX, 1), s);
+  DBuf<double2> rrot(ni * jacobi_log_len(JMAX), s);
+  DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s);
   // GEMM plans (reused every iteration)
   std::vector<GemmGroup> gxq, gxz, gq_gram, gz_gram, gq_app, gz_app, gt;
   for (int t = 0; t < ni; ++t) {
@@ -720,7 +731,6 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
   for (int t = 0; t < ni; ++t) {
     OrthJob o;
     o.G = Gm.p + goff[t];
-    o.Rinv = Rs.p + goff[t];
     o.M = Mm.p + goff[t];
     o.p = S[it[t]].p;
     o.pad = 0;
@@ -729,7 +739,8 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
     e.H = Tm.p + goff[t];
     e.V = Wv.p + goff[t];
     e.W = Wt.p + (int64_t)t * JMAX;
-    e.Vtmp = Vt.p + goff[t];
+    e.rot = rrot.p + t * jacobi_log_len(JMAX);
+    e.rpq = rrpq.p + t * jacobi_log_len(JMAX);
     e.n = S[it[t]].p;
     e.pad = 0;
     ejr.push_back(e);
@@ -760,7 +771,7 @@ static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const st
       // Rayleigh-Ritz: Z = op(X) Q; T = Z^T Z
       run_gemm(Pxq, FTN_F64, X, Qa.p, Za.p, nullptr, s);
       run_gemm(Pzg, FTN_F64, Za.p, Za.p, Tm.p, nullptr, s);
-      LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p, 40);
+      LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
       HIPC(hipMemcpyAsync(cur.data(), Wt.p, cur.size() * 8, hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
       bool done = !prev.empty();

@@ -57,15 +57,15 @@ static void init_pool() {
   }
 }
 
-void* dmalloc(size_t bytes, hipStream_t s) {
+void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
   if (bytes == 0) return nullptr;
   void* p = nullptr;
-  if (g_alloc) {
+  if (g_alloc && !persistent) {
     p = g_alloc(bytes, (ftn_stream_t)s, g_alloc_ctx);
     if (!p) fail(FTN_ENOMEM, "external allocator returned NULL for " + std::to_string(bytes) + " bytes");
     return p;
   }
-  if (s == nullptr) {
+  if (persistent) {
     HIPC(hipMalloc(&p, bytes));
     return p;
   }
@@ -79,19 +79,71 @@ void* dmalloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
-void dfree(void* p, hipStream_t s) {
+void dfree(void* p, hipStream_t s, bool persistent) {
   if (!p) return;
-  if (g_free) {
-    g_free(p, (ftn_stream_t)s, g_alloc_ctx);
+  if (persistent) {
+    (void)hipFree(p);
     return;
   }
-  if (s == nullptr) {
-    (void)hipFree(p);
+  if (g_free) {
+    g_free(p, (ftn_stream_t)s, g_alloc_ctx);
     return;
   }
   (void)hipFreeAsync(p, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// pinned staging ring for small host-to-device copies: 16 chunks of 4 MiB;
+// a copy never spans chunks, and a chunk is reused only after the event
+// recorded behind its last copy has completed
+namespace {
+constexpr size_t RING_CH = 4u << 20, RING_N = 16;
+std::mutex g_ring_mu;
+char* g_ring = nullptr;
+bool g_ring_failed = false;
+size_t g_ring_cur = 0, g_ring_off = 0;  // current chunk, offset inside it
+hipEvent_t g_ring_ev[RING_N];
+hipStream_t g_ring_st[RING_N];
+bool g_ring_used[RING_N];
+}  // namespace
+
+void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return;
+  std::lock_guard<std::mutex> g(g_ring_mu);
+  if (!g_ring && !g_ring_failed) {
+    if (hipHostMalloc((void**)&g_ring, RING_CH * RING_N, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      g_ring = nullptr;
+      g_ring_failed = true;
+    } else {
+      for (size_t c = 0; c < RING_N; ++c) {
+        HIPC(hipEventCreateWithFlags(&g_ring_ev[c], hipEventDisableTiming));
+        g_ring_used[c] = false;
+        g_ring_st[c] = nullptr;
+      }
+    }
+  }
+  if (!g_ring || bytes > RING_CH) {
+    HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return;
+  }
+  if (g_ring_off + bytes > RING_CH) {  // move to the next chunk once its copies are done
+    g_ring_cur = (g_ring_cur + 1) % RING_N;
+    g_ring_off = 0;
+    if (g_ring_used[g_ring_cur]) HIPC(hipEventSynchronize(g_ring_ev[g_ring_cur]));
+    g_ring_used[g_ring_cur] = false;
+  }
+  const size_t c = g_ring_cur;
+  if (g_ring_used[c] && g_ring_st[c] != s) HIPC(hipEventSynchronize(g_ring_ev[c]));
+  char* stage = g_ring + c * RING_CH + g_ring_off;
+  std::memcpy(stage, src, bytes);
+  HIPC(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, s));
+  HIPC(hipEventRecord(g_ring_ev[c], s));
+  g_ring_used[c] = true;
+  g_ring_st[c] = s;
+  g_ring_off = (g_ring_off + bytes + 255) & ~(size_t)255;
+}
 
 // ---------------------------------------------------------------------------
 // single-workgroup exclusive scan of int64 values (block counts, sizes)
