@@ -3,23 +3,30 @@
 //
 // For the bond between A (leg la) and B (leg lb), per bond charge q:
 //   A~_q (M x d) and B~_q (d x N) are the fused matrices of the contraction
-//   plan (signed permutes). G_A = A~^T A~ and G_B = B~ B~^T (split-K MFMA
-//   GEMMs) are factored by pivoted Cholesky, G_A = R_A^T R_A, G_B = R_B^T
-//   R_B, so A~ = Q_A R_A and B~ = R_B^T Q_B with orthonormal Q's. The SVD of
-//   X = R_A R_B^T = U S V^T gives the best rank-chi approximation of A~ B~,
-//   with the chi largest values kept over all charges. The projectors
-//   P_A = R_B^T V S^-1/2 and P_B = S^-1/2 U^T R_A give A' = A~ P_A and
-//   B' = P_B B~, computed as ordinary fermionic contractions of A and B with
-//   2-leg block-diagonal tensors followed by transpositions that put the new
-//   bond back in place. A per-sector sign (the bond parity of the local
-//   convention) commutes with the block-diagonal projectors, so the same
-//   A', B' serve both conventions.
-// The SVD of X: the smaller Gram matrix H of X is diagonalised with a cyclic
-// Jacobi method in LDS when its order is <= 128, otherwise its leading
-// eigenspace is found by subspace iteration (Cholesky-QR orthonormalisation)
-// followed by a Rayleigh-Ritz step on a 128-dimensional subspace.
+//   plan (signed permutes), and G_A = A~^T A~, G_B = B~ B~^T their Gram
+//   matrices (split-K MFMA GEMMs). With A~ = Q_A R_A (G_A = R_A^T R_A) and
+//   B~ = R_B^T Q_B, the best rank-chi approximation of A~ B~ comes from the
+//   SVD X = R_A R_B^T = U S V^T, the chi largest values kept over all
+//   charges, through the projectors P_A = R_B^T V S^-1/2 and
+//   P_B = S^-1/2 U^T R_A. Only R_A is formed: the eigenvectors U of
+//   T = X X^T = R_A G_B R_A^T (eigenvalues S^2) give V S = X^T U, hence
+//   P_A = G_B R_A^T U S^-3/2 and P_B = S^-1/2 (R_A^T U)^T, with no inverse
+//   of an ill-conditioned factor. A' = A~ P_A and B' = P_B B~ are ordinary
+//   fermionic contractions of A and B with 2-leg block-diagonal tensors
+//   followed by transpositions that put the new bond back in place. A
+//   per-sector sign (the bond parity of the local convention) commutes with
+//   the block-diagonal projectors, so the same A', B' serve both
+//   conventions.
+// R_A (and R_B for large sectors) come from a blocked right-looking Cholesky
+// that drops dependent columns (pivot below 1e-13 of the largest diagonal).
+// T is diagonalised by a cyclic Jacobi method in LDS when d <= 128; larger
+// sectors find the leading left singular subspace of X = R_A R_B^T by block
+// power iteration with X^T and X alternately on a 128-column basis.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 
 #include "common.h"
 
@@ -27,7 +34,6 @@ namespace ftn {
 
 constexpr int LT = 1024;     // threads of the factorisation kernels
 constexpr int JMAX = 128;    // largest order diagonalised in LDS
-constexpr int CHOL_MAX = 4096;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 static_assert(LT == 1024 && JMAX == 128, "register staging assumes 1024 threads and order 128");
@@ -35,130 +41,6 @@ static_assert(LT == 1024 && JMAX == 128, "register staging assumes 1024 threads 
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   return v;
-}
-
-// ---------------------------------------------------------------------------
-// Blocked pivoted Cholesky (Gram matrices up to 4096): a panel kernel factors
-// up to 64 pivoted columns per launch (one workgroup per matrix), followed by
-// an MFMA GEMM that removes the panel from the Schur complement,
-// G <- G - R_p^T R_p. R is kept in original column order (R[l][c]), so the
-// update needs no gather. Stops at the numerical rank (largest remaining
-// pivot not above tol * largest diagonal of G).
-struct CholState {
-  double* G;    // d x d, overwritten by the Schur complement
-  double* R;    // d x d, zeroed on entry
-  double* dp;   // d: remaining pivots by position
-  int* piv;     // d: original index at each position
-  double* thr;  // 1: absolute pivot threshold
-  int* rank;    // 1: -1 while running, then the rank
-  int d;
-  int pad;
-};
-
-__global__ void __launch_bounds__(LT) k_chol_init(const CholState* st, double tol) {
-  const CholState S = st[blockIdx.x];
-  const int d = S.d, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  __shared__ double red[LT / 64];
-  double m = 0.0;
-  for (int i = tid; i < d; i += LT) {
-    double v = S.G[(int64_t)i * d + i];
-    S.dp[i] = v;
-    S.piv[i] = i;
-    m = fmax(m, v);
-  }
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  if (lane == 0) red[w] = m;
-  __syncthreads();
-  if (tid == 0) {
-    double mm = 0.0;
-    for (int i = 0; i < LT / 64; ++i) mm = fmax(mm, red[i]);
-    S.thr[0] = tol * mm;
-    S.rank[0] = (mm > 0.0 && d > 0) ? -1 : 0;
-  }
-}
-
-__global__ void __launch_bounds__(LT) k_chol_panel(const CholState* st, int j0, int nb) {
-  const CholState S = st[blockIdx.x];
-  const int d = S.d, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (j0 >= d || S.rank[0] >= 0) return;
-  __shared__ double dp[CHOL_MAX];
-  __shared__ int piv[CHOL_MAX];
-  __shared__ double red_v[LT / 64];
-  __shared__ int red_i[LT / 64];
-  __shared__ int s_stop;
-  for (int i = tid; i < d; i += LT) {
-    dp[i] = S.dp[i];
-    piv[i] = S.piv[i];
-  }
-  if (tid == 0) s_stop = -1;
-  __syncthreads();
-  const double thr = S.thr[0];
-  const int jend = min(j0 + nb, d);
-  for (int j = j0; j < jend; ++j) {
-    double bv = -1.0;
-    int bi = d;
-    for (int i = j + tid; i < d; i += LT)
-      if (dp[i] > bv) {
-        bv = dp[i];
-        bi = i;
-      }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(bv, o);
-      int oi = __shfl_xor(bi, o);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      red_v[w] = bv;
-      red_i[w] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double v = -1.0;
-      int p = d;
-      for (int i = 0; i < LT / 64; ++i)
-        if (red_v[i] > v || (red_v[i] == v && red_i[i] < p)) {
-          v = red_v[i];
-          p = red_i[i];
-        }
-      if (!(v > thr)) {
-        s_stop = j;
-      } else if (p != j) {
-        double t = dp[j];
-        dp[j] = dp[p];
-        dp[p] = t;
-        int ti = piv[j];
-        piv[j] = piv[p];
-        piv[p] = ti;
-      }
-    }
-    __syncthreads();
-    if (s_stop >= 0) break;
-    const int cj = piv[j];
-    const double rjj = sqrt(dp[j]);
-    if (tid == 0) S.R[(int64_t)j * d + cj] = rjj;
-    for (int i = j + 1 + tid; i < d; i += LT) {
-      const int ci = piv[i];
-      double sacc = S.G[(int64_t)cj * d + ci];
-      for (int l = j0; l < j; ++l) sacc -= S.R[(int64_t)l * d + cj] * S.R[(int64_t)l * d + ci];
-      const double r = sacc / rjj;
-      S.R[(int64_t)j * d + ci] = r;
-      dp[i] = fmax(dp[i] - r * r, 0.0);
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < d; i += LT) {
-    S.dp[i] = dp[i];
-    S.piv[i] = piv[i];
-  }
-  if (tid == 0) {
-    if (s_stop >= 0)
-      S.rank[0] = s_stop;
-    else if (jend == d)
-      S.rank[0] = d;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,117 +222,114 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
 
 // ---------------------------------------------------------------------------
 // Rank-revealing orthonormalisation factor (one workgroup per matrix): for
-// the Gram matrix G = Y^T Y (p x p, p <= 128), symmetric-pivoted Cholesky
-// G = P^T R^T R P stops at the numerical rank r (largest remaining pivot not
-// above tol * largest diagonal). The output M (p x p) has
-// M[piv[i]][c] = R11^-1[i][c] for i <= c < r and zeros elsewhere, so Y M has
-// r orthonormal columns followed by zero columns: dependent directions are
-// dropped instead of amplified.
-// The factorisation is left-looking in LDS: row j of R is written over the
-// (no longer needed) row of G of the j-th pivot, eight threads per column
-// share each dot product, and every wave chooses the pivot itself from a
-// double-buffered diagonal, so a step costs one barrier. R is then
-// gathered into pivot order, padded with the identity to order 128, and
-// inverted in place: 16 x 16 diagonal blocks by back substitution, then
-// three doubling levels [U11 U12; 0 U22]^-1 = [U11^-1, -U11^-1 U12 U22^-1;
-// 0, U22^-1] with FP64 MFMA tiles (the product U11^-1 U12 is staged in the
-// free lower triangle).
+// the Gram matrix G = Y^T Y (p x p, p <= 128), Cholesky G = R^T R in which a
+// column whose pivot (its squared distance from the span of the previous
+// columns) is not above tol * (largest diagonal of G) is dropped: its row of
+// R is zero and its column of the output is zero. The output M (p x p) is
+// R^-1 with the dropped columns cleared, so Y M has orthonormal columns (up
+// to the conditioning of the kept ones) and zero columns: dependent
+// directions are dropped instead of amplified. R itself (rows of dropped
+// columns zero) can be written as well or instead.
+// Blocked in LDS, upper triangle only, panels of 16: one wave factors the
+// 16 x 16 diagonal block (no workgroup barrier inside), the panel row
+// R12 = R11^-T A12 is solved one column per thread, and the trailing
+// update A22 -= R12^T R12 runs on FP64 MFMA tiles. R is padded with the
+// identity to order 128 and inverted in place: 16 x 16 diagonal blocks by
+// back substitution, then three doubling levels
+// [U11 U12; 0 U22]^-1 = [U11^-1, -U11^-1 U12 U22^-1; 0, U22^-1] on MFMA
+// tiles (U11^-1 U12 is staged in the free lower triangle).
 struct OrthJob {
-  const double* G;
-  double* M;  // p x p output
-  int p;
-  int pad;
+  const double* G;    // p x p input, leading dimension ldg
+  double* R;          // optional: R (upper, dropped rows and lower part zero), ld ldr
+  double* M;          // optional: R^-1 with dropped columns zero, ld ldm
+  const double* thr;  // optional absolute pivot threshold (else tol * max diag)
+  int p, ldg, ldr, ldm;
 };
 
 __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double tol) {
   const OrthJob J = jobs[blockIdx.x];
   const int p = J.p;
   __shared__ double A[JMAX][JMAX + 1];
-  __shared__ double dpb[2][JMAX];
-  __shared__ int sel[JMAX], pos[JMAX];
+  __shared__ int dr[JMAX];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < p * p; e += LT) A[e / p][e % p] = J.G[e];
-  for (int i = tid; i < JMAX; i += LT) {
-    pos[i] = -1;
-    dpb[0][i] = (i < p) ? J.G[(int64_t)i * p + i] : -1.0;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < JMAX * JMAX; e += LT) {
+    const int i = e >> 7, c = e & 127;
+    A[i][c] = (i < p && c < p) ? J.G[(int64_t)i * J.ldg + c] : (i == c ? 1.0 : 0.0);
   }
   __syncthreads();
   double mx = 0.0;
-  for (int i = lane; i < p; i += 64) mx = fmax(mx, dpb[0][i]);
+  for (int i = lane; i < p; i += 64) mx = fmax(mx, A[i][i]);
   mx = wave_max(mx);
-  const double thr = tol * mx;
-  int r = (mx > 0.0) ? p : 0;
-  int cur = 0;
-  for (int j = 0; j < r; ++j) {
-    const double* dpc = dpb[cur];
-    double* dpn = dpb[cur ^ 1];
-    double bv = -1.0;
-    int bi = JMAX;
-    for (int i = lane; i < p; i += 64) {
-      const double v = dpc[i];
-      if (v > bv) {
-        bv = v;
-        bi = i;
+  const double thr = J.thr ? *J.thr : tol * mx;
+  for (int j0 = 0; j0 < JMAX; j0 += 16) {
+    if (w == 0) {  // 16 x 16 diagonal block, one wave
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = j0 + jj;
+        const double d = A[j][j];
+        const bool drop = (j < p) && !(d > thr);
+        const double r = drop ? 1.0 : sqrt(d), inv = 1.0 / r;
+        double v = 0.0;
+        if (lane > jj && lane < 16) v = drop ? 0.0 : A[j][j0 + lane] * inv;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane > jj && lane < 16) A[j][j0 + lane] = v;
+        if (lane == 0) {
+          A[j][j] = r;
+          dr[j] = drop ? 1 : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int e = lane; e < 256; e += 64) {
+          const int a = e >> 4, b = e & 15;
+          if (a > jj && b >= a) A[j0 + a][j0 + b] -= A[j][j0 + a] * A[j][j0 + b];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
+    __syncthreads();
+    const int rest = JMAX - j0 - 16;
+    if (tid < rest) {  // R12 = R11^-T A12, column c
+      const int c = j0 + 16 + tid;
+      double x[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        double sacc = A[j0 + jj][c];
+#pragma unroll
+        for (int l = 0; l < jj; ++l) sacc -= A[j0 + l][j0 + jj] * x[l];
+        x[jj] = dr[j0 + jj] ? 0.0 : sacc / A[j0 + jj][j0 + jj];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) A[j0 + jj][c] = x[jj];
+    }
+    __syncthreads();
+    if (rest > 0) {  // A22 -= R12^T R12 on the upper-triangle tiles
+      const int nt = rest / 16, ntile = nt * (nt + 1) / 2, base = j0 + 16;
+      for (int t = w; t < ntile; t += LT / 64) {
+        int ti = 0, u = t;
+        while (u >= nt - ti) {
+          u -= nt - ti;
+          ++ti;
+        }
+        const int tj = ti + u;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const double a = A[j0 + k0 + lk][base + 16 * ti + li];
+          const double bb = A[j0 + k0 + lk][base + 16 * tj + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[base + 16 * ti + lk + 4 * q][base + 16 * tj + li] -= acc[q];
       }
     }
-    if (!(bv > thr)) {
-      r = j;
-      break;
-    }
-    const int cj = bi;
-    const double rjj = sqrt(bv), inv = 1.0 / rjj;
-    const int c = tid >> 3, sub = tid & 7;
-    const bool act = c < p && c != cj && dpc[c] >= 0.0;
-    double sacc = 0.0;
-    if (act)
-      for (int l = sub; l < j; l += 8) {
-        const int o = sel[l];
-        sacc += A[o][cj] * A[o][c];
-      }
-    sacc += __shfl_xor(sacc, 1);
-    sacc += __shfl_xor(sacc, 2);
-    sacc += __shfl_xor(sacc, 4);
-    if (sub == 0 && c < p) {
-      if (act) {
-        const double v = (A[cj][c] - sacc) * inv;
-        A[cj][c] = v;
-        dpn[c] = fmax(dpc[c] - v * v, 0.0);
-      } else {
-        dpn[c] = -1.0;
-      }
-    }
-    if (tid == 0) {
-      A[cj][cj] = rjj;
-      sel[j] = cj;
-      pos[cj] = j;
-    }
-    cur ^= 1;
     __syncthreads();
   }
-  // R in pivot order, identity beyond the rank (through registers)
-  double v[JMAX * JMAX / LT];
-#pragma unroll
-  for (int u = 0; u < JMAX * JMAX / LT; ++u) {
-    const int e = tid + u * LT, l = e >> 7, i = e & 127;
-    double x = 0.0;
-    if (l <= i) x = (i < r) ? A[sel[l]][sel[i]] : (l == i ? 1.0 : 0.0);
-    v[u] = x;
+  if (J.R) {
+    for (int e = tid; e < p * p; e += LT) {
+      const int i = e / p, c = e % p;
+      J.R[(int64_t)i * J.ldr + c] = (i <= c && !dr[i]) ? A[i][c] : 0.0;
+    }
   }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < JMAX * JMAX / LT; ++u) {
-    const int e = tid + u * LT;
-    A[e >> 7][e & 127] = v[u];
-  }
-  __syncthreads();
+  if (!J.M) return;
   // 16 x 16 diagonal blocks: lane c of wave w solves column c of block w
   if (w < JMAX / 16 && lane < 16) {
     const int o = 16 * w, c = lane;
@@ -467,7 +346,6 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
       if (i <= c) A[o + i][o + c] = x[i];
   }
   __syncthreads();
-  const int li = lane & 15, lk = lane >> 4;
   for (int h = 16; h < JMAX; h *= 2) {
     const int m = 2 * h, nt = h / 16, tiles = (JMAX / m) * nt * nt;
     const int pr = w / (nt * nt), t = w % (nt * nt);
@@ -498,8 +376,8 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
     __syncthreads();
   }
   for (int e = tid; e < p * p; e += LT) {
-    const int o = e / p, c = e % p, i = pos[o];
-    J.M[e] = (i >= 0 && c < r && i <= c) ? A[i][c] : 0.0;
+    const int i = e / p, c = e % p;
+    J.M[(int64_t)i * J.ldm + c] = (i <= c && !dr[c]) ? A[i][c] : 0.0;
   }
 }
 
@@ -575,16 +453,16 @@ __global__ void k_fill_random(double* X, int64_t n, uint64_t seed) {
   X[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
-// column scaling: X[:, j] *= f(w[j]) for j < k (row-major rows x ld)
-// mode 0: 1/sqrt(w); mode 1: sqrt(w); mode 2: 1/w
-__global__ void k_scale_cols(double* X, int64_t rows, int64_t ld, int k, const double* w, int mode) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= rows * k) return;
-  int64_t r = e / k;
-  int j = (int)(e % k);
-  double v = w[j];
-  double f = mode == 0 ? 1.0 / sqrt(v) : (mode == 1 ? sqrt(v) : 1.0 / v);
-  X[r * ld + j] *= f;
+// Wa = Sa diag(s^-3/2) (d x k) and Pb = diag(s^-1/2) Sb^T (k x d)
+__global__ void k_wz_scale(const double* Sa, const double* Sb, int64_t d, int k, const double* sv, double* Wa,
+                           double* Pb) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= d * k) return;
+  const int64_t r = e / k;
+  const int c = (int)(e % k);
+  const double h = 1.0 / sqrt(sv[c]);
+  Wa[e] = Sa[e] * h * h * h;
+  Pb[(int64_t)c * d + r] = Sb[e] * h;
 }
 
 __global__ void k_sqrt_inplace(double* w, int n) {
@@ -627,169 +505,254 @@ static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int
 struct Sect {
   int64_t M, N, d;       // rows of A~, cols of B~, bond dim
   int64_t a_off, b_off;  // into A~ / B~
-  int rA = 0, rB = 0;    // Cholesky ranks
-  int ns = 0;            // order of H
-  int p = 0;             // subspace size (<= JMAX) or ns
+  int p = 0;             // eigenbasis size: d (direct) or JMAX (subspace iteration)
   bool iterate = false;
   int kept = 0;
   Q charge;
   int crank = 0;
 };
 
-// Leading spectral data of X (rA x rB) per sector. Output: eigenvalues of the
-// smaller Gram matrix H (= s^2, descending) in W and its eigenvectors in V
-// (ns x p, ld p), ns = min(rA, rB). Orders <= JMAX: Jacobi on H directly.
-// Larger orders: block power iteration with X and X^T alternately (the Gram
-// matrices of the iterates then span s^2, not s^4), each iterate
-// orthonormalised twice by the rank-revealing factor, and a Rayleigh-Ritz
-// step T = (X Q)^T (X Q) every 8 iterations until the leading Ritz values are
-// stable (relative change <= 1e-14 of the largest) or 96 iterations.
-static void eig_top(std::vector<Sect>& S, int64_t chi, const double* H, const std::vector<int64_t>& hoff,
-                    const double* X, const std::vector<int64_t>& xoff, double* V, const std::vector<int64_t>& voff,
-                    double* W, const std::vector<int64_t>& woff, hipStream_t s) {
-  const int ng = (int)S.size();
-  std::vector<EigJob> ej;
-  std::vector<int64_t> log_off;
-  int64_t log_n = 0;
-  for (int g = 0; g < ng; ++g)
-    if (!S[g].iterate && S[g].ns > 0) {
-      log_off.push_back(log_n);
-      log_n += jacobi_log_len(S[g].ns);
-    }
-  DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
-  DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
+// tol * (largest diagonal) per matrix
+struct DiagJob {
+  const double* G;
+  double* thr;
+  int d;
+  int pad;
+};
+__global__ void __launch_bounds__(256) k_diag_thr(const DiagJob* jobs, double tol) {
+  const DiagJob J = jobs[blockIdx.x];
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < J.d; i += 256) m = fmax(m, J.G[(int64_t)i * J.d + i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) J.thr[0] = tol * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// strict lower triangle of each d x d matrix <- 0
+__global__ void k_zero_lower(double* G, const int64_t* off, const int64_t* dim, int nm) {
+  const int m = blockIdx.y;
+  if (m >= nm) return;
+  const int64_t d = dim[m];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < d * d; e += (int64_t)gridDim.x * blockDim.x)
+    if (e / d > e % d) G[off[m] + e] = 0.0;
+}
+
+// In-place dropping Cholesky of the Gram matrices at offsets off[m] (d_m x
+// d_m) of Gm: on return each holds R (upper triangular, rows of dropped
+// columns zero, strict lower triangle zero) with R^T R = G on the kept
+// columns. Right-looking in panels of 128: the diagonal block is factored in
+// LDS (k_orth_factor, which also returns its inverse), the panel row is
+// R12 = R11^-T A12 (a GEMM with the inverse), and the trailing matrix is
+// updated by G22 -= R12^T R12 (GEMM). A column is dropped when its pivot is
+// not above tol * (largest diagonal of G).
+static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::vector<int64_t>& dim, double tol,
+                      hipStream_t s) {
+  const int nm = (int)off.size();
+  if (!nm) return;
+  const int64_t NB = JMAX;
+  DBuf<double> thr(nm, s);
   {
-    int t = 0;
-    for (int g = 0; g < ng; ++g)
-      if (!S[g].iterate && S[g].ns > 0) {
-        EigJob j;
-        j.H = H + hoff[g];
-        j.V = V + voff[g];
-        j.W = W + woff[g];
-        j.rot = lrot.p + log_off[t];
-        j.rpq = lpq.p + log_off[t++];
-        j.n = S[g].ns;
-        j.pad = 0;
-        ej.push_back(j);
+    std::vector<DiagJob> dj(nm);
+    for (int m = 0; m < nm; ++m) dj[m] = DiagJob{Gm + off[m], thr.p + m, (int)dim[m], 0};
+    DBuf<DiagJob> d = to_device(dj, s);
+    LAUNCH(k_diag_thr, dim3(nm), dim3(256), 0, s, d.p, tol);
+  }
+  int64_t dmax = 0, r12n = 0;
+  std::vector<int64_t> r12off(nm);
+  for (int m = 0; m < nm; ++m) {
+    dmax = std::max(dmax, dim[m]);
+    r12off[m] = r12n;
+    r12n += NB * std::max<int64_t>(dim[m] - NB, 0);
+  }
+  DBuf<double> Minv(nm * NB * NB, s), R12(std::max<int64_t>(r12n, 1), s);
+  for (int64_t j0 = 0; j0 < dmax; j0 += NB) {
+    std::vector<OrthJob> oj;
+    std::vector<GemmGroup> gt, gs;
+    for (int m = 0; m < nm; ++m) {
+      const int64_t d = dim[m];
+      if (d <= j0) continue;
+      const int64_t nb = std::min(NB, d - j0), rest = d - j0 - nb;
+      double* blk = Gm + off[m] + j0 * d + j0;
+      OrthJob o;
+      o.G = blk;
+      o.R = blk;
+      o.M = rest > 0 ? Minv.p + m * NB * NB : nullptr;
+      o.thr = thr.p + m;
+      o.p = (int)nb;
+      o.ldg = o.ldr = (int)d;
+      o.ldm = (int)NB;
+      oj.push_back(o);
+      if (rest > 0) {
+        gt.push_back(plain_group(nb, rest, nb, m * NB * NB, NB, 1, off[m] + j0 * d + j0 + nb, d, 0, r12off[m], rest));
+        gs.push_back(plain_group(rest, rest, nb, r12off[m], rest, 1, r12off[m], rest, 0,
+                                 off[m] + (j0 + nb) * d + j0 + nb, d));
       }
+    }
+    DBuf<OrthJob> doj = to_device(oj, s);
+    LAUNCH(k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
+    if (!gt.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Minv.p, Gm, R12.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
+      for (int m = 0; m < nm; ++m) {
+        const int64_t d = dim[m];
+        if (d <= j0 + NB) continue;
+        const int64_t rest = d - j0 - NB;
+        HIPC(hipMemcpy2DAsync(Gm + off[m] + j0 * d + j0 + NB, d * 8, R12.p + r12off[m], rest * 8, rest * 8, NB,
+                              hipMemcpyDeviceToDevice, s));
+      }
+    }
   }
-  if (!ej.empty()) {
+  DBuf<int64_t> doff = to_device(off, s), ddim = to_device(dim, s);
+  LAUNCH(k_zero_lower, dim3((unsigned)std::min<int64_t>(cdiv(dmax * dmax, 256), 4096), nm), dim3(256), 0, s, Gm,
+         doff.p, ddim.p, nm);
+}
+
+// Leading eigenpairs of X X^T per sector (d x d, eigenvalues s^2, the
+// squared singular values of A~ B~ restricted to the sector).
+// Outputs: E (d x p, ld p) eigenvectors (the left singular vectors of X),
+// lam (p) descending.
+// Orders d <= JMAX: cyclic Jacobi on T = R_A G_B R_A^T (= X X^T), given in
+// Hm. Larger orders: X = R_A R_B^T is given in Hm, and block power iteration
+// applies X^T and X alternately to a JMAX-column basis (so each product
+// scales the columns by s, not s^2), with one dropping Cholesky-QR after
+// each product (two before each Rayleigh-Ritz step, every 8 iterations)
+// until the leading Ritz values are stable (change <= 1e-14 of the largest)
+// or 96 iterations.
+static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
+                          double* Em, const std::vector<int64_t>& eoff, double* Lm, const std::vector<int64_t>& loff,
+                          hipStream_t s) {
+  const int ng = (int)S.size();
+  const double tol = 1e-13;
+  std::vector<int> dir, it;
+  for (int g = 0; g < ng; ++g) (S[g].iterate ? it : dir).push_back(g);
+  if (!dir.empty()) {
+    const int nd = (int)dir.size();
+    std::vector<int64_t> log_off(nd);
+    int64_t log_n = 0;
+    for (int t = 0; t < nd; ++t) {
+      log_off[t] = log_n;
+      log_n += jacobi_log_len((int)S[dir[t]].d);
+    }
+    DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
+    DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
+    std::vector<EigJob> ej;
+    for (int t = 0; t < nd; ++t) {
+      const int g = dir[t];
+      EigJob j;
+      j.H = Hm + hoff[g];
+      j.V = Em + eoff[g];
+      j.W = Lm + loff[g];
+      j.rot = lrot.p + log_off[t];
+      j.rpq = lpq.p + log_off[t];
+      j.n = (int)S[g].d;
+      j.pad = 0;
+      ej.push_back(j);
+    }
     DBuf<EigJob> dj = to_device(ej, s);
-    LAUNCH(k_jacobi_eig, dim3((unsigned)ej.size()), dim3(LT), 0, s, dj.p);
-    HIPC(hipStreamSynchronize(s));
+    LAUNCH(k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
   }
-  std::vector<int> it;
-  for (int g = 0; g < ng; ++g)
-    if (S[g].iterate) it.push_back(g);
   if (it.empty()) return;
   const int ni = (int)it.size();
-  // per iterated sector: eigen side e (dim ne), other side o (dim no)
-  std::vector<int64_t> ne(ni), no(ni), qoff(ni), zoff(ni), goff(ni);
-  int64_t qn = 0, zn = 0, gn = 0;
-  for (int t = 0; t < ni; ++t) {
-    const Sect& x = S[it[t]];
-    const bool eR = x.rB <= x.rA;  // eigenvectors live in the rB space
-    ne[t] = eR ? x.rB : x.rA;
-    no[t] = eR ? x.rA : x.rB;
-    qoff[t] = qn;
-    qn += ne[t] * x.p;
-    zoff[t] = zn;
-    zn += no[t] * x.p;
-    goff[t] = gn;
-    gn += (int64_t)x.p * x.p;
-  }
-  DBuf<double> Qa(qn, s), Qb(qn, s), Za(zn, s), Zb(zn, s), Gm(gn, s), Mm(gn, s), Tm(gn, s), Wv(gn, s),
-      Wt(std::max<int64_t>(ni * (int64_t)JMAX, 1), s);
+  const int64_t p = JMAX;
+  // iterates share the layout of Em (offsets eoff)
+  int64_t en = 0;
+  for (int g = 0; g < ng; ++g) en = std::max(en, eoff[g] + S[g].d * S[g].p);
+  DBuf<double> B0(en, s), B1(en, s), B2(en, s), B3(en, s), Gy(ni * p * p, s), Mm(ni * p * p, s),
+      Tr(ni * p * p, s), Zs(ni * p * p, s);
   DBuf<double2> rrot(ni * jacobi_log_len(JMAX), s);
   DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s);
-  // GEMM plans (reused every iteration)
-  std::vector<GemmGroup> gxq, gxz, gq_gram, gz_gram, gq_app, gz_app, gt;
+  std::vector<GemmGroup> gxt, gx, gg, gap, ge;
   for (int t = 0; t < ni; ++t) {
-    const Sect& x = S[it[t]];
-    const int64_t p = x.p;
-    const bool eR = x.rB <= x.rA;
-    // Z = op(X) Q : eR -> X (rA x rB) * Q (rB x p); else X^T (rB x rA) * Q (rA x p)
-    gxq.push_back(plain_group(no[t], p, ne[t], xoff[it[t]], x.rB, eR ? 0 : 1, qoff[t], p, 0, zoff[t], p));
-    // Q = op(X)^T Z : eR -> X^T * Z; else X * Z
-    gxz.push_back(plain_group(ne[t], p, no[t], xoff[it[t]], x.rB, eR ? 1 : 0, zoff[t], p, 0, qoff[t], p));
-    gq_gram.push_back(plain_group(p, p, ne[t], qoff[t], p, 1, qoff[t], p, 0, goff[t], p));
-    gz_gram.push_back(plain_group(p, p, no[t], zoff[t], p, 1, zoff[t], p, 0, goff[t], p));
-    gq_app.push_back(plain_group(ne[t], p, p, qoff[t], p, 0, goff[t], p, 0, qoff[t], p));
-    gz_app.push_back(plain_group(no[t], p, p, zoff[t], p, 0, goff[t], p, 0, zoff[t], p));
-    gt.push_back(plain_group(ne[t], p, p, qoff[t], p, 0, goff[t], p, 0, voff[it[t]], p));
+    const int g = it[t];
+    const int64_t d = S[g].d, go = (int64_t)t * p * p;
+    gxt.push_back(plain_group(d, p, d, hoff[g], d, 1, eoff[g], p, 0, eoff[g], p));  // Z = X^T Q
+    gx.push_back(plain_group(d, p, d, hoff[g], d, 0, eoff[g], p, 0, eoff[g], p));   // Q = X Z
+    gg.push_back(plain_group(p, p, d, eoff[g], p, 1, eoff[g], p, 0, go, p));        // Y^T Y
+    gap.push_back(plain_group(d, p, p, eoff[g], p, 0, go, p, 0, eoff[g], p));       // Y M
+    ge.push_back(plain_group(d, p, p, eoff[g], p, 0, go, p, 0, eoff[g], p));        // E = Q Zs
   }
-  GemmPlan Pxq, Pxz, Pqg, Pzg, Pqa, Pza, Pv;
-  gemm_plan(Pxq, gxq, FTN_GEMM_F64, s);
-  gemm_plan(Pxz, gxz, FTN_GEMM_F64, s);
-  gemm_plan(Pqg, gq_gram, FTN_GEMM_F64, s);
-  gemm_plan(Pzg, gz_gram, FTN_GEMM_F64, s);
-  gemm_plan(Pqa, gq_app, FTN_GEMM_F64, s);
-  gemm_plan(Pza, gz_app, FTN_GEMM_F64, s);
-  gemm_plan(Pv, gt, FTN_GEMM_F64, s);
+  GemmPlan Pxt, Px, Pg, Pap, Pe;
+  gemm_plan(Pxt, gxt, FTN_GEMM_F64, s);
+  gemm_plan(Px, gx, FTN_GEMM_F64, s);
+  gemm_plan(Pg, gg, FTN_GEMM_F64, s);
+  gemm_plan(Pap, gap, FTN_GEMM_F64, s);
+  gemm_plan(Pe, ge, FTN_GEMM_F64, s);
   std::vector<OrthJob> oj;
-  std::vector<EigJob> ejr;
+  std::vector<EigJob> ej;
   for (int t = 0; t < ni; ++t) {
+    const int g = it[t];
+    const int64_t go = (int64_t)t * p * p;
     OrthJob o;
-    o.G = Gm.p + goff[t];
-    o.M = Mm.p + goff[t];
-    o.p = S[it[t]].p;
-    o.pad = 0;
+    o.G = Gy.p + go;
+    o.R = nullptr;
+    o.M = Mm.p + go;
+    o.thr = nullptr;
+    o.p = o.ldg = o.ldr = o.ldm = (int)p;
     oj.push_back(o);
     EigJob e;
-    e.H = Tm.p + goff[t];
-    e.V = Wv.p + goff[t];
-    e.W = Wt.p + (int64_t)t * JMAX;
+    e.H = Tr.p + go;
+    e.V = Zs.p + go;
+    e.W = Lm + loff[g];
     e.rot = rrot.p + t * jacobi_log_len(JMAX);
     e.rpq = rrpq.p + t * jacobi_log_len(JMAX);
-    e.n = S[it[t]].p;
+    e.n = (int)p;
     e.pad = 0;
-    ejr.push_back(e);
+    ej.push_back(e);
   }
   DBuf<OrthJob> doj = to_device(oj, s);
-  DBuf<EigJob> dej = to_device(ejr, s);
-  HIPC(hipStreamSynchronize(s));
-  const double tol = 1e-13;
-  // Y (buffer y) <- orthonormal basis of its columns, through scratch o
-  auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double* y, double* o) {
-    run_gemm(gram, FTN_F64, y, y, Gm.p, nullptr, s);
+  DBuf<EigJob> dej = to_device(ej, s);
+  double *q = B0.p, *z = B1.p, *u = B2.p, *tmp = B3.p;
+  auto orth = [&](double*& y) {  // y <- orthonormal basis of span(y), dependent columns zeroed
+    run_gemm(Pg, FTN_F64, y, y, Gy.p, nullptr, s);
     LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
-    run_gemm(app, FTN_F64, y, Mm.p, o, nullptr, s);
+    run_gemm(Pap, FTN_F64, y, Mm.p, tmp, nullptr, s);
+    std::swap(y, tmp);
   };
-  LAUNCH(k_fill_random, dim3((unsigned)cdiv(qn, 256)), dim3(256), 0, s, Qa.p, qn, (uint64_t)0x5eedf00dull);
-  orth(Pqg, Pqa, Qa.p, Qb.p);
-  orth(Pqg, Pqa, Qb.p, Qa.p);  // Q in Qa
-  std::vector<double> prev, cur(ni * (int64_t)JMAX);
+  LAUNCH(k_fill_random, dim3((unsigned)cdiv(en, 256)), dim3(256), 0, s, q, en, (uint64_t)0x5eedf00dull);
+  orth(q);
+  orth(q);
+  std::vector<double> prev, cur(ni * p);
   const int max_iter = 96, check = 8;
+  static const bool trace = std::getenv("FTN_TRACE") != nullptr;
+  int iters = 0;
+  bool have_next = false;  // z already holds X^T q (computed for the last check)
   for (int k = 1; k <= max_iter; ++k) {
-    run_gemm(Pxq, FTN_F64, X, Qa.p, Za.p, nullptr, s);
-    orth(Pzg, Pza, Za.p, Zb.p);
-    orth(Pzg, Pza, Zb.p, Za.p);
-    run_gemm(Pxz, FTN_F64, X, Za.p, Qa.p, nullptr, s);
-    orth(Pqg, Pqa, Qa.p, Qb.p);
-    orth(Pqg, Pqa, Qb.p, Qa.p);
+    iters = k;
+    if (!have_next) run_gemm(Pxt, FTN_F64, Hm, q, z, nullptr, s);
+    have_next = false;
+    orth(z);
+    run_gemm(Px, FTN_F64, Hm, z, q, nullptr, s);
+    orth(q);
     if (k % check == 0 || k == max_iter) {
-      // Rayleigh-Ritz: Z = op(X) Q; T = Z^T Z
-      run_gemm(Pxq, FTN_F64, X, Qa.p, Za.p, nullptr, s);
-      run_gemm(Pzg, FTN_F64, Za.p, Za.p, Tm.p, nullptr, s);
+      orth(q);
+      // Rayleigh-Ritz: W = X^T Q, Tr = W^T W = Q^T X X^T Q
+      run_gemm(Pxt, FTN_F64, Hm, q, u, nullptr, s);
+      run_gemm(Pg, FTN_F64, u, u, Tr.p, nullptr, s);
       LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
-      HIPC(hipMemcpyAsync(cur.data(), Wt.p, cur.size() * 8, hipMemcpyDeviceToHost, s));
+      for (int t = 0; t < ni; ++t)
+        HIPC(hipMemcpyAsync(cur.data() + t * p, Lm + loff[it[t]], p * 8, hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
       bool done = !prev.empty();
       for (int t = 0; t < ni && done; ++t) {
-        const int kk = (int)std::min<int64_t>(chi, S[it[t]].p);
-        const double top = std::max(cur[(int64_t)t * JMAX], 1e-300);
-        for (int q = 0; q < kk; ++q)
-          if (std::fabs(cur[(int64_t)t * JMAX + q] - prev[(int64_t)t * JMAX + q]) > 1e-14 * top) done = false;
+        const int kk = (int)std::min<int64_t>(chi, p);
+        const double top = std::max(cur[t * p], 1e-300);
+        for (int j = 0; j < kk; ++j)
+          if (std::fabs(cur[t * p + j] - prev[t * p + j]) > 1e-14 * top) done = false;
       }
       prev = cur;
       if (done) break;
+      std::swap(z, u);  // the next half step X^T q is ready
+      have_next = true;
     }
   }
-  // outputs: eigenvalues, eigenvectors V = Q Wv
-  for (int t = 0; t < ni; ++t)
-    HIPC(hipMemcpyAsync(W + woff[it[t]], Wt.p + (int64_t)t * JMAX, S[it[t]].p * 8, hipMemcpyDeviceToDevice, s));
-  run_gemm(Pv, FTN_F64, Qa.p, Wv.p, V, nullptr, s);
-  HIPC(hipStreamSynchronize(s));
+  if (trace) {
+    std::string dd;
+    for (int t = 0; t < ni; ++t) dd += std::to_string(S[it[t]].d) + " ";
+    std::fprintf(stderr, "[ftn] subspace iteration: %d iterations, sectors %s\n", iters, dd.c_str());
+  }
+  run_gemm(Pe, FTN_F64, q, Zs.p, Em, nullptr, s);
 }
 
 CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff,
@@ -896,95 +859,56 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
-  // pivoted Cholesky of both Gram matrices (blocked: panel + MFMA update)
-  DBuf<double> Rm(std::max<int64_t>(gsz, 1), s);
-  HIPC(hipMemsetAsync(Rm.p, 0, std::max<int64_t>(gsz, 1) * 8, s));
-  {
-    const int nm = 2 * ng;
-    std::vector<int64_t> moff(nm), md(nm);
-    int64_t dsum = 0, dmax = 0;
-    for (int g = 0; g < ng; ++g) {
-      if (S[g].d > CHOL_MAX) fail(FTN_ENOTSUP, "bond sector larger than 4096");
-      moff[2 * g] = goffA[g];
-      moff[2 * g + 1] = goffB[g];
-      md[2 * g] = md[2 * g + 1] = S[g].d;
-      dsum += 2 * S[g].d;
-      dmax = std::max(dmax, S[g].d);
-    }
-    DBuf<double> dpv(std::max<int64_t>(dsum, 1), s), thr(nm, s);
-    DBuf<int> pv(std::max<int64_t>(dsum, 1), s), rk(nm, s);
-    std::vector<CholState> cs(nm);
-    int64_t o = 0;
-    for (int m = 0; m < nm; ++m) {
-      cs[m] = CholState{Gm.p + moff[m], Rm.p + moff[m], dpv.p + o, pv.p + o, thr.p + m, rk.p + m, (int)md[m], 0};
-      o += md[m];
-    }
-    DBuf<CholState> dcs = to_device(cs, s);
-    const int nb = 64;
-    LAUNCH(k_chol_init, dim3(nm), dim3(LT), 0, s, dcs.p, 1e-13);
-    std::vector<GemmPlan> upd;
-    for (int j0 = 0; j0 < dmax; j0 += nb) {
-      LAUNCH(k_chol_panel, dim3(nm), dim3(LT), 0, s, dcs.p, j0, nb);
-      std::vector<GemmGroup> gs;
-      for (int m = 0; m < nm; ++m) {
-        const int64_t d = md[m];
-        if (j0 + nb >= d) continue;  // no later panel reads this matrix
-        const int64_t kk = std::min<int64_t>(nb, d - j0);
-        gs.push_back(plain_group(d, d, kk, moff[m] + j0 * d, d, 1, moff[m] + j0 * d, d, 0, moff[m], d));
-      }
-      if (!gs.empty()) {
-        upd.emplace_back();
-        gemm_plan(upd.back(), gs, FTN_GEMM_F64, s);
-        run_gemm(upd.back(), FTN_F64, Rm.p, Rm.p, Gm.p, nullptr, s, -1.0, 1.0);
-      }
-    }
-    std::vector<int> rks(nm);
-    HIPC(hipMemcpyAsync(rks.data(), rk.p, nm * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    for (int g = 0; g < ng; ++g) {
-      S[g].rA = rks[2 * g];
-      S[g].rB = rks[2 * g + 1];
-      if (S[g].rA < 0 || S[g].rB < 0) fail(FTN_EINVAL, "internal: Cholesky did not finish");
-    }
-  }
-  // X = R_A R_B^T (rA x rB); H = X^T X (rB <= rA) or X X^T
-  std::vector<int64_t> xoff(ng), hoff(ng), voff(ng), woff(ng), uoff(ng);
-  int64_t xs = 0, hs = 0, vs = 0, ws = 0, us = 0;
+  // G_A = R_A^T R_A for every sector and G_B = R_B^T R_B for the large ones
+  // (dropping Cholesky, in place); H = R_A G_B R_A^T (= X X^T) for sectors
+  // with d <= JMAX, X = R_A R_B^T for the others
+  std::vector<int64_t> hoff(ng), eoff(ng), loff(ng);
+  int64_t hs = 0, es = 0, ls = 0;
   for (int g = 0; g < ng; ++g) {
     Sect& x = S[g];
-    x.ns = std::min(x.rA, x.rB);
-    x.iterate = x.ns > JMAX;
-    x.p = x.iterate ? JMAX : x.ns;
-    xoff[g] = xs;
-    xs += (int64_t)x.rA * x.rB;
+    x.iterate = x.d > JMAX;
+    x.p = (int)(x.iterate ? JMAX : x.d);
     hoff[g] = hs;
-    hs += (int64_t)x.ns * x.ns;
-    voff[g] = vs;
-    vs += (int64_t)x.ns * x.p;
-    woff[g] = ws;
-    ws += std::max(x.p, 1);
-    uoff[g] = us;
-    us += (int64_t)std::max(x.rA, x.rB) * std::max(x.p, 1);
+    hs += x.d * x.d;
+    eoff[g] = es;
+    es += x.d * x.p;
+    loff[g] = ls;
+    ls += x.p;
   }
-  DBuf<double> Xm(std::max<int64_t>(xs, 1), s), Hm(std::max<int64_t>(hs, 1), s), Vm(std::max<int64_t>(vs, 1), s),
-      Wm(std::max<int64_t>(ws, 1), s), Um(std::max<int64_t>(us, 1), s);
   {
-    std::vector<GemmGroup> gx, gh;
+    std::vector<int64_t> offs, dims;
     for (int g = 0; g < ng; ++g) {
-      const Sect& x = S[g];
-      // R_A rows are rA x d (row-major, ld d); X = R_A R_B^T
-      gx.push_back(plain_group(x.rA, x.rB, x.d, goffA[g], x.d, 0, goffB[g], x.d, 1, xoff[g], x.rB));
-      if (x.rB <= x.rA)  // H = X^T X (rB x rB)
-        gh.push_back(plain_group(x.rB, x.rB, x.rA, xoff[g], x.rB, 1, xoff[g], x.rB, 0, hoff[g], x.rB));
-      else  // H = X X^T (rA x rA)
-        gh.push_back(plain_group(x.rA, x.rA, x.rB, xoff[g], x.rB, 0, xoff[g], x.rB, 1, hoff[g], x.rA));
+      offs.push_back(goffA[g]);
+      dims.push_back(S[g].d);
+      if (S[g].iterate) {
+        offs.push_back(goffB[g]);
+        dims.push_back(S[g].d);
+      }
     }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rm.p, Rm.p, Xm.p, nullptr, s);
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Xm.p, Xm.p, Hm.p, nullptr, s);
+    chol_drop(Gm.p, offs, dims, 1e-13, s);
   }
-  eig_top(S, chi, Hm.p, hoff, Xm.p, xoff, Vm.p, voff, Wm.p, woff, s);
+  DBuf<double> Tm(std::max<int64_t>(hs, 1), s), Em(std::max<int64_t>(es, 1), s), Lm(std::max<int64_t>(ls, 1), s);
+  {
+    DBuf<double> U1(std::max<int64_t>(hs, 1), s);
+    std::vector<GemmGroup> gu, gt, gx;
+    for (int g = 0; g < ng; ++g) {
+      const int64_t d = S[g].d;
+      if (S[g].iterate) {
+        gx.push_back(plain_group(d, d, d, goffA[g], d, 0, goffB[g], d, 1, hoff[g], d));  // X = R_A R_B^T
+      } else {
+        gu.push_back(plain_group(d, d, d, goffB[g], d, 0, goffA[g], d, 1, hoff[g], d));  // U1 = G_B R_A^T
+        gt.push_back(plain_group(d, d, d, goffA[g], d, 0, hoff[g], d, 0, hoff[g], d));   // H = R_A U1
+      }
+    }
+    if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Gm.p, Gm.p, Tm.p, nullptr, s);
+    if (!gu.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Gm.p, U1.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Gm.p, U1.p, Tm.p, nullptr, s);
+    }
+  }
+  left_spectrum(S, chi, Tm.p, hoff, Em.p, eoff, Lm.p, loff, s);
   // singular values = sqrt(eigenvalues); selection
-  launch_1d(std::max<int64_t>(ws, 1), s, k_sqrt_inplace, Wm.p, (int)std::max<int64_t>(ws, 1));
+  launch_1d(std::max<int64_t>(ls, 1), s, k_sqrt_inplace, Lm.p, (int)std::max<int64_t>(ls, 1));
   {
     std::vector<int> grp, idx, crank(ng);
     std::vector<int64_t> pos;
@@ -993,12 +917,12 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       for (int i = 0; i < S[g].p; ++i) {
         grp.push_back(g);
         idx.push_back(i);
-        pos.push_back(woff[g] + i);
+        pos.push_back(loff[g] + i);
       }
     }
     const int n = (int)grp.size();
-    std::vector<double> hw(std::max<int64_t>(ws, 1));
-    HIPC(hipMemcpyAsync(hw.data(), Wm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
+    std::vector<double> hw(std::max<int64_t>(ls, 1));
+    HIPC(hipMemcpyAsync(hw.data(), Lm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     std::vector<double> vals(n);
     for (int i = 0; i < n; ++i) {
@@ -1023,94 +947,61 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     HIPC(hipMemcpyAsync(st.data(), dst.p, 32, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     res.discarded = st[0];
-    // values dropped because a side's Gram rank was below the sector dim are
-    // exactly zero and add nothing
     double a1 = st[1], a2 = st[2];
     res.near_tie = (a2 > 0 && std::fabs(a1 - a2) <= 1e3 * 2.220446049250313e-16 * std::fabs(a1));
+    static const bool trace = std::getenv("FTN_TRACE") != nullptr;
+    if (trace) {
+      double smax = 0;
+      for (double v : vals) smax = std::max(smax, v);
+      std::string d;
+      for (int g = 0; g < ng; ++g) d += std::to_string(S[g].d) + ":" + std::to_string(kept[g]) + " ";
+      std::fprintf(stderr, "[ftn] compress: sectors %s chi-th %.17g next %.17g max %.17g\n", d.c_str(), a1, a2, smax);
+    }
     for (int g = 0; g < ng; ++g) S[g].kept = kept[g];
     for (int g = 0; g < ng; ++g)
-      for (int i = 0; i < S[g].kept; ++i) res.svals.push_back(hw[woff[g] + i]);
+      for (int i = 0; i < S[g].kept; ++i) res.svals.push_back(hw[loff[g] + i]);
     std::sort(res.svals.begin(), res.svals.end(), std::greater<double>());
   }
-  // projectors. With H = X^T X: V (rB x k) from H, U = X V S^-1.
-  // With H = X X^T: U (rA x k) from H, V = X^T U S^-1.
-  // P_A = R_B^T V S^-1/2 (d x k); P_B = S^-1/2 U^T R_A (k x d)
-  std::vector<int64_t> pa_off(ng), pb_off(ng);
-  int64_t pas = 0;
+  // projectors, with U = E_k (d x k) and WZ = R_A^T U:
+  //   P_B = S^-1/2 WZ^T (k x d);
+  //   P_A = G_B WZ S^-3/2 (d x k) for direct sectors, and R_B^T (X^T U) S^-3/2
+  //   for iterated ones (their G_B has been overwritten by R_B)
+  std::vector<int64_t> pa_off(ng), pb_off(ng), wz_off(ng);
+  int64_t pas = 0, wzs = 0;
   for (int g = 0; g < ng; ++g) {
     pa_off[g] = pas;
     pas += S[g].d * S[g].kept;
     pb_off[g] = pas;
     pas += S[g].kept * S[g].d;
+    wz_off[g] = wzs;
+    wzs += S[g].d * S[g].kept;
   }
-  DBuf<double> PAB(std::max<int64_t>(pas, 1), s);
+  DBuf<double> PAB(std::max<int64_t>(pas, 1), s), WZ(std::max<int64_t>(wzs, 1), s), XE(std::max<int64_t>(wzs, 1), s),
+      WZa(std::max<int64_t>(wzs, 1), s);
   {
-    // the other singular vectors: O = X V or X^T U (then scaled by 1/s)
-    std::vector<GemmGroup> go;
+    std::vector<GemmGroup> gwz, gxe, gpa;
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.kept) continue;
-      if (x.rB <= x.rA)  // U = X V : (rA x rB)(rB x k)
-        go.push_back(plain_group(x.rA, x.kept, x.rB, xoff[g], x.rB, 0, voff[g], x.p, 0, uoff[g], x.kept));
-      else  // V = X^T U : (rB x rA)(rA x k)
-        go.push_back(plain_group(x.rB, x.kept, x.rA, xoff[g], x.rB, 1, voff[g], x.p, 0, uoff[g], x.kept));
-    }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, go, Xm.p, Vm.p, Um.p, nullptr, s);
-    for (int g = 0; g < ng; ++g) {
-      const Sect& x = S[g];
-      if (!x.kept) continue;
-      // O = X V (rows rA) or X^T U (rows rB); O / s are the other singular
-      // vectors, and both sides are then scaled by s^-1/2
-      const int64_t rows = x.rB <= x.rA ? x.rA : x.rB;
-      LAUNCH(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
-                         rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 2);
-      LAUNCH(k_scale_cols, dim3((unsigned)cdiv((int64_t)x.ns * x.kept, 256)), dim3(256), 0, s,
-                         Vm.p + voff[g], (int64_t)x.ns, (int64_t)x.p, x.kept, Wm.p + woff[g], 0);
-      LAUNCH(k_scale_cols, dim3((unsigned)cdiv(rows * x.kept, 256)), dim3(256), 0, s, Um.p + uoff[g],
-                         rows, (int64_t)x.kept, x.kept, Wm.p + woff[g], 0);
-      HIPC(hipGetLastError());
-    }
-    // now: Vs = V S^-1/2 and Us = U S^-1/2 (for whichever side)
-    std::vector<GemmGroup> gpa, gpb;
-    for (int g = 0; g < ng; ++g) {
-      const Sect& x = S[g];
-      if (!x.kept) continue;
-      if (x.rB <= x.rA) {
-        // eigen side = V (rB x k, ld p) in Vm; other = U (rA x k, ld k) in Um
-        // P_A = R_B^T V : (d x rB)(rB x k)
-        gpa.push_back(plain_group(x.d, x.kept, x.rB, goffB[g], x.d, 1, voff[g], x.p, 0, pa_off[g], x.kept));
-        // P_B = U^T R_A : (k x rA)(rA x d)
-        gpb.push_back(plain_group(x.kept, x.d, x.rA, uoff[g], x.kept, 1, goffA[g], x.d, 0, pb_off[g], x.d));
+      gwz.push_back(plain_group(x.d, x.kept, x.d, goffA[g], x.d, 1, eoff[g], x.p, 0, wz_off[g], x.kept));
+      if (x.iterate) {
+        gxe.push_back(plain_group(x.d, x.kept, x.d, hoff[g], x.d, 1, eoff[g], x.p, 0, wz_off[g], x.kept));
+        gpa.push_back(plain_group(x.d, x.kept, x.d, goffB[g], x.d, 1, wz_off[g], x.kept, 0, pa_off[g], x.kept));
       } else {
-        // eigen side = U (rA x k, ld p) in Vm; other = V (rB x k, ld k) in Um
-        gpa.push_back(plain_group(x.d, x.kept, x.rB, goffB[g], x.d, 1, uoff[g], x.kept, 0, pa_off[g], x.kept));
-        gpb.push_back(plain_group(x.kept, x.d, x.rA, voff[g], x.p, 1, goffA[g], x.d, 0, pb_off[g], x.d));
+        gpa.push_back(plain_group(x.d, x.kept, x.d, goffB[g], x.d, 0, wz_off[g], x.kept, 0, pa_off[g], x.kept));
       }
     }
-    // operand buffers differ per case; run each case separately
-    std::vector<GemmGroup> pa1, pa2, pb1, pb2;
-    {
-      int t = 0;
+    if (!gwz.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwz, Gm.p, Em.p, WZ.p, nullptr, s);
+      if (!gxe.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxe, Tm.p, Em.p, XE.p, nullptr, s);
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
         if (!x.kept) continue;
-        if (x.rB <= x.rA) {
-          pa1.push_back(gpa[t]);
-          pb1.push_back(gpb[t]);
-        } else {
-          pa2.push_back(gpa[t]);
-          pb2.push_back(gpb[t]);
-        }
-        ++t;
+        const int64_t dk = x.d * x.kept;
+        LAUNCH(k_wz_scale, dim3((unsigned)cdiv(dk, 256)), dim3(256), 0, s, (x.iterate ? XE.p : WZ.p) + wz_off[g],
+               WZ.p + wz_off[g], x.d, x.kept, Lm.p + loff[g], WZa.p + wz_off[g], PAB.p + pb_off[g]);
       }
-    }
-    if (!pa1.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pa1, Rm.p, Vm.p, PAB.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pb1, Um.p, Rm.p, PAB.p, nullptr, s);
-    }
-    if (!pa2.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pa2, Rm.p, Um.p, PAB.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, pb2, Vm.p, Rm.p, PAB.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gpa, Gm.p, WZa.p, PAB.p, nullptr, s);
     }
   }
   // projector tensors: P_A legs (conj of la, new) and P_B legs (new', conj of lb)

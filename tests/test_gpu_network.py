@@ -186,6 +186,33 @@ def test_compress_rank_deficient_subspace_iteration(P):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("dims", [(100, 300), (128, 129), (60, 40)])
+def test_compress_mixed_sector_sizes(P, dims):
+    # one bond sector small enough for the direct eigensolver, one that
+    # needs subspace iteration (or both small), with decaying spectra
+    rng = np.random.default_rng(803 + dims[0])
+    sym = S.Z2
+    from oracle.tensor import make_leg, FTensor
+    bond = make_leg(sym, [(0,), (1,)], list(dims), 1)
+    ra = make_leg(sym, [(0,), (1,)], [150, 170], 0)
+    rb = make_leg(sym, [(0,), (1,)], [160, 140], 1)
+    A = FTensor.zeros(sym, [ra, bond], (0,))
+    B = FTensor.zeros(sym, [partner(bond), rb], (0,))
+    for q in range(2):
+        d = dims[q]
+        m, n = ra.dims[q], rb.dims[q]
+        A.blocks[(q, q)] = torch.from_numpy(rng.standard_normal((m, d)) * np.logspace(0, -5, d)[None, :])
+        B.blocks[(q, q)] = torch.from_numpy(np.logspace(0, -3, d)[:, None] * rng.standard_normal((d, n)))
+    chi = 90
+    A2, B2, info = o_compress(A, B, 1, 0, chi, cutoff=1e-6)
+    ref = ftensordot(A2, B2, [1], [0]).to_dense()
+    GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-6)
+    assert GA.legs()[1][1] == list(A2.legs[1].dims)
+    got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
+    assert np.all(np.isfinite(got))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
 def test_c2_full_size_norm_and_hopping(P):
     # the full 40-site workload against the stored oracle values
     import json, os
