@@ -453,16 +453,17 @@ __global__ void k_fill_random(double* X, int64_t n, uint64_t seed) {
   X[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
-// Wa = Sa diag(s^-3/2) (d x k) and Pb = diag(s^-1/2) Sb^T (k x d)
-__global__ void k_wz_scale(const double* Sa, const double* Sb, int64_t d, int k, const double* sv, double* Wa,
-                           double* Pb) {
+// projector blocks from F, GF (d x k) and the singular values:
+//   side A: Pa = GF S^-3/2, Pb = S^-1/2 F^T;  side B: Pa = F S^-1/2, Pb = S^-3/2 GF^T
+__global__ void k_proj_out(const double* F, const double* GF, int64_t d, int k, const double* sv, int sideA,
+                           double* Pa, double* Pb) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= d * k) return;
   const int64_t r = e / k;
   const int c = (int)(e % k);
-  const double h = 1.0 / sqrt(sv[c]);
-  Wa[e] = Sa[e] * h * h * h;
-  Pb[(int64_t)c * d + r] = Sb[e] * h;
+  const double h = 1.0 / sqrt(sv[c]), h3 = h * h * h;
+  Pa[e] = sideA ? GF[e] * h3 : F[e] * h;
+  Pb[(int64_t)c * d + r] = sideA ? F[e] * h : GF[e] * h3;
 }
 
 __global__ void k_sqrt_inplace(double* w, int n) {
@@ -505,8 +506,11 @@ static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int
 struct Sect {
   int64_t M, N, d;       // rows of A~, cols of B~, bond dim
   int64_t a_off, b_off;  // into A~ / B~
-  int p = 0;             // eigenbasis size: d (direct) or JMAX (subspace iteration)
+  int rA = 0, rB = 0;    // ranks of the dropping Cholesky factors
+  int ns = 0;            // min(rA, rB)
+  int p = 0;             // number of singular values computed: ns or JMAX
   bool iterate = false;
+  bool sideA = true;     // eigenvectors live on the A side (U) or the B side (V)
   int kept = 0;
   Q charge;
   int crank = 0;
@@ -537,6 +541,50 @@ __global__ void k_zero_lower(double* G, const int64_t* off, const int64_t* dim, 
   const int64_t d = dim[m];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < d * d; e += (int64_t)gridDim.x * blockDim.x)
     if (e / d > e % d) G[off[m] + e] = 0.0;
+}
+
+// Rows of R with a non-zero diagonal (the kept columns) packed to the top of
+// the matrix at the same offset of Rc; rank[m] = their number. One
+// workgroup per matrix.
+__global__ void __launch_bounds__(1024) k_pack_rows(const double* G, const int64_t* off, const int64_t* dim,
+                                                    double* Rc, int* rank) {
+  const int m = blockIdx.x;
+  const int64_t d = dim[m];
+  const double* R = G + off[m];
+  double* O = Rc + off[m];
+  __shared__ int cnt[1024];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int64_t j0 = 0; j0 < d; j0 += 1024) {
+    const int64_t j = j0 + threadIdx.x;
+    const int kept = (j < d && R[j * d + j] != 0.0) ? 1 : 0;
+    cnt[threadIdx.x] = kept;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+      const int v = threadIdx.x >= o ? cnt[threadIdx.x - o] : 0;
+      __syncthreads();
+      cnt[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int pos = base + cnt[threadIdx.x] - kept;
+    const int tot = cnt[1023];
+    __syncthreads();
+    cnt[threadIdx.x] = kept ? -1 - pos : 0;  // destination row of each kept row
+    __syncthreads();
+    // copy this chunk's kept rows (one wave per row, round robin)
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = w; r < 1024 && j0 + r < d; r += 16) {
+      const int c = cnt[r];
+      if (c >= 0) continue;
+      const int64_t dst = -1 - c, src = j0 + r;
+      for (int64_t col = lane; col < d; col += 64) O[dst * d + col] = R[src * d + col];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rank[m] = base;
 }
 
 // In-place dropping Cholesky of the Gram matrices at offsets off[m] (d_m x
@@ -609,31 +657,31 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
          doff.p, ddim.p, nm);
 }
 
-// Leading eigenpairs of X X^T per sector (d x d, eigenvalues s^2, the
-// squared singular values of A~ B~ restricted to the sector).
-// Outputs: E (d x p, ld p) eigenvectors (the left singular vectors of X),
-// lam (p) descending.
-// Orders d <= JMAX: cyclic Jacobi on T = R_A G_B R_A^T (= X X^T), given in
-// Hm. Larger orders: X = R_A R_B^T is given in Hm, and block power iteration
-// applies X^T and X alternately to a JMAX-column basis (so each product
-// scales the columns by s, not s^2), with one dropping Cholesky-QR after
-// each product (two before each Rayleigh-Ritz step, every 8 iterations)
-// until the leading Ritz values are stable (change <= 1e-14 of the largest)
-// or 96 iterations.
-static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
-                          double* Em, const std::vector<int64_t>& eoff, double* Lm, const std::vector<int64_t>& loff,
-                          hipStream_t s) {
+// Leading singular triplets of X = R_A R_B^T (rA x rB) per sector.
+// Outputs: lam (p) = s^2 descending, and in E:
+//   ns = min(rA, rB) <= JMAX: the eigenvectors (ns x ns) of H (given in
+//   Hm: X X^T when rA <= rB, else X^T X), by cyclic Jacobi;
+//   larger: the left singular vectors U (rA x JMAX) from block power
+//   iteration applying X^T and X alternately to a JMAX-column basis (each
+//   product scales the columns by s, not s^2), with one dropping
+//   Cholesky-QR after each product (two before each Rayleigh-Ritz step,
+//   every 8 iterations) until the leading Ritz values are stable (change
+//   <= 1e-14 of the largest) or 96 iterations.
+static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
+                       const double* Xm, const std::vector<int64_t>& xoff, double* Em, const std::vector<int64_t>& eoff,
+                       double* Lm, const std::vector<int64_t>& loff, hipStream_t s) {
   const int ng = (int)S.size();
   const double tol = 1e-13;
   std::vector<int> dir, it;
-  for (int g = 0; g < ng; ++g) (S[g].iterate ? it : dir).push_back(g);
+  for (int g = 0; g < ng; ++g)
+    if (S[g].ns > 0) (S[g].iterate ? it : dir).push_back(g);
   if (!dir.empty()) {
     const int nd = (int)dir.size();
     std::vector<int64_t> log_off(nd);
     int64_t log_n = 0;
     for (int t = 0; t < nd; ++t) {
       log_off[t] = log_n;
-      log_n += jacobi_log_len((int)S[dir[t]].d);
+      log_n += jacobi_log_len(S[dir[t]].ns);
     }
     DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
     DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
@@ -646,7 +694,7 @@ static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, c
       j.W = Lm + loff[g];
       j.rot = lrot.p + log_off[t];
       j.rpq = lpq.p + log_off[t];
-      j.n = (int)S[g].d;
+      j.n = S[g].ns;
       j.pad = 0;
       ej.push_back(j);
     }
@@ -656,28 +704,37 @@ static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, c
   if (it.empty()) return;
   const int ni = (int)it.size();
   const int64_t p = JMAX;
-  // iterates share the layout of Em (offsets eoff)
-  int64_t en = 0;
-  for (int g = 0; g < ng; ++g) en = std::max(en, eoff[g] + S[g].d * S[g].p);
-  DBuf<double> B0(en, s), B1(en, s), B2(en, s), B3(en, s), Gy(ni * p * p, s), Mm(ni * p * p, s),
+  std::vector<int64_t> qo(ni), zo(ni);
+  int64_t qn = 0, zn = 0;
+  for (int t = 0; t < ni; ++t) {
+    qo[t] = qn;
+    qn += (int64_t)S[it[t]].rA * p;
+    zo[t] = zn;
+    zn += (int64_t)S[it[t]].rB * p;
+  }
+  DBuf<double> Q0(qn, s), Q1(qn, s), Z0(zn, s), Z1(zn, s), Z2(zn, s), Gy(ni * p * p, s), Mm(ni * p * p, s),
       Tr(ni * p * p, s), Zs(ni * p * p, s);
   DBuf<double2> rrot(ni * jacobi_log_len(JMAX), s);
   DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s);
-  std::vector<GemmGroup> gxt, gx, gg, gap, ge;
+  std::vector<GemmGroup> gxt, gx, ggq, ggz, gaq, gaz, ge;
   for (int t = 0; t < ni; ++t) {
     const int g = it[t];
-    const int64_t d = S[g].d, go = (int64_t)t * p * p;
-    gxt.push_back(plain_group(d, p, d, hoff[g], d, 1, eoff[g], p, 0, eoff[g], p));  // Z = X^T Q
-    gx.push_back(plain_group(d, p, d, hoff[g], d, 0, eoff[g], p, 0, eoff[g], p));   // Q = X Z
-    gg.push_back(plain_group(p, p, d, eoff[g], p, 1, eoff[g], p, 0, go, p));        // Y^T Y
-    gap.push_back(plain_group(d, p, p, eoff[g], p, 0, go, p, 0, eoff[g], p));       // Y M
-    ge.push_back(plain_group(d, p, p, eoff[g], p, 0, go, p, 0, eoff[g], p));        // E = Q Zs
+    const int64_t rA = S[g].rA, rB = S[g].rB, go = (int64_t)t * p * p;
+    gxt.push_back(plain_group(rB, p, rA, xoff[g], rB, 1, qo[t], p, 0, zo[t], p));  // Z = X^T Q
+    gx.push_back(plain_group(rA, p, rB, xoff[g], rB, 0, zo[t], p, 0, qo[t], p));   // Q = X Z
+    ggq.push_back(plain_group(p, p, rA, qo[t], p, 1, qo[t], p, 0, go, p));         // Q^T Q
+    ggz.push_back(plain_group(p, p, rB, zo[t], p, 1, zo[t], p, 0, go, p));         // Z^T Z
+    gaq.push_back(plain_group(rA, p, p, qo[t], p, 0, go, p, 0, qo[t], p));         // Q M
+    gaz.push_back(plain_group(rB, p, p, zo[t], p, 0, go, p, 0, zo[t], p));         // Z M
+    ge.push_back(plain_group(rA, p, p, qo[t], p, 0, go, p, 0, eoff[g], p));        // E = Q Zs
   }
-  GemmPlan Pxt, Px, Pg, Pap, Pe;
+  GemmPlan Pxt, Px, Pgq, Pgz, Paq, Paz, Pe;
   gemm_plan(Pxt, gxt, FTN_GEMM_F64, s);
   gemm_plan(Px, gx, FTN_GEMM_F64, s);
-  gemm_plan(Pg, gg, FTN_GEMM_F64, s);
-  gemm_plan(Pap, gap, FTN_GEMM_F64, s);
+  gemm_plan(Pgq, ggq, FTN_GEMM_F64, s);
+  gemm_plan(Pgz, ggz, FTN_GEMM_F64, s);
+  gemm_plan(Paq, gaq, FTN_GEMM_F64, s);
+  gemm_plan(Paz, gaz, FTN_GEMM_F64, s);
   gemm_plan(Pe, ge, FTN_GEMM_F64, s);
   std::vector<OrthJob> oj;
   std::vector<EigJob> ej;
@@ -703,16 +760,17 @@ static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, c
   }
   DBuf<OrthJob> doj = to_device(oj, s);
   DBuf<EigJob> dej = to_device(ej, s);
-  double *q = B0.p, *z = B1.p, *u = B2.p, *tmp = B3.p;
-  auto orth = [&](double*& y) {  // y <- orthonormal basis of span(y), dependent columns zeroed
-    run_gemm(Pg, FTN_F64, y, y, Gy.p, nullptr, s);
+  double *q = Q0.p, *qt = Q1.p, *z = Z0.p, *zt = Z1.p, *zu = Z2.p;
+  // y <- orthonormal basis of span(y), dependent columns zeroed
+  auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
+    run_gemm(gram, FTN_F64, y, y, Gy.p, nullptr, s);
     LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
-    run_gemm(Pap, FTN_F64, y, Mm.p, tmp, nullptr, s);
-    std::swap(y, tmp);
+    run_gemm(app, FTN_F64, y, Mm.p, yt, nullptr, s);
+    std::swap(y, yt);
   };
-  LAUNCH(k_fill_random, dim3((unsigned)cdiv(en, 256)), dim3(256), 0, s, q, en, (uint64_t)0x5eedf00dull);
-  orth(q);
-  orth(q);
+  LAUNCH(k_fill_random, dim3((unsigned)cdiv(qn, 256)), dim3(256), 0, s, q, qn, (uint64_t)0x5eedf00dull);
+  orth(Pgq, Paq, q, qt);
+  orth(Pgq, Paq, q, qt);
   std::vector<double> prev, cur(ni * p);
   const int max_iter = 96, check = 8;
   static const bool trace = std::getenv("FTN_TRACE") != nullptr;
@@ -720,16 +778,16 @@ static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, c
   bool have_next = false;  // z already holds X^T q (computed for the last check)
   for (int k = 1; k <= max_iter; ++k) {
     iters = k;
-    if (!have_next) run_gemm(Pxt, FTN_F64, Hm, q, z, nullptr, s);
+    if (!have_next) run_gemm(Pxt, FTN_F64, Xm, q, z, nullptr, s);
     have_next = false;
-    orth(z);
-    run_gemm(Px, FTN_F64, Hm, z, q, nullptr, s);
-    orth(q);
+    orth(Pgz, Paz, z, zt);
+    run_gemm(Px, FTN_F64, Xm, z, q, nullptr, s);
+    orth(Pgq, Paq, q, qt);
     if (k % check == 0 || k == max_iter) {
-      orth(q);
+      orth(Pgq, Paq, q, qt);
       // Rayleigh-Ritz: W = X^T Q, Tr = W^T W = Q^T X X^T Q
-      run_gemm(Pxt, FTN_F64, Hm, q, u, nullptr, s);
-      run_gemm(Pg, FTN_F64, u, u, Tr.p, nullptr, s);
+      run_gemm(Pxt, FTN_F64, Xm, q, zu, nullptr, s);
+      run_gemm(Pgz, FTN_F64, zu, zu, Tr.p, nullptr, s);
       LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
       for (int t = 0; t < ni; ++t)
         HIPC(hipMemcpyAsync(cur.data() + t * p, Lm + loff[it[t]], p * 8, hipMemcpyDeviceToHost, s));
@@ -743,13 +801,13 @@ static void left_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, c
       }
       prev = cur;
       if (done) break;
-      std::swap(z, u);  // the next half step X^T q is ready
+      std::swap(z, zu);  // the next half step X^T q is ready
       have_next = true;
     }
   }
   if (trace) {
     std::string dd;
-    for (int t = 0; t < ni; ++t) dd += std::to_string(S[it[t]].d) + " ";
+    for (int t = 0; t < ni; ++t) dd += std::to_string(S[it[t]].rA) + "x" + std::to_string(S[it[t]].rB) + " ";
     std::fprintf(stderr, "[ftn] subspace iteration: %d iterations, sectors %s\n", iters, dd.c_str());
   }
   run_gemm(Pe, FTN_F64, q, Zs.p, Em, nullptr, s);
@@ -859,54 +917,78 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
-  // G_A = R_A^T R_A for every sector and G_B = R_B^T R_B for the large ones
-  // (dropping Cholesky, in place); H = R_A G_B R_A^T (= X X^T) for sectors
-  // with d <= JMAX, X = R_A R_B^T for the others
-  std::vector<int64_t> hoff(ng), eoff(ng), loff(ng);
-  int64_t hs = 0, es = 0, ls = 0;
-  for (int g = 0; g < ng; ++g) {
-    Sect& x = S[g];
-    x.iterate = x.d > JMAX;
-    x.p = (int)(x.iterate ? JMAX : x.d);
-    hoff[g] = hs;
-    hs += x.d * x.d;
-    eoff[g] = es;
-    es += x.d * x.p;
-    loff[g] = ls;
-    ls += x.p;
-  }
+  // G_A = R_A^T R_A and G_B = R_B^T R_B by dropping Cholesky (on a copy, the
+  // Gram matrices are needed again); the kept rows are packed into Rc
+  // (rank x d at the Gram offsets)
+  std::vector<int> ranks(2 * ng);
+  DBuf<double> Rc(std::max<int64_t>(gsz, 1), s);
   {
+    DBuf<double> Fm(std::max<int64_t>(gsz, 1), s);
+    HIPC(hipMemcpyAsync(Fm.p, Gm.p, gsz * 8, hipMemcpyDeviceToDevice, s));
     std::vector<int64_t> offs, dims;
     for (int g = 0; g < ng; ++g) {
       offs.push_back(goffA[g]);
       dims.push_back(S[g].d);
-      if (S[g].iterate) {
-        offs.push_back(goffB[g]);
-        dims.push_back(S[g].d);
-      }
+      offs.push_back(goffB[g]);
+      dims.push_back(S[g].d);
     }
-    chol_drop(Gm.p, offs, dims, 1e-13, s);
+    chol_drop(Fm.p, offs, dims, 1e-13, s);
+    DBuf<int64_t> doff = to_device(offs, s), ddim = to_device(dims, s);
+    DBuf<int> drk(2 * ng, s);
+    LAUNCH(k_pack_rows, dim3(2 * ng), dim3(1024), 0, s, Fm.p, doff.p, ddim.p, Rc.p, drk.p);
+    HIPC(hipMemcpyAsync(ranks.data(), drk.p, 2 * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
   }
-  DBuf<double> Tm(std::max<int64_t>(hs, 1), s), Em(std::max<int64_t>(es, 1), s), Lm(std::max<int64_t>(ls, 1), s);
+  // per sector: the side with the smaller rank (A when rA <= rB, and always
+  // for iterated sectors) gives R = R_side, G_o = the other Gram matrix;
+  // direct sectors diagonalise H = R G_o R^T (r x r, = X X^T or X^T X),
+  // iterated ones use X = R_A R_B^T (rA x rB)
+  std::vector<int64_t> xoff(ng), hoff(ng), eoff(ng), loff(ng), u1off(ng);
+  int64_t xs = 0, hs = 0, es = 0, ls = 0, u1s = 0;
+  for (int g = 0; g < ng; ++g) {
+    Sect& x = S[g];
+    x.rA = ranks[2 * g];
+    x.rB = ranks[2 * g + 1];
+    x.ns = std::min(x.rA, x.rB);
+    x.iterate = x.ns > JMAX;
+    x.p = x.iterate ? JMAX : x.ns;
+    x.sideA = x.iterate || x.rA <= x.rB;
+    xoff[g] = xs;
+    xs += x.iterate ? (int64_t)x.rA * x.rB : 0;
+    hoff[g] = hs;
+    hs += x.iterate ? 0 : (int64_t)x.ns * x.ns;
+    u1off[g] = u1s;
+    u1s += x.iterate ? 0 : x.d * x.ns;
+    eoff[g] = es;
+    es += (int64_t)(x.iterate ? x.rA : x.ns) * x.p;
+    loff[g] = ls;
+    ls += std::max(x.p, 1);
+  }
+  DBuf<double> Xm(std::max<int64_t>(xs, 1), s), Hm(std::max<int64_t>(hs, 1), s), Em(std::max<int64_t>(es, 1), s),
+      Lm(std::max<int64_t>(ls, 1), s);
+  HIPC(hipMemsetAsync(Lm.p, 0, std::max<int64_t>(ls, 1) * 8, s));
   {
-    DBuf<double> U1(std::max<int64_t>(hs, 1), s);
-    std::vector<GemmGroup> gu, gt, gx;
+    DBuf<double> U1(std::max<int64_t>(u1s, 1), s);
+    std::vector<GemmGroup> gx, gu, gh;
     for (int g = 0; g < ng; ++g) {
-      const int64_t d = S[g].d;
-      if (S[g].iterate) {
-        gx.push_back(plain_group(d, d, d, goffA[g], d, 0, goffB[g], d, 1, hoff[g], d));  // X = R_A R_B^T
-      } else {
-        gu.push_back(plain_group(d, d, d, goffB[g], d, 0, goffA[g], d, 1, hoff[g], d));  // U1 = G_B R_A^T
-        gt.push_back(plain_group(d, d, d, goffA[g], d, 0, hoff[g], d, 0, hoff[g], d));   // H = R_A U1
+      const Sect& x = S[g];
+      if (!x.ns) continue;
+      if (x.iterate) {
+        gx.push_back(plain_group(x.rA, x.rB, x.d, goffA[g], x.d, 0, goffB[g], x.d, 1, xoff[g], x.rB));
+        continue;
       }
+      const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
+      // U1 = G_o R^T (d x r), H = R U1 (r x r)
+      gu.push_back(plain_group(x.d, x.ns, x.d, go, x.d, 0, ro, x.d, 1, u1off[g], x.ns));
+      gh.push_back(plain_group(x.ns, x.ns, x.d, ro, x.d, 0, u1off[g], x.ns, 0, hoff[g], x.ns));
     }
-    if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Gm.p, Gm.p, Tm.p, nullptr, s);
+    if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rc.p, Rc.p, Xm.p, nullptr, s);
     if (!gu.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Gm.p, U1.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Gm.p, U1.p, Tm.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Rc.p, U1.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Rc.p, U1.p, Hm.p, nullptr, s);
     }
   }
-  left_spectrum(S, chi, Tm.p, hoff, Em.p, eoff, Lm.p, loff, s);
+  x_spectrum(S, chi, Hm.p, hoff, Xm.p, xoff, Em.p, eoff, Lm.p, loff, s);
   // singular values = sqrt(eigenvalues); selection
   launch_1d(std::max<int64_t>(ls, 1), s, k_sqrt_inplace, Lm.p, (int)std::max<int64_t>(ls, 1));
   {
@@ -962,46 +1044,44 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       for (int i = 0; i < S[g].kept; ++i) res.svals.push_back(hw[loff[g] + i]);
     std::sort(res.svals.begin(), res.svals.end(), std::greater<double>());
   }
-  // projectors, with U = E_k (d x k) and WZ = R_A^T U:
-  //   P_B = S^-1/2 WZ^T (k x d);
-  //   P_A = G_B WZ S^-3/2 (d x k) for direct sectors, and R_B^T (X^T U) S^-3/2
-  //   for iterated ones (their G_B has been overwritten by R_B)
-  std::vector<int64_t> pa_off(ng), pb_off(ng), wz_off(ng);
-  int64_t pas = 0, wzs = 0;
+  // projectors. E_k (r x k): the leading eigenvectors of H (direct) or the
+  // left singular vectors of X (iterated). With F = R^T E_k and GF = G_o F
+  // (both d x k):
+  //   side A: P_A = GF S^-3/2, P_B = S^-1/2 F^T   (E_k = U)
+  //   side B: P_A = F S^-1/2,  P_B = S^-3/2 GF^T  (E_k = V)
+  // (from P_A = R_B^T V S^-1/2, P_B = S^-1/2 U^T R_A and X^T U = V S).
+  std::vector<int64_t> pa_off(ng), pb_off(ng), fo(ng);
+  int64_t pas = 0, fs = 0;
   for (int g = 0; g < ng; ++g) {
+    const Sect& x = S[g];
     pa_off[g] = pas;
-    pas += S[g].d * S[g].kept;
+    pas += x.d * x.kept;
     pb_off[g] = pas;
-    pas += S[g].kept * S[g].d;
-    wz_off[g] = wzs;
-    wzs += S[g].d * S[g].kept;
+    pas += x.kept * x.d;
+    fo[g] = fs;
+    fs += x.d * x.kept;
   }
-  DBuf<double> PAB(std::max<int64_t>(pas, 1), s), WZ(std::max<int64_t>(wzs, 1), s), XE(std::max<int64_t>(wzs, 1), s),
-      WZa(std::max<int64_t>(wzs, 1), s);
+  DBuf<double> PAB(std::max<int64_t>(pas, 1), s), Fk(std::max<int64_t>(fs, 1), s), GF(std::max<int64_t>(fs, 1), s);
   {
-    std::vector<GemmGroup> gwz, gxe, gpa;
+    std::vector<GemmGroup> gf, ggf;
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.kept) continue;
-      gwz.push_back(plain_group(x.d, x.kept, x.d, goffA[g], x.d, 1, eoff[g], x.p, 0, wz_off[g], x.kept));
-      if (x.iterate) {
-        gxe.push_back(plain_group(x.d, x.kept, x.d, hoff[g], x.d, 1, eoff[g], x.p, 0, wz_off[g], x.kept));
-        gpa.push_back(plain_group(x.d, x.kept, x.d, goffB[g], x.d, 1, wz_off[g], x.kept, 0, pa_off[g], x.kept));
-      } else {
-        gpa.push_back(plain_group(x.d, x.kept, x.d, goffB[g], x.d, 0, wz_off[g], x.kept, 0, pa_off[g], x.kept));
-      }
+      const int64_t r = x.sideA ? x.rA : x.rB;
+      const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
+      gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
+      ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
     }
-    if (!gwz.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwz, Gm.p, Em.p, WZ.p, nullptr, s);
-      if (!gxe.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxe, Tm.p, Em.p, XE.p, nullptr, s);
+    if (!gf.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gf, Rc.p, Em.p, Fk.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggf, Gm.p, Fk.p, GF.p, nullptr, s);
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
         if (!x.kept) continue;
-        const int64_t dk = x.d * x.kept;
-        LAUNCH(k_wz_scale, dim3((unsigned)cdiv(dk, 256)), dim3(256), 0, s, (x.iterate ? XE.p : WZ.p) + wz_off[g],
-               WZ.p + wz_off[g], x.d, x.kept, Lm.p + loff[g], WZa.p + wz_off[g], PAB.p + pb_off[g]);
+        const int64_t n = x.d * x.kept;
+        LAUNCH(k_proj_out, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, Fk.p + fo[g], GF.p + fo[g], x.d, x.kept,
+               Lm.p + loff[g], (int)x.sideA, PAB.p + pa_off[g], PAB.p + pb_off[g]);
       }
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gpa, Gm.p, WZa.p, PAB.p, nullptr, s);
     }
   }
   // projector tensors: P_A legs (conj of la, new) and P_B legs (new', conj of lb)
