@@ -111,9 +111,11 @@ def main():
     t0 = time.perf_counter()
     flops = 0.0
     for k in range(args.steps):
+        ts = time.perf_counter()
         res, st = gpu_step(g, chi)
         flops += st[0]["flops"] + st[1]["flops"]
-        print("[bench] step %d done" % k, file=sys.stderr, flush=True)
+        print("[bench] step %d done (%.1f ms host)" % (k, 1000 * (time.perf_counter() - ts)), file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     P.ftn.profile_enable(False)

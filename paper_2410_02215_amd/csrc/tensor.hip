@@ -2,7 +2,10 @@
 // enumeration (Eq. symmetryrule), dense <-> block conversion, elementwise ops.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <unordered_map>
+#include <vector>
 
 #include "common.h"
 
@@ -38,7 +41,6 @@ void hip_check(hipError_t e, const char* what) {
 static void* (*g_alloc)(size_t, ftn_stream_t, void*) = nullptr;
 static void (*g_free)(void*, ftn_stream_t, void*) = nullptr;
 static void* g_alloc_ctx = nullptr;
-static std::once_flag g_pool_once;
 
 void set_allocator(void* (*a)(size_t, ftn_stream_t, void*), void (*f)(void*, ftn_stream_t, void*),
                    void* ctx) {
@@ -47,15 +49,43 @@ void set_allocator(void* (*a)(size_t, ftn_stream_t, void*), void (*f)(void*, ftn
   g_alloc_ctx = ctx;
 }
 
-static void init_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
+// Caching allocator for temporaries. Freed blocks are kept per device in a
+// size-ordered pool tagged with the stream that freed them; a request on the
+// same stream may reuse a block at once (stream order makes it safe), and a
+// block freed on another stream is reused only once the event recorded at
+// its release has completed. Sizes are rounded to 512 B (small) or 2 MiB
+// (large) and a block is reused for requests down to half its size. On
+// out-of-memory every cached block is released and the allocation retried.
+namespace {
+struct Block {
+  void* p;
+  size_t size;
+  hipStream_t s;
+  hipEvent_t ev;  // recorded at release (for reuse on another stream)
+};
+struct DevCache {
+  std::multimap<size_t, Block> free_;      // by size
+  std::unordered_map<void*, size_t> live;  // pointer -> rounded size
+  std::vector<hipEvent_t> events;          // idle events for reuse
+};
+std::mutex g_cache_mu;
+std::unordered_map<int, DevCache>* g_cache = new std::unordered_map<int, DevCache>();
+
+size_t round_size(size_t b) {
+  const size_t big = 2u << 20;
+  return b < big ? (b + 511) & ~(size_t)511 : (b + big - 1) & ~(big - 1);
 }
+
+void release_cached(DevCache& c) {
+  if (c.free_.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c.free_) {
+    (void)hipFree(kv.second.p);
+    if (kv.second.ev) c.events.push_back(kv.second.ev);
+  }
+  c.free_.clear();
+}
+}  // namespace
 
 void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
   if (bytes == 0) return nullptr;
@@ -69,13 +99,35 @@ void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
     HIPC(hipMalloc(&p, bytes));
     return p;
   }
-  std::call_once(g_pool_once, init_pool);
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  const size_t sz = round_size(bytes);
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  DevCache& c = (*g_cache)[dev];
+  for (auto it = c.free_.lower_bound(sz); it != c.free_.end() && it->first <= 2 * sz; ++it) {
+    Block& b = it->second;
+    if (b.s != s && (!b.ev || hipEventQuery(b.ev) != hipSuccess)) {
+      (void)hipGetLastError();
+      continue;
+    }
+    p = b.p;
+    c.live[p] = it->first;
+    if (b.ev) c.events.push_back(b.ev);
+    c.free_.erase(it);
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, sz);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    release_cached(c);
+    e = hipMalloc(&p, sz);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     fail(e == hipErrorOutOfMemory ? FTN_ENOMEM : FTN_EHIP,
-         "hipMallocAsync(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+         "hipMalloc(" + std::to_string(sz) + "): " + hipGetErrorString(e));
   }
+  c.live[p] = sz;
   return p;
 }
 
@@ -89,9 +141,28 @@ void dfree(void* p, hipStream_t s, bool persistent) {
     g_free(p, (ftn_stream_t)s, g_alloc_ctx);
     return;
   }
-  (void)hipFreeAsync(p, s);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  DevCache& c = (*g_cache)[dev];
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;  // not from this cache
+  Block b{p, it->second, s, nullptr};
+  c.live.erase(it);
+  if (!c.events.empty()) {
+    b.ev = c.events.back();
+    c.events.pop_back();
+  } else if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    b.ev = nullptr;
+  }
+  if (b.ev && hipEventRecord(b.ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    c.events.push_back(b.ev);
+    b.ev = nullptr;
+  }
+  c.free_.emplace(b.size, b);
 }
-
 
 // ---------------------------------------------------------------------------
 // pinned staging ring for small host-to-device copies: 16 chunks of 4 MiB;
