@@ -36,8 +36,10 @@
  *     an `out` argument is new, owned by the caller and released with
  *     ftn_tensor_free / ftn_net_free.
  *   - Device memory: tensor data lives in device memory of the current HIP
- *     device, allocated by the library (hipMallocAsync on the given stream,
- *     or the allocator registered with ftn_set_allocator).
+ *     device, allocated by the library (its caching allocator: blocks freed
+ *     on a stream are reused in that stream's order and kept until the
+ *     process ends or an allocation fails; or the allocator registered with
+ *     ftn_set_allocator).
  *   - Streams: work is enqueued on the given stream. Calls that must know a
  *     data-dependent size (block counts of a new structure, the dims kept by
  *     a truncation) synchronise that stream before returning.
@@ -86,7 +88,7 @@ const char* ftn_version(void);
 
 /* Optional external device allocator (e.g. a framework's caching pool).
    alloc(bytes, stream, ctx) returns device memory or NULL; free(ptr, stream,
-   ctx) releases it. Pass NULLs to restore the built-in stream-ordered pool. */
+   ctx) releases it. Pass NULLs to restore the built-in caching allocator. */
 int ftn_set_allocator(void* (*alloc_fn)(size_t, ftn_stream_t, void*),
                       void (*free_fn)(void*, ftn_stream_t, void*), void* ctx);
 
