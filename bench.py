@@ -144,6 +144,8 @@ def main():
                    "contractions_per_step": 2, "terms": ["norm", "hopping(first edge)"]},
         "ftensordot_useful_tflops": flops / el / 1e12,
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "kernel_rate": {c: (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if c.startswith("gemm") else 1e9))
+                        for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
         "roofline": roof,
     }

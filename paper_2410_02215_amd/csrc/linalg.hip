@@ -64,6 +64,7 @@ struct EigJob {
   double* W;        // n eigenvalues, output (descending)
   double2* rot;     // rotation log: (c, s) per rotation
   int* rpq;         // rotation log: p | q << 16
+  int* rounds;      // optional: number of rounds done
   int n;
   int pad;
 };
@@ -184,6 +185,7 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
     }
   }
   for (int i = tid; i < n; i += LT) ev[i] = A[i][i];
+  if (tid == 0 && J.rounds) J.rounds[0] = nr;
   __syncthreads();
   for (int e = tid; e < n2 * n2; e += LT) {
     const int i = e / n2, j = e % n2;
@@ -502,6 +504,14 @@ static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int
   return g;
 }
 
+// launches timed under the factorisation class of the opt-in profiler
+#define FACTOR_LAUNCH(...)                  \
+  do {                                      \
+    void* tok_ = prof_begin(s);             \
+    LAUNCH(__VA_ARGS__);                    \
+    prof_end(tok_, s, FTN_PROF_FACTOR, 0);  \
+  } while (0)
+
 // per bond sector q
 struct Sect {
   int64_t M, N, d;       // rows of A~, cols of B~, bond dim
@@ -639,7 +649,7 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
       }
     }
     DBuf<OrthJob> doj = to_device(oj, s);
-    LAUNCH(k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
     if (!gt.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Minv.p, Gm, R12.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
@@ -675,8 +685,10 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   std::vector<int> dir, it;
   for (int g = 0; g < ng; ++g)
     if (S[g].ns > 0) (S[g].iterate ? it : dir).push_back(g);
+  static const bool trace = std::getenv("FTN_TRACE") != nullptr;
   if (!dir.empty()) {
     const int nd = (int)dir.size();
+    DBuf<int> drounds(nd, s);
     std::vector<int64_t> log_off(nd);
     int64_t log_n = 0;
     for (int t = 0; t < nd; ++t) {
@@ -694,12 +706,21 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       j.W = Lm + loff[g];
       j.rot = lrot.p + log_off[t];
       j.rpq = lpq.p + log_off[t];
+      j.rounds = trace ? drounds.p + t : nullptr;
       j.n = S[g].ns;
       j.pad = 0;
       ej.push_back(j);
     }
     DBuf<EigJob> dj = to_device(ej, s);
-    LAUNCH(k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
+    FACTOR_LAUNCH(k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
+    if (trace) {
+      std::vector<int> r(nd);
+      HIPC(hipMemcpyAsync(r.data(), drounds.p, nd * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      std::string t;
+      for (int i = 0; i < nd; ++i) t += std::to_string(S[dir[i]].ns) + ":" + std::to_string(r[i]) + " ";
+      std::fprintf(stderr, "[ftn] jacobi order:rounds %s\n", t.c_str());
+    }
   }
   if (it.empty()) return;
   const int ni = (int)it.size();
@@ -715,7 +736,8 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   DBuf<double> Q0(qn, s), Q1(qn, s), Z0(zn, s), Z1(zn, s), Z2(zn, s), Gy(ni * p * p, s), Mm(ni * p * p, s),
       Tr(ni * p * p, s), Zs(ni * p * p, s);
   DBuf<double2> rrot(ni * jacobi_log_len(JMAX), s);
-  DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s);
+  DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s), rr_rounds(ni, s);
+  std::string rr_trace;
   std::vector<GemmGroup> gxt, gx, ggq, ggz, gaq, gaz, ge;
   for (int t = 0; t < ni; ++t) {
     const int g = it[t];
@@ -754,6 +776,7 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
     e.W = Lm + loff[g];
     e.rot = rrot.p + t * jacobi_log_len(JMAX);
     e.rpq = rrpq.p + t * jacobi_log_len(JMAX);
+    e.rounds = trace ? rr_rounds.p + t : nullptr;
     e.n = (int)p;
     e.pad = 0;
     ej.push_back(e);
@@ -764,7 +787,7 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   // y <- orthonormal basis of span(y), dependent columns zeroed
   auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
     run_gemm(gram, FTN_F64, y, y, Gy.p, nullptr, s);
-    LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
     run_gemm(app, FTN_F64, y, Mm.p, yt, nullptr, s);
     std::swap(y, yt);
   };
@@ -773,7 +796,6 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   orth(Pgq, Paq, q, qt);
   std::vector<double> prev, cur(ni * p);
   const int max_iter = 96, check = 8;
-  static const bool trace = std::getenv("FTN_TRACE") != nullptr;
   int iters = 0;
   bool have_next = false;  // z already holds X^T q (computed for the last check)
   for (int k = 1; k <= max_iter; ++k) {
@@ -788,10 +810,13 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       // Rayleigh-Ritz: W = X^T Q, Tr = W^T W = Q^T X X^T Q
       run_gemm(Pxt, FTN_F64, Xm, q, zu, nullptr, s);
       run_gemm(Pgz, FTN_F64, zu, zu, Tr.p, nullptr, s);
-      LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
+      FACTOR_LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
       for (int t = 0; t < ni; ++t)
         HIPC(hipMemcpyAsync(cur.data() + t * p, Lm + loff[it[t]], p * 8, hipMemcpyDeviceToHost, s));
+      std::vector<int> rr(ni);
+      if (trace) HIPC(hipMemcpyAsync(rr.data(), rr_rounds.p, ni * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
+      if (trace) rr_trace += " " + std::to_string(rr[0]);
       bool done = !prev.empty();
       for (int t = 0; t < ni && done; ++t) {
         const int kk = (int)std::min<int64_t>(chi, p);
@@ -801,6 +826,12 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       }
       prev = cur;
       if (done) break;
+      // continue from the Ritz vectors: the next T is then nearly diagonal
+      // and its Jacobi solve converges in a few sweeps
+      run_gemm(Paq, FTN_F64, q, Zs.p, qt, nullptr, s);
+      std::swap(q, qt);
+      run_gemm(Paz, FTN_F64, zu, Zs.p, zt, nullptr, s);
+      std::swap(zu, zt);
       std::swap(z, zu);  // the next half step X^T q is ready
       have_next = true;
     }
@@ -808,7 +839,8 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   if (trace) {
     std::string dd;
     for (int t = 0; t < ni; ++t) dd += std::to_string(S[it[t]].rA) + "x" + std::to_string(S[it[t]].rB) + " ";
-    std::fprintf(stderr, "[ftn] subspace iteration: %d iterations, sectors %s\n", iters, dd.c_str());
+    std::fprintf(stderr, "[ftn] subspace iteration: %d iterations, sectors %s, Rayleigh-Ritz rounds%s\n", iters,
+                 dd.c_str(), rr_trace.c_str());
   }
   run_gemm(Pe, FTN_F64, q, Zs.p, Em, nullptr, s);
 }
