@@ -242,16 +242,37 @@ struct PermTask {
 
 std::vector<int64_t> block_sizes(const Structure& s);
 
-// a ready-to-launch permute: tasks and tile map resident on the device
+// Per-block copy descriptor, built on the device from a task: the block's
+// legs with size 1 removed and neighbours that are contiguous on both sides
+// merged (index 0 = innermost on the block side, block stride 1), and the
+// tiling chosen for it.
+struct PermDesc {
+  int64_t boff;        // block offset on the block side
+  int64_t moff;        // offset on the strided side
+  int64_t sb[MAXD];    // merged legs: block-side strides
+  int64_t ts[MAXD];    // merged legs: strided-side strides
+  int32_t dim[MAXD];   // merged legs: extents
+  int32_t m;           // number of merged legs
+  int32_t y;           // merged leg with strided-side stride 1, or -1
+  int32_t mode;        // 0 rows contiguous on both sides, 1 LDS transpose, 2 per element, 3 nothing
+  int32_t ta, tr;      // tile: extent along leg 0, rows per tile (powers of two)
+  int32_t neg;         // sign bit of the block
+  int64_t nx, nr;      // tiles along leg 0 and along the rows
+  int64_t rows;        // rows: mode 0 all outer positions, mode 1 the extent of leg y
+  int64_t nel;         // entries of the block
+};
+// a ready-to-launch permute: tasks, descriptors and tile map on the device
 struct PermPlan {
   SignOp op;
   DBuf<PermTask> tasks;
+  DBuf<PermDesc> desc;
   DBuf<int64_t> tile_start;
   int64_t ntasks = 0, ntiles = 0;
   int64_t nelem = 0;  // elements moved per run (for the profile)
 };
-// builds the tile map from per-task element counts (synchronises s)
-void perm_plan_tiles(PermPlan& p, const std::vector<int64_t>& task_elems, hipStream_t s);
+// builds descriptors and the tile map for the tasks of the blocks of `st`
+// (synchronises s once, for the tile count)
+void perm_plan_build(PermPlan& p, const Structure& st, hipStream_t s);
 // dir = 0: block -> strided region; dir = 1: strided region -> block.
 // `st` gives the block structure, dtype the element type. No host sync.
 void run_perm(int dir, const Structure& st, int dtype, const PermPlan& p, const void* src, void* dst,

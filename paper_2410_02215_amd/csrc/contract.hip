@@ -302,7 +302,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(A.nblocks(), 128)), dim3(128), 0, s, da,
                          A.S().d_keys.p, A.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pa.tasks.p);
     HIPC(hipGetLastError());
-    perm_plan_tiles(P->pa, block_sizes(A.S()), s);
+    perm_plan_build(P->pa, A.S(), s);
   }
   {
     DBuf<int32_t> dkm = to_device(kfb, s);
@@ -321,7 +321,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       LAUNCH(k_dot_tasks, dim3((unsigned)cdiv(B.nblocks(), 128)), dim3(128), 0, s, db,
                          B.S().d_keys.p, B.nblocks(), dkm.p, d1.p, d2.p, d3.p, dk.p, P->pb.tasks.p);
     HIPC(hipGetLastError());
-    perm_plan_tiles(P->pb, block_sizes(B.S()), s);
+    perm_plan_build(P->pb, B.S(), s);
   }
   // scatter tables + GEMM groups
   std::vector<int64_t> rcs, ccs, ccd, gboff(G, 0);

@@ -3,6 +3,8 @@
 // copies around the grouped GEMM. The sign of every block is computed on the
 // device from the parity bits of its sectors (integer, bit-exact).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -39,114 +41,283 @@ __device__ inline int sign_bit(const SignOp& op, uint32_t P, int extra) {
 }
 
 constexpr int PM_THREADS = 256;
-constexpr int PM_TILE = 2048;  // elements of one block handled by one workgroup
+constexpr int PM_TILE = 2048;  // entries of one workgroup tile
+
+__host__ __device__ inline int pow2ceil(int64_t v) {
+  int p = 1;
+  while (p < v && p < (1 << 30)) p <<= 1;
+  return p;
+}
+
+// one thread per task: strides of both sides, leg merging, tiling, sign
+__global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64_t ntasks,
+                            const int32_t* __restrict__ shapes, const int64_t* __restrict__ offsets,
+                            const uint32_t* __restrict__ parmask, PermDesc* __restrict__ desc,
+                            int64_t* __restrict__ tiles) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const PermTask tk = tasks[t];
+  PermDesc D;
+  D.boff = 0;
+  D.moff = 0;
+  D.m = 0;
+  D.y = -1;
+  D.mode = 3;
+  D.ta = D.tr = 1;
+  D.neg = 0;
+  D.nx = D.nr = D.rows = D.nel = 0;
+  for (int j = 0; j < MAXD; ++j) {
+    D.sb[j] = D.ts[j] = 0;
+    D.dim[j] = 1;
+  }
+  int64_t ntile = 0;
+  if (!tk.skip) {
+    const int64_t b = tk.block;
+    const int n = op.ndim;
+    int32_t d[MAXD];
+    int64_t str[MAXD];
+    for (int j = 0; j < n; ++j) d[j] = shapes[b * n + j];
+    // strided side: segments A | G | B of the destination order (Eq. transposition
+    // order, then the fused-matrix layout of the GEMM operands)
+    const int nA = op.nA, nAG = op.nA + op.nG;
+    int64_t st = 1;
+    for (int p = n - 1; p >= nAG; --p) {
+      str[op.perm[p]] = st;
+      st *= d[op.perm[p]];
+    }
+    int64_t g = 1;
+    for (int p = nAG - 1; p >= nA; --p) {
+      str[op.perm[p]] = tk.bext * g;
+      g *= d[op.perm[p]];
+    }
+    const int64_t gx = tk.gext ? tk.gext : g;
+    st = tk.bext * gx;
+    for (int p = nA - 1; p >= 0; --p) {
+      str[op.perm[p]] = st;
+      st *= d[op.perm[p]];
+    }
+    D.boff = offsets[b];
+    D.moff = tk.moff;
+    D.nel = offsets[b + 1] - offsets[b];
+    D.neg = sign_bit(op, parmask[b], tk.extra);
+    // merge from the innermost block leg outwards; size-1 legs carry nothing
+    int m = 0;
+    int64_t bst = 1;
+    for (int j = n - 1; j >= 0; --j) {
+      if (d[j] == 1) continue;
+      if (m > 0 && str[j] == D.ts[m - 1] * D.dim[m - 1]) {
+        D.dim[m - 1] *= d[j];
+      } else {
+        D.dim[m] = d[j];
+        D.sb[m] = bst;
+        D.ts[m] = str[j];
+        ++m;
+      }
+      bst *= d[j];
+    }
+    if (m == 0) {  // a single entry
+      D.dim[0] = 1;
+      D.sb[0] = 1;
+      D.ts[0] = 1;
+      m = 1;
+    }
+    D.m = m;
+    for (int k = 0; k < m; ++k)
+      if (D.ts[k] == 1) D.y = k;
+    const int64_t dx = D.dim[0];
+    if (D.nel == 0) {
+      D.mode = 3;
+    } else if (D.ts[0] == 1) {  // rows of leg 0 are contiguous on both sides
+      D.mode = 0;
+      D.rows = D.nel / dx;
+      D.ta = max(2, min(pow2ceil(dx), 256));
+      D.tr = PM_TILE / D.ta;
+      D.nx = (dx + D.ta - 1) / D.ta;
+      D.nr = (D.rows + D.tr - 1) / D.tr;
+      ntile = D.nx * D.nr;
+    } else if (D.y > 0) {  // transpose leg 0 against leg y through LDS
+      D.mode = 1;
+      const int64_t dy = D.dim[D.y];
+      D.rows = dy;
+      D.ta = min(pow2ceil(dx), 256);
+      D.tr = min(pow2ceil(dy), PM_TILE / D.ta);
+      if (D.ta * D.tr < PM_TILE) D.ta = min(pow2ceil(dx), PM_TILE / D.tr);
+      D.nx = (dx + D.ta - 1) / D.ta;
+      D.nr = (dy + D.tr - 1) / D.tr;
+      ntile = (D.nel / (dx * dy)) * D.nx * D.nr;
+    } else {
+      D.mode = 2;
+      ntile = (D.nel + PM_TILE - 1) / PM_TILE;
+    }
+  }
+  desc[t] = D;
+  tiles[t] = ntile;
+}
 
 template <typename T, int DIR>
 __global__ void __launch_bounds__(PM_THREADS)
-    k_block_matrix(SignOp op, const PermTask* __restrict__ tasks, const int64_t* __restrict__ tile_start,
-                   int64_t ntasks, const int32_t* __restrict__ shapes, const int64_t* __restrict__ offsets,
-                   const uint32_t* __restrict__ parmask, const T* __restrict__ src, T* __restrict__ dst,
-                   T alpha) {
-  __shared__ int64_t s_str[MAXD];
-  __shared__ int32_t s_dim[MAXD];
-  __shared__ int64_t s_info[4];  // task, block offset, nelem, moff
-  __shared__ T s_val;
-  const int64_t tile = blockIdx.x;
+    k_block_perm(const PermDesc* __restrict__ desc, const int64_t* __restrict__ tile_start, int64_t ntasks,
+                 const T* __restrict__ src, T* __restrict__ dst, T alpha) {
+  __shared__ T tile[PM_TILE + PM_TILE / 2];  // tr x (ta + 1), tr <= PM_TILE / 2
+  __shared__ int64_t rbase[PM_TILE / 2];
+  __shared__ PermDesc D;
+  __shared__ int64_t s_task, s_bb, s_sb;
+  const int64_t tl = blockIdx.x;
   if (threadIdx.x == 0) {
     int64_t lo = 0, hi = ntasks - 1;
     while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if (tile_start[mid] <= tile)
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= tl)
         lo = mid;
       else
         hi = mid - 1;
     }
-    const PermTask tk = tasks[lo];
-    s_info[0] = tk.skip ? -1 : lo;
-    if (!tk.skip) {
-      const int64_t b = tk.block;
-      const int n = op.ndim;
-      for (int j = 0; j < n; ++j) s_dim[j] = shapes[b * n + j];
-      // strides of the strided side, per destination position, then per leg
-      const int nA = op.nA, nAG = op.nA + op.nG;
-      int64_t st = 1;
-      for (int p = n - 1; p >= nAG; --p) {
-        s_str[op.perm[p]] = st;
-        st *= s_dim[op.perm[p]];
-      }
-      st = tk.bext;
-      int64_t g = 1;
-      for (int p = nAG - 1; p >= nA; --p) {
-        s_str[op.perm[p]] = st * g;
-        g *= s_dim[op.perm[p]];
-      }
-      int64_t gx = tk.gext ? tk.gext : g;
-      st = tk.bext * gx;
-      for (int p = nA - 1; p >= 0; --p) {
-        s_str[op.perm[p]] = st;
-        st *= s_dim[op.perm[p]];
-      }
-      s_info[1] = offsets[b];
-      s_info[2] = offsets[b + 1] - offsets[b];
-      s_info[3] = tk.moff;
-      int e = sign_bit(op, parmask[b], tk.extra);
-      s_val = e ? -alpha : alpha;
-    }
+    s_task = lo;
   }
   __syncthreads();
-  if (s_info[0] < 0) return;
-  const int n = op.ndim;
-  const int64_t first = (tile - tile_start[s_info[0]]) * PM_TILE;
-  const int64_t nel = s_info[2];
-  const int64_t boff = s_info[1], moff = s_info[3];
-  const T v = s_val;
-  for (int j = threadIdx.x; j < PM_TILE; j += PM_THREADS) {
-    int64_t e = first + j;
-    if (e >= nel) break;
-    uint32_t r = (uint32_t)e;  // one block stays below 2^32 entries
-    int64_t addr = moff;
-    for (int d = n - 1; d >= 0; --d) {
-      uint32_t dd = (uint32_t)s_dim[d];
-      uint32_t q = r / dd;
-      addr += (int64_t)(r - q * dd) * s_str[d];
-      r = q;
+  {
+    const int* srcw = (const int*)(desc + s_task);
+    int* dstw = (int*)&D;
+    for (int w = threadIdx.x; w < (int)(sizeof(PermDesc) / sizeof(int)); w += PM_THREADS) dstw[w] = srcw[w];
+  }
+  __syncthreads();
+  const int64_t lt = tl - tile_start[s_task];
+  const T v = D.neg ? -alpha : alpha;
+  const int ta = D.ta, tr = D.tr;
+  const int lta = __ffs(ta) - 1;  // ta, tr are powers of two
+  if (D.mode == 0) {
+    const int64_t ix = lt % D.nx, ir = lt / D.nx;
+    const int64_t x0 = ix * ta, r0 = ir * tr, dx = D.dim[0];
+    // strided-side base of each row of the tile (rows enumerate legs 1..m-1)
+    for (int r = threadIdx.x; r < tr; r += PM_THREADS) {
+      int64_t q = r0 + r, a = 0;
+      for (int k = 1; k < D.m; ++k) {
+        const int64_t dk = D.dim[k];
+        a += (q % dk) * D.ts[k];
+        q /= dk;
+      }
+      rbase[r] = a;
     }
-    if (DIR == 0)
-      dst[addr] = v * src[boff + e];
-    else
-      dst[boff + e] = v * src[addr];
+    __syncthreads();
+    for (int e = threadIdx.x; e < PM_TILE; e += PM_THREADS) {
+      const int r = e >> lta, i = e & (ta - 1);
+      const int64_t row = r0 + r, x = x0 + i;
+      if (row >= D.rows || x >= dx) continue;
+      const int64_t bi = D.boff + row * dx + x, si = D.moff + rbase[r] + x;
+      if (DIR == 0)
+        dst[si] = v * src[bi];
+      else
+        dst[bi] = v * src[si];
+    }
+  } else if (D.mode == 1) {
+    const int y = D.y;
+    const int64_t per = D.nx * D.nr;
+    const int64_t bt = lt / per, rem = lt % per;
+    const int64_t ix = rem % D.nx, ir = rem / D.nx;
+    const int64_t x0 = ix * ta, y0 = ir * tr, dx = D.dim[0], dy = D.dim[y];
+    if (threadIdx.x == 0) {  // batch position over the legs other than 0 and y
+      int64_t q = bt, bb = 0, sbb = 0;
+      for (int k = 1; k < D.m; ++k) {
+        if (k == y) continue;
+        const int64_t dk = D.dim[k];
+        const int64_t ik = q % dk;
+        q /= dk;
+        bb += ik * D.sb[k];
+        sbb += ik * D.ts[k];
+      }
+      s_bb = bb;
+      s_sb = sbb;
+    }
+    __syncthreads();
+    const int64_t bbase = D.boff + s_bb, sbase = D.moff + s_sb;
+    const int64_t sby = D.sb[y], tsx = D.ts[0];
+    const int ld = ta + 1, ltr = __ffs(tr) - 1, n = ta * tr;
+    // the block side is walked with leg 0 fastest, the strided side with leg y
+    if (DIR == 0) {
+      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        const int r = e >> lta, i = e & (ta - 1);
+        const int64_t yy = y0 + r, x = x0 + i;
+        if (yy < dy && x < dx) tile[r * ld + i] = v * src[bbase + yy * sby + x];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        const int r = e & (tr - 1), i = e >> ltr;
+        const int64_t yy = y0 + r, x = x0 + i;
+        if (yy < dy && x < dx) dst[sbase + yy + x * tsx] = tile[r * ld + i];
+      }
+    } else {
+      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        const int r = e & (tr - 1), i = e >> ltr;
+        const int64_t yy = y0 + r, x = x0 + i;
+        if (yy < dy && x < dx) tile[r * ld + i] = v * src[sbase + yy + x * tsx];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        const int r = e >> lta, i = e & (ta - 1);
+        const int64_t yy = y0 + r, x = x0 + i;
+        if (yy < dy && x < dx) dst[bbase + yy * sby + x] = tile[r * ld + i];
+      }
+    }
+  } else if (D.mode == 2) {
+    const int64_t first = lt * PM_TILE;
+    for (int j = threadIdx.x; j < PM_TILE; j += PM_THREADS) {
+      const int64_t e = first + j;
+      if (e >= D.nel) break;
+      int64_t q = e, a = 0;
+      for (int k = 0; k < D.m; ++k) {
+        const int64_t dk = D.dim[k];
+        a += (q % dk) * D.ts[k];
+        q /= dk;
+      }
+      if (DIR == 0)
+        dst[D.moff + a] = v * src[D.boff + e];
+      else
+        dst[D.boff + e] = v * src[D.moff + a];
+    }
   }
 }
 
-void perm_plan_tiles(PermPlan& p, const std::vector<int64_t>& task_elems, hipStream_t s) {
-  p.ntasks = (int64_t)task_elems.size();
-  std::vector<int64_t> ts(p.ntasks);
-  int64_t tiles = 0;
-  p.nelem = 0;
-  for (int64_t k = 0; k < p.ntasks; ++k) {
-    ts[k] = tiles;
-    tiles += cdiv(task_elems[k], PM_TILE);
-    p.nelem += task_elems[k];
-  }
-  if (tiles > 0x7fffffffLL) fail(FTN_EINVAL, "permute too large");
-  p.ntiles = tiles;
-  p.tile_start = persist_upload(ts, s);
+void perm_plan_build(PermPlan& p, const Structure& S, hipStream_t s) {
+  p.ntasks = S.nblocks;
+  p.nelem = S.size;
+  p.ntiles = 0;
+  if (!p.ntasks) return;
+  p.desc = persist<PermDesc>(p.ntasks);
+  p.tile_start = persist<int64_t>(p.ntasks);
+  DBuf<int64_t> total(1, s);
+  LAUNCH(k_perm_desc, dim3((unsigned)cdiv(p.ntasks, 128)), dim3(128), 0, s, p.op, p.tasks.p, p.ntasks,
+         S.d_shapes.p, S.d_offsets.p, S.d_parmask.p, p.desc.p, p.tile_start.p);
+  scan_exclusive(p.tile_start.p, p.ntasks, total.p, s);
+  int64_t tot = 0;
+  HIPC(hipMemcpyAsync(&tot, total.p, 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  if (tot > 0x7fffffffLL) fail(FTN_EINVAL, "permute too large");
+  p.ntiles = tot;
 }
 
 void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const void* src, void* dst,
               hipStream_t s, double alpha) {
   if (p.ntiles == 0) return;
+  static const bool trace = std::getenv("FTN_TRACE_PERM") != nullptr;
+  if (trace) {
+    int64_t big = 0;
+    for (int64_t b = 1; b < S.nblocks; ++b)
+      if (S.offsets[b + 1] - S.offsets[b] > S.offsets[big + 1] - S.offsets[big]) big = b;
+    std::string sh, pm;
+    for (int j = 0; j < S.ndim; ++j) sh += std::to_string(S.shapes[big * S.ndim + j]) + " ";
+    for (int j = 0; j < p.op.ndim; ++j) pm += std::to_string(p.op.perm[j]) + " ";
+    std::fprintf(stderr, "[perm] dir %d nel %lld nblocks %lld nA %d nG %d perm [%s] biggest [%s]\n", dir,
+                 (long long)p.nelem, (long long)S.nblocks, p.op.nA, p.op.nG, pm.c_str(), sh.c_str());
+  }
   void* tok = prof_begin(s);
+  const dim3 grid((unsigned)p.ntiles), block(PM_THREADS);
   if (dtype == FTN_F64) {
-    auto k = dir == 0 ? k_block_matrix<double, 0> : k_block_matrix<double, 1>;
-    LAUNCH(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
-                       p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
-                       (const double*)src, (double*)dst, alpha);
+    auto k = dir == 0 ? k_block_perm<double, 0> : k_block_perm<double, 1>;
+    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.ntasks, (const double*)src, (double*)dst, alpha);
   } else {
-    auto k = dir == 0 ? k_block_matrix<float, 0> : k_block_matrix<float, 1>;
-    LAUNCH(k, dim3((unsigned)p.ntiles), dim3(PM_THREADS), 0, s, p.op, p.tasks.p,
-                       p.tile_start.p, p.ntasks, S.d_shapes.p, S.d_offsets.p, S.d_parmask.p,
-                       (const float*)src, (float*)dst, (float)alpha);
+    auto k = dir == 0 ? k_block_perm<float, 0> : k_block_perm<float, 1>;
+    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.ntasks, (const float*)src, (float*)dst,
+           (float)alpha);
   }
   HIPC(hipGetLastError());
   prof_end(tok, s, FTN_PROF_PERMUTE, 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4));
@@ -255,7 +426,7 @@ static std::unique_ptr<Tensor> unary_signed(const Tensor& a, const std::vector<L
     U->pp.op = op;
     unary_tasks(a.S(), *U->out, op, remap, rbase, U->pp.tasks, s);
     if (U->out->size != a.size()) fail(FTN_EINVAL, "internal: unary permute changed the size");
-    perm_plan_tiles(U->pp, block_sizes(a.S()), s);
+    perm_plan_build(U->pp, a.S(), s);
     std::lock_guard<std::mutex> g(g_unary_mu);
     if (g_unary->size() > 8192) g_unary->clear();
     g_unary->emplace(key, U);
@@ -486,7 +657,7 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
   U->out = out->st;
   U->pp.op = op;
   U->pp.tasks = persist_upload(tasks, s);
-  perm_plan_tiles(U->pp, block_sizes(A), s);
+  perm_plan_build(U->pp, A, s);
   run_perm(0, A, a.dtype, U->pp, a.data, out->data, s);
   std::lock_guard<std::mutex> g(g_unary_mu);
   if (g_unary->size() > 8192) g_unary->clear();
