@@ -260,6 +260,7 @@ struct PermDesc {
   int64_t nx, nr;      // tiles along leg 0 and along the rows
   int64_t rows;        // rows: mode 0 all outer positions, mode 1 the extent of leg y
   int64_t nel;         // entries of the block
+  int64_t nsub;        // sub-tiles of the block (a workgroup takes up to PM_SUB)
 };
 // a ready-to-launch permute: tasks, descriptors and tile map on the device
 struct PermPlan {
@@ -267,6 +268,7 @@ struct PermPlan {
   DBuf<PermTask> tasks;
   DBuf<PermDesc> desc;
   DBuf<int64_t> tile_start;
+  DBuf<int32_t> tile_task;  // task of each tile
   int64_t ntasks = 0, ntiles = 0;
   int64_t nelem = 0;  // elements moved per run (for the profile)
 };

@@ -41,7 +41,8 @@ __device__ inline int sign_bit(const SignOp& op, uint32_t P, int extra) {
 }
 
 constexpr int PM_THREADS = 256;
-constexpr int PM_TILE = 2048;  // entries of one workgroup tile
+constexpr int PM_TILE = 2048;  // entries of one sub-tile
+constexpr int PM_SUB = 4;      // consecutive sub-tiles of one block per workgroup
 
 __host__ __device__ inline int pow2ceil(int64_t v) {
   int p = 1;
@@ -65,7 +66,7 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
   D.mode = 3;
   D.ta = D.tr = 1;
   D.neg = 0;
-  D.nx = D.nr = D.rows = D.nel = 0;
+  D.nx = D.nr = D.rows = D.nel = D.nsub = 0;
   for (int j = 0; j < MAXD; ++j) {
     D.sb[j] = D.ts[j] = 0;
     D.dim[j] = 1;
@@ -139,7 +140,9 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
       D.mode = 1;
       const int64_t dy = D.dim[D.y];
       D.rows = dy;
-      D.ta = min(pow2ceil(dx), 256);
+      // both walks should cover whole 256-byte runs: at most 64 along leg 0
+      // unless leg y is too short to fill the tile
+      D.ta = min(pow2ceil(dx), 64);
       D.tr = min(pow2ceil(dy), PM_TILE / D.ta);
       if (D.ta * D.tr < PM_TILE) D.ta = min(pow2ceil(dx), PM_TILE / D.tr);
       D.nx = (dx + D.ta - 1) / D.ta;
@@ -150,30 +153,40 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
       ntile = (D.nel + PM_TILE - 1) / PM_TILE;
     }
   }
+  D.nsub = ntile;
   desc[t] = D;
-  tiles[t] = ntile;
+  tiles[t] = (ntile + PM_SUB - 1) / PM_SUB;
+}
+
+// task of every tile (once per plan)
+__global__ void k_tile_task(const int64_t* __restrict__ tile_start, int64_t ntasks, int64_t ntiles,
+                            int32_t* __restrict__ tile_task) {
+  const int64_t tl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tl >= ntiles) return;
+  int64_t lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= tl)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  tile_task[tl] = (int32_t)lo;
 }
 
 template <typename T, int DIR>
 __global__ void __launch_bounds__(PM_THREADS)
-    k_block_perm(const PermDesc* __restrict__ desc, const int64_t* __restrict__ tile_start, int64_t ntasks,
-                 const T* __restrict__ src, T* __restrict__ dst, T alpha) {
-  __shared__ T tile[PM_TILE + PM_TILE / 2];  // tr x (ta + 1), tr <= PM_TILE / 2
-  __shared__ int64_t rbase[PM_TILE / 2];
+    k_block_perm(const PermDesc* __restrict__ desc, const int64_t* __restrict__ tile_start,
+                 const int32_t* __restrict__ tile_task, const T* __restrict__ src, T* __restrict__ dst,
+                 T alpha) {
+  // transpose staging (tr x (ta + 1) entries, tr <= PM_TILE / 2) or row bases
+  __shared__ double smem[PM_TILE + PM_TILE / 2];
   __shared__ PermDesc D;
   __shared__ int64_t s_task, s_bb, s_sb;
+  T* tile = (T*)smem;
+  int64_t* rbase = (int64_t*)smem;
   const int64_t tl = blockIdx.x;
-  if (threadIdx.x == 0) {
-    int64_t lo = 0, hi = ntasks - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (tile_start[mid] <= tl)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    s_task = lo;
-  }
+  if (threadIdx.x == 0) s_task = tile_task[tl];
   __syncthreads();
   {
     const int* srcw = (const int*)(desc + s_task);
@@ -181,99 +194,104 @@ __global__ void __launch_bounds__(PM_THREADS)
     for (int w = threadIdx.x; w < (int)(sizeof(PermDesc) / sizeof(int)); w += PM_THREADS) dstw[w] = srcw[w];
   }
   __syncthreads();
-  const int64_t lt = tl - tile_start[s_task];
+  const int64_t first = (tl - tile_start[s_task]) * PM_SUB;
   const T v = D.neg ? -alpha : alpha;
   const int ta = D.ta, tr = D.tr;
-  const int lta = __ffs(ta) - 1;  // ta, tr are powers of two
-  if (D.mode == 0) {
-    const int64_t ix = lt % D.nx, ir = lt / D.nx;
-    const int64_t x0 = ix * ta, r0 = ir * tr, dx = D.dim[0];
-    // strided-side base of each row of the tile (rows enumerate legs 1..m-1)
-    for (int r = threadIdx.x; r < tr; r += PM_THREADS) {
-      int64_t q = r0 + r, a = 0;
-      for (int k = 1; k < D.m; ++k) {
-        const int64_t dk = D.dim[k];
-        a += (q % dk) * D.ts[k];
-        q /= dk;
-      }
-      rbase[r] = a;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < PM_TILE; e += PM_THREADS) {
-      const int r = e >> lta, i = e & (ta - 1);
-      const int64_t row = r0 + r, x = x0 + i;
-      if (row >= D.rows || x >= dx) continue;
-      const int64_t bi = D.boff + row * dx + x, si = D.moff + rbase[r] + x;
-      if (DIR == 0)
-        dst[si] = v * src[bi];
-      else
-        dst[bi] = v * src[si];
-    }
-  } else if (D.mode == 1) {
-    const int y = D.y;
-    const int64_t per = D.nx * D.nr;
-    const int64_t bt = lt / per, rem = lt % per;
-    const int64_t ix = rem % D.nx, ir = rem / D.nx;
-    const int64_t x0 = ix * ta, y0 = ir * tr, dx = D.dim[0], dy = D.dim[y];
-    if (threadIdx.x == 0) {  // batch position over the legs other than 0 and y
-      int64_t q = bt, bb = 0, sbb = 0;
-      for (int k = 1; k < D.m; ++k) {
-        if (k == y) continue;
-        const int64_t dk = D.dim[k];
-        const int64_t ik = q % dk;
-        q /= dk;
-        bb += ik * D.sb[k];
-        sbb += ik * D.ts[k];
-      }
-      s_bb = bb;
-      s_sb = sbb;
-    }
-    __syncthreads();
-    const int64_t bbase = D.boff + s_bb, sbase = D.moff + s_sb;
-    const int64_t sby = D.sb[y], tsx = D.ts[0];
-    const int ld = ta + 1, ltr = __ffs(tr) - 1, n = ta * tr;
-    // the block side is walked with leg 0 fastest, the strided side with leg y
-    if (DIR == 0) {
-      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
-        const int r = e >> lta, i = e & (ta - 1);
-        const int64_t yy = y0 + r, x = x0 + i;
-        if (yy < dy && x < dx) tile[r * ld + i] = v * src[bbase + yy * sby + x];
+  const int lta = __ffs(ta) - 1, ltr = __ffs(tr) - 1;  // ta, tr are powers of two
+  for (int k = 0; k < PM_SUB; ++k) {
+    const int64_t lt = first + k;
+    if (lt >= D.nsub) break;
+    if (D.mode == 0) {
+      const int64_t ix = lt % D.nx, ir = lt / D.nx;
+      const int64_t x0 = ix * ta, r0 = ir * tr, dx = D.dim[0];
+      // strided-side base of each row of the sub-tile (rows enumerate legs 1..m-1)
+      for (int r = threadIdx.x; r < tr; r += PM_THREADS) {
+        int64_t q = r0 + r, a = 0;
+        for (int j = 1; j < D.m; ++j) {
+          const int64_t dj = D.dim[j];
+          a += (q % dj) * D.ts[j];
+          q /= dj;
+        }
+        rbase[r] = a;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
-        const int r = e & (tr - 1), i = e >> ltr;
-        const int64_t yy = y0 + r, x = x0 + i;
-        if (yy < dy && x < dx) dst[sbase + yy + x * tsx] = tile[r * ld + i];
+      for (int e = threadIdx.x; e < PM_TILE; e += PM_THREADS) {
+        const int r = e >> lta, i = e & (ta - 1);
+        const int64_t row = r0 + r, x = x0 + i;
+        if (row >= D.rows || x >= dx) continue;
+        const int64_t bi = D.boff + row * dx + x, si = D.moff + rbase[r] + x;
+        if (DIR == 0)
+          dst[si] = v * src[bi];
+        else
+          dst[bi] = v * src[si];
       }
-    } else {
-      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
-        const int r = e & (tr - 1), i = e >> ltr;
-        const int64_t yy = y0 + r, x = x0 + i;
-        if (yy < dy && x < dx) tile[r * ld + i] = v * src[sbase + yy + x * tsx];
+    } else if (D.mode == 1) {
+      const int y = D.y;
+      const int64_t per = D.nx * D.nr;
+      const int64_t bt = lt / per, rem = lt % per;
+      const int64_t ix = rem % D.nx, ir = rem / D.nx;
+      const int64_t x0 = ix * ta, y0 = ir * tr, dx = D.dim[0], dy = D.dim[y];
+      if (threadIdx.x == 0) {  // batch position over the legs other than 0 and y
+        int64_t q = bt, bb = 0, sbb = 0;
+        for (int j = 1; j < D.m; ++j) {
+          if (j == y) continue;
+          const int64_t dj = D.dim[j];
+          const int64_t ij = q % dj;
+          q /= dj;
+          bb += ij * D.sb[j];
+          sbb += ij * D.ts[j];
+        }
+        s_bb = bb;
+        s_sb = sbb;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < n; e += PM_THREADS) {
-        const int r = e >> lta, i = e & (ta - 1);
-        const int64_t yy = y0 + r, x = x0 + i;
-        if (yy < dy && x < dx) dst[bbase + yy * sby + x] = tile[r * ld + i];
+      const int64_t bbase = D.boff + s_bb, sbase = D.moff + s_sb;
+      const int64_t sby = D.sb[y], tsx = D.ts[0];
+      const int ld = ta + 1, n = ta * tr;
+      // the block side is walked with leg 0 fastest, the strided side with leg y
+      if (DIR == 0) {
+        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+          const int r = e >> lta, i = e & (ta - 1);
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (yy < dy && x < dx) tile[r * ld + i] = v * src[bbase + yy * sby + x];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+          const int r = e & (tr - 1), i = e >> ltr;
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (yy < dy && x < dx) dst[sbase + yy + x * tsx] = tile[r * ld + i];
+        }
+      } else {
+        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+          const int r = e & (tr - 1), i = e >> ltr;
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (yy < dy && x < dx) tile[r * ld + i] = v * src[sbase + yy + x * tsx];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+          const int r = e >> lta, i = e & (ta - 1);
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (yy < dy && x < dx) dst[bbase + yy * sby + x] = tile[r * ld + i];
+        }
+      }
+    } else if (D.mode == 2) {
+      const int64_t e0 = lt * PM_TILE;
+      for (int j = threadIdx.x; j < PM_TILE; j += PM_THREADS) {
+        const int64_t e = e0 + j;
+        if (e >= D.nel) break;
+        int64_t q = e, a = 0;
+        for (int i = 0; i < D.m; ++i) {
+          const int64_t di = D.dim[i];
+          a += (q % di) * D.ts[i];
+          q /= di;
+        }
+        if (DIR == 0)
+          dst[D.moff + a] = v * src[D.boff + e];
+        else
+          dst[D.boff + e] = v * src[D.moff + a];
       }
     }
-  } else if (D.mode == 2) {
-    const int64_t first = lt * PM_TILE;
-    for (int j = threadIdx.x; j < PM_TILE; j += PM_THREADS) {
-      const int64_t e = first + j;
-      if (e >= D.nel) break;
-      int64_t q = e, a = 0;
-      for (int k = 0; k < D.m; ++k) {
-        const int64_t dk = D.dim[k];
-        a += (q % dk) * D.ts[k];
-        q /= dk;
-      }
-      if (DIR == 0)
-        dst[D.moff + a] = v * src[D.boff + e];
-      else
-        dst[D.boff + e] = v * src[D.moff + a];
-    }
+    __syncthreads();  // the staging buffer is reused by the next sub-tile
   }
 }
 
@@ -293,6 +311,11 @@ void perm_plan_build(PermPlan& p, const Structure& S, hipStream_t s) {
   HIPC(hipStreamSynchronize(s));
   if (tot > 0x7fffffffLL) fail(FTN_EINVAL, "permute too large");
   p.ntiles = tot;
+  if (tot > 0) {
+    p.tile_task = persist<int32_t>(tot);
+    LAUNCH(k_tile_task, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, p.tile_start.p, p.ntasks, tot,
+           p.tile_task.p);
+  }
 }
 
 void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const void* src, void* dst,
@@ -313,10 +336,10 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
   const dim3 grid((unsigned)p.ntiles), block(PM_THREADS);
   if (dtype == FTN_F64) {
     auto k = dir == 0 ? k_block_perm<double, 0> : k_block_perm<double, 1>;
-    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.ntasks, (const double*)src, (double*)dst, alpha);
+    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.tile_task.p, (const double*)src, (double*)dst, alpha);
   } else {
     auto k = dir == 0 ? k_block_perm<float, 0> : k_block_perm<float, 1>;
-    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.ntasks, (const float*)src, (float*)dst,
+    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.tile_task.p, (const float*)src, (float*)dst,
            (float)alpha);
   }
   HIPC(hipGetLastError());
