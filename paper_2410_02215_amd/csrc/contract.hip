@@ -402,6 +402,8 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   P->sc.boff = P->boff.p;
   gemm_plan(P->gp, groups, gemm, s, true);
   P->flops = gemm_flops(groups);
+  // cached plans may be used on other streams: finish building them here
+  HIPC(hipStreamSynchronize(s));
   return P;
 }
 

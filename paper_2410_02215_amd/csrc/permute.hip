@@ -450,6 +450,7 @@ static std::unique_ptr<Tensor> unary_signed(const Tensor& a, const std::vector<L
     unary_tasks(a.S(), *U->out, op, remap, rbase, U->pp.tasks, s);
     if (U->out->size != a.size()) fail(FTN_EINVAL, "internal: unary permute changed the size");
     perm_plan_build(U->pp, a.S(), s);
+    HIPC(hipStreamSynchronize(s));  // cached plans may be used on other streams
     std::lock_guard<std::mutex> g(g_unary_mu);
     if (g_unary->size() > 8192) g_unary->clear();
     g_unary->emplace(key, U);
@@ -681,6 +682,7 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
   U->pp.op = op;
   U->pp.tasks = persist_upload(tasks, s);
   perm_plan_build(U->pp, A, s);
+  HIPC(hipStreamSynchronize(s));  // cached plans may be used on other streams
   run_perm(0, A, a.dtype, U->pp, a.data, out->data, s);
   std::lock_guard<std::mutex> g(g_unary_mu);
   if (g_unary->size() > 8192) g_unary->clear();

@@ -213,6 +213,34 @@ def test_compress_mixed_sector_sizes(P, dims):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
 
 
+def test_concurrent_contractions_on_two_streams(P):
+    # two independent approximate contractions issued from two host threads on
+    # two streams give exactly the results of running them one after another
+    import threading
+    from paper_2410_02215_amd import peps as GP
+    cfg = W.c2(n_sites=12, chi=24)
+    spec = cfg["spec"]
+    kets = GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
+    op = GP.operator_tensor(spec, operator_dense("hop", "Z2"))
+    nets = [GP.norm_network(spec, kets), GP.norm_network(spec, kets, op=op, op_sites=cfg["op_sites"])]
+    paths = [W.norm_path(spec, chi=24, seed=1), W.norm_path(spec, chi=24, seed=1, op_sites=cfg["op_sites"])]
+    serial = [nets[k].contract(paths[k], chi=24)[:2] for k in range(2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = [None, None]
+
+    def run(k):
+        with torch.cuda.stream(streams[k]):
+            for _ in range(3):
+                out[k] = nets[k].contract(paths[k], chi=24)[:2]
+
+    th = threading.Thread(target=run, args=(1,))
+    th.start()
+    run(0)
+    th.join()
+    torch.cuda.synchronize()
+    assert out == serial
+
+
 def test_c2_full_size_norm_and_hopping(P):
     # the full 40-site workload against the stored oracle values
     import json, os
