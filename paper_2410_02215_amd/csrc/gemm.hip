@@ -75,7 +75,7 @@ struct EpiTab {
 template <int BM, int BN>
 __device__ inline void build_epi(EpiTab<BM, BN>& e, const GemmGroup& G, const GemmScatter& sc,
                                  int64_t m0, int64_t n0) {
-  for (int r = threadIdx.x; r < BM; r += GT) {
+  for (int r = threadIdx.x; r < BM; r += blockDim.x) {
     int64_t m = m0 + r;
     if (m < G.M) {
       int fi = upper_index(sc.rc_start + G.rc_base, G.nrc, m);
@@ -83,7 +83,7 @@ __device__ inline void build_epi(EpiTab<BM, BN>& e, const GemmGroup& G, const Ge
       e.rlr[r] = m - sc.rc_start[G.rc_base + fi];
     }
   }
-  for (int c = threadIdx.x; c < BN; c += GT) {
+  for (int c = threadIdx.x; c < BN; c += blockDim.x) {
     int64_t n = n0 + c;
     if (n < G.N) {
       int gj = upper_index(sc.cc_start + G.cc_base, G.ncc, n);
@@ -130,13 +130,13 @@ struct MfmaOp<float> {
 
 
 template <typename T, int BM, int BN, int WGM, int WGN>
-__global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__ A, const T* __restrict__ B,
+__global__ void __launch_bounds__(64 * WGM * WGN) k_gemm(GemmLaunch L, const T* __restrict__ A, const T* __restrict__ B,
                                              T* __restrict__ C, T* __restrict__ Wk) {
-  static_assert(WGM * WGN == GT / 64, "four waves");
+  constexpr int NT = 64 * WGM * WGN;  // threads
   typedef typename MfmaOp<T>::acc_t acc_t;
   constexpr int WM = BM / WGM, WN = BN / WGN;  // per-wave tile
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int NA = BM * GBK / GT, NB = BN * GBK / GT;
+  constexpr int NA = BM * GBK / NT, NB = BN * GBK / NT;
   static_assert(TM >= 1 && TN >= 1 && NA >= 1 && NB >= 1, "tile shape");
   __shared__ T As[2][GBK][BM + 1];
   __shared__ T Bs[2][GBK][BN + 1];
@@ -154,40 +154,81 @@ __global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__
   const T* Ag = A + G.a_off;
   const T* Bg = B + G.b_off;
 
+  // Operand loaders. A thread's share of the A slice is NA entries e = tid +
+  // NT u: either 16 consecutive k of rows tid / 16 + 16 u (A row-major along k)
+  // or consecutive m of k-rows tid / BM + (NT / BM) u (A stored transposed);
+  // B likewise. Each entry is base + u su + kt sk; the masks for the fixed
+  // dimension are computed once, and out-of-range entries load a valid
+  // address and are zeroed (no branches in the K loop).
+  const int t = threadIdx.x;
+  int64_t a_base, a_su, a_sk, b_base, b_su, b_sk;
+  int a_k0, a_ku, a_l0, a_lu, b_k0, b_ku, b_l0, b_lu;  // k of entry u, LDS column of entry u
+  uint32_t a_ok = 0, b_ok = 0;
+  if (!G.transA) {
+    a_base = (m0 + t / GBK) * G.lda + t % GBK;
+    a_su = (int64_t)(NT / GBK) * G.lda;
+    a_sk = GBK;
+    a_k0 = t % GBK;
+    a_ku = 0;
+    a_l0 = t / GBK;
+    a_lu = NT / GBK;
+#pragma unroll
+    for (int u = 0; u < NA; ++u)
+      if (m0 + a_l0 + a_lu * u < G.M) a_ok |= 1u << u;
+  } else {
+    a_base = (int64_t)(t / BM) * G.lda + m0 + t % BM;
+    a_su = (int64_t)(NT / BM) * G.lda;
+    a_sk = (int64_t)GBK * G.lda;
+    a_k0 = t / BM;
+    a_ku = NT / BM;
+    a_l0 = t % BM;
+    a_lu = 0;
+    if (m0 + a_l0 < G.M) a_ok = ~0u;
+  }
+  if (!G.transB) {
+    b_base = (int64_t)(t / BN) * G.ldb + n0 + t % BN;
+    b_su = (int64_t)(NT / BN) * G.ldb;
+    b_sk = (int64_t)GBK * G.ldb;
+    b_k0 = t / BN;
+    b_ku = NT / BN;
+    b_l0 = t % BN;
+    b_lu = 0;
+    if (n0 + b_l0 < G.N) b_ok = ~0u;
+  } else {
+    b_base = (n0 + t / GBK) * G.ldb + t % GBK;
+    b_su = (int64_t)(NT / GBK) * G.ldb;
+    b_sk = GBK;
+    b_k0 = t % GBK;
+    b_ku = 0;
+    b_l0 = t / GBK;
+    b_lu = NT / GBK;
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (n0 + b_l0 + b_lu * u < G.N) b_ok |= 1u << u;
+  }
   T ra[NA], rb[NB];
-  auto fetch = [&](int64_t k0) {
+  auto fetch = [&](int64_t kt) {
+    const int64_t k0 = kt * GBK;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + GT * u;
-      const int mm = G.transA ? e % BM : e / GBK, kk = G.transA ? e / BM : e % GBK;
-      const int64_t m = m0 + mm, k = k0 + kk;
-      T v = T(0);
-      if (m < G.M && k < G.K) v = G.transA ? Ag[k * G.lda + m] : Ag[m * G.lda + k];
-      ra[u] = v;
+      const bool ok = ((a_ok >> u) & 1u) && (k0 + a_k0 + a_ku * u < G.K);
+      const int64_t off = a_base + u * a_su + kt * a_sk;
+      const T v = Ag[ok ? off : 0];
+      ra[u] = ok ? v : T(0);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int e = threadIdx.x + GT * u;
-      const int nn = G.transB ? e / GBK : e % BN, kk = G.transB ? e % GBK : e / BN;
-      const int64_t k = k0 + kk, n = n0 + nn;
-      T v = T(0);
-      if (k < G.K && n < G.N) v = G.transB ? Bg[n * G.ldb + k] : Bg[k * G.ldb + n];
-      rb[u] = v;
+      const bool ok = ((b_ok >> u) & 1u) && (k0 + b_k0 + b_ku * u < G.K);
+      const int64_t off = b_base + u * b_su + kt * b_sk;
+      const T v = Bg[ok ? off : 0];
+      rb[u] = ok ? v : T(0);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = threadIdx.x + GT * u;
-      const int mm = G.transA ? e % BM : e / GBK, kk = G.transA ? e / BM : e % GBK;
-      As[buf][kk][mm] = ra[u];
-    }
+    for (int u = 0; u < NA; ++u) As[buf][a_k0 + a_ku * u][a_l0 + a_lu * u] = ra[u];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = threadIdx.x + GT * u;
-      const int nn = G.transB ? e / GBK : e % BN, kk = G.transB ? e % GBK : e / BN;
-      Bs[buf][kk][nn] = rb[u];
-    }
+    for (int u = 0; u < NB; ++u) Bs[buf][b_k0 + b_ku * u][b_l0 + b_lu * u] = rb[u];
   };
 
   acc_t acc[TM][TN];
@@ -206,7 +247,7 @@ __global__ void __launch_bounds__(GT) k_gemm(GemmLaunch L, const T* __restrict__
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) fetch((kt + 1) * GBK);
+    if (kt + 1 < nk) fetch(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       T a[TM], b[TN];
@@ -498,7 +539,7 @@ template <typename T>
 static void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmLaunch& L, const T* A, const T* B, T* C, T* W) {
   switch (cfg) {
     case CFG_128:
-      LAUNCH((k_gemm<T, 128, 128, 2, 2>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      LAUNCH((k_gemm<T, 128, 128, 2, 4>), grid, dim3(512), 0, s, L, A, B, C, W);
       break;
     case CFG_256x16:
       LAUNCH((k_gemm<T, 256, 16, 4, 1>), grid, dim3(GT), 0, s, L, A, B, C, W);
