@@ -198,6 +198,21 @@ int ftn_ftensordot(ftn_tensor_t a, ftn_tensor_t b, int naxes, const int32_t* axe
                    const int32_t* axes_b, ftn_conv conv, ftn_gemm gemm,
                    ftn_stream_t stream, ftn_tensor_t* out);
 
+/* Adjoint (reverse-mode derivative) of ftn_ftensordot. The contraction is
+   bilinear in A and B (Eq. standardcontract), so for a cotangent dC of C:
+   dA = sum over blocks of the same signed pairing with dC and B (the free
+   legs of B contracted), dB likewise with A and dC, with exactly the signs of
+   the forward call. dc must have the structure of the forward output (same
+   legs, duals and total charge as ftn_ftensordot(a, b, ...) returns); da and
+   db are new tensors with the structures of a and b. Arguments as in
+   ftn_ftensordot; runs as the forward permutes, one gather of dC into the
+   per-charge fused matrices, two grouped GEMMs (dA~ = dC B~^T,
+   dB~ = A~^T dC) and the permutes run backwards. */
+int ftn_ftensordot_backward(ftn_tensor_t a, ftn_tensor_t b, ftn_tensor_t dc, int naxes,
+                            const int32_t* axes_a, const int32_t* axes_b, ftn_conv conv,
+                            ftn_gemm gemm, ftn_stream_t stream, ftn_tensor_t* da,
+                            ftn_tensor_t* db);
+
 /* ---------------------------------------------------------------------------
  * Bond compression (Sec. II.A truncated SVD; Sec. III approximate trees)
  * ------------------------------------------------------------------------ */

@@ -1,0 +1,84 @@
+"""Reverse-mode derivatives of the oracle's contractions (test infrastructure).
+
+A pairwise contraction is bilinear in its two operands (Eq.
+standardcontract: every output entry is a signed sum of products of one
+entry of each), and the value of a closed network is linear in each of its
+tensors (Eqs. fermionictn, fermionictn2). The derivatives below are obtained
+by torch's reverse-mode differentiation of the oracle's own block arithmetic
+(``ops.ftensordot``, ``network.contract_network`` with no truncation), so
+they inherit its signs: nothing is re-derived here.
+
+* ``ftensordot_vjp``: cotangents (dA, dB) of C = ftensordot(A, B) for a
+  given output cotangent dC, i.e. the gradients of <dC, C>.
+* ``network_grad``: value of a closed network and its gradient with respect
+  to every allowed entry of every tensor.
+"""
+
+import torch
+
+from .tensor import FTensor
+from .ops import ftensordot
+from .network import Network, contract_network
+
+
+def _leaf_copy(T):
+    out = FTensor(T.sym, T.legs, T.total)
+    for k in T.keys():
+        out.blocks[k] = T.block(k).detach().clone().requires_grad_(True)
+    return out
+
+
+def inner(X, Y):
+    """<X, Y> = sum over common blocks of the entrywise products."""
+    s = 0.0
+    for k in X.keys():
+        if k in Y.blocks:
+            s = s + (X.block(k) * Y.block(k)).sum()
+    return s
+
+
+def ftensordot_vjp(A, B, dC, axes_a, axes_b, conv="local"):
+    """(dA, dB) = gradients of <dC, ftensordot(A, B, axes_a, axes_b)>."""
+    A1, B1 = _leaf_copy(A), _leaf_copy(B)
+    C = ftensordot(A1, B1, axes_a, axes_b, conv=conv)
+    L = inner(dC, C)
+    if not torch.is_tensor(L) or not L.requires_grad:
+        return FTensor.zeros(A.sym, A.legs, A.total), FTensor.zeros(B.sym, B.legs, B.total)
+    leaves = [A1, B1]
+    keys = [T.keys() for T in leaves]
+    flat = [T.blocks[k] for T, ks in zip(leaves, keys) for k in ks]
+    gs = torch.autograd.grad(L, flat, allow_unused=True) if flat else []
+    outs, i = [], 0
+    for T, ks in zip(leaves, keys):
+        o = FTensor(T.sym, T.legs, T.total)
+        for k in ks:
+            g = gs[i]
+            o.blocks[k] = torch.zeros_like(T.blocks[k].detach()) if g is None else g.detach()
+            i += 1
+        outs.append(o)
+    return outs[0], outs[1]
+
+
+def network_grad(net, path):
+    """(value, {tensor id: gradient FTensor}) of a closed network, exact."""
+    leaves = {t: _leaf_copy(x) for t, x in net.tensors.items()}
+    net2 = Network(leaves, net.bonds, conv=net.conv, positions=net.positions)
+    T, labs, e, _ = contract_network(net2, path, chi=None, renorm=False)
+    if T.ndim != 0:
+        raise ValueError("network is not closed")
+    b = T.blocks.get(())
+    ids = sorted(leaves)
+    flat = [leaves[t].blocks[k] for t in ids for k in leaves[t].keys()]
+    if b is None or not b.requires_grad:
+        gs = [None] * len(flat)
+    else:
+        gs = torch.autograd.grad(b.sum(), flat, allow_unused=True)
+    grads, i = {}, 0
+    for t in ids:
+        o = FTensor(leaves[t].sym, leaves[t].legs, leaves[t].total)
+        for k in leaves[t].keys():
+            g = gs[i]
+            o.blocks[k] = torch.zeros_like(leaves[t].blocks[k].detach()) if g is None else g.detach()
+            i += 1
+        grads[t] = o
+    return (0.0 if b is None else float(b.detach())), grads

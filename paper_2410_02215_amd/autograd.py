@@ -1,0 +1,209 @@
+"""Reverse-mode derivatives of fermionic contractions on the GPU.
+
+``dot`` is a differentiable ``ftensordot``. Its backward pass calls
+``ftn_ftensordot_backward``: the contraction of Eq. (standardcontract) is
+bilinear, so with the signed fused matrices A~, B~ of the forward pass the
+cotangents are dA~ = dC B~^T and dB~ = A~^T dC per fused charge, returned to
+the block layouts by the inverse signed permutes. ``transpose`` is a
+differentiable ``ftranspose``: a signed permutation is orthogonal, so its
+adjoint is the inverse permutation with the same signs.
+
+``contract_exact`` contracts a network in the local convention (Sec. II.E,
+Eq. fermionictn2) along an SSA path with these operations, so that
+``torch.autograd`` differentiates the network value with respect to the
+block data of every tensor. Odd tensors receive a size-1 odd dummy leg in
+front (it changes no block data); at the end the dummies are sorted by the
+chosen global order of their tensors, dropped, and the phase (-1)^{m(m-1)/2}
+of having prepended m of them is removed. Shared bonds of a step are paired
+in increasing bond order. Every step runs in the HIP library; torch only
+holds the block data and records the graph.
+"""
+
+import torch
+
+from . import ftn
+
+
+def _neg(sym, q):
+    return ((-q[0]) % 2, 0) if sym == ftn.Z2 else (-q[0], -q[1] if sym == ftn.U1xU1 else 0)
+
+
+def _parity(sym, q):
+    return (q[0] + (q[1] if sym == ftn.U1xU1 else 0)) % 2
+
+
+def _sub(sym, a, b):
+    if sym == ftn.Z2:
+        return ((a[0] - b[0]) % 2, 0)
+    return (a[0] - b[0], a[1] - b[1] if sym == ftn.U1xU1 else 0)
+
+
+class DTensor:
+    """Block data (1-D torch device tensor, may require grad) plus structure.
+
+    ``legs``: list of (charges, dims, dual) as taken by ``ftn.Tensor.create``;
+    ``total``: the total charge as a pair.
+    """
+
+    def __init__(self, sym, legs, total, data):
+        self.sym = int(sym)
+        self.legs = [([tuple(q) for q in c], [int(x) for x in d], int(u)) for (c, d, u) in legs]
+        self.total = tuple(int(x) for x in total)
+        self.data = data
+
+    @property
+    def dtype(self):
+        return ftn.F64 if self.data.dtype == torch.float64 else ftn.F32
+
+    @property
+    def ndim(self):
+        return len(self.legs)
+
+    @property
+    def parity(self):
+        return _parity(self.sym, self.total)
+
+    def handle(self, data=None):
+        """An ftn.Tensor holding a copy of ``data`` (default: the current data)."""
+        d = (self.data if data is None else data).detach().contiguous()
+        return ftn.Tensor.create(self.sym, self.legs, self.total, self.dtype, data=d)
+
+    @classmethod
+    def from_tensor(cls, t, requires_grad=False):
+        inf = t.info()
+        data = t.data()
+        if requires_grad:
+            data.requires_grad_(True)
+        return cls(inf["sym"], t.legs(), inf["total"], data)
+
+
+class _Dot(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a_data, b_data, a, b, axes_a, axes_b, conv, gemm, out):
+        A, B = a.handle(a_data), b.handle(b_data)
+        C = ftn.ftensordot(A, B, axes_a, axes_b, conv, gemm)
+        inf = C.info()
+        out.append((C.legs(), inf["total"]))
+        ctx.A, ctx.B = A, B
+        ctx.args = (axes_a, axes_b, conv, gemm, a.sym, C.legs(), inf["total"], a.dtype)
+        return C.data()
+
+    @staticmethod
+    def backward(ctx, dc):
+        axes_a, axes_b, conv, gemm, sym, legs, total, dtype = ctx.args
+        DC = ftn.Tensor.create(sym, legs, total, dtype, data=dc.detach().contiguous())
+        dA, dB = ftn.ftensordot_backward(ctx.A, ctx.B, DC, axes_a, axes_b, conv, gemm)
+        return dA.data(), dB.data(), None, None, None, None, None, None, None
+
+
+class _Transpose(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, data, a, perm, out):
+        T = ftn.ftranspose(a.handle(data), perm)
+        out.append(T.legs())
+        ctx.a, ctx.perm = a, perm
+        return T.data()
+
+    @staticmethod
+    def backward(ctx, dt):
+        a, perm = ctx.a, ctx.perm
+        inv = [0] * len(perm)
+        for i, p in enumerate(perm):
+            inv[p] = i
+        legs = [a.legs[p] for p in perm]
+        D = ftn.Tensor.create(a.sym, legs, a.total, a.dtype, data=dt.detach().contiguous())
+        return ftn.ftranspose(D, inv).data(), None, None, None
+
+
+def dot(a, b, axes_a, axes_b, conv=ftn.LOCAL, gemm=ftn.GEMM_F64):
+    """Differentiable ftensordot of two DTensors (output legs: free(a) ++ free(b))."""
+    st = []
+    data = _Dot.apply(a.data, b.data, a, b, [int(x) for x in axes_a], [int(x) for x in axes_b],
+                      int(conv), int(gemm), st)
+    legs, total = st[0]
+    return DTensor(a.sym, legs, total, data)
+
+
+def transpose(a, perm):
+    """Differentiable ftranspose of a DTensor."""
+    perm = [int(p) for p in perm]
+    if sorted(perm) != list(range(a.ndim)):
+        raise ValueError("not a permutation")
+    st = []
+    data = _Transpose.apply(a.data, a, perm, st)
+    return DTensor(a.sym, st[0], a.total, data)
+
+
+def add_dummy(a):
+    """Prepend the size-1 odd dummy leg ('+', charge -s(T)); the data is unchanged."""
+    if not a.parity:
+        raise ValueError("add_dummy needs an odd tensor")
+    q = _neg(a.sym, a.total)
+    return DTensor(a.sym, [([q], [1], 0)] + a.legs, (0, 0), a.data)
+
+
+def drop_leading_dummies(a, m):
+    """Remove m leading size-1 dummy legs (block data unchanged)."""
+    tot = a.total
+    for (c, d, u) in a.legs[:m]:
+        if len(c) != 1 or d != [1] or u != 0:
+            raise ValueError("leg is not a dummy")
+        tot = _sub(a.sym, tot, c[0])
+    return DTensor(a.sym, a.legs[m:], tot, a.data)
+
+
+def contract_exact(tensors, bonds, path, order=None, gemm=ftn.GEMM_F64):
+    """Contract a network exactly in the local convention.
+
+    ``tensors``: list of DTensor; ``bonds``: (t1, l1, t2, l2) with opposite
+    duals; ``path``: SSA pairs; ``order``: global position of every tensor
+    (sorts the dummy legs; default: list order). Returns ``(T, labels)``:
+    the final DTensor (open legs only) and the (tensor, leg) of each leg.
+    """
+    n = len(tensors)
+    T = dict(enumerate(tensors))
+    lab = {t: [("o", t, l) for l in range(x.ndim)] for t, x in T.items()}
+    for bi, (t1, l1, t2, l2) in enumerate(bonds):
+        lab[t1][l1] = ("b", bi)
+        lab[t2][l2] = ("b", bi)
+    pos = list(range(n)) if order is None else [int(x) for x in order]
+    for t in range(n):
+        if T[t].parity:
+            T[t] = add_dummy(T[t])
+            lab[t] = [("d", t)] + lab[t]
+    ssa = {i: i for i in range(n)}
+    nid = n
+    for (i, j) in path:
+        x, y = ssa[i], ssa[j]
+        pairs = [(k, lab[y].index(l)) for k, l in enumerate(lab[x]) if l[0] == "b" and l in lab[y]]
+        pairs.sort(key=lambda p: lab[x][p[0]][1])
+        lx, ly = [p[0] for p in pairs], [p[1] for p in pairs]
+        T[nid] = dot(T[x], T[y], lx, ly, ftn.LOCAL, gemm)
+        lab[nid] = [l for k, l in enumerate(lab[x]) if k not in lx] + [l for k, l in enumerate(lab[y]) if k not in ly]
+        for t in (x, y):
+            del T[t]
+            del lab[t]
+        ssa[len(ssa)] = nid
+        nid += 1
+    if len(T) != 1:
+        raise ValueError("path does not contract the network to one tensor")
+    (z, Z), = T.items()
+    labs = lab[z]
+    dpos = [k for k, l in enumerate(labs) if l[0] == "d"]
+    m = len(dpos)
+    if m:
+        others = [k for k in range(Z.ndim) if k not in dpos]
+        ds = sorted(dpos, key=lambda k: pos[labs[k][1]])
+        Z = drop_leading_dummies(transpose(Z, ds + others), m)
+        if (m * (m - 1) // 2) % 2:
+            Z = DTensor(Z.sym, Z.legs, Z.total, -Z.data)
+        labs = [labs[k] for k in others]
+    return Z, [(l[1], l[2]) if l[0] == "o" else l for l in labs]
+
+
+def network_value(tensors, bonds, path, order=None, gemm=ftn.GEMM_F64):
+    """Value of a closed network as a 0-d torch tensor (differentiable)."""
+    Z, labs = contract_exact(tensors, bonds, path, order, gemm)
+    if Z.ndim:
+        raise ValueError("network is not closed")
+    return Z.data.sum()

@@ -228,6 +228,19 @@ int ftn_ftensordot(ftn_tensor_t a, ftn_tensor_t b, int naxes, const int32_t* axe
   });
 }
 
+int ftn_ftensordot_backward(ftn_tensor_t a, ftn_tensor_t b, ftn_tensor_t dc, int naxes, const int32_t* axes_a,
+                            const int32_t* axes_b, ftn_conv conv, ftn_gemm gemm, ftn_stream_t stream,
+                            ftn_tensor_t* da, ftn_tensor_t* db) {
+  return guarded([&] {
+    if (!da || !db || naxes < 0 || (naxes && (!axes_a || !axes_b))) fail(FTN_EINVAL, "bad arguments");
+    std::vector<int> xa(axes_a, axes_a + naxes), xb(axes_b, axes_b + naxes);
+    std::unique_ptr<Tensor> ga, gb;
+    op_ftensordot_backward(T(a), T(b), T(dc), xa, xb, conv, gemm, (hipStream_t)stream, ga, gb);
+    *da = wrap(std::move(ga));
+    *db = wrap(std::move(gb));
+  });
+}
+
 int ftn_compress_bond(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int64_t chi, double cutoff,
                       ftn_conv conv, ftn_stream_t stream, ftn_tensor_t* a_out, ftn_tensor_t* b_out,
                       double* discarded_weight, double* svals, int64_t* nkept) {

@@ -378,6 +378,10 @@ struct DotPlanView {
 std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
                                   const std::vector<int>& axb, int conv, int gemm, hipStream_t s);
 DotPlanView dot_plan_view(const DotPlan& p);
+// adjoint of op_ftensordot: da, db (structures of a, b) from dc
+void op_ftensordot_backward(const Tensor& a, const Tensor& b, const Tensor& dc, const std::vector<int>& axa,
+                            const std::vector<int>& axb, int conv, int gemm, hipStream_t s,
+                            std::unique_ptr<Tensor>& da, std::unique_ptr<Tensor>& db);
 
 // block copies between dense and block layouts
 void gather_dense(Tensor& t, const void* dense, hipStream_t s);

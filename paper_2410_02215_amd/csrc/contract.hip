@@ -467,6 +467,121 @@ std::unique_ptr<Tensor> op_ftensordot(const Tensor& a, const Tensor& b, const st
   return out;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the contraction (the map is bilinear, Eq. standardcontract):
+// with the signed fused matrices A~_Q, B~_Q and C_Q = A~_Q B~_Q,
+//   dA~_Q = dC_Q B~_Q^T,  dB~_Q = A~_Q^T dC_Q,
+// and dA, dB are the signed permutes run backwards (a signed permutation is
+// inverted by its transpose, which carries the same signs).
+
+// largest i in [0, n) with v[i] <= x
+__device__ inline int upper_idx(const int64_t* v, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// dC (block layout of C) -> fused matrices F_g (M_g x N_g at f_off[g])
+template <typename T>
+__global__ void k_gather_fused(const GemmGroup* __restrict__ groups, int ng, const int64_t* __restrict__ f_off,
+                               int64_t total, GemmScatter sc, const T* __restrict__ dC, T* __restrict__ F) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int g = upper_idx(f_off, ng, e);
+  const GemmGroup G = groups[g];
+  const int64_t loc = e - f_off[g];
+  const int64_t m = loc / G.N, n = loc % G.N;
+  const int rfi = upper_idx(sc.rc_start + G.rc_base, G.nrc, m);
+  const int cgj = upper_idx(sc.cc_start + G.cc_base, G.ncc, n);
+  const int64_t rlr = m - sc.rc_start[G.rc_base + rfi];
+  const int64_t clc = n - sc.cc_start[G.cc_base + cgj];
+  const int64_t cnd = sc.cc_dim[G.cc_base + cgj];
+  const int64_t bo = sc.boff[G.boff_base + (int64_t)rfi * G.ncc + cgj];
+  F[e] = bo >= 0 ? dC[bo + rlr * cnd + clc] : T(0);
+}
+
+void op_ftensordot_backward(const Tensor& a, const Tensor& b, const Tensor& dc, const std::vector<int>& axa,
+                            const std::vector<int>& axb, int conv, int gemm, hipStream_t s,
+                            std::unique_ptr<Tensor>& da, std::unique_ptr<Tensor>& db) {
+  if (a.sym() != b.sym() || dc.sym() != a.sym()) fail(FTN_EINVAL, "symmetry mismatch");
+  if (a.dtype != b.dtype || dc.dtype != a.dtype) fail(FTN_ENOTSUP, "operands must have the same dtype");
+  if (axa.size() != axb.size()) fail(FTN_EINVAL, "axes length mismatch");
+  if (conv != FTN_LOCAL && conv != FTN_GLOBAL) fail(FTN_EINVAL, "unknown convention");
+  if (gemm == FTN_GEMM_F64 && a.dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
+  if (gemm != FTN_GEMM_F64 && a.dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 / split-BF16 GEMM needs FP32 tensors");
+  std::shared_ptr<DotPlan> P = dot_plan(a, b, axa, axb, conv, gemm, s);
+  if (dc.st->skey != P->cst->skey) fail(FTN_EINVAL, "dC does not have the structure of the contraction's output");
+  da = make_tensor(a.st, a.dtype, s, true);
+  db = make_tensor(b.st, b.dtype, s, true);
+  const std::vector<GemmGroup>& groups = P->gp.host;
+  if (groups.empty() || dc.size() == 0) return;
+  const size_t es = a.esize();
+  std::vector<int64_t> f_off(groups.size());
+  int64_t ftot = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    f_off[g] = ftot;
+    ftot += groups[g].M * groups[g].N;
+  }
+  DBuf<char> At(P->asz * es, s), Bt(P->bsz * es, s), dAt(P->asz * es, s), dBt(P->bsz * es, s), F(ftot * es, s);
+  if (P->asz) HIPC(hipMemsetAsync(dAt.p, 0, P->asz * es, s));
+  if (P->bsz) HIPC(hipMemsetAsync(dBt.p, 0, P->bsz * es, s));
+  run_perm(0, a.S(), a.dtype, P->pa, a.data, At.p, s);
+  run_perm(0, b.S(), b.dtype, P->pb, b.data, Bt.p, s);
+  {
+    DBuf<int64_t> dfo = to_device(f_off, s);
+    const dim3 grid((unsigned)cdiv(ftot, 256)), block(256);
+    if (a.dtype == FTN_F64)
+      LAUNCH(k_gather_fused<double>, grid, block, 0, s, P->gp.groups.p, (int)groups.size(), dfo.p, ftot, P->sc,
+             (const double*)dc.data, (double*)F.p);
+    else
+      LAUNCH(k_gather_fused<float>, grid, block, 0, s, P->gp.groups.p, (int)groups.size(), dfo.p, ftot, P->sc,
+             (const float*)dc.data, (float*)F.p);
+  }
+  std::vector<GemmGroup> ga, gb;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const GemmGroup& G = groups[g];
+    GemmGroup x;
+    std::memset(&x, 0, sizeof(x));
+    if (G.K > 0) {  // dA~ = F B~^T (M x K)
+      x.M = G.M;
+      x.N = G.K;
+      x.K = G.N;
+      x.a_off = f_off[g];
+      x.lda = G.N;
+      x.b_off = G.b_off;
+      x.ldb = G.ldb;
+      x.transB = 1;
+      x.c_off = G.a_off;
+      x.ldc = G.lda;
+      ga.push_back(x);
+      std::memset(&x, 0, sizeof(x));  // dB~ = A~^T F (K x N)
+      x.M = G.K;
+      x.N = G.N;
+      x.K = G.M;
+      x.a_off = G.a_off;
+      x.lda = G.lda;
+      x.transA = 1;
+      x.b_off = f_off[g];
+      x.ldb = G.N;
+      x.c_off = G.b_off;
+      x.ldc = G.ldb;
+      gb.push_back(x);
+    }
+  }
+  if (!ga.empty()) {
+    run_grouped_gemm(gemm, a.dtype, ga, F.p, Bt.p, dAt.p, nullptr, s);
+    run_grouped_gemm(gemm, a.dtype, gb, At.p, F.p, dBt.p, nullptr, s);
+  }
+  run_perm(1, a.S(), a.dtype, P->pa, dAt.p, da->data, s);
+  run_perm(1, b.S(), b.dtype, P->pb, dBt.p, db->data, s);
+}
+
 void clear_plan_cache() {
   std::lock_guard<std::mutex> g(g_plan_mu);
   g_plans.clear();

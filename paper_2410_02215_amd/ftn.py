@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ftn_dagger", _I, [_P, _P, _PP]),
     ("ftn_fuse", _I, [_P, _I, _PI32, _I, _I, _P, _PP]),
     ("ftn_ftensordot", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP]),
+    ("ftn_ftensordot_backward", _I, [_P, _P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP, _PP]),
     ("ftn_compress_bond", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _PP, _PP, _PD, _PD, _PI64]),
     ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
     ("ftn_net_free", _I, [_P]),
@@ -281,6 +282,15 @@ def ftensordot(a, b, axes_a, axes_b, conv=LOCAL, gemm=GEMM_F64):
                                _arr([int(x) for x in axes_b], ctypes.c_int32), int(conv), int(gemm),
                                _stream(), ctypes.byref(out)))
     return Tensor(out)
+
+
+def ftensordot_backward(a, b, dc, axes_a, axes_b, conv=LOCAL, gemm=GEMM_F64):
+    """Adjoint of ftensordot: (dA, dB) for the cotangent dC of its output."""
+    da, db = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(_lib.ftn_ftensordot_backward(a.h, b.h, dc.h, len(axes_a), _arr([int(x) for x in axes_a], ctypes.c_int32),
+                                        _arr([int(x) for x in axes_b], ctypes.c_int32), int(conv), int(gemm),
+                                        _stream(), ctypes.byref(da), ctypes.byref(db)))
+    return Tensor(da), Tensor(db)
 
 
 def compress_bond(a, b, leg_a, leg_b, chi, cutoff=1e-12, conv=LOCAL):

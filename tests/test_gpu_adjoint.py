@@ -1,0 +1,148 @@
+"""GPU parity of the adjoint contraction and of network gradients.
+
+``ftensordot_backward`` (C ABI) is compared block by block with the
+oracle's reverse-mode derivative of its own contraction; the structures of
+dA and dB (the structures of A and B) must match bit-exactly. FP64 values
+agree up to summation order: each cotangent entry is a dot product of
+length N (dA) or M (dB) of O(1) terms, checked as a max error of 1e-12
+relative to the largest entry. Network gradients go through the autograd
+driver (every contraction and transposition in the library) and are
+compared with the oracle's gradient of the exact network value at 1e-11
+relative (a few chained FP64 contractions).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import symmetry as S
+from oracle.adjoint import ftensordot_vjp, network_grad
+from oracle.network import Network, network_value
+from oracle.ops import ftensordot
+from oracle.tensor import make_leg
+from tests.helpers import rand_tensor, random_network, random_ssa_path
+from tests.gpu_helpers import to_gpu, assert_same_structure, flat_blocks, legs_abi, SYM
+from tests.test_gpu_ops import _rand_pair
+
+pytestmark = pytest.mark.gpu
+
+SYMS = [S.Z2, S.U1, S.U1U1]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_02215_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    P.load_library()
+    return P
+
+
+def _data(G):
+    return G.data().double().cpu().numpy()
+
+
+def _check(ref, G, tol):
+    assert_same_structure(ref, G)
+    r = flat_blocks(ref)
+    err = np.abs(_data(G) - r).max(initial=0)
+    assert err <= tol * max(1.0, np.abs(r).max(initial=0)), err
+
+
+def _backward_case(P, A, B, ax_a, ax_b, conv, rng, dtype=torch.float64, gemm=None, tol=1e-12):
+    ref_c = ftensordot(A, B, ax_a, ax_b, conv=conv)
+    dC = rand_tensor(rng, A.sym, ref_c.legs, total=ref_c.total)
+    dA, dB = ftensordot_vjp(A, B, dC, ax_a, ax_b, conv)
+    c = P.LOCAL if conv == "local" else P.GLOBAL
+    g = P.GEMM_F64 if gemm is None else gemm
+    GdA, GdB = P.ftensordot_backward(to_gpu(A, dtype), to_gpu(B, dtype), to_gpu(dC, dtype), ax_a, ax_b,
+                                     conv=c, gemm=g)
+    _check(dA, GdA, tol)
+    _check(dB, GdB, tol)
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", SYMS)
+def test_ftensordot_backward_fp64(P, sym, conv):
+    rng = np.random.default_rng(21)
+    for trial in range(8):
+        k = int(rng.integers(0, 4))
+        A, B, ax_a, ax_b = _rand_pair(rng, sym, k, int(rng.integers(0, 4)), int(rng.integers(0, 4)), 3)
+        _backward_case(P, A, B, ax_a, ax_b, conv, rng)
+
+
+def test_ftensordot_backward_tiles_and_ragged_tails(P):
+    # sectors spanning several GEMM tiles in every role (M, N and K of both
+    # adjoint products) with ragged edges
+    rng = np.random.default_rng(22)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(37, 141, 0), l(70, 9, 1), l(213, 30, 0)], total=(0,))
+    B = rand_tensor(rng, sym, [l(213, 30, 1), l(150, 3, 0)], total=(1,))
+    _backward_case(P, A, B, [2], [0], "local", rng)
+    _backward_case(P, A, B, [2], [0], "global", rng)
+
+
+def test_ftensordot_backward_scalar_output(P):
+    # full contraction of two tensors: C is one number, dA = dC * B (signed)
+    rng = np.random.default_rng(23)
+    sym = S.U1
+    l = lambda d: make_leg(sym, [(-1,), (0,), (1,)], [2, 3, 1], d)
+    A = rand_tensor(rng, sym, [l(0), l(1), l(0)], total=(0,))
+    B = rand_tensor(rng, sym, [l(1), l(0), l(1)], total=(0,))
+    _backward_case(P, A, B, [0, 1, 2], [2, 1, 0], "local", rng)
+    _backward_case(P, A, B, [2, 0, 1], [0, 2, 1], "global", rng)
+
+
+@pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
+def test_ftensordot_backward_fp32_forms(P, gemm):
+    rng = np.random.default_rng(24)
+    g = P.GEMM_F32 if gemm == "f32" else P.GEMM_BF16X3
+    tol = {"f32": 1e-5, "bf16x3": 1e-4}[gemm]
+    for trial in range(4):
+        A, B, ax_a, ax_b = _rand_pair(rng, S.U1U1, int(rng.integers(1, 3)), 2, 2, 4)
+        _backward_case(P, A, B, ax_a, ax_b, "local", rng, dtype=torch.float32, gemm=g, tol=tol)
+
+
+def test_ftensordot_backward_rejects_wrong_cotangent(P):
+    rng = np.random.default_rng(25)
+    A, B, ax_a, ax_b = _rand_pair(rng, S.Z2, 1, 2, 1, 3)
+    with pytest.raises(P.FtnError) as e:
+        P.ftensordot_backward(to_gpu(A), to_gpu(B), to_gpu(B), ax_a, ax_b)
+    assert e.value.code == -1
+
+
+def _dtensor(T):
+    from paper_2410_02215_amd.autograd import DTensor
+    G = to_gpu(T)
+    d = G.data()
+    d.requires_grad_(True)
+    tot = tuple(T.total) + ((0,) if len(T.total) == 1 else ())
+    return DTensor(SYM[T.sym], legs_abi(T.legs), tot, d)
+
+
+@pytest.mark.parametrize("sym", [S.Z2, S.U1, S.U1U1])
+def test_network_gradient_matches_oracle(P, sym):
+    from paper_2410_02215_amd import autograd as AG
+    rng = np.random.default_rng(26)
+    done = 0
+    while done < 3:
+        n = int(rng.integers(3, 7))
+        tensors, bonds = random_network(rng, sym, n, n + 2, odd_frac=0.4)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        path = random_ssa_path(rng, tensors, bonds)
+        order = [int(x) for x in rng.permutation(n)]
+        net = Network(tensors, bonds, conv="local", positions=order)
+        v, grads = network_grad(net, path)
+        if abs(v) < 1e-3:
+            continue
+        D = [_dtensor(tensors[t]) for t in range(n)]
+        val = AG.network_value(D, bonds, path, order=order)
+        assert abs(float(val.detach()) - v) <= 1e-11 * max(1.0, abs(v))
+        gs = torch.autograd.grad(val, [d.data for d in D])
+        for t in range(n):
+            r = flat_blocks(grads[t])
+            err = np.abs(gs[t].double().cpu().numpy() - r).max(initial=0)
+            assert err <= 1e-11 * max(1.0, np.abs(r).max(initial=0)), (t, err)
+        done += 1

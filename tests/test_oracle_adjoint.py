@@ -1,0 +1,130 @@
+"""Pins of the oracle's derivatives (``oracle.adjoint``).
+
+The derivatives come from reverse-mode differentiation of the oracle's
+block arithmetic; they are pinned here by what the mathematics fixes:
+
+* a pairwise contraction C(A, B) is bilinear (Eq. standardcontract), so for
+  any cotangent dC: <dA, A> = <dC, C> = <dB, B>, and the directional
+  difference L(A + V) - L(A - V) equals 2 <dA, V> exactly (up to rounding)
+  for L(A) = <dC, C(A, B)>;
+* the value of a closed network is linear in each tensor (Eq.
+  fermionictn2): <grad_t, T_t> equals the value for every t (Euler's
+  identity for degree-1 homogeneous functions), and the directional
+  difference in T_t equals 2 <grad_t, V>;
+* a gradient entry of a block the value does not depend on is zero.
+
+A sign dropped or flipped in any block of the derivative changes one of
+these sums.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import symmetry as S
+from oracle.adjoint import ftensordot_vjp, network_grad, inner
+from oracle.ops import ftensordot
+from oracle.network import Network, network_value
+from tests.helpers import rand_leg, partner, rand_tensor, random_network, random_ssa_path
+
+SYMS = [S.Z2, S.U1, S.U1U1]
+
+
+def _pair(rng, sym, k, nfa, nfb, maxd=3):
+    bond = [rand_leg(rng, sym, maxd=maxd) for _ in range(k)]
+    fa = [rand_leg(rng, sym, maxd=maxd) for _ in range(nfa)]
+    fb = [rand_leg(rng, sym, maxd=maxd) for _ in range(nfb)]
+    A_legs, B_legs = fa + bond, [partner(b) for b in bond] + fb
+    pa, pb = list(rng.permutation(len(A_legs))), list(rng.permutation(len(B_legs)))
+    A = rand_tensor(rng, sym, [A_legs[p] for p in pa])
+    B = rand_tensor(rng, sym, [B_legs[p] for p in pb])
+    return A, B, [pa.index(nfa + t) for t in range(k)], [pb.index(t) for t in range(k)]
+
+
+def _rel(x, y):
+    return abs(float(x) - float(y)) / max(1.0, abs(float(y)))
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", SYMS)
+def test_vjp_bilinear_identity_and_difference(sym, conv):
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        A, B, ax_a, ax_b = _pair(rng, sym, int(rng.integers(0, 4)), int(rng.integers(0, 3)),
+                                 int(rng.integers(0, 3)))
+        C = ftensordot(A, B, ax_a, ax_b, conv=conv)
+        dC = rand_tensor(rng, sym, C.legs, total=C.total)
+        dA, dB = ftensordot_vjp(A, B, dC, ax_a, ax_b, conv)
+        c = inner(dC, C)
+        assert _rel(inner(dA, A), c) < 1e-12
+        assert _rel(inner(dB, B), c) < 1e-12
+        V = rand_tensor(rng, sym, A.legs, total=A.total)
+        W = rand_tensor(rng, sym, B.legs, total=B.total)
+        Ap = A.copy(); Am = A.copy()
+        Bp = B.copy(); Bm = B.copy()
+        for k in A.keys():
+            Ap.blocks[k] = A.block(k) + V.block(k)
+            Am.blocks[k] = A.block(k) - V.block(k)
+        for k in B.keys():
+            Bp.blocks[k] = B.block(k) + W.block(k)
+            Bm.blocks[k] = B.block(k) - W.block(k)
+        da = inner(dC, ftensordot(Ap, B, ax_a, ax_b, conv=conv)) - inner(dC, ftensordot(Am, B, ax_a, ax_b, conv=conv))
+        db = inner(dC, ftensordot(A, Bp, ax_a, ax_b, conv=conv)) - inner(dC, ftensordot(A, Bm, ax_a, ax_b, conv=conv))
+        assert _rel(da, 2 * inner(dA, V)) < 1e-12
+        assert _rel(db, 2 * inner(dB, W)) < 1e-12
+
+
+def test_vjp_sign_of_a_single_block():
+    # Z2, one bond: C = A B with the local pairing sign on the odd sector when
+    # A's end of the bond is '+'. Brute force per entry: dA[i, k] = sum_j
+    # dC[i, j] * sign(k) * B[k, j], the sign being -1 on the odd sector only.
+    from oracle.tensor import make_leg
+    rng = np.random.default_rng(12)
+    lf = make_leg(S.Z2, [(0,), (1,)], [2, 3], 0)
+    lb = make_leg(S.Z2, [(0,), (1,)], [2, 2], 0)
+    A = rand_tensor(rng, S.Z2, [lf, lb], total=(0,))
+    B = rand_tensor(rng, S.Z2, [partner(lb), partner(lf)], total=(0,))
+    C = ftensordot(A, B, [1], [0], conv="local")
+    dC = rand_tensor(rng, S.Z2, C.legs, total=C.total)
+    dA, _ = ftensordot_vjp(A, B, dC, [1], [0], "local")
+    a = A.to_dense(); b = B.to_dense(); dc = dC.to_dense()
+    sgn = np.array([1, 1, -1, -1.0])
+    ref = dc @ (sgn[:, None] * b).T
+    mask = np.zeros_like(ref)
+    for k in A.keys():
+        sl = tuple(slice(l.offset(i), l.offset(i) + l.dims[i]) for l, i in zip(A.legs, k))
+        mask[sl] = 1
+    np.testing.assert_allclose(dA.to_dense(), ref * mask, rtol=0, atol=1e-12)
+
+
+def _networks(sym, n, count):
+    rng = np.random.default_rng(13)
+    out = []
+    while len(out) < count:
+        tensors, bonds = random_network(rng, sym, n, n + 2, odd_frac=0.4)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        path = random_ssa_path(rng, tensors, bonds)
+        net = Network(tensors, bonds, conv="local", positions=list(rng.permutation(n)))
+        if abs(network_value(net, path)[0]) < 1e-3:
+            continue
+        out.append((net, path, rng))
+    return out
+
+
+@pytest.mark.parametrize("sym", [S.Z2, S.U1])
+def test_network_grad_euler_and_difference(sym):
+    for net, path, rng in _networks(sym, 5, 3):
+        v, g = network_grad(net, path)
+        for t, T in net.tensors.items():
+            assert _rel(inner(g[t], T), v) < 1e-11
+            V = rand_tensor(rng, sym, T.legs, total=T.total)
+            vals = []
+            for s in (1.0, -1.0):
+                X = T.copy()
+                for k in T.keys():
+                    X.blocks[k] = T.block(k) + s * V.block(k)
+                tens = dict(net.tensors)
+                tens[t] = X
+                m, e = network_value(Network(tens, net.bonds, conv="local", positions=net.positions), path)
+                vals.append(m * 2.0 ** e)
+            assert _rel(vals[0] - vals[1], 2 * inner(g[t], V)) < 1e-11
