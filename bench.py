@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -24,8 +25,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# per profiler class: (peak, unit, bound). The factorisation kernels (Cholesky,
+# Jacobi) run FP64 vector arithmetic, priced against the FP64 vector peak
+# (256 CUs x 2.4 GHz x 128 FP64 flops per CU per clock = 78.6 TFLOP/s).
 PEAK = {"gemm_f64": (78.6, "TFLOP/s", "mfma"), "gemm_f32": (157.3, "TFLOP/s", "mfma"),
-        "gemm_bf16x3": (2500.0, "TFLOP/s", "mfma"), "permute": (8000.0, "GB/s", "hbm")}
+        "gemm_bf16x3": (2500.0, "TFLOP/s", "mfma"), "permute": (8000.0, "GB/s", "hbm"),
+        "factor": (78.6, "TFLOP/s", "alu")}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_z2_rrg40_chi64.md")
+
+
+def source_hash():
+    """SHA-256 over the library sources (kernels, plans, launch code)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2410_02215_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a class from the committed PMC summary, or None.
+
+    The summary records the source hash it was measured at; any change of
+    the library sources since then makes the figure stale (None).
+    """
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"^source-hash: ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(r"^traffic-per-launch %s ([0-9.eE+]+)$" % re.escape(cls), text, re.M)
+    return float(m.group(1)) if m else None
 
 
 def load_paths():
@@ -158,16 +194,15 @@ def main():
     value = 2.0 * args.steps / el
     norm = res[0] * 2.0 ** res[1]
     hop = (res[2] / res[0]) * 2.0 ** (res[3] - res[1])
-    # dominant kernel class by time
+    # dominant kernel class by time (HIP events on the library's streams)
     dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
     ms, cnt, work = prof[dom]
     peak, unit, bound = PEAK[dom]
-    if unit == "TFLOP/s":
-        achieved = work / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    else:
-        achieved = work / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    achieved = work / (ms * 1e-3) / scale if ms > 0 else 0.0
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": None, "kernel": dom, "launches": cnt, "avg_launch_ms": ms / max(cnt, 1)}
+            "traffic": measured_traffic(dom), "kernel": dom, "launches": cnt,
+            "avg_launch_ms": ms / max(cnt, 1), "work_per_launch": work / max(cnt, 1)}
     out = {
         "metric": "ftensordot useful TFLOP/s + fPEPS contractions/sec on 1 GPU at stated err vs FP64",
         "value": value, "unit": "contractions/s", "n_gpus": 1, "steps": args.steps,
@@ -178,7 +213,8 @@ def main():
                    "streams": 1 if args.serial else 2},
         "ftensordot_useful_tflops": flops / el / 1e12,
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
-        "kernel_rate": {c: (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if c.startswith("gemm") else 1e9))
+        "kernel_rate": {c: "%.4g %s" % (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
+                                        PEAK[c][1])
                         for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
         "roofline": roof,

@@ -283,7 +283,9 @@ enum {
   FTN_PROF_GEMM_F32 = 1,    /* grouped GEMM, FP32 MFMA; work = useful flops */
   FTN_PROF_GEMM_BF16X3 = 2, /* grouped GEMM, split BF16; work = useful flops */
   FTN_PROF_PERMUTE = 3,     /* signed block permutes; work = bytes read + written */
-  FTN_PROF_FACTOR = 4,      /* Cholesky / Jacobi / selection kernels */
+  FTN_PROF_FACTOR = 4,      /* Cholesky / Jacobi kernels; work = textbook flops
+                               (Cholesky p^3/3, triangular inverse p^3/3,
+                               symmetric eigensolver with vectors 9 n^3) */
   FTN_PROF_NCLASS = 6
 };
 

@@ -504,13 +504,32 @@ static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int
   return g;
 }
 
-// launches timed under the factorisation class of the opt-in profiler
-#define FACTOR_LAUNCH(...)                  \
-  do {                                      \
-    void* tok_ = prof_begin(s);             \
-    LAUNCH(__VA_ARGS__);                    \
-    prof_end(tok_, s, FTN_PROF_FACTOR, 0);  \
+// launches timed under the factorisation class of the opt-in profiler; the
+// work figure is the textbook flop count of what the launch computes:
+// Cholesky of a p x p matrix p^3/3, a triangular inverse p^3/3, and a
+// symmetric eigendecomposition with eigenvectors 9 n^3 (tridiagonal
+// reduction plus implicit QR), whatever the algorithm actually runs
+#define FACTOR_LAUNCH(work, ...)                 \
+  do {                                           \
+    void* tok_ = prof_begin(s);                  \
+    LAUNCH(__VA_ARGS__);                         \
+    prof_end(tok_, s, FTN_PROF_FACTOR, (work));  \
   } while (0)
+
+static double orth_flops(const std::vector<OrthJob>& oj) {
+  double f = 0;
+  for (const OrthJob& o : oj) {
+    const double p3 = (double)o.p * o.p * o.p;
+    f += p3 / 3.0 + (o.M ? p3 / 3.0 : 0.0);
+  }
+  return f;
+}
+
+static double eig_flops(const std::vector<EigJob>& ej) {
+  double f = 0;
+  for (const EigJob& e : ej) f += 9.0 * (double)e.n * e.n * e.n;
+  return f;
+}
 
 // per bond sector q
 struct Sect {
@@ -649,7 +668,7 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
       }
     }
     DBuf<OrthJob> doj = to_device(oj, s);
-    FACTOR_LAUNCH(k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
     if (!gt.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Minv.p, Gm, R12.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
@@ -712,7 +731,7 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       ej.push_back(j);
     }
     DBuf<EigJob> dj = to_device(ej, s);
-    FACTOR_LAUNCH(k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
+    FACTOR_LAUNCH(eig_flops(ej), k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
     if (trace) {
       std::vector<int> r(nd);
       HIPC(hipMemcpyAsync(r.data(), drounds.p, nd * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -783,11 +802,12 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   }
   DBuf<OrthJob> doj = to_device(oj, s);
   DBuf<EigJob> dej = to_device(ej, s);
+  const double of_it = orth_flops(oj), ef_it = eig_flops(ej);
   double *q = Q0.p, *qt = Q1.p, *z = Z0.p, *zt = Z1.p, *zu = Z2.p;
   // y <- orthonormal basis of span(y), dependent columns zeroed
   auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
     run_gemm(gram, FTN_F64, y, y, Gy.p, nullptr, s);
-    FACTOR_LAUNCH(k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(of_it, k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
     run_gemm(app, FTN_F64, y, Mm.p, yt, nullptr, s);
     std::swap(y, yt);
   };
@@ -810,7 +830,7 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       // Rayleigh-Ritz: W = X^T Q, Tr = W^T W = Q^T X X^T Q
       run_gemm(Pxt, FTN_F64, Xm, q, zu, nullptr, s);
       run_gemm(Pgz, FTN_F64, zu, zu, Tr.p, nullptr, s);
-      FACTOR_LAUNCH(k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
+      FACTOR_LAUNCH(ef_it, k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
       for (int t = 0; t < ni; ++t)
         HIPC(hipMemcpyAsync(cur.data() + t * p, Lm + loff[it[t]], p * 8, hipMemcpyDeviceToHost, s));
       std::vector<int> rr(ni);

@@ -1,0 +1,144 @@
+"""Summaries of rocprofv3 runs of the library, by kernel and by kernel class.
+
+Usage (CSV output of rocprofv3, ``--output-format csv``):
+
+    python3 -m paper_2410_02215_amd.rocprof_summary stats <dir>
+        per-kernel table from the ``*_kernel_stats.csv`` of a
+        ``--kernel-trace --stats`` run, plus the library's profiler classes
+    python3 -m paper_2410_02215_amd.rocprof_summary pmc <dir>
+        per-class sums and per-launch means of every counter in the
+        ``*_counter_collection.csv`` files of a ``--pmc`` run
+    python3 -m paper_2410_02215_amd.rocprof_summary copy <MiB>
+        one device-to-device copy of the given size (calibration target for
+        the FETCH_SIZE / WRITE_SIZE counters: it reads and writes exactly
+        that many bytes)
+
+Classes match the library's own profiler: one "launch" of a class is one
+timed call (a grouped GEMM is its GEMM kernel plus, when the plan splits K,
+its reduction kernel; a permute is one block-permute kernel; a factor
+launch is one Cholesky or Jacobi kernel).
+"""
+
+import csv
+import glob
+import os
+import re
+import sys
+
+CLASSES = [
+    ("gemm_f64", re.compile(r"k_gemm<double"), True),
+    ("gemm_f64", re.compile(r"k_splitk_reduce<double"), False),
+    ("gemm_f32", re.compile(r"k_gemm<float"), True),
+    ("gemm_f32", re.compile(r"k_splitk_reduce<float"), False),
+    ("gemm_bf16x3", re.compile(r"k_gemm_bf16x3"), True),
+    ("permute", re.compile(r"k_block_perm<"), True),
+    ("factor", re.compile(r"k_jacobi_eig|k_orth_factor"), True),
+    ("copy", re.compile(r"__amd_rocclr_copyBuffer"), True),
+]
+
+
+def kernel_class(name):
+    """(class, counts_as_launch) of a kernel name, or (None, False)."""
+    for cls, rx, launch in CLASSES:
+        if rx.search(name):
+            return cls, launch
+    return None, False
+
+
+def short(name):
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def _find(d, suffix):
+    out = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not out:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    return out
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(names)
+
+
+def stats(d, top=30):
+    rows = []
+    for f in _find(d, "kernel_stats.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((short(_col(r, "Name", "KernelName")), int(_col(r, "Calls")),
+                             float(_col(r, "TotalDurationNs")) / 1e6))
+    agg = {}
+    for n, c, ms in rows:
+        a = agg.setdefault(n, [0, 0.0])
+        a[0] += c
+        a[1] += ms
+    tot = sum(v[1] for v in agg.values())
+    print("Kernel time %.3f ms over %d dispatches.\n" % (tot, sum(v[0] for v in agg.values())))
+    print("| kernel | calls | total ms | avg us | share |")
+    print("|---|---|---|---|---|")
+    for n, (c, ms) in sorted(agg.items(), key=lambda x: -x[1][1])[:top]:
+        print("| `%s` | %d | %.3f | %.1f | %.1f%% |" % (n, c, ms, 1000 * ms / c, 100 * ms / max(tot, 1e-30)))
+    cls = {}
+    for n, (c, ms) in agg.items():
+        k, launch = kernel_class(n)
+        if k is None:
+            continue
+        a = cls.setdefault(k, [0, 0.0])
+        a[0] += c if launch else 0
+        a[1] += ms
+    print("\n| class | launches | total ms | avg ms per launch |")
+    print("|---|---|---|---|")
+    for k, (c, ms) in sorted(cls.items(), key=lambda x: -x[1][1]):
+        print("| %s | %d | %.3f | %.4f |" % (k, c, ms, ms / max(c, 1)))
+
+
+def pmc(d):
+    per = {}
+    launches = {}
+    seen = set()
+    for f in _find(d, "counter_collection.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                n = short(_col(r, "Kernel_Name", "Kernel-Name", "KernelName"))
+                k, launch = kernel_class(n)
+                if k is None:
+                    k = "other"
+                cn = _col(r, "Counter_Name", "Counter-Name", "CounterName")
+                v = float(_col(r, "Counter_Value", "Counter-Value", "CounterValue"))
+                did = (f, _col(r, "Dispatch_Id", "Dispatch-Id", "DispatchId"))
+                per.setdefault(k, {}).setdefault(cn, 0.0)
+                per[k][cn] += v
+                if did not in seen:
+                    seen.add(did)
+                    if launch:
+                        launches[k] = launches.get(k, 0) + 1
+    print("| class | launches | counter | sum | per launch |")
+    print("|---|---|---|---|---|")
+    for k in sorted(per):
+        for cn in sorted(per[k]):
+            nl = launches.get(k, 0)
+            print("| %s | %d | %s | %.6g | %.6g |" % (k, nl, cn, per[k][cn], per[k][cn] / max(nl, 1)))
+
+
+def copy(mib):
+    import torch
+    n = int(mib) * (1 << 20) // 8
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print("copied %d bytes (read %d, written %d)" % (8 * n, 8 * n, 8 * n))
+
+
+def main(argv):
+    if len(argv) < 3 or argv[1] not in ("stats", "pmc", "copy"):
+        raise SystemExit(__doc__)
+    {"stats": stats, "pmc": pmc, "copy": copy}[argv[1]](argv[2])
+
+
+if __name__ == "__main__":
+    main(sys.argv)
