@@ -20,9 +20,11 @@ Modules and the part of the paper each follows:
                 all index assignments, swap-gate bosonisation
 * ``physics``   Jordan-Wigner Fock space, Hubbard terms (Eq.
                 fermi-hubbard-ham), PEPS norm networks (Fig. 4)
-* ``bmps``      boundary-MPS contraction of square-lattice PEPS
+* ``amplitude`` amplitudes <n|psi>: projected single-layer networks and the
+                sign of fixing the physical legs
+* ``adjoint``   reverse-mode derivatives of contractions and networks
 """
 
-from . import symmetry, tensor, ops, linalg, network, dense, physics
+from . import symmetry, tensor, ops, linalg, network, dense, physics, amplitude, adjoint
 
-__all__ = ["symmetry", "tensor", "ops", "linalg", "network", "dense", "physics"]
+__all__ = ["symmetry", "tensor", "ops", "linalg", "network", "dense", "physics", "amplitude", "adjoint"]

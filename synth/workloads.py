@@ -181,3 +181,41 @@ def c5(lx=6, ly=6, chi=32):
     spec = z2_peps(n, edges, 2, 2)
     return dict(name="c5_z2_%dx%d_grad_chi%d" % (lx, ly, chi), spec=spec,
                 seed=seed_of(5), chi=chi, std=1.0, lx=lx, ly=ly)
+
+
+# --- amplitudes <n|psi> (projected single-layer networks) -------------------
+
+def amplitude_bonds(spec):
+    """Bonds ``(t1, leg1, t2, leg2)`` of the ket network in site-tensor legs.
+
+    Leg 0 of every site tensor is physical; the amplitude network joins the
+    bond legs (>= 1) of the site tensors, tensor id = site id.
+    """
+    out = []
+    for (a, b) in spec.edges:
+        out.append((a, spec.bond_leg(a, b), b, spec.bond_leg(b, a)))
+    return out
+
+
+def boundary_path(lx, ly):
+    """SSA path that absorbs an ``lx`` x ``ly`` square lattice row by row.
+
+    Sites are numbered row-major (``s = x * ly + y``). The boundary starts as
+    row 0; every later row is absorbed column by column (boundary tensor y
+    with site (x, y)), and the final boundary is contracted left to right.
+    """
+    n = lx * ly
+    cur = list(range(ly))
+    path = []
+    nxt = n
+    for x in range(1, lx):
+        for y in range(ly):
+            path.append((cur[y], x * ly + y))
+            cur[y] = nxt
+            nxt += 1
+    acc = cur[0]
+    for y in range(1, ly):
+        path.append((acc, cur[y]))
+        acc = nxt
+        nxt += 1
+    return path
