@@ -273,6 +273,30 @@ int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int
                          ftn_gemm gemm, ftn_stream_t stream, double* mantissa, int64_t* exp2,
                          ftn_tensor_t* open_out, int32_t* leg_src, double* stats);
 
+/* Amplitudes <n|psi> of a fermionic tensor network state (the coefficient
+   tensor of the ket network, Secs. II.D-II.E): for every sample k,
+   mantissa[k] * 2^exp2[k] = Psi_{n^k} for the configuration
+   n^k = configs[k * nsites + i], i = 0..nsites-1 (physical index of site i).
+   sites: nsites tensors whose leg 0 is the physical leg (borrowed); the site
+   order is the global order, so the coefficient has the physical legs in
+   site order. bond_ends: nbonds x (site, leg, site, leg) with legs >= 1 (the
+   closed network of the projected tensors; legs keep their numbering).
+   Each site tensor is projected on the physical index (entries T[n_i, ...],
+   computed once per distinct index), the closed network of projections is
+   contracted along ssa_path (nsites-1 steps) in the local convention with
+   compression to chi as ftn_contract_network does (chi <= 0: exact), and
+   the sign of fixing the physical legs, (-1)^E with
+   E = sum_i p(n_i) sum_{j<i} (p(T_j) + p(n_j)), is applied (the physical
+   leg of site i passes the bond legs of the earlier sites). Configurations
+   of the wrong total charge give mantissa 0. Samples are independent:
+   nworkers host threads (1..64), each with its own HIP stream, take them
+   from a shared counter. Inputs must be ready on `stream`; the call returns
+   when every amplitude is written (host arrays). */
+int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds, const int32_t* bond_ends,
+                   int nsteps, const int32_t* ssa_path, int64_t chi, ftn_gemm gemm, int64_t nsamples,
+                   const int32_t* configs, int nworkers, ftn_stream_t stream, double* mantissa,
+                   int64_t* exp2);
+
 /* ---------------------------------------------------------------------------
  * Kernel timing (measurement support)
  * ------------------------------------------------------------------------ */

@@ -540,6 +540,7 @@ struct Sect {
   int p = 0;             // number of singular values computed: ns or JMAX
   bool iterate = false;
   bool sideA = true;     // eigenvectors live on the A side (U) or the B side (V)
+  bool acc = false;      // d <= 128: accurate factors, X formed explicitly
   int kept = 0;
   Q charge;
   int crank = 0;
@@ -684,6 +685,138 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
   DBuf<int64_t> doff = to_device(off, s), ddim = to_device(dim, s);
   LAUNCH(k_zero_lower, dim3((unsigned)std::min<int64_t>(cdiv(dmax * dmax, 256), 4096), nm), dim3(256), 0, s, Gm,
          doff.p, ddim.p, nm);
+}
+
+// ---------------------------------------------------------------------------
+// Accurate triangular factors of small sectors (d <= 128). The Gram matrix
+// G = A^T A of a factor A (m x d) holds a direction of A with singular value
+// s only to about eps * |A|^2 / s^2, so directions below ~1e-8 of |A| are
+// lost, although the product X = R_A R_B^T can need them when the leading
+// directions of the two sides are nearly orthogonal. For d <= 128 the factor
+// is therefore taken as A itself when m <= d (R = A, rank m), and otherwise
+// by shifted Cholesky QR applied three times: R1 = chol(G + sigma I) with
+// sigma = 11 (m d + d (d + 1)) u |A|_F^2 (u = 2^-53), Q1 = A R1^-1, then two
+// dropping Cholesky QR passes on Q1, R = R3 R2 R1. The shift keeps the
+// first factorisation defined for any conditioning and the later passes
+// recover the small directions from A itself; rows whose pivot is not above
+// 1e-13 of the largest in a later pass (exact dependencies) are dropped.
+
+struct ShiftJob {
+  const double* G;  // d x d Gram matrix (ld d)
+  double* W;        // output G + sigma I (ld d)
+  int d;
+  int pad;
+  int64_t m;        // rows of the factor
+};
+
+__global__ void __launch_bounds__(256) k_shift_diag(const ShiftJob* jobs) {
+  const ShiftJob J = jobs[blockIdx.x];
+  const int d = J.d;
+  __shared__ double red[4];
+  double t = 0;
+  for (int i = threadIdx.x; i < d; i += 256) t += J.G[(int64_t)i * d + i];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  const double tr = red[0] + red[1] + red[2] + red[3];
+  const double sigma = 11.0 * ((double)J.m * d + (double)d * (d + 1)) * 0x1p-53 * tr;
+  for (int64_t e = threadIdx.x; e < (int64_t)d * d; e += 256) {
+    const int64_t i = e / d, c = e % d;
+    J.W[e] = J.G[e] + (i == c ? sigma : 0.0);
+  }
+}
+
+struct RowsJob {
+  const double* src;  // A (m x d, ld) or, transposed, B (d x m, ld)
+  double* dst;        // m x d (ld d)
+  int64_t ld, m;
+  int d, trans;
+};
+
+__global__ void k_copy_rows(const RowsJob* jobs) {
+  const RowsJob J = jobs[blockIdx.y];
+  const int64_t n = J.m * J.d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / J.d, c = e % J.d;
+    J.dst[e] = J.trans ? J.src[c * J.ld + i] : J.src[i * J.ld + c];
+  }
+}
+
+// one factor to refine: the source matrix is A (rows x d, ld) or B^T
+// (B is d x rows with ld, trans = 1), side 0 = A~ buffer, 1 = B~ buffer
+struct AccSrc {
+  int side;
+  int trans;
+  int64_t off, ld, m;
+  int64_t goff;  // Gram matrix and output R (d x d) offset
+  int d;
+};
+
+// R (d x d, zero rows for dropped directions) of every listed factor into
+// Rout at goff, from the Gram matrices Gm at goff and the sources
+static void acc_factor(const std::vector<AccSrc>& J, const double* At, const double* Bt, const double* Gm,
+                       double* Rout, hipStream_t s) {
+  const int nj = (int)J.size();
+  if (!nj) return;
+  std::vector<int64_t> wo(nj), qo(nj);
+  int64_t ws = 0, qs = 0;
+  for (int j = 0; j < nj; ++j) {
+    wo[j] = ws;
+    ws += (int64_t)J[j].d * J[j].d;
+    qo[j] = qs;
+    qs += J[j].m * J[j].d;
+  }
+  // W: R1 | R2 | R3 | M1 | M2 | T (each ws); Q: Q1 | Q2 (each qs)
+  DBuf<double> W(6 * ws, s), Q(2 * qs, s);
+  double *R1 = W.p, *R2 = W.p + ws, *R3 = W.p + 2 * ws, *M1 = W.p + 3 * ws, *M2 = W.p + 4 * ws;
+  {
+    std::vector<ShiftJob> sj(nj);
+    for (int j = 0; j < nj; ++j) sj[j] = ShiftJob{Gm + J[j].goff, R1 + wo[j], J[j].d, 0, J[j].m};
+    DBuf<ShiftJob> d = to_device(sj, s);
+    LAUNCH(k_shift_diag, dim3(nj), dim3(256), 0, s, d.p);
+  }
+  auto factor = [&](double* R, double* M, double tol) {
+    std::vector<OrthJob> oj(nj);
+    for (int j = 0; j < nj; ++j) {
+      OrthJob& o = oj[j];
+      o.G = R + wo[j];
+      o.R = R + wo[j];
+      o.M = M ? M + wo[j] : nullptr;
+      o.thr = nullptr;
+      o.p = o.ldg = o.ldr = o.ldm = J[j].d;
+    }
+    DBuf<OrthJob> d = to_device(oj, s);
+    FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)nj), dim3(LT), 0, s, d.p, tol);
+  };
+  // pass 1: no column is dropped (G + sigma I is positive definite)
+  factor(R1, M1, 0.0);
+  {
+    // Q1 = source * R1^-1, per side (the sources live in two buffers)
+    for (int side = 0; side < 2; ++side) {
+      std::vector<GemmGroup> g;
+      for (int j = 0; j < nj; ++j)
+        if (J[j].side == side)
+          g.push_back(plain_group(J[j].m, J[j].d, J[j].d, J[j].off, J[j].ld, J[j].trans, 3 * ws + wo[j], J[j].d, 0,
+                                  qo[j], J[j].d));
+      if (!g.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g, side ? Bt : At, W.p, Q.p, nullptr, s);
+    }
+  }
+  std::vector<GemmGroup> gg2, gq2, gg3, gt, gr;
+  for (int j = 0; j < nj; ++j) {
+    const int64_t d = J[j].d, m = J[j].m;
+    gg2.push_back(plain_group(d, d, m, qo[j], d, 1, qo[j], d, 0, ws + wo[j], d));               // G2 = Q1^T Q1
+    gq2.push_back(plain_group(m, d, d, qo[j], d, 0, 4 * ws + wo[j], d, 0, qs + qo[j], d));      // Q2 = Q1 M2
+    gg3.push_back(plain_group(d, d, m, qs + qo[j], d, 1, qs + qo[j], d, 0, 2 * ws + wo[j], d)); // G3 = Q2^T Q2
+    gt.push_back(plain_group(d, d, d, 2 * ws + wo[j], d, 0, ws + wo[j], d, 0, 5 * ws + wo[j], d));  // T = R3 R2
+    gr.push_back(plain_group(d, d, d, 5 * ws + wo[j], d, 0, wo[j], d, 0, J[j].goff, d));         // R = T R1
+  }
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gg2, Q.p, Q.p, W.p, nullptr, s);
+  factor(R2, M2, 1e-13);
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gq2, Q.p, W.p, Q.p, nullptr, s);
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gg3, Q.p, Q.p, W.p, nullptr, s);
+  factor(R3, nullptr, 1e-13);
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, W.p, W.p, W.p, nullptr, s);
+  run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gr, W.p, W.p, Rout, nullptr, s);
 }
 
 // Leading singular triplets of X = R_A R_B^T (rA x rB) per sector.
@@ -969,27 +1102,74 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
-  // G_A = R_A^T R_A and G_B = R_B^T R_B by dropping Cholesky (on a copy, the
-  // Gram matrices are needed again); the kept rows are packed into Rc
-  // (rank x d at the Gram offsets)
-  std::vector<int> ranks(2 * ng);
+  // G_A = R_A^T R_A and G_B = R_B^T R_B. Sectors with d <= 128 take the
+  // accurate factors (the factor itself when it has at most d rows, else
+  // shifted Cholesky QR three times); larger ones a dropping Cholesky of a
+  // copy of the Gram matrix (the Gram matrices are needed again). The kept
+  // rows are packed into Rc (rank x d at the Gram offsets).
+  std::vector<int> ranks(2 * ng, -1);
   DBuf<double> Rc(std::max<int64_t>(gsz, 1), s);
   {
     DBuf<double> Fm(std::max<int64_t>(gsz, 1), s);
-    HIPC(hipMemcpyAsync(Fm.p, Gm.p, gsz * 8, hipMemcpyDeviceToDevice, s));
-    std::vector<int64_t> offs, dims;
+    std::vector<int64_t> coffs, cdims, poffs, pdims;
+    std::vector<int> pidx;
+    std::vector<AccSrc> acc;
+    std::vector<RowsJob> rows;
+    int64_t maxrows = 0;
     for (int g = 0; g < ng; ++g) {
-      offs.push_back(goffA[g]);
-      dims.push_back(S[g].d);
-      offs.push_back(goffB[g]);
-      dims.push_back(S[g].d);
+      const Sect& x = S[g];
+      for (int side = 0; side < 2; ++side) {
+        const int64_t off = side ? goffB[g] : goffA[g];
+        const int64_t m = side ? x.N : x.M;
+        if (x.d > JMAX) {
+          HIPC(hipMemcpyAsync(Fm.p + off, Gm.p + off, x.d * x.d * 8, hipMemcpyDeviceToDevice, s));
+          coffs.push_back(off);
+          cdims.push_back(x.d);
+        } else if (m <= x.d) {
+          RowsJob r;
+          r.src = side ? Bt.p + x.b_off : At.p + x.a_off;
+          r.dst = Rc.p + off;
+          r.ld = side ? x.N : x.d;
+          r.m = m;
+          r.d = (int)x.d;
+          r.trans = side;
+          rows.push_back(r);
+          maxrows = std::max(maxrows, m * x.d);
+          ranks[2 * g + side] = (int)m;
+          continue;
+        } else {
+          AccSrc a;
+          a.side = side;
+          a.trans = side;
+          a.off = side ? x.b_off : x.a_off;
+          a.ld = side ? x.N : x.d;
+          a.m = m;
+          a.goff = off;
+          a.d = (int)x.d;
+          acc.push_back(a);
+        }
+        poffs.push_back(off);
+        pdims.push_back(x.d);
+        pidx.push_back(2 * g + side);
+      }
     }
-    chol_drop(Fm.p, offs, dims, 1e-13, s);
-    DBuf<int64_t> doff = to_device(offs, s), ddim = to_device(dims, s);
-    DBuf<int> drk(2 * ng, s);
-    LAUNCH(k_pack_rows, dim3(2 * ng), dim3(1024), 0, s, Fm.p, doff.p, ddim.p, Rc.p, drk.p);
-    HIPC(hipMemcpyAsync(ranks.data(), drk.p, 2 * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (!coffs.empty()) chol_drop(Fm.p, coffs, cdims, 1e-13, s);
+    acc_factor(acc, At.p, Bt.p, Gm.p, Fm.p, s);
+    if (!rows.empty()) {
+      DBuf<RowsJob> dr = to_device(rows, s);
+      LAUNCH(k_copy_rows, dim3((unsigned)std::min<int64_t>(cdiv(maxrows, 256), 1024), (unsigned)rows.size()),
+             dim3(256), 0, s, dr.p);
+    }
+    const int np = (int)poffs.size();
+    std::vector<int> prk(std::max(np, 1));
+    if (np) {
+      DBuf<int64_t> doff = to_device(poffs, s), ddim = to_device(pdims, s);
+      DBuf<int> drk(np, s);
+      LAUNCH(k_pack_rows, dim3(np), dim3(1024), 0, s, Fm.p, doff.p, ddim.p, Rc.p, drk.p);
+      HIPC(hipMemcpyAsync(prk.data(), drk.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     HIPC(hipStreamSynchronize(s));
+    for (int i = 0; i < np; ++i) ranks[pidx[i]] = prk[i];
   }
   // per sector: the side with the smaller rank (A when rA <= rB, and always
   // for iterated sectors) gives R = R_side, G_o = the other Gram matrix;
@@ -1005,8 +1185,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     x.iterate = x.ns > JMAX;
     x.p = x.iterate ? JMAX : x.ns;
     x.sideA = x.iterate || x.rA <= x.rB;
+    x.acc = x.d <= JMAX;
     xoff[g] = xs;
-    xs += x.iterate ? (int64_t)x.rA * x.rB : 0;
+    xs += (x.iterate || x.acc) ? (int64_t)x.rA * x.rB : 0;
     hoff[g] = hs;
     hs += x.iterate ? 0 : (int64_t)x.ns * x.ns;
     u1off[g] = u1s;
@@ -1021,7 +1202,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   HIPC(hipMemsetAsync(Lm.p, 0, std::max<int64_t>(ls, 1) * 8, s));
   {
     DBuf<double> U1(std::max<int64_t>(u1s, 1), s);
-    std::vector<GemmGroup> gx, gu, gh;
+    std::vector<GemmGroup> gx, gu, gh, gxs, gxh;
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.ns) continue;
@@ -1030,11 +1211,22 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         continue;
       }
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
+      if (x.acc) {
+        // accurate factors: X = R R_o^T (r x r_o), H = X X^T
+        const int64_t r = x.ns, r_o = x.sideA ? x.rB : x.rA;
+        gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
+        gxh.push_back(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r));
+        continue;
+      }
       // U1 = G_o R^T (d x r), H = R U1 (r x r)
       gu.push_back(plain_group(x.d, x.ns, x.d, go, x.d, 0, ro, x.d, 1, u1off[g], x.ns));
       gh.push_back(plain_group(x.ns, x.ns, x.d, ro, x.d, 0, u1off[g], x.ns, 0, hoff[g], x.ns));
     }
     if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rc.p, Rc.p, Xm.p, nullptr, s);
+    if (!gxs.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxh, Xm.p, Xm.p, Hm.p, nullptr, s);
+    }
     if (!gu.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Rc.p, U1.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Rc.p, U1.p, Hm.p, nullptr, s);
@@ -1115,18 +1307,37 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   }
   DBuf<double> PAB(std::max<int64_t>(pas, 1), s), Fk(std::max<int64_t>(fs, 1), s), GF(std::max<int64_t>(fs, 1), s);
   {
-    std::vector<GemmGroup> gf, ggf;
+    // with accurate factors GF = R_o^T (X^T E_k) replaces G_o F
+    std::vector<GemmGroup> gf, ggf, gw, gwf;
+    std::vector<int64_t> wo(ng);
+    int64_t wsz = 0;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      wo[g] = wsz;
+      if (x.kept && x.acc) wsz += (int64_t)(x.sideA ? x.rB : x.rA) * x.kept;
+    }
+    DBuf<double> Wk(std::max<int64_t>(wsz, 1), s);
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.kept) continue;
       const int64_t r = x.sideA ? x.rA : x.rB;
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
       gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
-      ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
+      if (x.acc) {
+        const int64_t r_o = x.sideA ? x.rB : x.rA;
+        gw.push_back(plain_group(r_o, x.kept, r, xoff[g], r_o, 1, eoff[g], x.p, 0, wo[g], x.kept));
+        gwf.push_back(plain_group(x.d, x.kept, r_o, go, x.d, 1, wo[g], x.kept, 0, fo[g], x.kept));
+      } else {
+        ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
+      }
     }
     if (!gf.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gf, Rc.p, Em.p, Fk.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggf, Gm.p, Fk.p, GF.p, nullptr, s);
+      if (!ggf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggf, Gm.p, Fk.p, GF.p, nullptr, s);
+      if (!gw.empty()) {
+        run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gw, Xm.p, Em.p, Wk.p, nullptr, s);
+        run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);
+      }
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
         if (!x.kept) continue;

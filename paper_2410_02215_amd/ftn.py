@@ -61,6 +61,7 @@ SIGNATURES = [
     ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
     ("ftn_net_free", _I, [_P]),
     ("ftn_contract_network", _I, [_P, _I, _PI32, _I64, _I, _P, _PD, _PI64, _PP, _PI32, _PD]),
+    ("ftn_amplitudes", _I, [_I, _PP, _I, _PI32, _I, _PI32, _I64, _I, _I64, _PI32, _I, _P, _PD, _PI64]),
     ("ftn_profile_enable", _I, [_I]),
     ("ftn_profile_collect", _I, [_PD, _PD, _PD]),
 ]
@@ -344,3 +345,31 @@ class Network:
             n = t.ndim
             return t, e.value, [(src[2 * k], src[2 * k + 1]) for k in range(n)], stats
         return m.value, e.value, stats
+
+
+def amplitudes(sites, bonds, path, configs, chi=0, gemm=GEMM_F64, nworkers=8):
+    """<n|psi> for every row of ``configs`` (physical index per site).
+
+    ``sites``: Tensors with the physical leg first, in global (site) order;
+    ``bonds``: (site, leg, site, leg) with legs >= 1; ``path``: SSA pairs over
+    the sites. Returns (mantissa, exp2) numpy arrays: amplitude = m * 2**e.
+    """
+    load_library()
+    cfg = np.ascontiguousarray(np.asarray(configs, dtype=np.int32))
+    if cfg.ndim != 2 or cfg.shape[1] != len(sites):
+        raise ValueError("configs must be (nsamples, nsites)")
+    ns = cfg.shape[0]
+    hs = (ctypes.c_void_p * len(sites))(*[t.h.value for t in sites])
+    ends = []
+    for b in bonds:
+        ends += [int(x) for x in b]
+    flat = []
+    for (i, j) in path:
+        flat += [int(i), int(j)]
+    m = np.zeros(ns, dtype=np.float64)
+    e = np.zeros(ns, dtype=np.int64)
+    _check(_lib.ftn_amplitudes(len(sites), hs, len(bonds), _arr(ends, ctypes.c_int32), len(path),
+                               _arr(flat, ctypes.c_int32), int(chi or 0), int(gemm), ns,
+                               cfg.ctypes.data_as(_PI32), int(nworkers), _stream(),
+                               m.ctypes.data_as(_PD), e.ctypes.data_as(_PI64)))
+    return m, e

@@ -119,6 +119,48 @@ def test_compress_bond_matches_oracle(P, sym, conv):
         np.testing.assert_allclose(ginfo["svals"], kept, rtol=1e-9)
 
 
+@pytest.mark.parametrize("sym", [S.Z2, S.U1])
+def test_compress_bond_odd_tensors(P, sym):
+    # network bodies of odd tensors are compressed without dummy legs
+    rng = np.random.default_rng(802)
+    for trial, (ta, tb) in enumerate([((1,), (1,)), ((1,), (0,)), ((0,), (1,)), ((1,), (1,))]):
+        bond = rand_leg(rng, sym, maxd=6)
+        A = rand_tensor(rng, sym, [rand_leg(rng, sym, maxd=3), bond, rand_leg(rng, sym, maxd=3)], total=ta)
+        B = rand_tensor(rng, sym, [partner(bond), rand_leg(rng, sym, maxd=3)], total=tb)
+        chi = int(rng.integers(2, 8))
+        A2, B2, info = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-6)
+        ref = ftensordot(A2, B2, [1], [0], "local").to_dense()
+        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-6, P.LOCAL)
+        assert GA.legs()[1][1] == list(A2.legs[1].dims)
+        got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_networks_with_odd_tensors_compressed(P, seed):
+    # odd tensors, parallel bonds fused and compressed: the sign bookkeeping
+    # of the dummies must agree with the oracle's materialised dummy legs
+    # (Z2: random U(1) totals almost never close to a nonzero value)
+    sym = S.Z2
+    rng = np.random.default_rng(710 + seed)
+    chi = 3
+    while True:
+        nt = int(rng.integers(4, 7))
+        tensors, bonds = random_network(rng, sym, nt, nt + 3, odd_frac=0.5, maxd=3)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        pos = [int(x) for x in rng.permutation(nt)]
+        path = random_ssa_path(rng, tensors, bonds)
+        onet = ONet(tensors, bonds, conv="local", positions=pos)
+        T, labs, e, infos = o_contract(onet, path, chi=chi)
+        ref = (float(T.blocks[()]) if () in T.blocks else 0.0) * 2.0 ** e
+        if ref != 0.0 and infos and sum(1 for t in tensors.values() if t.parity) >= 2:
+            break
+    gnet = P.Network([to_gpu(tensors[t]) for t in range(nt)], bonds, conv=P.LOCAL, positions=pos)
+    m, ge, _ = gnet.contract(path, chi=chi)
+    assert abs(_val(m, ge) - ref) <= 1e-9 * max(abs(ref), 1e-300), (m, ge, ref)
+
+
 def test_compress_large_sector_subspace_iteration(P):
     # bond sectors above 128 exercise the subspace-iteration SVD path
     rng = np.random.default_rng(801)
