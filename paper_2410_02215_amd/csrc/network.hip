@@ -470,6 +470,11 @@ extern "C" int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds,
       }
       if (ws) {
         (void)hipStreamSynchronize(ws);
+        try {
+          prof_retire_stream(ws);
+          retire_stream(ws);
+        } catch (...) {
+        }
         (void)hipStreamDestroy(ws);
       }
     };
