@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 PEAK = {"gemm_f64": (78.6, "TFLOP/s", "mfma"), "gemm_f32": (157.3, "TFLOP/s", "mfma"),
         "gemm_bf16x3": (2500.0, "TFLOP/s", "mfma"), "permute": (8000.0, "GB/s", "hbm"),
         "factor": (78.6, "TFLOP/s", "alu")}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_z2_rrg40_chi64.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def source_hash():
@@ -46,14 +46,14 @@ def source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, workload):
     """HBM bytes per launch of a class from the committed PMC summary, or None.
 
-    The summary records the source hash it was measured at; any change of
-    the library sources since then makes the figure stale (None).
+    The summary of a workload records the source hash it was measured at;
+    any change of the library sources since then makes the figure stale.
     """
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(PROFILES, "hbm_traffic_%s.md" % workload)) as f:
             text = f.read()
     except OSError:
         return None
@@ -147,6 +147,96 @@ def cpu_baseline(cfg, paths):
                 log2_norm=math.log2(abs(m)) + e if m else None)
 
 
+def amplitude_setup(cfg):
+    import torch
+    from paper_2410_02215_amd import peps as GP
+    from synth import workloads as W
+    from synth.peps import occupation_samples
+    spec = cfg["spec"]
+    kets = GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
+    torch.cuda.synchronize()
+    return dict(kets=kets, bonds=W.amplitude_bonds(spec), path=W.boundary_path(cfg["lx"], cfg["ly"]),
+                samples=occupation_samples(spec.n_sites, cfg["n_samples"], cfg["seed"] + 1))
+
+
+def amplitude_cpu_baseline(cfg, g, n):
+    """The oracle on the host cores: n amplitudes of the same workload, timed."""
+    import torch
+    from oracle import physics as OP
+    from oracle.amplitude import amplitude
+    from synth import workloads as W
+    spec = cfg["spec"]
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    kets = OP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
+    t0 = time.time()
+    for c in g["samples"][:n]:
+        amplitude(kets, g["bonds"], c, g["path"], chi=cfg["chi"])
+    el = time.time() - t0
+    return dict(value=n / el, unit="contractions/s", cores=cores, kind="oracle",
+                sample="%d amplitudes <n|psi> of the same workload, one after the other (%.1f s, FP64, torch "
+                       "CPU with %d threads)" % (n, el, cores))
+
+
+def main_amplitudes(args):
+    """Amplitude workload: a step is one batch of sampled configurations."""
+    import torch
+    import paper_2410_02215_amd as P
+    from synth import workloads as W
+    cfg = W.c4()
+    g = amplitude_setup(cfg)
+    B = args.batch
+    need = B * (args.warmup + args.steps)
+    if need > len(g["samples"]):
+        raise SystemExit("batch x (warmup + steps) exceeds the %d samples" % len(g["samples"]))
+    print("[bench] workload %s: batch %d, workers %d" % (cfg["name"], B, args.workers), file=sys.stderr, flush=True)
+    k = 0
+    for _ in range(args.warmup):
+        P.amplitudes(g["kets"], g["bonds"], g["path"], g["samples"][k:k + B], chi=cfg["chi"], nworkers=args.workers)
+        k += B
+        print("[bench] warmup batch done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    P.ftn.profile_collect()
+    P.ftn.profile_enable(True)
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        m, e = P.amplitudes(g["kets"], g["bonds"], g["path"], g["samples"][k:k + B], chi=cfg["chi"],
+                            nworkers=args.workers)
+        k += B
+        print("[bench] batch %d done" % st, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.ftn.profile_enable(False)
+    prof = P.ftn.profile_collect()
+    el = t1 - t0
+    out = {
+        "metric": "ftensordot useful TFLOP/s + fPEPS contractions/sec on 1 GPU at stated err vs FP64",
+        "value": B * args.steps / el, "unit": "contractions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": cfg["chi"],
+                   "amplitudes_per_step": B, "workers": args.workers},
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "roofline": roofline(prof, cfg["name"]),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, %d amplitudes)" % args.cpu_samples, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = amplitude_cpu_baseline(cfg, g, args.cpu_samples)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(prof, workload):
+    """Roofline entry of the dominant kernel class by time."""
+    dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
+    ms, cnt, work = prof[dom]
+    peak, unit, bound = PEAK[dom]
+    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    achieved = work / (ms * 1e-3) / scale if ms > 0 else 0.0
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": measured_traffic(dom, workload), "kernel": dom, "launches": cnt,
+            "avg_launch_ms": ms / max(cnt, 1), "work_per_launch": work / max(cnt, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +244,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true", help="run the two contractions of a step one after the other")
+    ap.add_argument("--workload", choices=["c2", "amplitudes"], default="c2",
+                    help="c2: the 40-site norm and hopping contractions (default); amplitudes: <n|psi> of the "
+                         "8x8 lattice at chi = 36")
+    ap.add_argument("--batch", type=int, default=64, help="amplitudes per step (amplitude workload)")
+    ap.add_argument("--workers", type=int, default=4, help="host worker threads (amplitude workload)")
+    ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a single approximate contraction does not shard "
@@ -166,6 +262,8 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     P.load_library()
+    if args.workload == "amplitudes":
+        return main_amplitudes(args)
     cfg = W.c2()
     chi = cfg["chi"]
     paths = load_paths()
@@ -195,14 +293,7 @@ def main():
     norm = res[0] * 2.0 ** res[1]
     hop = (res[2] / res[0]) * 2.0 ** (res[3] - res[1])
     # dominant kernel class by time (HIP events on the library's streams)
-    dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
-    ms, cnt, work = prof[dom]
-    peak, unit, bound = PEAK[dom]
-    scale = 1e12 if unit == "TFLOP/s" else 1e9
-    achieved = work / (ms * 1e-3) / scale if ms > 0 else 0.0
-    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic(dom), "kernel": dom, "launches": cnt,
-            "avg_launch_ms": ms / max(cnt, 1), "work_per_launch": work / max(cnt, 1)}
+    roof = roofline(prof, cfg["name"])
     out = {
         "metric": "ftensordot useful TFLOP/s + fPEPS contractions/sec on 1 GPU at stated err vs FP64",
         "value": value, "unit": "contractions/s", "n_gpus": 1, "steps": args.steps,
