@@ -42,7 +42,9 @@
  *     ftn_set_allocator).
  *   - Streams: work is enqueued on the given stream. Calls that must know a
  *     data-dependent size (block counts of a new structure, the dims kept by
- *     a truncation) synchronise that stream before returning.
+ *     a truncation) synchronise that stream before returning. A tensor's
+ *     memory is released in the order of the stream that created it, so that
+ *     stream must outlive the tensor.
  *   - Threads: a handle must not be used by two threads at once.
  */
 #ifndef FTN_H
@@ -289,8 +291,8 @@ int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int
    E = sum_i p(n_i) sum_{j<i} (p(T_j) + p(n_j)), is applied (the physical
    leg of site i passes the bond legs of the earlier sites). Configurations
    of the wrong total charge give mantissa 0. Samples are independent:
-   nworkers host threads (1..64), each with its own HIP stream, take them
-   from a shared counter. Inputs must be ready on `stream`; the call returns
+   nworkers host threads (1..64), each with its own HIP stream (created on
+   first use and kept by the library), take them from a shared counter. Inputs must be ready on `stream`; the call returns
    when every amplitude is written (host arrays). */
 int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds, const int32_t* bond_ends,
                    int nsteps, const int32_t* ssa_path, int64_t chi, ftn_gemm gemm, int64_t nsamples,

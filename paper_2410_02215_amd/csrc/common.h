@@ -85,10 +85,6 @@ void dfree(void* p, hipStream_t s, bool persistent = false);
 // host-to-device copy ordered on s; small copies go through a pinned staging
 // ring so that they are asynchronous, and src may be reused on return
 void h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
-// call after synchronising a stream and before destroying it: the staging
-// ring, the allocator cache and the profiler stop referring to it
-void retire_stream(hipStream_t s);
-void prof_retire_stream(hipStream_t s);
 
 template <typename T>
 struct DBuf {  // owning device buffer, released stream-ordered

@@ -47,16 +47,19 @@ __device__ inline double wave_max(double v) {
 // Cyclic Jacobi eigensolver for a symmetric n x n matrix (n <= 128), one
 // workgroup per matrix, in two phases.
 // Phase 1 keeps the upper triangle in LDS and sweeps it in round-robin
-// order: per round, n/2 disjoint rotations are chosen, then every 2 x 2
-// block (pair k1, pair k2) is updated as J_k1^T A J_k2 by one thread, which
-// needs one barrier per round and no eigenvector traffic. The rotations are
-// logged to global memory. Phase 2 reuses the LDS for V = I and replays the
+// order: per round, n/2 disjoint rotations are chosen (every wave computes
+// all of them, one per lane, and takes the ones it needs by cross-lane
+// reads), then every 2 x 2 block (pair k1, pair k2) is updated as
+// J_k1^T A J_k2 by one thread (a fixed list of at most three blocks per
+// thread). A round needs two barriers (inputs read, updates written) and no
+// eigenvector traffic. The rotations are logged to global memory. Phase 2 reuses the LDS for V = I and replays the
 // log: each wave owns a set of rows of V and applies every round to them
 // (lane k = rotation k), so rounds need no workgroup barrier. Sweeps stop
 // when the off-diagonal norm^2 is <= 1e-30 of the diagonal norm^2.
 // Outputs: eigenvalues descending (ties: lower index first) and the matching
 // eigenvector columns (row-major n x n).
 constexpr int JAC_SWEEPS = 30;
+constexpr int NPAIR = 3;  // block pairs per thread: 64 * 65 / 2 <= 3 * 1024
 
 struct EigJob {
   const double* H;  // n x n input
@@ -95,8 +98,6 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
   const int n = J.n;
   if (n <= 0) return;
   __shared__ double A[JMAX][JMAX + 1];
-  __shared__ double2 cs[JMAX / 2];
-  __shared__ int pq[JMAX / 2];
   __shared__ double ev[JMAX];
   __shared__ int rk[JMAX];
   __shared__ double red[2][LT / 64];
@@ -108,6 +109,24 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
     if (i <= j) A[i][j] = (j < n) ? J.H[(int64_t)i * n + j] : 0.0;
   }
   __syncthreads();
+  // the block pairs (k1 <= k2) this thread updates every round
+  int pk1[NPAIR], pk2[NPAIR];
+  bool pact[NPAIR];
+  {
+    const int npairs = np * (np + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < NPAIR; ++u) {
+      const int e = tid + u * LT;
+      pact[u] = e < npairs;
+      int k1 = 0, rem = pact[u] ? e : 0;
+      while (rem >= np - k1) {
+        rem -= np - k1;
+        ++k1;
+      }
+      pk1[u] = k1;
+      pk2[u] = k1 + rem;
+    }
+  }
   int nr = 0;  // rounds done (the same in every thread)
   for (int sweep = 0; sweep < JAC_SWEEPS; ++sweep) {
     double off = 0.0, tot = 0.0;
@@ -136,49 +155,71 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
     __syncthreads();
     if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
     for (int r = 0; r < n2 - 1; ++r, ++nr) {
-      if (tid < np) {
-        int p, q;
-        rr_pair(n2, r, tid, p, q);
-        double c = 1.0, s = 0.0;
+      // every wave computes the round's rotations (lane k: pair k) and takes
+      // the ones it needs by cross-lane reads (no shared-memory round trip)
+      int p = 0, q = 0;
+      double c = 1.0, sn = 0.0;
+      if (lane < np) {
+        rr_pair(n2, r, lane, p, q);
         const double apq = A[p][q];
         if (apq != 0.0) {
           const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
           const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
+          sn = t * c;
         }
-        cs[tid] = make_double2(c, s);
-        pq[tid] = p | (q << 16);
-        J.rot[(int64_t)nr * np + tid] = make_double2(c, s);
-        J.rpq[(int64_t)nr * np + tid] = p | (q << 16);
+        if (w == 0) {
+          J.rot[(int64_t)nr * np + lane] = make_double2(c, sn);
+          J.rpq[(int64_t)nr * np + lane] = p | (q << 16);
+        }
       }
-      __syncthreads();
-      for (int e = tid; e < np * np; e += LT) {
-        const int k1 = e / np, k2 = e % np;
-        if (k1 > k2) continue;
-        const int v1 = pq[k1];
-        const int p1 = v1 & 0xffff, q1 = v1 >> 16;
-        const double2 r1 = cs[k1];
-        if (k1 == k2) {
-          const double apq = A[p1][q1], t = r1.y / r1.x;
-          A[p1][p1] -= t * apq;
-          A[q1][q1] += t * apq;
-          A[p1][q1] = 0.0;
+      const int pq_l = p | (q << 16);
+      double b[NPAIR][4];
+      int ad[NPAIR][4];
+      double2 r1v[NPAIR], r2v[NPAIR];
+#pragma unroll
+      for (int u = 0; u < NPAIR; ++u) {
+        // all lanes take part in the cross-lane reads (uniform control flow)
+        const int v1 = __shfl(pq_l, pk1[u]), v2 = __shfl(pq_l, pk2[u]);
+        r1v[u] = make_double2(__shfl(c, pk1[u]), __shfl(sn, pk1[u]));
+        r2v[u] = make_double2(__shfl(c, pk2[u]), __shfl(sn, pk2[u]));
+        const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
+        if (pk1[u] == pk2[u]) {
+          ad[u][0] = p1 * (JMAX + 1) + p1;
+          ad[u][1] = p1 * (JMAX + 1) + q1;
+          ad[u][2] = q1 * (JMAX + 1) + q1;
+          ad[u][3] = ad[u][1];
         } else {
-          const int v2 = pq[k2];
-          const int p2 = v2 & 0xffff, q2 = v2 >> 16;
-          const double2 r2 = cs[k2];
-          double* a00 = &A[min(p1, p2)][max(p1, p2)];
-          double* a01 = &A[min(p1, q2)][max(p1, q2)];
-          double* a10 = &A[min(q1, p2)][max(q1, p2)];
-          double* a11 = &A[min(q1, q2)][max(q1, q2)];
-          const double b00 = *a00, b01 = *a01, b10 = *a10, b11 = *a11;
-          const double r00 = r1.x * b00 - r1.y * b10, r01 = r1.x * b01 - r1.y * b11;
-          const double r10 = r1.y * b00 + r1.x * b10, r11 = r1.y * b01 + r1.x * b11;
-          *a00 = r2.x * r00 - r2.y * r01;
-          *a01 = r2.y * r00 + r2.x * r01;
-          *a10 = r2.x * r10 - r2.y * r11;
-          *a11 = r2.y * r10 + r2.x * r11;
+          ad[u][0] = min(p1, p2) * (JMAX + 1) + max(p1, p2);
+          ad[u][1] = min(p1, q2) * (JMAX + 1) + max(p1, q2);
+          ad[u][2] = min(q1, p2) * (JMAX + 1) + max(q1, p2);
+          ad[u][3] = min(q1, q2) * (JMAX + 1) + max(q1, q2);
+        }
+      }
+      double* Af = &A[0][0];
+#pragma unroll
+      for (int u = 0; u < NPAIR; ++u)
+        if (pact[u])
+          for (int z = 0; z < 4; ++z) b[u][z] = Af[ad[u][z]];
+      // every wave has read its rotation inputs (the diagonal entries and
+      // a_pq of each pair) before any of them is overwritten
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NPAIR; ++u) {
+        if (!pact[u]) continue;
+        const double2 ra = r1v[u], rb = r2v[u];
+        if (pk1[u] == pk2[u]) {
+          const double apq = b[u][1], t = ra.y / ra.x;
+          Af[ad[u][0]] = b[u][0] - t * apq;
+          Af[ad[u][2]] = b[u][2] + t * apq;
+          Af[ad[u][1]] = 0.0;
+        } else {
+          const double r00 = ra.x * b[u][0] - ra.y * b[u][2], r01 = ra.x * b[u][1] - ra.y * b[u][3];
+          const double r10 = ra.y * b[u][0] + ra.x * b[u][2], r11 = ra.y * b[u][1] + ra.x * b[u][3];
+          Af[ad[u][0]] = rb.x * r00 - rb.y * r01;
+          Af[ad[u][1]] = rb.y * r00 + rb.x * r01;
+          Af[ad[u][2]] = rb.x * r10 - rb.y * r11;
+          Af[ad[u][3]] = rb.y * r10 + rb.x * r11;
         }
       }
       __syncthreads();
@@ -193,14 +234,35 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
   }
   __syncthreads();
   if (lane < np) {
-    for (int t = 0; t < nr; ++t) {
-      const double2 r = J.rot[(int64_t)t * np + lane];
-      const int v = J.rpq[(int64_t)t * np + lane];
-      const int p = v & 0xffff, q = v >> 16;
-      for (int i = w; i < n2; i += LT / 64) {
-        const double vp = A[i][p], vq = A[i][q];
-        A[i][p] = r.x * vp - r.y * vq;
-        A[i][q] = r.y * vp + r.x * vq;
+    // the log is read PF rounds ahead so that its latency hides behind the
+    // updates of the rounds in between
+    constexpr int PF = 8;
+    double2 rb[PF];
+    int vb[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (k < nr) {
+        rb[k] = J.rot[(int64_t)k * np + lane];
+        vb[k] = J.rpq[(int64_t)k * np + lane];
+      }
+    for (int t0 = 0; t0 < nr; t0 += PF) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int t = t0 + k;
+        if (t < nr) {
+          const double2 r = rb[k];
+          const int v = vb[k];
+          if (t + PF < nr) {
+            rb[k] = J.rot[(int64_t)(t + PF) * np + lane];
+            vb[k] = J.rpq[(int64_t)(t + PF) * np + lane];
+          }
+          const int p = v & 0xffff, q = v >> 16;
+          for (int i = w; i < n2; i += LT / 64) {
+            const double vp = A[i][p], vq = A[i][q];
+            A[i][p] = r.x * vp - r.y * vq;
+            A[i][q] = r.y * vp + r.x * vq;
+          }
+        }
       }
     }
   }

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -348,7 +349,22 @@ extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ss
 // arrow head this contraction carries no sign, so it is exactly T[v, ...].
 // Every projection needed is made once; samples then run as independent
 // closed networks, pulled from a shared counter by worker threads that each
-// own a HIP stream.
+// own a HIP stream. The worker streams are created once per device and kept
+// for the life of the process.
+
+static std::mutex g_ws_mu;
+static std::map<int, std::vector<hipStream_t>> g_ws;
+
+static std::vector<hipStream_t> worker_streams(int dev, int n) {
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  std::vector<hipStream_t>& v = g_ws[dev];
+  while ((int)v.size() < n) {
+    hipStream_t st = nullptr;
+    HIPC(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    v.push_back(st);
+  }
+  return std::vector<hipStream_t>(v.begin(), v.begin() + n);
+}
 
 static std::unique_ptr<Tensor> one_hot_partner(const Tensor& t, int64_t v, hipStream_t s) {
   const int sym = t.sym();
@@ -427,11 +443,11 @@ extern "C" int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds,
     std::mutex mu;
     int err_code = 0;
     std::string err_msg;
-    auto work = [&]() {
-      hipStream_t ws = nullptr;
+    const std::vector<hipStream_t> wss = worker_streams(dev, nw);
+    auto work = [&](int w) {
+      hipStream_t ws = wss[w];
       try {
         HIPC(hipSetDevice(dev));
-        HIPC(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
         std::vector<const Tensor*> P(nsites);
         for (;;) {
           const int64_t k = next.fetch_add(1);
@@ -468,19 +484,11 @@ extern "C" int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds,
         }
         stop = true;
       }
-      if (ws) {
-        (void)hipStreamSynchronize(ws);
-        try {
-          prof_retire_stream(ws);
-          retire_stream(ws);
-        } catch (...) {
-        }
-        (void)hipStreamDestroy(ws);
-      }
+      (void)hipStreamSynchronize(ws);
     };
     std::vector<std::thread> th;
-    for (int w = 1; w < nw; ++w) th.emplace_back(work);
-    work();
+    for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+    work(0);
     for (auto& t : th) t.join();
     if (err_code) fail(err_code, err_msg);
   });

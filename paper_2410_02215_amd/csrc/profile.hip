@@ -70,15 +70,6 @@ void prof_end(void* tok, hipStream_t s, int cls, double work) {
   if (g_recs.size() > 4096) drain_locked();
 }
 
-// before a stream is destroyed: resolve every pending record and drop the
-// pooled events (any of them may last have been recorded on that stream)
-void prof_retire_stream(hipStream_t) {
-  std::lock_guard<std::mutex> g(g_mu);
-  drain_locked();
-  for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
-  g_pool.clear();
-}
-
 void prof_enable(int on) {
   std::lock_guard<std::mutex> g(g_mu);
   drain_locked();

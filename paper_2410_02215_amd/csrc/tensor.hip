@@ -62,7 +62,6 @@ struct Block {
   size_t size;
   hipStream_t s;
   hipEvent_t ev;  // recorded at release (for reuse on another stream)
-  bool ready;     // its stream was retired: reusable on any stream at once
 };
 struct DevCache {
   std::multimap<size_t, Block> free_;      // by size
@@ -107,7 +106,7 @@ void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
   DevCache& c = (*g_cache)[dev];
   for (auto it = c.free_.lower_bound(sz); it != c.free_.end() && it->first <= 2 * sz; ++it) {
     Block& b = it->second;
-    if (!b.ready && b.s != s && (!b.ev || hipEventQuery(b.ev) != hipSuccess)) {
+    if (b.s != s && (!b.ev || hipEventQuery(b.ev) != hipSuccess)) {
       (void)hipGetLastError();
       continue;
     }
@@ -148,7 +147,7 @@ void dfree(void* p, hipStream_t s, bool persistent) {
   DevCache& c = (*g_cache)[dev];
   auto it = c.live.find(p);
   if (it == c.live.end()) return;  // not from this cache
-  Block b{p, it->second, s, nullptr, false};
+  Block b{p, it->second, s, nullptr};
   c.live.erase(it);
   if (!c.events.empty()) {
     b.ev = c.events.back();
@@ -215,37 +214,6 @@ void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   g_ring_used[c] = true;
   g_ring_st[c] = s;
   g_ring_off = (g_ring_off + bytes + 255) & ~(size_t)255;
-}
-
-// A stream about to be destroyed (the caller has synchronised it, so every
-// copy and release recorded on it is complete): no event of the staging
-// ring or of the cache may keep referring to it.
-void retire_stream(hipStream_t s) {
-  {
-    std::lock_guard<std::mutex> g(g_ring_mu);
-    if (g_ring)
-      for (size_t c = 0; c < RING_N; ++c)
-        if (g_ring_st[c] == s) {
-          (void)hipEventDestroy(g_ring_ev[c]);
-          HIPC(hipEventCreateWithFlags(&g_ring_ev[c], hipEventDisableTiming));
-          g_ring_used[c] = false;
-          g_ring_st[c] = nullptr;
-        }
-  }
-  std::lock_guard<std::mutex> g(g_cache_mu);
-  for (auto& dc : *g_cache) {
-    for (auto& kv : dc.second.free_) {
-      Block& b = kv.second;
-      if (b.s != s) continue;
-      if (b.ev) (void)hipEventDestroy(b.ev);
-      b.ev = nullptr;
-      b.s = nullptr;
-      b.ready = true;
-    }
-    // pooled events may last have been recorded on s
-    for (hipEvent_t e : dc.second.events) (void)hipEventDestroy(e);
-    dc.second.events.clear();
-  }
 }
 
 // ---------------------------------------------------------------------------
