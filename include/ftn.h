@@ -238,6 +238,25 @@ int ftn_compress_bond(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int6
                       ftn_tensor_t* b_out, double* discarded_weight, double* svals,
                       int64_t* nkept);
 
+/* Adjoint of ftn_compress_bond: for cotangents da_out, db_out of its outputs
+   (structures of a_out, b_out), the cotangents da, db (structures of a, b,
+   new handles) of the map (a, b) -> (a_out, b_out) computed with the same
+   arguments, the number of values kept per charge held fixed. This is the
+   derivative of the truncated SVD of the bond matrix C = A~ B~ per charge
+   (Sec. II.A): with C = U S V^T and a_out = U_k S_k^1/2, b_out = S_k^1/2 V_k^T,
+   dC = U Y V^T + (I - U U^T) G_u S_k^-1 V_k^T + U_k S_k^-1 G_v^T (I - V V^T),
+   G_u = da_out S_k^1/2, G_v = db_out^T S_k^1/2, and Y the usual coupling
+   matrix (s_i^2 - s_j^2)^-1 over all nonzero singular values; then
+   dA~ = dC B~^T and dB~ = A~^T dC, run back through the signed permutes.
+   Valid for losses unchanged by a_out -> a_out D, b_out -> D b_out with D
+   diagonal +-1 (sign of each kept singular vector pair); couplings of
+   singular values closer than 1e-13 s_max^2 are dropped. FP64 only
+   (FTN_ENOTSUP otherwise); bond sectors of dimension up to 128 (FTN_ENOTSUP
+   for larger ones). Synchronises the stream. */
+int ftn_compress_bond_backward(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int64_t chi,
+                               double cutoff, ftn_conv conv, ftn_tensor_t da_out, ftn_tensor_t db_out,
+                               ftn_stream_t stream, ftn_tensor_t* da, ftn_tensor_t* db);
+
 /* ---------------------------------------------------------------------------
  * Networks (Secs. II.C-II.E; Fig. 1)
  * ------------------------------------------------------------------------ */

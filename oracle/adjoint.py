@@ -12,6 +12,8 @@ they inherit its signs: nothing is re-derived here.
   given output cotangent dC, i.e. the gradients of <dC, C>.
 * ``network_grad``: value of a closed network and its gradient with respect
   to every allowed entry of every tensor.
+* ``compress_vjp``: cotangents of bond compression (Sec. II.A truncated SVD),
+  by reverse mode through the oracle's QR and SVD with the kept counts fixed.
 """
 
 import torch
@@ -82,3 +84,27 @@ def network_grad(net, path):
             i += 1
         grads[t] = o
     return (0.0 if b is None else float(b.detach())), grads
+
+
+def compress_vjp(A, B, la, lb, chi, dA2, dB2, conv="local", cutoff=1e-6):
+    """(dA, dB) = gradients of <dA2, A2> + <dB2, B2> for (A2, B2) =
+    compress_bond(A, B, ...), by reverse mode through the QR and SVD of
+    ``linalg.compress_bond`` (the kept counts are fixed by the forward)."""
+    from .linalg import compress_bond
+    A1, B1 = _leaf_copy(A), _leaf_copy(B)
+    A2, B2, _ = compress_bond(A1, B1, la, lb, chi, conv=conv, cutoff=cutoff)
+    L = inner(dA2, A2) + inner(dB2, B2)
+    outs = []
+    leaves = [A1, B1]
+    flat = [T.blocks[k] for T in leaves for k in T.keys()]
+    gs = torch.autograd.grad(L, flat, allow_unused=True) if (flat and torch.is_tensor(L) and L.requires_grad) \
+        else [None] * len(flat)
+    i = 0
+    for T in leaves:
+        o = FTensor(T.sym, T.legs, T.total)
+        for k in T.keys():
+            g = gs[i]
+            o.blocks[k] = torch.zeros_like(T.blocks[k].detach()) if g is None else g.detach()
+            i += 1
+        outs.append(o)
+    return outs[0], outs[1]

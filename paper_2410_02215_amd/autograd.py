@@ -8,6 +8,9 @@ the block layouts by the inverse signed permutes. ``transpose`` is a
 differentiable ``ftranspose``: a signed permutation is orthogonal, so its
 adjoint is the inverse permutation with the same signs.
 
+``compress`` is a differentiable ``compress_bond`` through
+``ftn_compress_bond_backward`` (the truncated-SVD derivative).
+
 ``contract_exact`` contracts a network in the local convention (Sec. II.E,
 Eq. fermionictn2) along an SSA path with these operations, so that
 ``torch.autograd`` differentiates the network value with respect to the
@@ -113,6 +116,40 @@ class _Transpose(torch.autograd.Function):
         legs = [a.legs[p] for p in perm]
         D = ftn.Tensor.create(a.sym, legs, a.total, a.dtype, data=dt.detach().contiguous())
         return ftn.ftranspose(D, inv).data(), None, None, None
+
+
+class _Compress(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a_data, b_data, a, b, la, lb, chi, cutoff, conv, out):
+        A, B = a.handle(a_data), b.handle(b_data)
+        A2, B2, _ = ftn.compress_bond(A, B, la, lb, chi, cutoff, conv)
+        sa = (A2.legs(), A2.info()["total"])
+        sb = (B2.legs(), B2.info()["total"])
+        out.append((sa, sb))
+        ctx.A, ctx.B = A, B
+        ctx.args = (a.sym, la, lb, chi, cutoff, conv, sa, sb)
+        return A2.data(), B2.data()
+
+    @staticmethod
+    def backward(ctx, dA2, dB2):
+        sym, la, lb, chi, cutoff, conv, sa, sb = ctx.args
+        DA = ftn.Tensor.create(sym, sa[0], sa[1], ftn.F64, data=dA2.detach().contiguous())
+        DB = ftn.Tensor.create(sym, sb[0], sb[1], ftn.F64, data=dB2.detach().contiguous())
+        da, db = ftn.compress_bond_backward(ctx.A, ctx.B, la, lb, chi, DA, DB, cutoff, conv)
+        return da.data(), db.data(), None, None, None, None, None, None, None, None
+
+
+def compress(a, b, la, lb, chi, cutoff=1e-6, conv=ftn.LOCAL):
+    """Differentiable compress_bond of two FP64 DTensors (kept counts fixed).
+
+    The backward pass is ``ftn_compress_bond_backward``, the derivative of
+    the truncated SVD; it holds for losses that do not depend on the sign of
+    each kept singular vector pair (e.g. any function of the product).
+    """
+    st = []
+    da, db = _Compress.apply(a.data, b.data, a, b, int(la), int(lb), int(chi), float(cutoff), int(conv), st)
+    (la_, ta), (lb_, tb) = st[0]
+    return DTensor(a.sym, la_, ta, da), DTensor(b.sym, lb_, tb, db)
 
 
 def dot(a, b, axes_a, axes_b, conv=ftn.LOCAL, gemm=ftn.GEMM_F64):

@@ -260,6 +260,23 @@ int ftn_compress_bond(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int6
   });
 }
 
+int ftn_compress_bond_backward(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int64_t chi, double cutoff,
+                               ftn_conv conv, ftn_tensor_t da_out, ftn_tensor_t db_out, ftn_stream_t stream,
+                               ftn_tensor_t* da, ftn_tensor_t* db) {
+  return guarded([&] {
+    if (!da || !db) fail(FTN_EINVAL, "null out");
+    if (chi < 1) fail(FTN_EINVAL, "chi must be >= 1");
+    const Tensor& x = T(a);
+    const Tensor& y = T(b);
+    if (leg_a < 0 || leg_a >= x.ndim() || leg_b < 0 || leg_b >= y.ndim()) fail(FTN_EINVAL, "leg out of range");
+    std::unique_ptr<Tensor> ga, gb;
+    op_compress_bond_backward(x, y, leg_a, leg_b, chi, cutoff, conv, T(da_out), T(db_out), (hipStream_t)stream, ga,
+                              gb);
+    *da = wrap(std::move(ga));
+    *db = wrap(std::move(gb));
+  });
+}
+
 }  // extern "C"
 
 // helpers for the network driver (same translation unit family)

@@ -364,6 +364,11 @@ struct CompressResult {
 };
 CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi,
                                 double cutoff, int conv, hipStream_t s);
+// cotangents (da, db) of compress_bond for cotangents (dao, dbo) of its
+// outputs (kept counts fixed; FP64; bond sectors up to 128)
+void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff,
+                               int conv, const Tensor& dao, const Tensor& dbo, hipStream_t s,
+                               std::unique_ptr<Tensor>& da, std::unique_ptr<Tensor>& db);
 double op_max_abs(const Tensor& a, hipStream_t s);  // synchronises
 
 // contraction plans (shared with the compression code)
@@ -378,6 +383,11 @@ struct DotPlanView {
 std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
                                   const std::vector<int>& axb, int conv, int gemm, hipStream_t s);
 DotPlanView dot_plan_view(const DotPlan& p);
+// the fused per-group matrices (group g: M_g x N_g row-major at f_off[g], the
+// GEMM output layout before the block scatter) of a tensor c that has the
+// plan's output structure; F may be null to get only the size
+int64_t dot_gather_output(const DotPlan& P, const Tensor& c, double* F, std::vector<int64_t>& f_off,
+                          hipStream_t s);
 // adjoint of op_ftensordot: da, db (structures of a, b) from dc
 void op_ftensordot_backward(const Tensor& a, const Tensor& b, const Tensor& dc, const std::vector<int>& axa,
                             const std::vector<int>& axb, int conv, int gemm, hipStream_t s,

@@ -329,7 +329,9 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   std::vector<GemmGroup> groups;
   int64_t boff_n = 0;
   for (int g = 0; g < G; ++g) {
-    if (N[g] == 0) continue;
+    // a group without rows or columns writes nothing (and the GEMM plan
+    // drops it, so the charge list must skip it too)
+    if (N[g] == 0 || M[g] == 0) continue;
     GemmGroup gg;
     std::memset(&gg, 0, sizeof(gg));
     gg.M = M[g];
@@ -504,6 +506,28 @@ __global__ void k_gather_fused(const GemmGroup* __restrict__ groups, int ng, con
   const int64_t cnd = sc.cc_dim[G.cc_base + cgj];
   const int64_t bo = sc.boff[G.boff_base + (int64_t)rfi * G.ncc + cgj];
   F[e] = bo >= 0 ? dC[bo + rlr * cnd + clc] : T(0);
+}
+
+int64_t dot_gather_output(const DotPlan& P, const Tensor& c, double* F, std::vector<int64_t>& f_off,
+                          hipStream_t s) {
+  if (c.st->skey != P.cst->skey) fail(FTN_EINVAL, "tensor does not have the structure of the contraction's output");
+  if (c.dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 only");
+  const std::vector<GemmGroup>& groups = P.gp.host;
+  f_off.assign(groups.size(), 0);
+  int64_t ftot = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    f_off[g] = ftot;
+    ftot += groups[g].M * groups[g].N;
+  }
+  if (!F || ftot == 0) return ftot;
+  if (c.size() == 0) {
+    HIPC(hipMemsetAsync(F, 0, ftot * 8, s));
+    return ftot;
+  }
+  DBuf<int64_t> dfo = to_device(f_off, s);
+  LAUNCH(k_gather_fused<double>, dim3((unsigned)cdiv(ftot, 256)), dim3(256), 0, s, P.gp.groups.p, (int)groups.size(),
+         dfo.p, ftot, P.sc, (const double*)c.data, F);
+  return ftot;
 }
 
 void op_ftensordot_backward(const Tensor& a, const Tensor& b, const Tensor& dc, const std::vector<int>& axa,

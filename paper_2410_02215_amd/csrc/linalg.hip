@@ -812,12 +812,15 @@ struct AccSrc {
   int64_t off, ld, m;
   int64_t goff;  // Gram matrix and output R (d x d) offset
   int d;
+  int64_t qoff = 0;  // optional output Q (m x d) offset
 };
 
 // R (d x d, zero rows for dropped directions) of every listed factor into
-// Rout at goff, from the Gram matrices Gm at goff and the sources
+// Rout at goff, from the Gram matrices Gm at goff and the sources; with Qout,
+// also Q (m x d, orthonormal kept columns, zero dropped ones) at qoff, so
+// that the source equals Q R
 static void acc_factor(const std::vector<AccSrc>& J, const double* At, const double* Bt, const double* Gm,
-                       double* Rout, hipStream_t s) {
+                       double* Rout, hipStream_t s, double* Qout = nullptr) {
   const int nj = (int)J.size();
   if (!nj) return;
   std::vector<int64_t> wo(nj), qo(nj);
@@ -828,9 +831,10 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
     qo[j] = qs;
     qs += J[j].m * J[j].d;
   }
-  // W: R1 | R2 | R3 | M1 | M2 | T (each ws); Q: Q1 | Q2 (each qs)
-  DBuf<double> W(6 * ws, s), Q(2 * qs, s);
-  double *R1 = W.p, *R2 = W.p + ws, *R3 = W.p + 2 * ws, *M1 = W.p + 3 * ws, *M2 = W.p + 4 * ws;
+  // W: R1 | R2 | R3 | M1 | M2 | T | M3 (each ws); Q: Q1 | Q2 (each qs)
+  DBuf<double> W(7 * ws, s), Q(2 * qs, s);
+  double *R1 = W.p, *R2 = W.p + ws, *R3 = W.p + 2 * ws, *M1 = W.p + 3 * ws, *M2 = W.p + 4 * ws,
+         *M3 = W.p + 6 * ws;
   {
     std::vector<ShiftJob> sj(nj);
     for (int j = 0; j < nj; ++j) sj[j] = ShiftJob{Gm + J[j].goff, R1 + wo[j], J[j].d, 0, J[j].m};
@@ -876,9 +880,16 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
   factor(R2, M2, 1e-13);
   run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gq2, Q.p, W.p, Q.p, nullptr, s);
   run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gg3, Q.p, Q.p, W.p, nullptr, s);
-  factor(R3, nullptr, 1e-13);
+  factor(R3, Qout ? M3 : nullptr, 1e-13);
   run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, W.p, W.p, W.p, nullptr, s);
   run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gr, W.p, W.p, Rout, nullptr, s);
+  if (Qout) {
+    std::vector<GemmGroup> gq3;  // Q = Q2 M3
+    for (int j = 0; j < nj; ++j)
+      gq3.push_back(plain_group(J[j].m, J[j].d, J[j].d, qs + qo[j], J[j].d, 0, 6 * ws + wo[j], J[j].d, 0, J[j].qoff,
+                                J[j].d));
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gq3, Q.p, W.p, Qout, nullptr, s);
+  }
 }
 
 // Leading singular triplets of X = R_A R_B^T (rA x rB) per sector.
@@ -1470,6 +1481,411 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   res.b = op_ftranspose(*B1, perm_b, s);
   (void)conv;
   return res;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of bond compression (derivative of the truncated SVD, the kept
+// count per sector held fixed). Per bond charge, with the fused matrices
+// A~ (M x d) and B~ (d x N) of the forward contraction, the product
+// C = A~ B~ = U S V^T and the outputs A' = U_k S_k^1/2, B' = S_k^1/2 V_k^T.
+// Exact factors A~ = Q_A R_A, B~^T = Q_B R_B (shifted Cholesky QR three
+// times, Q explicit) give X = R_A R_B^T = U_X S V_X^T with U = Q_A U_X and
+// V = Q_B V_X. For cotangents dA', dB' the cotangent of C is
+//   dC = U Y V^T + (I - U U^T) Gu S_k^-1 V_k^T + U_k S_k^-1 Gv^T (I - V V^T)
+// with Gu = dA' S_k^1/2, Gv = dB'^T S_k^1/2, a = U^T Gu, b = V^T Gv and
+//   Y_xy = [y < k, x != y] (a_xy s_y + b_xy s_x) / (s_y^2 - s_x^2)
+//        + [x < k, x != y] (a_yx s_y + b_yx s_x) / (s_x^2 - s_y^2)
+//        + [x = y < k] (a_xx + b_xx) / (2 s_x)
+// (U and V over the nonzero singular values; the projections onto their
+// complements carry the directions outside the column and row spaces). Then
+// dA~ = dC B~^T = dA' P_A^T + Q_A W_A and dB~ = A~^T dC = P_B^T dB' + W_B Q_B^T
+// with the projectors P_A = R_B^T V_k S_k^-1/2, P_B = S_k^-1/2 U_k^T R_A and
+//   W_A = U_X [Y G1 - a S_k^-1 G1_k + E_k (S_k^-1/2 qb^T R_B - S_k^-1 b^T G1)],
+//   W_B = R_A^T [U_X (Y V_X^T - a S_k^-1 V_Xk^T) - U_Xk S_k^-1 b^T V_X^T
+//                + qa S_k^-1/2 V_Xk^T],
+// where G1 = V_X^T R_B, qa = Q_A^T dA' and qb = Q_B^T dB'^T (so that
+// a = U_X^T qa S_k^1/2 and b = V_X^T qb S_k^1/2). Only these products touch
+// the tall dimensions. The signs of the kept singular vectors follow the
+// forward outputs (the derivative of a loss that is invariant under
+// A' -> A' D, B' -> D B' for diagonal D = +-1 does not depend on them).
+// Couplings between singular values closer than 1e-13 of s_max^2 are dropped.
+
+struct AdjJob {
+  const double *U, *lam, *X, *RA, *RB;  // d x d (U columns = eigenvectors of X X^T, descending)
+  const double *qa, *qb, *qf;           // d x k: Q_A^T dA', Q_B^T dB'^T, Q_A^T A'
+  double *WA, *WB, *PAt, *PB;           // d x d, d x d, k x d, k x d
+  double* ws;                           // scratch: 7 d x d
+  int d, k;
+};
+
+__device__ inline void adj_sync() { __syncthreads(); }
+
+__global__ void __launch_bounds__(1024) k_svd_adjoint(const AdjJob* jobs) {
+  const AdjJob J = jobs[blockIdx.x];
+  const int d = J.d, k = J.k, tid = threadIdx.x;
+  __shared__ double sv[JMAX], sg[JMAX];
+  __shared__ int rho_s;
+  const int64_t dd = (int64_t)d * d;
+  double *Us = J.ws, *V = J.ws + dd, *al = J.ws + 2 * dd, *be = J.ws + 3 * dd, *Y = J.ws + 4 * dd,
+         *G1 = J.ws + 5 * dd, *Z = J.ws + 6 * dd;
+  for (int j = tid; j < d; j += blockDim.x) sv[j] = sqrt(fmax(J.lam[j], 0.0));
+  adj_sync();
+  if (tid == 0) {
+    int r = 0;
+    while (r < d && sv[r] > 1e-12 * sv[0]) ++r;
+    rho_s = r;
+  }
+  // signs of the kept vectors from the forward outputs
+  for (int i = tid; i < k; i += blockDim.x) {
+    double t = 0;
+    for (int l = 0; l < d; ++l) t += J.qf[(int64_t)l * k + i] * J.U[(int64_t)l * d + i];
+    sg[i] = t < 0 ? -1.0 : 1.0;
+  }
+  adj_sync();
+  const int rho = rho_s;
+  const double s0 = sv[0], tie = 1e-13 * s0 * s0;
+  for (int64_t e = tid; e < dd; e += blockDim.x) {
+    const int j = (int)(e % d);
+    Us[e] = J.U[e] * (j < k ? sg[j] : 1.0);
+  }
+  adj_sync();
+  // V (d x rho) = X^T U S^-1
+  for (int64_t e = tid; e < (int64_t)d * rho; e += blockDim.x) {
+    const int r = (int)(e / rho), j = (int)(e % rho);
+    double t = 0;
+    for (int l = 0; l < d; ++l) t += J.X[(int64_t)l * d + r] * Us[(int64_t)l * d + j];
+    V[(int64_t)r * d + j] = t / sv[j];
+  }
+  adj_sync();
+  // a, b (rho x k)
+  for (int64_t e = tid; e < (int64_t)rho * k; e += blockDim.x) {
+    const int j = (int)(e / k), i = (int)(e % k);
+    double ta = 0, tb = 0;
+    for (int l = 0; l < d; ++l) {
+      ta += Us[(int64_t)l * d + j] * J.qa[(int64_t)l * k + i];
+      tb += V[(int64_t)l * d + j] * J.qb[(int64_t)l * k + i];
+    }
+    const double r = sqrt(sv[i]);
+    al[(int64_t)j * d + i] = ta * r;
+    be[(int64_t)j * d + i] = tb * r;
+  }
+  adj_sync();
+  // Y (rho x rho)
+  for (int64_t e = tid; e < (int64_t)rho * rho; e += blockDim.x) {
+    const int x = (int)(e / rho), y = (int)(e % rho);
+    double t = 0;
+    if (x == y) {
+      if (x < k) t = (al[(int64_t)x * d + x] + be[(int64_t)x * d + x]) / (2.0 * sv[x]);
+    } else {
+      const double sx = sv[x], sy = sv[y];
+      const double del = sy * sy - sx * sx;  // s_y^2 - s_x^2
+      if (fabs(del) > tie) {
+        if (y < k) t += (al[(int64_t)x * d + y] * sy + be[(int64_t)x * d + y] * sx) / del;
+        if (x < k) t -= (al[(int64_t)y * d + x] * sy + be[(int64_t)y * d + x] * sx) / del;
+      }
+    }
+    Y[(int64_t)x * d + y] = t;
+  }
+  adj_sync();
+  // G1 = V^T R_B (rho x d)
+  for (int64_t e = tid; e < (int64_t)rho * d; e += blockDim.x) {
+    const int j = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int l = 0; l < d; ++l) t += V[(int64_t)l * d + j] * J.RB[(int64_t)l * d + c];
+    G1[(int64_t)j * d + c] = t;
+  }
+  adj_sync();
+  // Z = Y G1 - a S^-1 G1_k + E_k (S^-1/2 qb^T R_B - S^-1 b^T G1)   (rho x d)
+  for (int64_t e = tid; e < (int64_t)rho * d; e += blockDim.x) {
+    const int x = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int y = 0; y < rho; ++y) t += Y[(int64_t)x * d + y] * G1[(int64_t)y * d + c];
+    for (int i = 0; i < k; ++i) t -= al[(int64_t)x * d + i] / sv[i] * G1[(int64_t)i * d + c];
+    if (x < k) {
+      double u = 0, w = 0;
+      for (int l = 0; l < d; ++l) u += J.qb[(int64_t)l * k + x] * J.RB[(int64_t)l * d + c];
+      for (int j = 0; j < rho; ++j) w += be[(int64_t)j * d + x] * G1[(int64_t)j * d + c];
+      t += u / sqrt(sv[x]) - w / sv[x];
+    }
+    Z[(int64_t)x * d + c] = t;
+  }
+  adj_sync();
+  // W_A = U_rho Z (d x d); P_A^T = S^-1/2 G1_k; P_B = S^-1/2 U_k^T R_A
+  for (int64_t e = tid; e < dd; e += blockDim.x) {
+    const int r = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int x = 0; x < rho; ++x) t += Us[(int64_t)r * d + x] * Z[(int64_t)x * d + c];
+    J.WA[e] = t;
+  }
+  for (int64_t e = tid; e < (int64_t)k * d; e += blockDim.x) {
+    const int i = (int)(e / d), c = (int)(e % d);
+    J.PAt[e] = G1[(int64_t)i * d + c] / sqrt(sv[i]);
+    double t = 0;
+    for (int l = 0; l < d; ++l) t += Us[(int64_t)l * d + i] * J.RA[(int64_t)l * d + c];
+    J.PB[e] = t / sqrt(sv[i]);
+  }
+  adj_sync();
+  // Z <- Y V^T - a S^-1 V_k^T - E_k S^-1 b^T V^T   (rho x d, columns = rows of V)
+  for (int64_t e = tid; e < (int64_t)rho * d; e += blockDim.x) {
+    const int x = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int y = 0; y < rho; ++y) t += Y[(int64_t)x * d + y] * V[(int64_t)c * d + y];
+    for (int i = 0; i < k; ++i) t -= al[(int64_t)x * d + i] / sv[i] * V[(int64_t)c * d + i];
+    if (x < k) {
+      double w = 0;
+      for (int j = 0; j < rho; ++j) w += be[(int64_t)j * d + x] * V[(int64_t)c * d + j];
+      t -= w / sv[x];
+    }
+    Z[(int64_t)x * d + c] = t;
+  }
+  adj_sync();
+  // inner (d x d) = U_rho Z + qa S^-1/2 V_k^T, kept in G1's place
+  double* In = G1;
+  for (int64_t e = tid; e < dd; e += blockDim.x) {
+    const int r = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int x = 0; x < rho; ++x) t += Us[(int64_t)r * d + x] * Z[(int64_t)x * d + c];
+    for (int i = 0; i < k; ++i) t += J.qa[(int64_t)r * k + i] / sqrt(sv[i]) * V[(int64_t)c * d + i];
+    In[e] = t;
+  }
+  adj_sync();
+  // W_B = R_A^T inner
+  for (int64_t e = tid; e < dd; e += blockDim.x) {
+    const int r = (int)(e / d), c = (int)(e % d);
+    double t = 0;
+    for (int l = 0; l < d; ++l) t += J.RA[(int64_t)l * d + r] * In[(int64_t)l * d + c];
+    J.WB[e] = t;
+  }
+}
+
+void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff, int conv,
+                               const Tensor& dao, const Tensor& dbo, hipStream_t s, std::unique_ptr<Tensor>& da,
+                               std::unique_ptr<Tensor>& db) {
+  if (a.dtype != FTN_F64 || b.dtype != FTN_F64 || dao.dtype != FTN_F64 || dbo.dtype != FTN_F64)
+    fail(FTN_ENOTSUP, "compress_bond_backward: FP64 only");
+  // the forward outputs (the same deterministic computation)
+  CompressResult fw = op_compress_bond(a, b, la, lb, chi, cutoff, conv, s);
+  if (dao.st->skey != fw.a->st->skey || dbo.st->skey != fw.b->st->skey)
+    fail(FTN_EINVAL, "compress_bond_backward: cotangents must have the structures of the compressed tensors");
+  const int sym = a.sym();
+  const Leg& LA = a.legs()[la];
+  const Leg& LB = b.legs()[lb];
+  const Leg& nla = fw.a->legs()[la];
+  const Leg& nlb = fw.b->legs()[lb];
+  Leg cla = LA, clb = LB;
+  cla.dual = 1 - LA.dual;
+  clb.dual = 1 - LB.dual;
+  Q zero{0, 0};
+  da = make_tensor(a.st, FTN_F64, s, true);
+  db = make_tensor(b.st, FTN_F64, s, true);
+  if (nla.nsect() == 0) return;  // nothing kept: the outputs do not depend on a, b
+  // plans of the forward's absorptions A1 = F(a P_A), B1 = F(P_B b)
+  auto PA0 = make_tensor(sym, FTN_F64, {cla, nla}, zero, s, true);
+  auto PB0 = make_tensor(sym, FTN_F64, {nlb, clb}, zero, s, true);
+  auto PlA = dot_plan(a, *PA0, {la}, {0}, FTN_GLOBAL, FTN_GEMM_F64, s);
+  auto PlB = dot_plan(*PB0, b, {1}, {lb}, FTN_GLOBAL, FTN_GEMM_F64, s);
+  const DotPlanView va = dot_plan_view(*PlA), vb = dot_plan_view(*PlB);
+  // A1 / B1 layouts of the outputs and cotangents (bond leg moved back)
+  const int na = a.ndim(), nb = b.ndim();
+  std::vector<int> inv_a(na), inv_b(nb);
+  {
+    int t = 0;
+    for (int i = 0; i < na; ++i)
+      if (i != la) inv_a[t++] = i;
+    inv_a[na - 1] = la;
+    inv_b[0] = lb;
+    t = 1;
+    for (int i = 0; i < nb; ++i)
+      if (i != lb) inv_b[t++] = i;
+  }
+  auto A1 = op_ftranspose(*fw.a, inv_a, s), dA1 = op_ftranspose(dao, inv_a, s);
+  auto dB1 = op_ftranspose(dbo, inv_b, s);
+  std::vector<int64_t> fa_off, fb_off;
+  const int64_t fa_n = dot_gather_output(*PlA, *A1, nullptr, fa_off, s);
+  const int64_t fb_n = dot_gather_output(*PlB, *dB1, nullptr, fb_off, s);
+  DBuf<double> Af(std::max<int64_t>(fa_n, 1), s), dAf(std::max<int64_t>(fa_n, 1), s), dBf(std::max<int64_t>(fb_n, 1), s);
+  dot_gather_output(*PlA, *A1, Af.p, fa_off, s);
+  dot_gather_output(*PlA, *dA1, dAf.p, fa_off, s);
+  dot_gather_output(*PlB, *dB1, dBf.p, fb_off, s);
+  // fused inputs
+  DBuf<double> At(std::max<int64_t>(va.asz, 1), s), Bt(std::max<int64_t>(vb.bsz, 1), s);
+  run_perm(0, a.S(), FTN_F64, *va.pa, a.data, At.p, s);
+  run_perm(0, b.S(), FTN_F64, *vb.pb, b.data, Bt.p, s);
+  // sectors: groups of the A plan matched to groups of the B plan by charge
+  struct BS {
+    int ga, gb;
+    int64_t M, N, d, k;
+    int64_t a_off, b_off, fa, fb;
+  };
+  std::vector<BS> S;
+  for (size_t g = 0; g < va.groups.size(); ++g) {
+    const GemmGroup& G = va.groups[g];
+    if (G.K == 0 || G.N == 0) continue;
+    int h = -1;
+    for (size_t j = 0; j < vb.groups.size(); ++j)
+      if (q_eq(vb.gq[j], va.gq[g])) h = (int)j;
+    if (h < 0) fail(FTN_EINVAL, "internal: compress backward sector without a partner");
+    const GemmGroup& H = vb.groups[h];
+    if (H.K != G.K || H.M != G.N) fail(FTN_EINVAL, "internal: compress backward sector mismatch");
+    if (G.K > JMAX) fail(FTN_ENOTSUP, "compress_bond_backward: bond sectors larger than 128 are not supported");
+    BS x;
+    x.ga = (int)g;
+    x.gb = h;
+    x.M = G.M;
+    x.N = H.N;
+    x.d = G.K;
+    x.k = G.N;
+    x.a_off = G.a_off;
+    x.b_off = H.b_off;
+    x.fa = fa_off[g];
+    x.fb = fb_off[h];
+    S.push_back(x);
+  }
+  const int ns = (int)S.size();
+  if (!ns) return;
+  // per-sector buffers
+  std::vector<int64_t> go(ns), qao(ns), qbo(ns), ko(ns);
+  int64_t gs = 0, qas = 0, qbs = 0, ks = 0;
+  for (int i = 0; i < ns; ++i) {
+    go[i] = gs;
+    gs += S[i].d * S[i].d;
+    qao[i] = qas;
+    qas += S[i].M * S[i].d;
+    qbo[i] = qbs;
+    qbs += S[i].N * S[i].d;
+    ko[i] = ks;
+    ks += S[i].d * S[i].k;
+  }
+  DBuf<double> GA(gs, s), GB(gs, s), RA(gs, s), RB(gs, s), QA(std::max<int64_t>(qas, 1), s),
+      QB(std::max<int64_t>(qbs, 1), s), X(gs, s), Hm(gs, s), U(gs, s), lam(std::max<int64_t>(gs, 1), s);
+  {
+    std::vector<GemmGroup> ga, gb;
+    for (int i = 0; i < ns; ++i) {
+      const BS& x = S[i];
+      ga.push_back(plain_group(x.d, x.d, x.M, x.a_off, x.d, 1, x.a_off, x.d, 0, go[i], x.d));
+      gb.push_back(plain_group(x.d, x.d, x.N, x.b_off, x.N, 0, x.b_off, x.N, 1, go[i], x.d));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ga, At.p, At.p, GA.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gb, Bt.p, Bt.p, GB.p, nullptr, s);
+  }
+  {
+    std::vector<AccSrc> ja, jb;
+    for (int i = 0; i < ns; ++i) {
+      const BS& x = S[i];
+      AccSrc u;
+      u.side = 0;
+      u.trans = 0;
+      u.off = x.a_off;
+      u.ld = x.d;
+      u.m = x.M;
+      u.goff = go[i];
+      u.d = (int)x.d;
+      u.qoff = qao[i];
+      ja.push_back(u);
+      u.side = 1;
+      u.trans = 1;
+      u.off = x.b_off;
+      u.ld = x.N;
+      u.m = x.N;
+      u.qoff = qbo[i];
+      jb.push_back(u);
+    }
+    acc_factor(ja, At.p, Bt.p, GA.p, RA.p, s, QA.p);
+    acc_factor(jb, At.p, Bt.p, GB.p, RB.p, s, QB.p);
+  }
+  {
+    // X = R_A R_B^T, H = X X^T, all eigenpairs of H
+    std::vector<GemmGroup> gx, gh;
+    for (int i = 0; i < ns; ++i) {
+      const int64_t d = S[i].d;
+      gx.push_back(plain_group(d, d, d, go[i], d, 0, go[i], d, 1, go[i], d));
+      gh.push_back(plain_group(d, d, d, go[i], d, 0, go[i], d, 1, go[i], d));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, RA.p, RB.p, X.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, X.p, X.p, Hm.p, nullptr, s);
+    int64_t log_n = 0;
+    std::vector<int64_t> log_off(ns);
+    for (int i = 0; i < ns; ++i) {
+      log_off[i] = log_n;
+      log_n += jacobi_log_len((int)S[i].d);
+    }
+    DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
+    DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
+    std::vector<EigJob> ej(ns);
+    for (int i = 0; i < ns; ++i) {
+      EigJob& j = ej[i];
+      j.H = Hm.p + go[i];
+      j.V = U.p + go[i];
+      j.W = lam.p + go[i];
+      j.rot = lrot.p + log_off[i];
+      j.rpq = lpq.p + log_off[i];
+      j.rounds = nullptr;
+      j.n = (int)S[i].d;
+      j.pad = 0;
+    }
+    DBuf<EigJob> dj = to_device(ej, s);
+    FACTOR_LAUNCH(eig_flops(ej), k_jacobi_eig, dim3((unsigned)ns), dim3(LT), 0, s, dj.p);
+  }
+  // qa = Q_A^T dA', qb = Q_B^T dB'^T, qf = Q_A^T A'   (d x k)
+  DBuf<double> qa(std::max<int64_t>(ks, 1), s), qb(std::max<int64_t>(ks, 1), s), qf(std::max<int64_t>(ks, 1), s);
+  {
+    std::vector<GemmGroup> g1, g2;
+    for (int i = 0; i < ns; ++i) {
+      const BS& x = S[i];
+      g1.push_back(plain_group(x.d, x.k, x.M, qao[i], x.d, 1, x.fa, x.k, 0, ko[i], x.k));
+      g2.push_back(plain_group(x.d, x.k, x.N, qbo[i], x.d, 1, x.fb, x.N, 1, ko[i], x.k));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g1, QA.p, dAf.p, qa.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g1, QA.p, Af.p, qf.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g2, QB.p, dBf.p, qb.p, nullptr, s);
+  }
+  // the small adjoint algebra, one workgroup per sector
+  DBuf<double> WA(gs, s), WB(gs, s), PAt(std::max<int64_t>(ks, 1), s), PB(std::max<int64_t>(ks, 1), s),
+      scratch(7 * gs, s);
+  {
+    std::vector<AdjJob> jobs(ns);
+    for (int i = 0; i < ns; ++i) {
+      AdjJob& j = jobs[i];
+      j.U = U.p + go[i];
+      j.lam = lam.p + go[i];
+      j.X = X.p + go[i];
+      j.RA = RA.p + go[i];
+      j.RB = RB.p + go[i];
+      j.qa = qa.p + ko[i];
+      j.qb = qb.p + ko[i];
+      j.qf = qf.p + ko[i];
+      j.WA = WA.p + go[i];
+      j.WB = WB.p + go[i];
+      j.PAt = PAt.p + ko[i];
+      j.PB = PB.p + ko[i];
+      j.ws = scratch.p + 7 * go[i];
+      j.d = (int)S[i].d;
+      j.k = (int)S[i].k;
+    }
+    DBuf<AdjJob> dj = to_device(jobs, s);
+    LAUNCH(k_svd_adjoint, dim3((unsigned)ns), dim3(1024), 0, s, dj.p);
+  }
+  // dA~ = dA' P_A^T + Q_A W_A ; dB~ = P_B^T dB' + W_B Q_B^T (in the A / B plan layouts)
+  DBuf<double> dAt(std::max<int64_t>(va.asz, 1), s), dBt(std::max<int64_t>(vb.bsz, 1), s);
+  if (va.asz) HIPC(hipMemsetAsync(dAt.p, 0, va.asz * 8, s));
+  if (vb.bsz) HIPC(hipMemsetAsync(dBt.p, 0, vb.bsz * 8, s));
+  {
+    std::vector<GemmGroup> a1, a2, b1, b2;
+    for (int i = 0; i < ns; ++i) {
+      const BS& x = S[i];
+      a1.push_back(plain_group(x.M, x.d, x.k, x.fa, x.k, 0, ko[i], x.d, 0, x.a_off, x.d));
+      a2.push_back(plain_group(x.M, x.d, x.d, qao[i], x.d, 0, go[i], x.d, 0, x.a_off, x.d));
+      b1.push_back(plain_group(x.d, x.N, x.k, ko[i], x.d, 1, x.fb, x.N, 0, x.b_off, x.N));
+      b2.push_back(plain_group(x.d, x.N, x.d, go[i], x.d, 0, qbo[i], x.d, 1, x.b_off, x.N));
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, a1, dAf.p, PAt.p, dAt.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, a2, QA.p, WA.p, dAt.p, nullptr, s, 1.0, 1.0);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, b1, PB.p, dBf.p, dBt.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, b2, WB.p, QB.p, dBt.p, nullptr, s, 1.0, 1.0);
+  }
+  run_perm(1, a.S(), FTN_F64, *va.pa, dAt.p, da->data, s);
+  run_perm(1, b.S(), FTN_F64, *vb.pb, dBt.p, db->data, s);
+  HIPC(hipStreamSynchronize(s));
 }
 
 }  // namespace ftn

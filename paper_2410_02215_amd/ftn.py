@@ -58,6 +58,7 @@ SIGNATURES = [
     ("ftn_ftensordot", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP]),
     ("ftn_ftensordot_backward", _I, [_P, _P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP, _PP]),
     ("ftn_compress_bond", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _PP, _PP, _PD, _PD, _PI64]),
+    ("ftn_compress_bond_backward", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _P, _P, _PP, _PP]),
     ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
     ("ftn_net_free", _I, [_P]),
     ("ftn_contract_network", _I, [_P, _I, _PI32, _I64, _I, _P, _PD, _PI64, _PP, _PI32, _PD]),
@@ -303,6 +304,14 @@ def compress_bond(a, b, leg_a, leg_b, chi, cutoff=1e-12, conv=LOCAL):
                                   _stream(), ctypes.byref(ao), ctypes.byref(bo), ctypes.byref(disc), sv,
                                   ctypes.byref(nk)))
     return Tensor(ao), Tensor(bo), dict(discarded=disc.value, svals=list(sv[:nk.value]))
+
+
+def compress_bond_backward(a, b, leg_a, leg_b, chi, da_out, db_out, cutoff=1e-12, conv=LOCAL):
+    """Cotangents (da, db) of compress_bond for cotangents of its outputs."""
+    da, db = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(_lib.ftn_compress_bond_backward(a.h, b.h, int(leg_a), int(leg_b), int(chi), float(cutoff), int(conv),
+                                           da_out.h, db_out.h, _stream(), ctypes.byref(da), ctypes.byref(db)))
+    return Tensor(da), Tensor(db)
 
 
 class Network:

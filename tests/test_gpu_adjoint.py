@@ -16,11 +16,11 @@ import pytest
 import torch
 
 from oracle import symmetry as S
-from oracle.adjoint import ftensordot_vjp, network_grad
+from oracle.adjoint import ftensordot_vjp, network_grad, inner
 from oracle.network import Network, network_value
 from oracle.ops import ftensordot
 from oracle.tensor import make_leg
-from tests.helpers import rand_tensor, random_network, random_ssa_path
+from tests.helpers import rand_leg, partner, rand_tensor, random_network, random_ssa_path
 from tests.gpu_helpers import to_gpu, assert_same_structure, flat_blocks, legs_abi, SYM
 from tests.test_gpu_ops import _rand_pair
 
@@ -146,3 +146,87 @@ def test_network_gradient_matches_oracle(P, sym):
             err = np.abs(gs[t].double().cpu().numpy() - r).max(initial=0)
             assert err <= 1e-11 * max(1.0, np.abs(r).max(initial=0)), (t, err)
         done += 1
+
+
+def _compress_case(P, A, B, la, lb, chi, conv, rng):
+    from oracle.linalg import compress_bond as o_compress
+    from oracle.adjoint import compress_vjp
+    A2, B2, _ = o_compress(A, B, la, lb, chi, conv=conv, cutoff=1e-6)
+    C = ftensordot(A2, B2, [la], [lb], conv=conv)
+    W = rand_tensor(rng, A.sym, C.legs, total=C.total)
+    dA2, dB2 = ftensordot_vjp(A2, B2, W, [la], [lb], conv)
+    gA, gB = compress_vjp(A, B, la, lb, chi, dA2, dB2, conv=conv)
+    cv = P.LOCAL if conv == "local" else P.GLOBAL
+    ga, gb = to_gpu(A), to_gpu(B)
+    GA, GB, _ = P.compress_bond(ga, gb, la, lb, chi, 1e-6, cv)
+    dGA, dGB = P.ftensordot_backward(GA, GB, to_gpu(W), [la], [lb], conv=cv)
+    da, db = P.compress_bond_backward(ga, gb, la, lb, chi, dGA, dGB, 1e-6, cv)
+    # the loss depends on the compressed pair only through its product, so
+    # the gradient does not depend on either side's sign choices
+    _check(gA, da, 1e-8)
+    _check(gB, db, 1e-8)
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", SYMS)
+def test_compress_bond_backward_matches_oracle(P, sym, conv):
+    rng = np.random.default_rng(27)
+    for trial in range(4):
+        bond = rand_leg(rng, sym, maxd=6)
+        la_ = [rand_leg(rng, sym, maxd=3) for _ in range(2)]
+        lb_ = [rand_leg(rng, sym, maxd=3) for _ in range(2)]
+        pa, pb = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        A = rand_tensor(rng, sym, la_[:pa] + [bond] + la_[pa:], total=S.zero(sym))
+        B = rand_tensor(rng, sym, lb_[:pb] + [partner(bond)] + lb_[pb:], total=S.zero(sym))
+        _compress_case(P, A, B, pa, pb, int(rng.integers(2, 8)), conv, rng)
+
+
+def test_compress_bond_backward_tall_factors_and_odd_tensors(P):
+    # sectors with many more rows than columns (shifted Cholesky QR), odd
+    # tensors, and a bond dimension of 60 per sector
+    rng = np.random.default_rng(28)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(20, 17, 0), l(30, 30, 1), l(9, 8, 0)], total=(1,))
+    B = rand_tensor(rng, sym, [l(30, 30, 0), l(25, 33, 1)], total=(0,))
+    _compress_case(P, A, B, 1, 0, 24, "local", rng)
+
+
+def test_compress_bond_backward_rejects_large_sectors(P):
+    rng = np.random.default_rng(29)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(200, 200, 0), l(130, 2, 1)], total=(0,))
+    B = rand_tensor(rng, sym, [l(130, 2, 0), l(150, 150, 1)], total=(0,))
+    ga, gb = to_gpu(A), to_gpu(B)
+    GA, GB, _ = P.compress_bond(ga, gb, 1, 0, 16, 1e-6, P.LOCAL)
+    with pytest.raises(P.FtnError) as e:
+        P.compress_bond_backward(ga, gb, 1, 0, 16, GA, GB, 1e-6, P.LOCAL)
+    assert e.value.code == -6
+
+
+def test_autograd_compress_then_contract(P):
+    from paper_2410_02215_amd import autograd as AG
+    from oracle.linalg import compress_bond as o_compress
+    from oracle.adjoint import compress_vjp
+    rng = np.random.default_rng(30)
+    sym = S.U1
+    bond = make_leg(sym, [(-1,), (0,), (1,)], [3, 5, 4], 0)
+    A = rand_tensor(rng, sym, [make_leg(sym, [(-1,), (0,), (1,)], [2, 3, 2], 1), bond], total=(0,))
+    B = rand_tensor(rng, sym, [partner(bond), make_leg(sym, [(-1,), (0,), (1,)], [2, 2, 3], 0)], total=(0,))
+    chi = 5
+    A2, B2, _ = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-6)
+    C = ftensordot(A2, B2, [1], [0], conv="local")
+    W = rand_tensor(rng, sym, C.legs, total=C.total)
+    dA2, dB2 = ftensordot_vjp(A2, B2, W, [1], [0], "local")
+    gA, gB = compress_vjp(A, B, 1, 0, chi, dA2, dB2, conv="local")
+    a, b = _dtensor(A), _dtensor(B)
+    a2, b2 = AG.compress(a, b, 1, 0, chi)
+    c = AG.dot(a2, b2, [1], [0])
+    w = to_gpu(W).data()
+    loss = (c.data * w).sum()
+    da, db = torch.autograd.grad(loss, [a.data, b.data])
+    for g_ref, g in ((gA, da), (gB, db)):
+        r = flat_blocks(g_ref)
+        err = np.abs(g.double().cpu().numpy() - r).max(initial=0)
+        assert err <= 1e-8 * max(1.0, np.abs(r).max(initial=0)), err

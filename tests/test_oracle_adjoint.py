@@ -128,3 +128,39 @@ def test_network_grad_euler_and_difference(sym):
                 m, e = network_value(Network(tens, net.bonds, conv="local", positions=net.positions), path)
                 vals.append(m * 2.0 ** e)
             assert _rel(vals[0] - vals[1], 2 * inner(g[t], V)) < 1e-11
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", [S.Z2, S.U1])
+def test_compress_vjp_directional_difference(sym, conv):
+    # L = <W, F(A' B')> is unchanged by the sign of each kept singular vector
+    # pair, so its derivative through the truncated SVD is well defined; a
+    # central difference (kept counts unchanged) must agree with it
+    from oracle.linalg import compress_bond
+    from oracle.adjoint import compress_vjp
+    rng = np.random.default_rng(14)
+    for trial in range(3):
+        bond = rand_leg(rng, sym, maxd=5)
+        A = rand_tensor(rng, sym, [rand_leg(rng, sym, maxd=3), bond, rand_leg(rng, sym, maxd=3)],
+                        total=S.zero(sym))
+        B = rand_tensor(rng, sym, [partner(bond), rand_leg(rng, sym, maxd=3)], total=S.zero(sym))
+        chi = int(rng.integers(2, 5))
+
+        def loss(A_, B_, W):
+            A2, B2, _ = compress_bond(A_, B_, 1, 0, chi, conv=conv, cutoff=1e-6)
+            return inner(W, ftensordot(A2, B2, [1], [0], conv=conv)), A2, B2
+
+        A2, B2, _ = compress_bond(A, B, 1, 0, chi, conv=conv, cutoff=1e-6)
+        C = ftensordot(A2, B2, [1], [0], conv=conv)
+        W = rand_tensor(rng, sym, C.legs, total=C.total)
+        dA2, dB2 = ftensordot_vjp(A2, B2, W, [1], [0], conv)
+        gA, gB = compress_vjp(A, B, 1, 0, chi, dA2, dB2, conv=conv)
+        V = rand_tensor(rng, sym, A.legs, total=A.total)
+        h = 1e-6
+        Ap, Am = A.copy(), A.copy()
+        for k in A.keys():
+            Ap.blocks[k] = A.block(k) + h * V.block(k)
+            Am.blocks[k] = A.block(k) - h * V.block(k)
+        fd = (float(loss(Ap, B, W)[0]) - float(loss(Am, B, W)[0])) / (2 * h)
+        an = float(inner(gA, V))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
