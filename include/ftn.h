@@ -181,6 +181,13 @@ int ftn_dagger(ftn_tensor_t a, ftn_stream_t stream, ftn_tensor_t* out);
 int ftn_fuse(ftn_tensor_t a, int nlegs, const int32_t* legs, ftn_conv conv, int rev,
              ftn_stream_t stream, ftn_tensor_t* out);
 
+/* Adjoint of ftn_fuse: for a cotangent dout of the fused tensor (its
+   structure), the cotangent da of a (new handle, structure of a). Fusion
+   moves every entry of a to one entry of the output with a sign, so da reads
+   each entry back with the same sign. */
+int ftn_fuse_backward(ftn_tensor_t a, int nlegs, const int32_t* legs, ftn_conv conv, int rev,
+                      ftn_tensor_t dout, ftn_stream_t stream, ftn_tensor_t* da);
+
 /* ---------------------------------------------------------------------------
  * Contraction, Eq. (standardcontract)
  * ------------------------------------------------------------------------ */

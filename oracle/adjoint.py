@@ -12,8 +12,9 @@ they inherit its signs: nothing is re-derived here.
   given output cotangent dC, i.e. the gradients of <dC, C>.
 * ``network_grad``: value of a closed network and its gradient with respect
   to every allowed entry of every tensor.
-* ``compress_vjp``: cotangents of bond compression (Sec. II.A truncated SVD),
-  by reverse mode through the oracle's QR and SVD with the kept counts fixed.
+* ``compress_product_grad``: gradient of <W, F(A'B')> through bond
+  compression (Sec. II.A truncated SVD, kept counts fixed); the compressed
+  factors are differentiated through the SVD of the bond matrix itself.
 """
 
 import torch
@@ -61,11 +62,12 @@ def ftensordot_vjp(A, B, dC, axes_a, axes_b, conv="local"):
     return outs[0], outs[1]
 
 
-def network_grad(net, path):
-    """(value, {tensor id: gradient FTensor}) of a closed network, exact."""
+def network_grad(net, path, chi=None):
+    """(value, {tensor id: gradient FTensor}) of a closed network, exact or
+    approximate (compression as early as possible, kept counts fixed)."""
     leaves = {t: _leaf_copy(x) for t, x in net.tensors.items()}
     net2 = Network(leaves, net.bonds, conv=net.conv, positions=net.positions)
-    T, labs, e, _ = contract_network(net2, path, chi=None, renorm=False)
+    T, labs, e, _ = contract_network(net2, path, chi=chi, renorm=False)
     if T.ndim != 0:
         raise ValueError("network is not closed")
     b = T.blocks.get(())
@@ -86,20 +88,20 @@ def network_grad(net, path):
     return (0.0 if b is None else float(b.detach())), grads
 
 
-def compress_vjp(A, B, la, lb, chi, dA2, dB2, conv="local", cutoff=1e-6):
-    """(dA, dB) = gradients of <dA2, A2> + <dB2, B2> for (A2, B2) =
-    compress_bond(A, B, ...), by reverse mode through the QR and SVD of
-    ``linalg.compress_bond`` (the kept counts are fixed by the forward)."""
+def compress_product_grad(A, B, la, lb, chi, W, conv="local", cutoff=1e-6):
+    """(dA, dB) = gradients of <W, F(A' B')> over the bond, for
+    (A', B') = compress_bond(A, B, ...): a loss that does not depend on the
+    sign chosen for each kept singular vector pair, taken in one reverse-mode
+    pass through the oracle's truncated SVD (kept counts fixed)."""
     from .linalg import compress_bond
     A1, B1 = _leaf_copy(A), _leaf_copy(B)
     A2, B2, _ = compress_bond(A1, B1, la, lb, chi, conv=conv, cutoff=cutoff)
-    L = inner(dA2, A2) + inner(dB2, B2)
-    outs = []
+    L = inner(W, ftensordot(A2, B2, [la], [lb], conv=conv))
     leaves = [A1, B1]
     flat = [T.blocks[k] for T in leaves for k in T.keys()]
-    gs = torch.autograd.grad(L, flat, allow_unused=True) if (flat and torch.is_tensor(L) and L.requires_grad) \
-        else [None] * len(flat)
-    i = 0
+    ok = flat and torch.is_tensor(L) and L.requires_grad
+    gs = torch.autograd.grad(L, flat, allow_unused=True) if ok else [None] * len(flat)
+    outs, i = [], 0
     for T in leaves:
         o = FTensor(T.sym, T.legs, T.total)
         for k in T.keys():

@@ -247,13 +247,20 @@ def compress_bond(A, B, la, lb, chi, conv="local", cutoff=1e-12):
         MB, cl = bmats[q]
         if MA.shape[0] == 0 or MB.shape[1] == 0:
             continue
-        QA, RA = torch.linalg.qr(MA, mode="reduced")
-        QBt, RBt = torch.linalg.qr(MB.T, mode="reduced")
-        LBm = RBt.T
-        QB = QBt.T
-        X = RA @ LBm
-        U, s, Vh = torch.linalg.svd(X, full_matrices=False)
-        facs[q] = (QA, U, s, Vh, QB, rl, cl)
+        if MA.requires_grad or MB.requires_grad:
+            # derivatives are taken through the SVD of the bond matrix itself:
+            # reverse mode through the QR of a rank-deficient factor divides
+            # by its zero pivots (the values are the same either way)
+            U, s, Vh = torch.linalg.svd(MA @ MB, full_matrices=False)
+            facs[q] = (None, U, s, Vh, None, rl, cl)
+        else:
+            QA, RA = torch.linalg.qr(MA, mode="reduced")
+            QBt, RBt = torch.linalg.qr(MB.T, mode="reduced")
+            LBm = RBt.T
+            QB = QBt.T
+            X = RA @ LBm
+            U, s, Vh = torch.linalg.svd(X, full_matrices=False)
+            facs[q] = (QA, U, s, Vh, QB, rl, cl)
         for i, v in enumerate(s.tolist()):
             svals.append((-v, q, i))
     keep = select_top(svals, chi, cutoff)
@@ -268,12 +275,12 @@ def compress_bond(A, B, la, lb, chi, conv="local", cutoff=1e-12):
     sv_out = {}
     for q, (QA, U, s, Vh, QB, rl, cl) in facs.items():
         k = keep.get(q, 0)
-        discarded += float((s[k:] ** 2).sum())
+        discarded += float((s[k:] ** 2).sum().detach())
         if k == 0:
             continue
         sq = torch.sqrt(s[:k])
-        LA_ = (QA @ U[:, :k]) * sq[None, :]
-        RB_ = (sq[:, None] * Vh[:k]) @ QB
+        LA_ = (U[:, :k] if QA is None else QA @ U[:, :k]) * sq[None, :]
+        RB_ = sq[:, None] * Vh[:k] if QB is None else (sq[:, None] * Vh[:k]) @ QB
         sv_out[q] = s[:k]
         qi = chs.index(q)
         r0 = 0

@@ -152,6 +152,31 @@ def compress(a, b, la, lb, chi, cutoff=1e-6, conv=ftn.LOCAL):
     return DTensor(a.sym, la_, ta, da), DTensor(b.sym, lb_, tb, db)
 
 
+class _Fuse(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, data, a, legs, conv, rev, out):
+        A = a.handle(data)
+        F = ftn.fuse(A, legs, conv, rev)
+        sf = (F.legs(), F.info()["total"])
+        out.append(sf)
+        ctx.A = A
+        ctx.args = (a.sym, a.dtype, legs, conv, rev, sf)
+        return F.data()
+
+    @staticmethod
+    def backward(ctx, dF):
+        sym, dtype, legs, conv, rev, sf = ctx.args
+        D = ftn.Tensor.create(sym, sf[0], sf[1], dtype, data=dF.detach().contiguous())
+        return ftn.fuse_backward(ctx.A, legs, D, conv, rev).data(), None, None, None, None, None
+
+
+def fuse(a, legs, conv=ftn.LOCAL, rev=0):
+    """Differentiable fusion of the given legs of a DTensor (Sec. IV.A)."""
+    st = []
+    data = _Fuse.apply(a.data, a, [int(l) for l in legs], int(conv), int(rev), st)
+    return DTensor(a.sym, st[0][0], st[0][1], data)
+
+
 def dot(a, b, axes_a, axes_b, conv=ftn.LOCAL, gemm=ftn.GEMM_F64):
     """Differentiable ftensordot of two DTensors (output legs: free(a) ++ free(b))."""
     st = []
@@ -244,3 +269,87 @@ def network_value(tensors, bonds, path, order=None, gemm=ftn.GEMM_F64):
     if Z.ndim:
         raise ValueError("network is not closed")
     return Z.data.sum()
+
+
+def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64):
+    """Approximate (chi) or exact contraction, differentiable.
+
+    The same steps as ``ftn_contract_network`` in the local convention, each
+    a differentiable library call: pairwise ``dot`` over all shared bonds
+    (paired in bond order), then for every neighbour (in creation order)
+    the shared bonds fused into one and a bond larger than chi compressed
+    (cutoff 1e-6), then a rescaling by a power of two. Odd tensors carry
+    dummy ranks (by ``order``) whose moves and final sort are a sign.
+    Returns ``(T, labels, exp2)``: the final DTensor scaled by 2^-exp2 and
+    the (tensor, leg) of each open leg.
+    """
+    import math
+    n = len(tensors)
+    pos = list(range(n)) if order is None else [int(x) for x in order]
+    T = list(tensors)
+    L = [[("o", t, l) for l in range(x.ndim)] for t, x in enumerate(tensors)]
+    for bi, (t1, l1, t2, l2) in enumerate(bonds):
+        L[t1][l1] = ("b", bi)
+        L[t2][l2] = ("b", bi)
+    odd = sorted([t for t in range(n) if T[t].parity], key=lambda t: pos[t])
+    D = [[] for _ in range(n)]
+    for r, t in enumerate(odd):
+        D[t] = [r]
+    sgn = 0
+    alive = [True] * n
+    ssa = list(range(n))
+    next_bond = len(bonds)
+    e2 = 0
+
+    def shared(x, y):
+        pairs = [(L[x][k][1], k, L[y].index(l)) for k, l in enumerate(L[x]) if l[0] == "b" and l in L[y]]
+        pairs.sort()
+        return [p[1] for p in pairs], [p[2] for p in pairs]
+
+    for (i, j) in path:
+        x, y = ssa[i], ssa[j]
+        lx, ly = shared(x, y)
+        Z = dot(T[x], T[y], lx, ly, ftn.LOCAL, gemm)
+        e = (len(D[x]) & 1) & (len(D[y]) & 1)
+        for a in D[x]:
+            for b in D[y]:
+                e ^= int(a > b)
+        sgn ^= e
+        D.append(sorted(D[x] + D[y]))
+        L.append([l for k, l in enumerate(L[x]) if k not in lx] + [l for k, l in enumerate(L[y]) if k not in ly])
+        T.append(Z)
+        alive.append(True)
+        alive[x] = alive[y] = False
+        z = len(T) - 1
+        ssa.append(z)
+        if chi:
+            nbs = [w for w in range(len(T)) if w != z and alive[w] and shared(z, w)[0]]
+            for w in nbs:
+                lz, lw = shared(z, w)
+                if len(lz) > 1:
+                    Tz, Tw = fuse(T[z], lz, ftn.LOCAL, 0), fuse(T[w], lw, ftn.LOCAL, 0)
+                    nb = ("b", next_bond)
+                    next_bond += 1
+                    for t_, ls, X in ((z, lz, Tz), (w, lw, Tw)):
+                        rest = [l for k, l in enumerate(L[t_]) if k not in ls]
+                        p_ = sum(1 for k in range(len(L[t_])) if k not in ls and k < ls[0])
+                        L[t_] = rest[:p_] + [nb] + rest[p_:]
+                        T[t_] = X
+                    lz, lw = shared(z, w)
+                dim = sum(T[z].legs[lz[0]][1])
+                if dim > chi and T[z].data.numel() and T[w].data.numel():
+                    T[z], T[w] = compress(T[z], T[w], lz[0], lw[0], chi, 1e-6, ftn.LOCAL)
+        m = float(T[z].data.detach().abs().max()) if T[z].data.numel() else 0.0
+        if m > 0 and math.isfinite(m):
+            ex = math.frexp(m)[1]
+            T[z] = DTensor(T[z].sym, T[z].legs, T[z].total, T[z].data * (2.0 ** -ex))
+            e2 += ex
+    fin = [t for t in range(len(T)) if alive[t]]
+    if len(fin) != 1:
+        raise ValueError("path does not contract the network to one tensor")
+    F = T[fin[0]]
+    m = len(D[fin[0]])
+    if ((m * (m - 1) // 2) & 1) ^ sgn:
+        F = DTensor(F.sym, F.legs, F.total, -F.data)
+    labs = [(l[1], l[2]) if l[0] == "o" else l for l in L[fin[0]]]
+    return F, labs, e2

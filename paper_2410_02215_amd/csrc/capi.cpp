@@ -219,6 +219,15 @@ int ftn_fuse(ftn_tensor_t a, int nlegs, const int32_t* legs, ftn_conv conv, int 
   });
 }
 
+int ftn_fuse_backward(ftn_tensor_t a, int nlegs, const int32_t* legs, ftn_conv conv, int rev, ftn_tensor_t dout,
+                      ftn_stream_t stream, ftn_tensor_t* da) {
+  return guarded([&] {
+    if (!da || !legs || nlegs < 1) fail(FTN_EINVAL, "bad arguments");
+    std::vector<int> l(legs, legs + nlegs);
+    *da = wrap(op_fuse_backward(T(a), l, conv, rev, T(dout), (hipStream_t)stream));
+  });
+}
+
 int ftn_ftensordot(ftn_tensor_t a, ftn_tensor_t b, int naxes, const int32_t* axes_a, const int32_t* axes_b,
                    ftn_conv conv, ftn_gemm gemm, ftn_stream_t stream, ftn_tensor_t* out) {
   return guarded([&] {

@@ -350,6 +350,8 @@ std::unique_ptr<Tensor> op_flip_dual(const Tensor& a, int leg, int with_sign, hi
 std::unique_ptr<Tensor> op_dagger(const Tensor& a, hipStream_t s);
 std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& legs, int conv, int rev,
                                 hipStream_t s);
+std::unique_ptr<Tensor> op_fuse_backward(const Tensor& a, const std::vector<int>& glegs, int conv, int rev,
+                                         const Tensor& dout, hipStream_t s);
 std::unique_ptr<Tensor> op_scale(const Tensor& a, double alpha, hipStream_t s);
 std::unique_ptr<Tensor> op_cast(const Tensor& a, int dtype, hipStream_t s);
 std::unique_ptr<Tensor> op_leg_sign(const Tensor& a, int leg, hipStream_t s);

@@ -690,4 +690,27 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& glegs, 
   return out;
 }
 
+// Adjoint of fusion: every entry of the fused tensor is one entry of a with
+// a sign, so the cotangent of a is the same signed map read backwards
+std::unique_ptr<Tensor> op_fuse_backward(const Tensor& a, const std::vector<int>& glegs, int conv, int rev,
+                                         const Tensor& dout, hipStream_t s) {
+  std::string key = a.st->skey + "|f|" + std::to_string(conv) + "," + std::to_string(rev) + "|";
+  for (int l : glegs) key += std::to_string(l) + ",";
+  std::shared_ptr<UnaryPlan> U;
+  for (int attempt = 0; attempt < 2 && !U; ++attempt) {
+    {
+      std::lock_guard<std::mutex> g(g_unary_mu);
+      auto it = g_unary->find(key);
+      if (it != g_unary->end()) U = it->second;
+    }
+    if (!U) (void)op_fuse(a, glegs, conv, rev, s);  // builds and caches the plan
+  }
+  if (!U) fail(FTN_EINVAL, "internal: fusion plan not available");
+  if (dout.st->skey != U->out->skey) fail(FTN_EINVAL, "cotangent does not have the structure of the fused tensor");
+  if (dout.dtype != a.dtype) fail(FTN_ENOTSUP, "cotangent dtype differs");
+  auto da = make_tensor(a.st, a.dtype, s, false);  // every entry is read back from one fused entry
+  if (a.size()) run_perm(1, a.S(), a.dtype, U->pp, dout.data, da->data, s);
+  return da;
+}
+
 }  // namespace ftn

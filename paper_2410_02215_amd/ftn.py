@@ -58,6 +58,7 @@ SIGNATURES = [
     ("ftn_ftensordot", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP]),
     ("ftn_ftensordot_backward", _I, [_P, _P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP, _PP]),
     ("ftn_compress_bond", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _PP, _PP, _PD, _PD, _PI64]),
+    ("ftn_fuse_backward", _I, [_P, _I, _PI32, _I, _I, _P, _P, _PP]),
     ("ftn_compress_bond_backward", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _P, _P, _PP, _PP]),
     ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
     ("ftn_net_free", _I, [_P]),
@@ -275,6 +276,14 @@ def fuse(a, legs, conv=LOCAL, rev=0):
     out = ctypes.c_void_p()
     _check(_lib.ftn_fuse(a.h, len(legs), _arr([int(l) for l in legs], ctypes.c_int32), int(conv), int(rev),
                          _stream(), ctypes.byref(out)))
+    return Tensor(out)
+
+
+def fuse_backward(a, legs, dout, conv=LOCAL, rev=0):
+    """Cotangent of a for the cotangent dout of fuse(a, legs, conv, rev)."""
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_fuse_backward(a.h, len(legs), _arr([int(l) for l in legs], ctypes.c_int32), int(conv), int(rev),
+                                  dout.h, _stream(), ctypes.byref(out)))
     return Tensor(out)
 
 

@@ -150,12 +150,11 @@ def test_network_gradient_matches_oracle(P, sym):
 
 def _compress_case(P, A, B, la, lb, chi, conv, rng):
     from oracle.linalg import compress_bond as o_compress
-    from oracle.adjoint import compress_vjp
+    from oracle.adjoint import compress_product_grad
     A2, B2, _ = o_compress(A, B, la, lb, chi, conv=conv, cutoff=1e-6)
     C = ftensordot(A2, B2, [la], [lb], conv=conv)
     W = rand_tensor(rng, A.sym, C.legs, total=C.total)
-    dA2, dB2 = ftensordot_vjp(A2, B2, W, [la], [lb], conv)
-    gA, gB = compress_vjp(A, B, la, lb, chi, dA2, dB2, conv=conv)
+    gA, gB = compress_product_grad(A, B, la, lb, chi, W, conv=conv)
     cv = P.LOCAL if conv == "local" else P.GLOBAL
     ga, gb = to_gpu(A), to_gpu(B)
     GA, GB, _ = P.compress_bond(ga, gb, la, lb, chi, 1e-6, cv)
@@ -208,7 +207,7 @@ def test_compress_bond_backward_rejects_large_sectors(P):
 def test_autograd_compress_then_contract(P):
     from paper_2410_02215_amd import autograd as AG
     from oracle.linalg import compress_bond as o_compress
-    from oracle.adjoint import compress_vjp
+    from oracle.adjoint import compress_product_grad
     rng = np.random.default_rng(30)
     sym = S.U1
     bond = make_leg(sym, [(-1,), (0,), (1,)], [3, 5, 4], 0)
@@ -218,8 +217,7 @@ def test_autograd_compress_then_contract(P):
     A2, B2, _ = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-6)
     C = ftensordot(A2, B2, [1], [0], conv="local")
     W = rand_tensor(rng, sym, C.legs, total=C.total)
-    dA2, dB2 = ftensordot_vjp(A2, B2, W, [1], [0], "local")
-    gA, gB = compress_vjp(A, B, 1, 0, chi, dA2, dB2, conv="local")
+    gA, gB = compress_product_grad(A, B, 1, 0, chi, W, conv="local")
     a, b = _dtensor(A), _dtensor(B)
     a2, b2 = AG.compress(a, b, 1, 0, chi)
     c = AG.dot(a2, b2, [1], [0])
@@ -230,3 +228,100 @@ def test_autograd_compress_then_contract(P):
         r = flat_blocks(g_ref)
         err = np.abs(g.double().cpu().numpy() - r).max(initial=0)
         assert err <= 1e-8 * max(1.0, np.abs(r).max(initial=0)), err
+
+
+def _net_grad_case(P, tensors, bonds, path, pos, chi, tol):
+    from paper_2410_02215_amd import autograd as AG
+    n = len(tensors)
+    net = Network(tensors, bonds, conv="local", positions=pos)
+    v, grads = network_grad(net, path, chi=chi)
+    D = [_dtensor(tensors[t]) for t in range(n)]
+    F, labs, e2 = AG.contract(D, bonds, path, chi=chi, order=pos)
+    assert F.ndim == 0
+    val = F.data.sum()
+    got = float(val.detach()) * 2.0 ** e2
+    assert abs(got - v) <= tol * max(abs(v), 1e-300), (got, v)
+    # the library's own driver takes the same steps
+    m, e, _ = P.Network([to_gpu(tensors[t]) for t in range(n)], bonds, conv=P.LOCAL, positions=pos).contract(path, chi=chi or 0)
+    assert abs(m * 2.0 ** e - got) <= 1e-13 * abs(got)
+    gs = torch.autograd.grad(val, [d.data for d in D])
+    for t in range(n):
+        r = flat_blocks(grads[t])
+        g = gs[t].double().cpu().numpy() * 2.0 ** e2
+        err = np.abs(g - r).max(initial=0)
+        assert err <= tol * max(1e-300, np.abs(r).max(initial=0)), (t, err, np.abs(r).max(initial=0))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_approximate_network_gradient_matches_oracle(P, seed):
+    # odd tensors, parallel bonds fused and compressed at chi = 3
+    rng = np.random.default_rng(740 + seed)
+    while True:
+        nt = int(rng.integers(4, 7))
+        tensors, bonds = random_network(rng, S.Z2, nt, nt + 3, odd_frac=0.5, maxd=3)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        pos = [int(x) for x in rng.permutation(nt)]
+        path = random_ssa_path(rng, tensors, bonds)
+        from oracle.network import contract_network
+        T, _, _, infos = contract_network(Network(tensors, bonds, conv="local", positions=pos), path, chi=3)
+        if () in T.blocks and float(T.blocks[()]) != 0.0 and infos:
+            break
+    _net_grad_case(P, tensors, bonds, path, pos, 3, 1e-7)
+
+
+def test_peps_norm_gradient_with_compression(P):
+    from oracle import physics as OP
+    from synth import workloads as W
+    from synth.graphs import square_lattice
+    n, edges = square_lattice(2, 3)
+    spec = W.z2_peps(n, edges, 2, 2)
+    rng = np.random.default_rng(31)
+    kets = OP.ket_tensors(spec, [rng.standard_normal(s.dense_shape) for s in spec.sites])
+    net = OP.norm_network(spec, kets, conv="local")
+    path = W.norm_path(spec, seed=1)
+    tensors = [net.tensors[t] for t in range(2 * n)]
+    _net_grad_case(P, tensors, net.bonds, path, net.positions, 6, 1e-7)
+
+
+@pytest.mark.parametrize("conv", ["local", "global"])
+@pytest.mark.parametrize("sym", [S.Z2, S.U1])
+def test_fuse_backward_matches_oracle(P, sym, conv):
+    from oracle.ops import fuse as o_fuse
+    from oracle.adjoint import _leaf_copy
+    rng = np.random.default_rng(32)
+    for trial in range(6):
+        n = int(rng.integers(2, 5))
+        legs = [rand_leg(rng, sym, maxd=3) for _ in range(n)]
+        T = rand_tensor(rng, sym, legs)
+        m = int(rng.integers(1, n + 1))
+        gl = [int(x) for x in rng.permutation(n)[:m]]
+        rev = int(rng.integers(0, 2))
+        T1 = _leaf_copy(T)
+        F, _ = o_fuse(T1, gl, conv=conv, rev=rev)
+        W = rand_tensor(rng, sym, F.legs, total=F.total)
+        L = inner(W, F)
+        keys = T1.keys()
+        gs = torch.autograd.grad(L, [T1.blocks[k] for k in keys], allow_unused=True) if torch.is_tensor(L) and L.requires_grad else [None] * len(keys)
+        ref = np.concatenate([np.zeros(T1.blocks[k].numel()) if g is None else g.numpy().ravel() for k, g in zip(keys, gs)]) if keys else np.zeros(0)
+        c = P.LOCAL if conv == "local" else P.GLOBAL
+        G = to_gpu(T)
+        got = P.fuse_backward(G, gl, to_gpu(W), conv=c, rev=rev).data().double().cpu().numpy()
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_exact_gradient_of_a_network_with_fused_bonds(P):
+    # the same small network contracted exactly and with chi = 3
+    rng = np.random.default_rng(741)
+    while True:
+        nt = int(rng.integers(4, 7))
+        tensors, bonds = random_network(rng, S.Z2, nt, nt + 3, odd_frac=0.5, maxd=3)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        pos = [int(x) for x in rng.permutation(nt)]
+        path = random_ssa_path(rng, tensors, bonds)
+        from oracle.network import contract_network
+        T, _, _, infos = contract_network(Network(tensors, bonds, conv="local", positions=pos), path, chi=3)
+        if () in T.blocks and float(T.blocks[()]) != 0.0 and infos:
+            break
+    _net_grad_case(P, tensors, bonds, path, pos, None, 1e-10)

@@ -132,12 +132,12 @@ def test_network_grad_euler_and_difference(sym):
 
 @pytest.mark.parametrize("conv", ["local", "global"])
 @pytest.mark.parametrize("sym", [S.Z2, S.U1])
-def test_compress_vjp_directional_difference(sym, conv):
+def test_compress_product_grad_directional_difference(sym, conv):
     # L = <W, F(A' B')> is unchanged by the sign of each kept singular vector
     # pair, so its derivative through the truncated SVD is well defined; a
     # central difference (kept counts unchanged) must agree with it
     from oracle.linalg import compress_bond
-    from oracle.adjoint import compress_vjp
+    from oracle.adjoint import compress_product_grad
     rng = np.random.default_rng(14)
     for trial in range(3):
         bond = rand_leg(rng, sym, maxd=5)
@@ -153,8 +153,7 @@ def test_compress_vjp_directional_difference(sym, conv):
         A2, B2, _ = compress_bond(A, B, 1, 0, chi, conv=conv, cutoff=1e-6)
         C = ftensordot(A2, B2, [1], [0], conv=conv)
         W = rand_tensor(rng, sym, C.legs, total=C.total)
-        dA2, dB2 = ftensordot_vjp(A2, B2, W, [1], [0], conv)
-        gA, gB = compress_vjp(A, B, 1, 0, chi, dA2, dB2, conv=conv)
+        gA, gB = compress_product_grad(A, B, 1, 0, chi, W, conv=conv)
         V = rand_tensor(rng, sym, A.legs, total=A.total)
         h = 1e-6
         Ap, Am = A.copy(), A.copy()
@@ -164,3 +163,39 @@ def test_compress_vjp_directional_difference(sym, conv):
         fd = (float(loss(Ap, B, W)[0]) - float(loss(Am, B, W)[0])) / (2 * h)
         an = float(inner(gA, V))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_network_grad_with_compression_rank_deficient_factors():
+    # compressions whose factors are rank deficient (a one-row factor, bonds
+    # of rank one): the oracle's derivative must still agree with central
+    # differences of the compressed network value
+    from tests.helpers import random_network, random_ssa_path
+    rng = np.random.default_rng(741)
+    while True:
+        nt = int(rng.integers(4, 7))
+        tensors, bonds = random_network(rng, S.Z2, nt, nt + 3, odd_frac=0.5, maxd=3)
+        if sum(tensors[t].parity for t in tensors) % 2:
+            continue
+        pos = [int(x) for x in rng.permutation(nt)]
+        path = random_ssa_path(rng, tensors, bonds)
+        from oracle.network import contract_network
+        T, _, _, infos = contract_network(Network(tensors, bonds, conv="local", positions=pos), path, chi=3)
+        if () in T.blocks and float(T.blocks[()]) != 0.0 and infos:
+            break
+    net = Network(tensors, bonds, conv="local", positions=pos)
+    v, g = network_grad(net, path, chi=3)
+    r2 = np.random.default_rng(5)
+    for t in range(nt):
+        V = rand_tensor(r2, S.Z2, tensors[t].legs, total=tensors[t].total)
+        vals = []
+        for h in (1e-5, -1e-5):
+            X = tensors[t].copy()
+            for k in X.keys():
+                X.blocks[k] = tensors[t].block(k) + h * V.block(k)
+            tt = dict(tensors)
+            tt[t] = X
+            m, e = network_value(Network(tt, bonds, conv="local", positions=pos), path, chi=3)
+            vals.append(m * 2.0 ** e)
+        fd = (vals[0] - vals[1]) / 2e-5
+        an = float(inner(g[t], V))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (t, fd, an)
