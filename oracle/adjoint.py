@@ -110,3 +110,35 @@ def compress_product_grad(A, B, la, lb, chi, W, conv="local", cutoff=1e-6):
             i += 1
         outs.append(o)
     return outs[0], outs[1]
+
+
+def energy_grad(spec, kets, terms, paths, chi=None):
+    """(E, [dE/dket_s]) for E = sum_t <psi|G_t|psi> / <psi|psi>.
+
+    ``terms``: list of (G FTensor, (u, v)); ``paths``: {None: norm path,
+    (u, v): term path}. Every network is contracted (approximately with
+    chi) by ``network.contract_network`` in the local convention; the bra
+    tensors are the daggers of the kets, so both layers carry the gradient.
+    """
+    from .physics import norm_network
+    leaves = [_leaf_copy(k) for k in kets]
+
+    def value(op=None, sites=None):
+        net = norm_network(spec, leaves, op=op, op_sites=sites, conv="local")
+        T, _, e, _ = contract_network(net, paths[None if op is None else tuple(sites)], chi=chi, renorm=False)
+        b = T.blocks.get(())
+        return (b if b is not None else torch.zeros((), dtype=torch.float64)) * 2.0 ** e
+
+    N = value()
+    E = sum(value(G, s) for G, s in terms) / N
+    flat = [T.blocks[k] for T in leaves for k in T.keys()]
+    gs = torch.autograd.grad(E, flat, allow_unused=True)
+    out, i = [], 0
+    for T in leaves:
+        o = FTensor(T.sym, T.legs, T.total)
+        for k in T.keys():
+            g = gs[i]
+            o.blocks[k] = torch.zeros_like(T.blocks[k].detach()) if g is None else g.detach()
+            i += 1
+        out.append(o)
+    return float(E.detach()), out

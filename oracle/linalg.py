@@ -179,6 +179,60 @@ def near_tie(svals, chi, rel=1e3 * np.finfo(np.float64).eps):
     return abs(a - b) <= rel * max(abs(a), 1e-300)
 
 
+class _TruncatedSVD(torch.autograd.Function):
+    """(A', B') = (U_k S_k^1/2, S_k^1/2 V_k^T) for C = MA MB = U S V^T.
+
+    Backward: the derivative of the leading k singular triplets (Sec. II.A
+    truncated SVD). With Gu = dA' S^1/2, Gv = dB'^T S^1/2, a = U^T Gu,
+    b = V^T Gv over the r nonzero singular values (> 1e-12 s_max),
+        dC = U Y V^T + (I - U U^T) Gu S_k^-1 V_k^T + U_k S_k^-1 Gv^T (I - V V^T),
+        Y[x, y] = [y < k] (a[x, y] s_y + b[x, y] s_x) / (s_y^2 - s_x^2)
+                + [x < k] (a[y, x] s_y + b[y, x] s_x) / (s_x^2 - s_y^2)   (x != y)
+        Y[x, x] = [x < k] (a[x, x] + b[x, x]) / (2 s_x),
+    then dMA = dC MB^T, dMB = MA^T dC. Pairs of singular values closer than
+    1e-13 s_max^2 are treated as degenerate: a loss that is a function of the
+    compressed product does not depend on the rotation inside such a pair,
+    and its coupling term is zero.
+    """
+
+    @staticmethod
+    def forward(ctx, MA, MB, k):
+        C = MA @ MB
+        U, s, Vh = torch.linalg.svd(C, full_matrices=False)
+        sq = torch.sqrt(s[:k])
+        ctx.save_for_backward(MA, MB, U, s, Vh)
+        ctx.k = k
+        return U[:, :k] * sq[None, :], sq[:, None] * Vh[:k]
+
+    @staticmethod
+    def backward(ctx, dA, dB):
+        MA, MB, U, s, Vh = ctx.saved_tensors
+        k = ctx.k
+        r = int((s > 1e-12 * s[0]).sum()) if s.numel() and s[0] > 0 else 0
+        U, V, s = U[:, :r], Vh[:r].T, s[:r]
+        sk = s[:k]
+        Gu = dA * torch.sqrt(sk)[None, :]
+        Gv = dB.T * torch.sqrt(sk)[None, :]
+        a = U.T @ Gu
+        b = V.T @ Gv
+        tie = 1e-13 * float(s[0]) ** 2 if r else 0.0
+        den = s[None, :] ** 2 - s[:, None] ** 2          # den[x, y] = s_y^2 - s_x^2
+        ok = den.abs() > tie                               # excludes x == y
+        safe = torch.where(ok, den, torch.ones_like(den))
+        Y = torch.zeros((r, r), dtype=torch.float64)
+        t1 = (a * s[None, :k] + b * s[:, None]) / safe[:, :k]          # y < k
+        Y[:, :k] += torch.where(ok[:, :k], t1, torch.zeros_like(t1))
+        t2 = (a.T * s[None, :] + b.T * s[:k, None]) / safe[:k, :]      # x < k
+        Y[:k, :] -= torch.where(ok[:k, :], t2, torch.zeros_like(t2))
+        idx = torch.arange(k)
+        Y[idx, idx] = (a[idx, idx] + b[idx, idx]) / (2 * sk)
+        dC = U @ Y @ V.T
+        dC = dC + (Gu - U @ a) @ (V[:, :k] / sk[None, :]).T
+        dC = dC + (U[:, :k] / sk[None, :]) @ (Gv - V @ b).T
+        return dC @ MB.T, MA.T @ dC, None
+
+
+
 def compress_bond(A, B, la, lb, chi, conv="local", cutoff=1e-12):
     """Truncate the single bond (A leg ``la``, B leg ``lb``) to at most chi.
 
@@ -248,11 +302,12 @@ def compress_bond(A, B, la, lb, chi, conv="local", cutoff=1e-12):
         if MA.shape[0] == 0 or MB.shape[1] == 0:
             continue
         if MA.requires_grad or MB.requires_grad:
-            # derivatives are taken through the SVD of the bond matrix itself:
-            # reverse mode through the QR of a rank-deficient factor divides
-            # by its zero pivots (the values are the same either way)
-            U, s, Vh = torch.linalg.svd(MA @ MB, full_matrices=False)
-            facs[q] = (None, U, s, Vh, None, rl, cl)
+            # derivatives go through the SVD of the bond matrix itself, with
+            # the textbook adjoint (_TruncatedSVD): reverse mode through the QR
+            # of a rank-deficient factor divides by its zero pivots, and
+            # through torch's SVD by differences of equal zero singular values
+            s = torch.linalg.svdvals((MA @ MB).detach())
+            facs[q] = (None, (MA, MB), s, None, None, rl, cl)
         else:
             QA, RA = torch.linalg.qr(MA, mode="reduced")
             QBt, RBt = torch.linalg.qr(MB.T, mode="reduced")
@@ -278,9 +333,12 @@ def compress_bond(A, B, la, lb, chi, conv="local", cutoff=1e-12):
         discarded += float((s[k:] ** 2).sum().detach())
         if k == 0:
             continue
-        sq = torch.sqrt(s[:k])
-        LA_ = (U[:, :k] if QA is None else QA @ U[:, :k]) * sq[None, :]
-        RB_ = sq[:, None] * Vh[:k] if QB is None else (sq[:, None] * Vh[:k]) @ QB
+        if QA is None:  # differentiable route: U holds the factors (MA, MB)
+            LA_, RB_ = _TruncatedSVD.apply(U[0], U[1], k)
+        else:
+            sq = torch.sqrt(s[:k])
+            LA_ = (QA @ U[:, :k]) * sq[None, :]
+            RB_ = (sq[:, None] * Vh[:k]) @ QB
         sv_out[q] = s[:k]
         qi = chs.index(q)
         r0 = 0

@@ -170,6 +170,31 @@ class _Fuse(torch.autograd.Function):
         return ftn.fuse_backward(ctx.A, legs, D, conv, rev).data(), None, None, None, None, None
 
 
+class _Dagger(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, data, a, out):
+        A = a.handle(data)
+        D = ftn.dagger(A)
+        sd = (D.legs(), D.info()["total"])
+        out.append(sd)
+        ctx.args = (a.sym, a.dtype, sd)
+        return D.data()
+
+    @staticmethod
+    def backward(ctx, dD):
+        sym, dtype, sd = ctx.args
+        G = ftn.Tensor.create(sym, sd[0], sd[1], dtype, data=dD.detach().contiguous())
+        # the map is a permutation of entries without signs and an involution
+        return ftn.dagger(G).data(), None, None
+
+
+def dagger(a):
+    """Differentiable Hermitian conjugate (legs reversed, duals flipped)."""
+    st = []
+    data = _Dagger.apply(a.data, a, st)
+    return DTensor(a.sym, st[0][0], st[0][1], data)
+
+
 def fuse(a, legs, conv=ftn.LOCAL, rev=0):
     """Differentiable fusion of the given legs of a DTensor (Sec. IV.A)."""
     st = []
@@ -353,3 +378,36 @@ def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64):
         F = DTensor(F.sym, F.legs, F.total, -F.data)
     labs = [(l[1], l[2]) if l[0] == "o" else l for l in L[fin[0]]]
     return F, labs, e2
+
+
+def norm_tensors(spec, kets, op=None, op_sites=None):
+    """DTensors, bonds and global positions of <psi|psi> (or <psi|G|psi>).
+
+    Tensor ids as in the library's norm networks: bra of site s is s (the
+    dagger of the ket), ket of site s is n + s, the two-site operator 2n
+    (legs out_u, out_v, in_v, in_u); positions follow Fig. 4(a).
+    """
+    from synth.workloads import norm_network_bonds, norm_network_positions
+    n = spec.n_sites
+    tensors = [dagger(k) for k in kets] + list(kets) + ([op] if op is not None else [])
+    bonds = [(t1, l1, t2, l2) for (t1, l1, t2, l2, _) in
+             norm_network_bonds(spec, op_sites if op is not None else None)]
+    return tensors, bonds, norm_network_positions(n, op is not None)
+
+
+def expectation_ratio(spec, kets, terms, paths, chi=None, gemm=ftn.GEMM_F64):
+    """sum_t <psi|G_t|psi> / <psi|psi> as a 0-d torch tensor (differentiable).
+
+    ``terms``: list of (G DTensor, (u, v)); ``paths``: {None: norm path,
+    (u, v): path of that term}. Every network is contracted approximately
+    with compression to chi (exact when chi is None).
+    """
+    t, b, p = norm_tensors(spec, kets)
+    N, _, eN = contract(t, b, paths[None], chi, p, gemm)
+    nval = N.data.sum()
+    tot = 0.0
+    for G, sites in terms:
+        t, b, p = norm_tensors(spec, kets, G, sites)
+        X, _, eX = contract(t, b, paths[tuple(sites)], chi, p, gemm)
+        tot = tot + X.data.sum() * (2.0 ** (eX - eN))
+    return tot / nval

@@ -219,3 +219,18 @@ def boundary_path(lx, ly):
         acc = nxt
         nxt += 1
     return path
+
+
+def hubbard_terms(spec):
+    """Two-site terms of the Hubbard Hamiltonian (Eq. fermi-hubbard-ham).
+
+    ``[(kind, (u, v))]`` with u < v: a hopping term on every edge, and the
+    on-site term of every site s on the pair (s, first neighbour of s),
+    kind ``onsite_u_first`` when s is the smaller site of the pair and
+    ``onsite_u_second`` otherwise (see ``synth.operators``).
+    """
+    out = [("hop", (a, b)) for (a, b) in spec.edges]
+    for s in range(spec.n_sites):
+        nb = spec.sites[s].neighbours[0]
+        out.append(("onsite_u_first", (s, nb)) if s < nb else ("onsite_u_second", (nb, s)))
+    return out

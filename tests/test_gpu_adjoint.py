@@ -325,3 +325,25 @@ def test_exact_gradient_of_a_network_with_fused_bonds(P):
         if () in T.blocks and float(T.blocks[()]) != 0.0 and infos:
             break
     _net_grad_case(P, tensors, bonds, path, pos, None, 1e-10)
+
+
+@pytest.mark.parametrize("shape,d,chi", [((2, 2), (2, 1), None), ((2, 3), (2, 2), 6)])
+def test_hubbard_energy_gradient_matches_oracle(P, shape, d, chi):
+    from paper_2410_02215_amd import autograd as AG
+    from paper_2410_02215_amd import peps as GP
+    from oracle.adjoint import energy_grad
+    from synth import workloads as W
+    from synth.operators import operator_dense
+    from tests.test_oracle_adjoint import _hubbard_setup
+    spec, kets, terms, paths = _hubbard_setup(shape, d, 35)
+    E, grads = energy_grad(spec, kets, terms, paths, chi=chi)
+    D = [_dtensor(k) for k in kets]
+    gterms = [(AG.DTensor.from_tensor(GP.operator_tensor(spec, operator_dense(kind, "Z2"))), sites)
+              for kind, sites in W.hubbard_terms(spec)]
+    Eg = AG.expectation_ratio(spec, D, gterms, paths, chi=chi)
+    assert abs(float(Eg.detach()) - E) <= 1e-9 * abs(E)
+    gs = torch.autograd.grad(Eg, [x.data for x in D])
+    for s in range(len(kets)):
+        r = flat_blocks(grads[s])
+        err = np.abs(gs[s].double().cpu().numpy() - r).max(initial=0)
+        assert err <= 1e-7 * max(1e-300, np.abs(r).max(initial=0)), (s, err)

@@ -199,3 +199,58 @@ def test_network_grad_with_compression_rank_deficient_factors():
         fd = (vals[0] - vals[1]) / 2e-5
         an = float(inner(g[t], V))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (t, fd, an)
+
+
+def _hubbard_setup(shape, d, seed):
+    from oracle import physics as OP
+    from oracle.tensor import FTensor
+    from synth import workloads as W
+    from synth.graphs import square_lattice
+    from synth.operators import operator_dense
+    n, edges = square_lattice(*shape)
+    spec = W.z2_peps(n, edges, *d)
+    rng = np.random.default_rng(seed)
+    kets = OP.ket_tensors(spec, [rng.standard_normal(s.dense_shape) for s in spec.sites])
+    phys = kets[0].legs[0]
+    from oracle.tensor import Leg
+    out_l, in_l = phys, Leg(phys.charges, phys.dims, 1)
+    terms = []
+    for kind, sites in W.hubbard_terms(spec):
+        G = FTensor.from_dense(S.Z2, [out_l, out_l, in_l, in_l], (0,), operator_dense(kind, "Z2"))
+        terms.append((G, sites))
+    paths = {None: W.norm_path(spec, seed=1)}
+    for _, sites in terms:
+        paths[tuple(sites)] = W.norm_path(spec, seed=1, op_sites=tuple(sites))
+    return spec, kets, terms, paths
+
+
+@pytest.mark.parametrize("chi", [None, 4])
+def test_energy_gradient_directional_difference(chi):
+    from oracle.adjoint import energy_grad
+    from oracle import physics as OP
+    from oracle.network import contract_network
+    spec, kets, terms, paths = _hubbard_setup((2, 2), (2, 1), 33)
+    E, grads = energy_grad(spec, kets, terms, paths, chi=chi)
+
+    def energy(ks):
+        def value(op=None, sites=None):
+            net = OP.norm_network(spec, ks, op=op, op_sites=sites, conv="local")
+            T, _, e, _ = contract_network(net, paths[None if op is None else tuple(sites)], chi=chi)
+            return (float(T.blocks[()]) if () in T.blocks else 0.0) * 2.0 ** e
+        return sum(value(G, s) for G, s in terms) / value()
+
+    assert abs(energy(kets) - E) <= 1e-10 * abs(E)
+    rng = np.random.default_rng(34)
+    for s in (0, 3):
+        V = rand_tensor(rng, S.Z2, kets[s].legs, total=kets[s].total)
+        vals = []
+        for h in (1e-5, -1e-5):
+            X = kets[s].copy()
+            for k in X.keys():
+                X.blocks[k] = kets[s].block(k) + h * V.block(k)
+            ks = list(kets)
+            ks[s] = X
+            vals.append(energy(ks))
+        fd = (vals[0] - vals[1]) / 2e-5
+        an = float(inner(grads[s], V))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (s, fd, an)
