@@ -225,6 +225,92 @@ def main_amplitudes(args):
     print(json.dumps(out), flush=True)
 
 
+GRAD_CHI = 16  # bond sectors of the operator terms stay within the 128 the compression adjoint handles
+
+
+def main_gradient(args):
+    """Energy-gradient workload: a step is one gradient of
+    E = sum_t <psi|h_t|psi> / <psi|psi> (Hubbard, t = 1, U = 8) with respect
+    to every ket tensor, every network compressed as early as possible."""
+    import torch
+    import paper_2410_02215_amd as P
+    from paper_2410_02215_amd import autograd as AG, peps as GP
+    from synth import workloads as W
+    from synth.operators import operator_dense
+    cfg = W.c5()
+    spec = cfg["spec"]
+    chi = GRAD_CHI
+    lx, ly = cfg["lx"], cfg["ly"]
+    kets = [AG.DTensor.from_tensor(k, requires_grad=True)
+            for k in GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"], std=cfg["std"]))]
+    terms = W.hubbard_terms(spec)
+    paths = {None: W.norm_layer_path(spec, lx, ly)}
+    for _, sites in terms:
+        paths[tuple(sites)] = W.norm_layer_path(spec, lx, ly, tuple(sites))
+    gterms = [(AG.DTensor.from_tensor(GP.operator_tensor(spec, operator_dense(kind, "Z2"))), sites)
+              for kind, sites in terms]
+    nnet = len(terms) + 1
+    print("[bench] workload %s at chi %d: %d networks per gradient" % (cfg["name"], chi, nnet), file=sys.stderr,
+          flush=True)
+
+    def step():
+        E = AG.expectation_ratio(spec, kets, gterms, paths, chi=chi)
+        gs = torch.autograd.grad(E, [k.data for k in kets])
+        return float(E.detach()), gs
+
+    for _ in range(args.warmup):
+        E, _ = step()
+        print("[bench] warmup gradient done: E = %.10f" % E, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    P.ftn.profile_collect()
+    P.ftn.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        E, gs = step()
+        print("[bench] gradient %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.ftn.profile_enable(False)
+    prof = P.ftn.profile_collect()
+    el = t1 - t0
+    gnorm = math.sqrt(sum(float((g.double() ** 2).sum()) for g in gs))
+    out = {
+        "metric": "ftensordot useful TFLOP/s + fPEPS contractions/sec on 1 GPU at stated err vs FP64",
+        "value": nnet * args.steps / el, "unit": "contractions/s (forward + backward)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"].replace("chi%d" % cfg["chi"], "chi%d" % chi), "sites": spec.n_sites,
+                   "chi": chi, "networks_per_gradient": nnet, "gradients_per_s": args.steps / el},
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "result": {"energy": E, "grad_norm": gnorm},
+        "roofline": roofline(prof, cfg["name"]),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, gradient of the norm network)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = gradient_cpu_baseline(cfg, chi, paths)
+    print(json.dumps(out), flush=True)
+
+
+def gradient_cpu_baseline(cfg, chi, paths):
+    """The oracle on the host cores: value and gradient of <psi|psi> alone."""
+    import torch
+    from oracle import physics as OP
+    from oracle.adjoint import network_grad
+    from synth import workloads as W
+    spec = cfg["spec"]
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    kets = OP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"], std=cfg["std"]))
+    net = OP.norm_network(spec, kets, conv="local")
+    t0 = time.time()
+    network_grad(net, paths[None], chi=chi)
+    el = time.time() - t0
+    return dict(value=1.0 / el, unit="contractions/s (forward + backward)", cores=cores, kind="oracle",
+                sample="value and gradient of <psi|psi> (one of the %d networks of a gradient) on the same "
+                       "lattice and chi (%.1f s, FP64, torch CPU with %d threads)" % (len(W.hubbard_terms(spec)) + 1,
+                                                                                      el, cores))
+
+
 def roofline(prof, workload):
     """Roofline entry of the dominant kernel class by time."""
     dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
@@ -244,9 +330,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true", help="run the two contractions of a step one after the other")
-    ap.add_argument("--workload", choices=["c2", "amplitudes"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "amplitudes", "gradient"], default="c2",
                     help="c2: the 40-site norm and hopping contractions (default); amplitudes: <n|psi> of the "
-                         "8x8 lattice at chi = 36")
+                         "8x8 lattice at chi = 36; gradient: Hubbard energy gradient on the 6x6 lattice")
     ap.add_argument("--batch", type=int, default=64, help="amplitudes per step (amplitude workload)")
     ap.add_argument("--workers", type=int, default=4, help="host worker threads (amplitude workload)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
@@ -264,6 +350,8 @@ def main():
     P.load_library()
     if args.workload == "amplitudes":
         return main_amplitudes(args)
+    if args.workload == "gradient":
+        return main_gradient(args)
     cfg = W.c2()
     chi = cfg["chi"]
     paths = load_paths()

@@ -234,3 +234,109 @@ def hubbard_terms(spec):
         nb = spec.sites[s].neighbours[0]
         out.append(("onsite_u_first", (s, nb)) if s < nb else ("onsite_u_second", (nb, s)))
     return out
+
+
+def norm_boundary_path(spec, lx, ly, op_sites=None):
+    """SSA path of a norm network on an ``lx`` x ``ly`` lattice, row by row.
+
+    Tensor ids as in ``norm_network_bonds``. Each bra is first contracted
+    with its ket (the operator of a term joins the ket and then the bra of
+    its first site, and stays bonded to the second site); the double-layer
+    sites are then absorbed into a boundary row by row, column by column,
+    and the final boundary is contracted left to right (the boundary-MPS
+    order, with compression as early as possible applied by the driver).
+    """
+    n = lx * ly
+    path = []
+    nxt = 2 * n + (1 if op_sites is not None else 0)
+    owner = {}
+    if op_sites is not None:
+        u, v = op_sites
+        path.append((n + u, 2 * n))
+        path.append((u, nxt))
+        owner[u] = nxt + 1
+        nxt += 2
+    for s in range(n):
+        if s in owner:
+            continue
+        path.append((s, n + s))
+        owner[s] = nxt
+        nxt += 1
+    # boundary: column -> current id; ids covering several columns are
+    # shared and updated together
+    col = [owner[y] for y in range(ly)]
+    absorbed = set(owner[y] for y in range(ly))
+
+    def merge(a, b):
+        nonlocal nxt
+        path.append((a, b))
+        new = nxt
+        nxt += 1
+        for c in range(ly):
+            if col[c] in (a, b):
+                col[c] = new
+        return new
+
+    for x in range(1, lx):
+        for y in range(ly):
+            t = owner[x * ly + y]
+            if t in absorbed:
+                continue
+            absorbed.add(t)
+            new = merge(col[y], t)
+            # an operator pair spanning two columns of this row joins them
+            for c in range(ly):
+                if c != y and owner[x * ly + c] == t and col[c] != new:
+                    merge(new, col[c])
+    done = []
+    for c in range(ly):
+        if col[c] not in done:
+            done.append(col[c])
+    acc = done[0]
+    for t in done[1:]:
+        path.append((acc, t))
+        acc = nxt
+        nxt += 1
+    return path
+
+
+def norm_layer_path(spec, lx, ly, op_sites=None):
+    """SSA path of a norm network absorbed layer by layer, row by row.
+
+    Tensor ids as in ``norm_network_bonds``. The boundary starts as the
+    kets of row 0; the bras of that row are absorbed column by column, then
+    for every later row its kets and then its bras. The operator of a term
+    is first contracted with the ket of its first site. Absorbing one layer
+    at a time keeps the bonds that form between boundary tensors at
+    chi * D (bra and ket bonds are never absorbed together), the order of
+    boundary-MPS contraction with compression as early as possible.
+    """
+    n = lx * ly
+    path = []
+    nxt = 2 * n + (1 if op_sites is not None else 0)
+    ket = {s: n + s for s in range(n)}
+    if op_sites is not None:
+        path.append((n + op_sites[0], 2 * n))
+        ket[op_sites[0]] = nxt
+        nxt += 1
+    col = [ket[y] for y in range(ly)]
+
+    def absorb(y, t):
+        nonlocal nxt
+        path.append((col[y], t))
+        col[y] = nxt
+        nxt += 1
+
+    for y in range(ly):
+        absorb(y, y)
+    for x in range(1, lx):
+        for y in range(ly):
+            absorb(y, ket[x * ly + y])
+        for y in range(ly):
+            absorb(y, x * ly + y)
+    acc = col[0]
+    for t in col[1:]:
+        path.append((acc, t))
+        acc = nxt
+        nxt += 1
+    return path
