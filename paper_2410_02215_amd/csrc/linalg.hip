@@ -44,22 +44,26 @@ __device__ inline double wave_max(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic Jacobi eigensolver for a symmetric n x n matrix (n <= 128), one
-// workgroup per matrix, in two phases.
-// Phase 1 keeps the upper triangle in LDS and sweeps it in round-robin
-// order: per round, n/2 disjoint rotations are chosen (every wave computes
-// all of them, one per lane, and takes the ones it needs by cross-lane
-// reads), then every 2 x 2 block (pair k1, pair k2) is updated as
-// J_k1^T A J_k2 by one thread (a fixed list of at most three blocks per
-// thread). A round needs two barriers (inputs read, updates written) and no
-// eigenvector traffic. The rotations are logged to global memory. Phase 2 reuses the LDS for V = I and replays the
-// log: each wave owns a set of rows of V and applies every round to them
-// (lane k = rotation k), so rounds need no workgroup barrier. Sweeps stop
-// when the off-diagonal norm^2 is <= 1e-30 of the diagonal norm^2.
+// Cyclic Jacobi eigensolver for a symmetric n x n matrix (n <= 128), in two
+// kernels.
+// k_jacobi_sweep (one workgroup per matrix) keeps the upper triangle in LDS
+// and sweeps it in round-robin order. Per round, wave 0 computes the n/2
+// disjoint rotations (lane k: pair k) and publishes them in LDS; after one
+// barrier every thread updates its 2 x 2 blocks (pair k1, pair k2) as
+// J_k1^T A J_k2 in place (a fixed list of at most three blocks per thread;
+// every element belongs to exactly one block of a round, so reads and
+// writes of a round need no barrier between them); a second barrier ends
+// the round. The rotations are logged to global memory. Sweeps stop when the
+// off-diagonal norm^2 is <= 1e-30 of the diagonal norm^2. The eigenvalues
+// are written sorted, with the rank of each diagonal position.
+// k_jacobi_vectors replays the log onto V = I: rows of V are independent, so
+// each wave owns one row, the log is read ahead in blocks of rounds, and no
+// barrier is needed; the columns are scattered to their eigenvalue ranks.
 // Outputs: eigenvalues descending (ties: lower index first) and the matching
 // eigenvector columns (row-major n x n).
 constexpr int JAC_SWEEPS = 30;
 constexpr int NPAIR = 3;  // block pairs per thread: 64 * 65 / 2 <= 3 * 1024
+constexpr int JV_WAVES = 4;  // rows of V per workgroup of k_jacobi_vectors
 
 struct EigJob {
   const double* H;  // n x n input
@@ -67,7 +71,8 @@ struct EigJob {
   double* W;        // n eigenvalues, output (descending)
   double2* rot;     // rotation log: (c, s) per rotation
   int* rpq;         // rotation log: p | q << 16
-  int* rounds;      // optional: number of rounds done
+  int* rounds;      // number of rounds done (written by the sweeps)
+  int* rk;          // n: rank of each diagonal position (written by the sweeps)
   int n;
   int pad;
 };
@@ -79,28 +84,37 @@ __host__ __device__ inline int64_t jacobi_log_len(int n) {
 
 __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
   // round-robin tournament on n2 (even) players: fixed player n2-1
+  const int m = n2 - 1;
   if (i == 0) {
     p = r;
-    q = n2 - 1;
+    q = m;
   } else {
-    p = (r + i) % (n2 - 1);
-    q = (r - i + (n2 - 1)) % (n2 - 1);
+    p = r + i;
+    if (p >= m) p -= m;
+    q = r - i;
+    if (q < 0) q += m;
   }
   if (p > q) {
-    int t = p;
+    const int t = p;
     p = q;
     q = t;
   }
 }
 
-__global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
+// workgroup barrier that orders LDS only (the rotation log stores to global
+// memory stay in flight)
+__device__ inline void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__global__ void __launch_bounds__(LT) k_jacobi_sweep(const EigJob* jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int n = J.n;
   if (n <= 0) return;
   __shared__ double A[JMAX][JMAX + 1];
   __shared__ double ev[JMAX];
-  __shared__ int rk[JMAX];
   __shared__ double red[2][LT / 64];
+  __shared__ double2 rcs[JMAX / 2];  // the round's rotations (c, s)
+  __shared__ double rt[JMAX / 2];    // and t = s / c
+  __shared__ int rpq_s[JMAX / 2];    // and p | q << 16
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n2 = n + (n & 1);  // an odd order gets a zero row / column
   const int np = n2 / 2;
@@ -155,12 +169,10 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
     __syncthreads();
     if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
     for (int r = 0; r < n2 - 1; ++r, ++nr) {
-      // every wave computes the round's rotations (lane k: pair k) and takes
-      // the ones it needs by cross-lane reads (no shared-memory round trip)
-      int p = 0, q = 0;
-      double c = 1.0, sn = 0.0;
-      if (lane < np) {
+      if (w == 0 && lane < np) {
+        int p, q;
         rr_pair(n2, r, lane, p, q);
+        double c = 1.0, sn = 0.0;
         const double apq = A[p][q];
         if (apq != 0.0) {
           const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
@@ -168,104 +180,46 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
           c = 1.0 / sqrt(1.0 + t * t);
           sn = t * c;
         }
-        if (w == 0) {
-          J.rot[(int64_t)nr * np + lane] = make_double2(c, sn);
-          J.rpq[(int64_t)nr * np + lane] = p | (q << 16);
-        }
+        rcs[lane] = make_double2(c, sn);
+        rt[lane] = sn / c;
+        rpq_s[lane] = p | (q << 16);
+        J.rot[(int64_t)nr * np + lane] = make_double2(c, sn);
+        J.rpq[(int64_t)nr * np + lane] = p | (q << 16);
       }
-      const int pq_l = p | (q << 16);
-      double b[NPAIR][4];
-      int ad[NPAIR][4];
-      double2 r1v[NPAIR], r2v[NPAIR];
-#pragma unroll
-      for (int u = 0; u < NPAIR; ++u) {
-        // all lanes take part in the cross-lane reads (uniform control flow)
-        const int v1 = __shfl(pq_l, pk1[u]), v2 = __shfl(pq_l, pk2[u]);
-        r1v[u] = make_double2(__shfl(c, pk1[u]), __shfl(sn, pk1[u]));
-        r2v[u] = make_double2(__shfl(c, pk2[u]), __shfl(sn, pk2[u]));
-        const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
-        if (pk1[u] == pk2[u]) {
-          ad[u][0] = p1 * (JMAX + 1) + p1;
-          ad[u][1] = p1 * (JMAX + 1) + q1;
-          ad[u][2] = q1 * (JMAX + 1) + q1;
-          ad[u][3] = ad[u][1];
-        } else {
-          ad[u][0] = min(p1, p2) * (JMAX + 1) + max(p1, p2);
-          ad[u][1] = min(p1, q2) * (JMAX + 1) + max(p1, q2);
-          ad[u][2] = min(q1, p2) * (JMAX + 1) + max(q1, p2);
-          ad[u][3] = min(q1, q2) * (JMAX + 1) + max(q1, q2);
-        }
-      }
+      sync_lds();
       double* Af = &A[0][0];
-#pragma unroll
-      for (int u = 0; u < NPAIR; ++u)
-        if (pact[u])
-          for (int z = 0; z < 4; ++z) b[u][z] = Af[ad[u][z]];
-      // every wave has read its rotation inputs (the diagonal entries and
-      // a_pq of each pair) before any of them is overwritten
-      __syncthreads();
 #pragma unroll
       for (int u = 0; u < NPAIR; ++u) {
         if (!pact[u]) continue;
-        const double2 ra = r1v[u], rb = r2v[u];
+        const int v1 = rpq_s[pk1[u]], v2 = rpq_s[pk2[u]];
+        const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
         if (pk1[u] == pk2[u]) {
-          const double apq = b[u][1], t = ra.y / ra.x;
-          Af[ad[u][0]] = b[u][0] - t * apq;
-          Af[ad[u][2]] = b[u][2] + t * apq;
-          Af[ad[u][1]] = 0.0;
+          // diagonal block: a_pq is annihilated
+          const int a0 = p1 * (JMAX + 1) + p1, a1 = p1 * (JMAX + 1) + q1, a2 = q1 * (JMAX + 1) + q1;
+          const double b0 = Af[a0], b1 = Af[a1], b2 = Af[a2], t = rt[pk1[u]];
+          Af[a0] = b0 - t * b1;
+          Af[a2] = b2 + t * b1;
+          Af[a1] = 0.0;
         } else {
-          const double r00 = ra.x * b[u][0] - ra.y * b[u][2], r01 = ra.x * b[u][1] - ra.y * b[u][3];
-          const double r10 = ra.y * b[u][0] + ra.x * b[u][2], r11 = ra.y * b[u][1] + ra.x * b[u][3];
-          Af[ad[u][0]] = rb.x * r00 - rb.y * r01;
-          Af[ad[u][1]] = rb.y * r00 + rb.x * r01;
-          Af[ad[u][2]] = rb.x * r10 - rb.y * r11;
-          Af[ad[u][3]] = rb.y * r10 + rb.x * r11;
+          const double2 ra = rcs[pk1[u]], rb = rcs[pk2[u]];
+          const int a0 = min(p1, p2) * (JMAX + 1) + max(p1, p2);
+          const int a1 = min(p1, q2) * (JMAX + 1) + max(p1, q2);
+          const int a2 = min(q1, p2) * (JMAX + 1) + max(q1, p2);
+          const int a3 = min(q1, q2) * (JMAX + 1) + max(q1, q2);
+          const double b0 = Af[a0], b1 = Af[a1], b2 = Af[a2], b3 = Af[a3];
+          const double r00 = ra.x * b0 - ra.y * b2, r01 = ra.x * b1 - ra.y * b3;
+          const double r10 = ra.y * b0 + ra.x * b2, r11 = ra.y * b1 + ra.x * b3;
+          Af[a0] = rb.x * r00 - rb.y * r01;
+          Af[a1] = rb.y * r00 + rb.x * r01;
+          Af[a2] = rb.x * r10 - rb.y * r11;
+          Af[a3] = rb.y * r10 + rb.x * r11;
         }
       }
-      __syncthreads();
+      sync_lds();
     }
   }
   for (int i = tid; i < n; i += LT) ev[i] = A[i][i];
-  if (tid == 0 && J.rounds) J.rounds[0] = nr;
-  __syncthreads();
-  for (int e = tid; e < n2 * n2; e += LT) {
-    const int i = e / n2, j = e % n2;
-    A[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (lane < np) {
-    // the log is read PF rounds ahead so that its latency hides behind the
-    // updates of the rounds in between
-    constexpr int PF = 8;
-    double2 rb[PF];
-    int vb[PF];
-#pragma unroll
-    for (int k = 0; k < PF; ++k)
-      if (k < nr) {
-        rb[k] = J.rot[(int64_t)k * np + lane];
-        vb[k] = J.rpq[(int64_t)k * np + lane];
-      }
-    for (int t0 = 0; t0 < nr; t0 += PF) {
-#pragma unroll
-      for (int k = 0; k < PF; ++k) {
-        const int t = t0 + k;
-        if (t < nr) {
-          const double2 r = rb[k];
-          const int v = vb[k];
-          if (t + PF < nr) {
-            rb[k] = J.rot[(int64_t)(t + PF) * np + lane];
-            vb[k] = J.rpq[(int64_t)(t + PF) * np + lane];
-          }
-          const int p = v & 0xffff, q = v >> 16;
-          for (int i = w; i < n2; i += LT / 64) {
-            const double vp = A[i][p], vq = A[i][q];
-            A[i][p] = r.x * vp - r.y * vq;
-            A[i][q] = r.y * vp + r.x * vq;
-          }
-        }
-      }
-    }
-  }
+  if (tid == 0) J.rounds[0] = nr;
   __syncthreads();
   for (int i = tid; i < n; i += LT) {
     const double v = ev[i];
@@ -274,14 +228,63 @@ __global__ void __launch_bounds__(LT) k_jacobi_eig(const EigJob* jobs) {
       const double u = ev[j];
       rank += (u > v) || (u == v && j < i);
     }
-    rk[i] = rank;
+    J.rk[i] = rank;
     J.W[rank] = v;
   }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += LT) {
-    const int r = e / n, i = e % n;
-    J.V[(int64_t)r * n + rk[i]] = A[r][i];
+}
+
+// grid (jobs, ceil(n / JV_WAVES)), JV_WAVES waves: wave w owns row
+// blockIdx.y * JV_WAVES + w of V and lane k applies rotation k of every
+// round; the log is read PF rounds ahead, double-buffered in registers.
+__global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const EigJob* jobs) {
+  constexpr int PF = 8;
+  const EigJob J = jobs[blockIdx.x];
+  const int n = J.n;
+  const int n2 = n + (n & 1), np = n2 / 2;
+  __shared__ double Vs[JV_WAVES][JMAX + 2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = blockIdx.y * JV_WAVES + w;
+  if (row >= n) return;
+  double* V = Vs[w];
+  for (int j = lane; j < n2; j += 64) V[j] = (row == j) ? 1.0 : 0.0;
+  const int nr = *J.rounds;
+  if (lane < np && nr > 0) {
+    auto load = [&](int t, double2& r, int& v) {
+      const int tt = min(t, nr - 1);  // reads past the last round are clamped (and unused)
+      r = J.rot[(int64_t)tt * np + lane];
+      v = J.rpq[(int64_t)tt * np + lane];
+    };
+    auto apply = [&](const double2 r, const int v) {
+      const int p = v & 0xffff, q = v >> 16;
+      const double vp = V[p], vq = V[q];
+      V[p] = r.x * vp - r.y * vq;
+      V[q] = r.y * vp + r.x * vq;
+    };
+    double2 ra[PF], rb[PF];
+    int va[PF], vb[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) load(k, ra[k], va[k]);
+    const int nfull = nr / PF;
+    int b = 0;
+    for (; b + 2 <= nfull; b += 2) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) load((b + 1) * PF + k, rb[k], vb[k]);
+#pragma unroll
+      for (int k = 0; k < PF; ++k) apply(ra[k], va[k]);
+#pragma unroll
+      for (int k = 0; k < PF; ++k) load((b + 2) * PF + k, ra[k], va[k]);
+#pragma unroll
+      for (int k = 0; k < PF; ++k) apply(rb[k], vb[k]);
+    }
+    for (int t = b * PF; t < nr; ++t) {
+      double2 r;
+      int v;
+      load(t, r, v);
+      apply(r, v);
+    }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int c = lane; c < n; c += 64) J.V[(int64_t)row * n + J.rk[c]] = V[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -591,6 +594,47 @@ static double eig_flops(const std::vector<EigJob>& ej) {
   double f = 0;
   for (const EigJob& e : ej) f += 9.0 * (double)e.n * e.n * e.n;
   return f;
+}
+
+// Eigendecompositions of the jobs' matrices (H, V, W and n set by the
+// caller): the sweeps, then the replay of their rotation logs onto V, timed
+// as one factorisation launch. The logs and per-job counters are allocated
+// here. With `rounds`, the rounds each job took are copied back (the stream
+// is synchronised).
+static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>* rounds = nullptr) {
+  const int nj = (int)ej.size();
+  if (nj == 0) return;
+  int64_t log_n = 0;
+  int nmax = 0;
+  for (const EigJob& e : ej) {
+    log_n += jacobi_log_len(e.n);
+    nmax = std::max(nmax, e.n);
+  }
+  DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
+  DBuf<int> lpq(std::max<int64_t>(log_n, 1), s), aux((int64_t)nj * (JMAX + 1), s);
+  int64_t o = 0;
+  for (int t = 0; t < nj; ++t) {
+    EigJob& e = ej[t];
+    if (e.n > JMAX) fail(FTN_ENOTSUP, "eigensolver order above 128");
+    e.rot = lrot.p + o;
+    e.rpq = lpq.p + o;
+    o += jacobi_log_len(e.n);
+    e.rounds = aux.p + (int64_t)t * (JMAX + 1);
+    e.rk = e.rounds + 1;
+    e.pad = 0;
+  }
+  DBuf<EigJob> dj = to_device(ej, s);
+  void* tok = prof_begin(s);
+  LAUNCH(k_jacobi_sweep, dim3((unsigned)nj), dim3(LT), 0, s, dj.p);
+  if (nmax > 0)
+    LAUNCH(k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(nmax, JV_WAVES)), dim3(64 * JV_WAVES), 0, s, dj.p);
+  prof_end(tok, s, FTN_PROF_FACTOR, eig_flops(ej));
+  if (rounds) {
+    rounds->assign(nj, 0);
+    for (int t = 0; t < nj; ++t)
+      HIPC(hipMemcpyAsync(rounds->data() + t, aux.p + (int64_t)t * (JMAX + 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+  }
 }
 
 // per bond sector q
@@ -913,35 +957,19 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   static const bool trace = std::getenv("FTN_TRACE") != nullptr;
   if (!dir.empty()) {
     const int nd = (int)dir.size();
-    DBuf<int> drounds(nd, s);
-    std::vector<int64_t> log_off(nd);
-    int64_t log_n = 0;
-    for (int t = 0; t < nd; ++t) {
-      log_off[t] = log_n;
-      log_n += jacobi_log_len(S[dir[t]].ns);
-    }
-    DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
-    DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
     std::vector<EigJob> ej;
     for (int t = 0; t < nd; ++t) {
       const int g = dir[t];
-      EigJob j;
+      EigJob j{};
       j.H = Hm + hoff[g];
       j.V = Em + eoff[g];
       j.W = Lm + loff[g];
-      j.rot = lrot.p + log_off[t];
-      j.rpq = lpq.p + log_off[t];
-      j.rounds = trace ? drounds.p + t : nullptr;
       j.n = S[g].ns;
-      j.pad = 0;
       ej.push_back(j);
     }
-    DBuf<EigJob> dj = to_device(ej, s);
-    FACTOR_LAUNCH(eig_flops(ej), k_jacobi_eig, dim3((unsigned)nd), dim3(LT), 0, s, dj.p);
+    std::vector<int> r;
+    jacobi_eig(ej, s, trace ? &r : nullptr);
     if (trace) {
-      std::vector<int> r(nd);
-      HIPC(hipMemcpyAsync(r.data(), drounds.p, nd * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPC(hipStreamSynchronize(s));
       std::string t;
       for (int i = 0; i < nd; ++i) t += std::to_string(S[dir[i]].ns) + ":" + std::to_string(r[i]) + " ";
       std::fprintf(stderr, "[ftn] jacobi order:rounds %s\n", t.c_str());
@@ -960,8 +988,6 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   }
   DBuf<double> Q0(qn, s), Q1(qn, s), Z0(zn, s), Z1(zn, s), Z2(zn, s), Gy(ni * p * p, s), Mm(ni * p * p, s),
       Tr(ni * p * p, s), Zs(ni * p * p, s);
-  DBuf<double2> rrot(ni * jacobi_log_len(JMAX), s);
-  DBuf<int> rrpq(ni * jacobi_log_len(JMAX), s), rr_rounds(ni, s);
   std::string rr_trace;
   std::vector<GemmGroup> gxt, gx, ggq, ggz, gaq, gaz, ge;
   for (int t = 0; t < ni; ++t) {
@@ -995,20 +1021,15 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
     o.thr = nullptr;
     o.p = o.ldg = o.ldr = o.ldm = (int)p;
     oj.push_back(o);
-    EigJob e;
+    EigJob e{};
     e.H = Tr.p + go;
     e.V = Zs.p + go;
     e.W = Lm + loff[g];
-    e.rot = rrot.p + t * jacobi_log_len(JMAX);
-    e.rpq = rrpq.p + t * jacobi_log_len(JMAX);
-    e.rounds = trace ? rr_rounds.p + t : nullptr;
     e.n = (int)p;
-    e.pad = 0;
     ej.push_back(e);
   }
   DBuf<OrthJob> doj = to_device(oj, s);
-  DBuf<EigJob> dej = to_device(ej, s);
-  const double of_it = orth_flops(oj), ef_it = eig_flops(ej);
+  const double of_it = orth_flops(oj);
   double *q = Q0.p, *qt = Q1.p, *z = Z0.p, *zt = Z1.p, *zu = Z2.p;
   // y <- orthonormal basis of span(y), dependent columns zeroed
   auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
@@ -1036,11 +1057,10 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       // Rayleigh-Ritz: W = X^T Q, Tr = W^T W = Q^T X X^T Q
       run_gemm(Pxt, FTN_F64, Xm, q, zu, nullptr, s);
       run_gemm(Pgz, FTN_F64, zu, zu, Tr.p, nullptr, s);
-      FACTOR_LAUNCH(ef_it, k_jacobi_eig, dim3((unsigned)ni), dim3(LT), 0, s, dej.p);
+      std::vector<int> rr;
+      jacobi_eig(ej, s, trace ? &rr : nullptr);
       for (int t = 0; t < ni; ++t)
         HIPC(hipMemcpyAsync(cur.data() + t * p, Lm + loff[it[t]], p * 8, hipMemcpyDeviceToHost, s));
-      std::vector<int> rr(ni);
-      if (trace) HIPC(hipMemcpyAsync(rr.data(), rr_rounds.p, ni * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
       if (trace) rr_trace += " " + std::to_string(rr[0]);
       bool done = !prev.empty();
@@ -1803,28 +1823,16 @@ void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb,
     }
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, RA.p, RB.p, X.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, X.p, X.p, Hm.p, nullptr, s);
-    int64_t log_n = 0;
-    std::vector<int64_t> log_off(ns);
-    for (int i = 0; i < ns; ++i) {
-      log_off[i] = log_n;
-      log_n += jacobi_log_len((int)S[i].d);
-    }
-    DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
-    DBuf<int> lpq(std::max<int64_t>(log_n, 1), s);
     std::vector<EigJob> ej(ns);
     for (int i = 0; i < ns; ++i) {
       EigJob& j = ej[i];
+      j = EigJob{};
       j.H = Hm.p + go[i];
       j.V = U.p + go[i];
       j.W = lam.p + go[i];
-      j.rot = lrot.p + log_off[i];
-      j.rpq = lpq.p + log_off[i];
-      j.rounds = nullptr;
       j.n = (int)S[i].d;
-      j.pad = 0;
     }
-    DBuf<EigJob> dj = to_device(ej, s);
-    FACTOR_LAUNCH(eig_flops(ej), k_jacobi_eig, dim3((unsigned)ns), dim3(LT), 0, s, dj.p);
+    jacobi_eig(ej, s);
   }
   // qa = Q_A^T dA', qb = Q_B^T dB'^T, qf = Q_A^T A'   (d x k)
   DBuf<double> qa(std::max<int64_t>(ks, 1), s), qb(std::max<int64_t>(ks, 1), s), qf(std::max<int64_t>(ks, 1), s);

@@ -16,7 +16,8 @@ Usage (CSV output of rocprofv3, ``--output-format csv``):
 Classes match the library's own profiler: one "launch" of a class is one
 timed call (a grouped GEMM is its GEMM kernel plus, when the plan splits K,
 its reduction kernel; a permute is one block-permute kernel; a factor
-launch is one Cholesky or Jacobi kernel).
+launch is one Cholesky kernel, or one Jacobi eigensolve: its sweep kernel
+plus the kernel that accumulates its eigenvectors).
 """
 
 import csv
@@ -32,7 +33,8 @@ CLASSES = [
     ("gemm_f32", re.compile(r"k_splitk_reduce<float"), False),
     ("gemm_bf16x3", re.compile(r"k_gemm_bf16x3"), True),
     ("permute", re.compile(r"k_block_perm<"), True),
-    ("factor", re.compile(r"k_jacobi_eig|k_orth_factor"), True),
+    ("factor", re.compile(r"k_jacobi_sweep|k_orth_factor"), True),
+    ("factor", re.compile(r"k_jacobi_vectors"), False),
     ("copy", re.compile(r"__amd_rocclr_copyBuffer"), True),
 ]
 
