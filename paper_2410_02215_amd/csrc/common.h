@@ -299,6 +299,10 @@ struct GemmGroup {
   int64_t c_off, ldc;
   // scatter tables (when scatter == 1): row combos / col combos of the group
   int32_t scatter;
+  // sym: op(A) op(B) is symmetric (M == N, B the transpose of A); only the
+  // tiles on and above the diagonal are multiplied and the result is
+  // mirrored, so C is still written in full
+  int32_t sym;
   int32_t nrc, ncc;         // number of row / col combos
   int64_t rc_base, cc_base; // offsets into the combo start arrays
   int64_t boff_base;        // offset into block offset table (nrc * ncc)
@@ -316,7 +320,7 @@ struct GemmScatter {
 struct SplitRed {
   int64_t M, N, c_off, ldc, w_off, e0;
   int S;
-  int pad;
+  int sym;  // element (m, n) with m > n is taken from the partials at (n, m)
 };
 // a ready-to-launch grouped GEMM (group table resident on the device). Groups
 // whose tiles alone cannot fill the chip are cut into K slices that write

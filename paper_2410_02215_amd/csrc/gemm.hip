@@ -38,6 +38,18 @@ __device__ inline int64_t xcd_tile(int64_t bid, int64_t nt) {
   return x * base + (x < rem ? x : rem) + i;
 }
 
+// tile (tm, tn), tm <= tn, of index lt in the row-major upper triangle of an
+// nt x nt tile grid
+__device__ inline void tri_tile(int64_t lt, int64_t nt, int64_t& tm, int64_t& tn) {
+  int64_t r = 0;
+  while (lt >= nt - r) {
+    lt -= nt - r;
+    ++r;
+  }
+  tm = r;
+  tn = r + lt;
+}
+
 __device__ inline int find_group(const GemmGroup* g, int ng, int64_t tile) {
   int lo = 0, hi = ng - 1;
   while (lo < hi) {
@@ -148,7 +160,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_gemm(GemmLaunch L, const T* 
   __syncthreads();
   const GemmGroup G = L.groups[s_g];
   const int64_t lt = tile - G.tile0;
-  const int64_t m0 = (lt / G.ntn) * BM, n0 = (lt % G.ntn) * BN;
+  int64_t tm = lt / G.ntn, tn = lt % G.ntn;
+  if (G.sym) tri_tile(lt, G.ntn, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const bool mirror = G.sym && G.scatter == 0 && tm != tn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   const T* Ag = A + G.a_off;
@@ -289,6 +304,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_gemm(GemmLaunch L, const T* 
           const T v = alpha * acc[i][j][r];
           T* p = C + G.c_off + m * G.ldc + n;
           *p = beta != (T)0 ? v + beta * *p : v;
+          if (mirror) {
+            T* pt = C + G.c_off + n * G.ldc + m;
+            *pt = beta != (T)0 ? v + beta * *pt : v;
+          }
         }
       }
 }
@@ -310,8 +329,9 @@ __global__ void k_splitk_reduce(const SplitRed* __restrict__ R, int nr, int64_t 
   const SplitRed r = R[lo];
   const int64_t loc = e - r.e0, mn = r.M * r.N;
   const int64_t m = loc / r.N, n = loc % r.N;
+  const int64_t src = (r.sym && m > n) ? n * r.N + m : loc;
   T sum = T(0);
-  for (int q = 0; q < r.S; ++q) sum += Wk[r.w_off + q * mn + loc];
+  for (int q = 0; q < r.S; ++q) sum += Wk[r.w_off + q * mn + src];
   T* p = C + r.c_off + m * r.ldc + n;
   const T v = (T)alpha * sum;
   *p = beta != 0.0 ? v + (T)beta * *p : v;
@@ -438,7 +458,9 @@ __global__ void __launch_bounds__(GT) k_gemm_bf16x3(GemmLaunch L, const float* _
 // ---------------------------------------------------------------------------
 double gemm_flops(const std::vector<GemmGroup>& groups) {
   double f = 0;
-  for (auto& g : groups) f += 2.0 * (double)g.M * (double)g.N * (double)g.K;
+  // a symmetric product is priced as its triangle: M (M + 1) K
+  for (auto& g : groups)
+    f += (g.sym ? (double)(g.M + 1) : 2.0 * (double)g.N) * (double)g.M * (double)g.K;
   return f;
 }
 
@@ -455,7 +477,8 @@ static int choose_cfg(const std::vector<GemmGroup>& gs) {
   for (auto& g : gs) {
     maxM = std::max(maxM, g.M);
     maxN = std::max(maxN, g.N);
-    t128 += cdiv(g.M, 128) * cdiv(g.N, 128);
+    const int64_t a = cdiv(g.M, 128);
+    t128 += (g.sym && g.M == g.N) ? a * (a + 1) / 2 : a * cdiv(g.N, 128);
   }
   if (maxN <= 16 && maxM >= 256) return CFG_256x16;
   if (maxN <= 32 && maxM >= 256) return CFG_256x32;
@@ -477,8 +500,16 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   p.flops = gemm_flops(gs);
   p.cfg = kind == FTN_GEMM_BF16X3 ? CFG_64 : choose_cfg(gs);
   const int bm = kind == FTN_GEMM_BF16X3 ? TBM : CFG_BM[p.cfg], bn = kind == FTN_GEMM_BF16X3 ? TBN : CFG_BN[p.cfg];
+  // the triangle of tiles needs square tiles, a square product and a plain
+  // output (the split-BF16 kernel multiplies the full grid)
+  for (auto& g : gs)
+    if (g.sym && (kind == FTN_GEMM_BF16X3 || bm != bn || g.M != g.N || g.scatter == 1)) g.sym = 0;
+  auto ntiles_of = [&](const GemmGroup& g) {
+    const int64_t a = cdiv(g.M, bm), b = cdiv(g.N, bn);
+    return g.sym ? a * (a + 1) / 2 : a * b;
+  };
   int64_t tiles = 0;
-  for (auto& g : gs) tiles += cdiv(g.M, bm) * cdiv(g.N, bn);
+  for (auto& g : gs) tiles += ntiles_of(g);
   // split-K for plain outputs when the tiles alone cannot fill the chip
   int64_t split = 1;
   if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < NCU) split = std::max<int64_t>(1, cdiv(2 * NCU, tiles));
@@ -489,7 +520,7 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
     g.ntn = cdiv(g.N, bn);
     if (S <= 1) {
       g.tile0 = t;
-      t += g.ntm * g.ntn;
+      t += ntiles_of(g);
       p.host.push_back(g);
       continue;
     }
@@ -503,6 +534,7 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
     r.ldc = g.ldc;
     r.w_off = p.ws_elems;
     r.S = (int)ns;
+    r.sym = g.sym;
     p.red_host.push_back(r);
     for (int64_t q = 0; q < ns; ++q) {
       GemmGroup h = g;
@@ -514,7 +546,7 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
       h.c_off = p.ws_elems + q * g.M * g.N;
       h.ldc = g.N;
       h.tile0 = t;
-      t += h.ntm * h.ntn;
+      t += ntiles_of(h);
       p.host.push_back(h);
     }
     p.ws_elems += ns * g.M * g.N;

@@ -569,6 +569,13 @@ static GemmGroup plain_group(int64_t M, int64_t N, int64_t K, int64_t a_off, int
   return g;
 }
 
+// a product known to be symmetric (op(B) = op(A)^T): only its upper tiles
+// are multiplied, the output is still written in full
+static GemmGroup sym_group(GemmGroup g) {
+  g.sym = 1;
+  return g;
+}
+
 // launches timed under the factorisation class of the opt-in profiler; the
 // work figure is the textbook flop count of what the launch computes:
 // Cholesky of a p x p matrix p^3/3, a triangular inverse p^3/3, and a
@@ -770,8 +777,8 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
       oj.push_back(o);
       if (rest > 0) {
         gt.push_back(plain_group(nb, rest, nb, m * NB * NB, NB, 1, off[m] + j0 * d + j0 + nb, d, 0, r12off[m], rest));
-        gs.push_back(plain_group(rest, rest, nb, r12off[m], rest, 1, r12off[m], rest, 0,
-                                 off[m] + (j0 + nb) * d + j0 + nb, d));
+        gs.push_back(sym_group(plain_group(rest, rest, nb, r12off[m], rest, 1, r12off[m], rest, 0,
+                                           off[m] + (j0 + nb) * d + j0 + nb, d)));
       }
     }
     DBuf<OrthJob> doj = to_device(oj, s);
@@ -914,9 +921,9 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
   std::vector<GemmGroup> gg2, gq2, gg3, gt, gr;
   for (int j = 0; j < nj; ++j) {
     const int64_t d = J[j].d, m = J[j].m;
-    gg2.push_back(plain_group(d, d, m, qo[j], d, 1, qo[j], d, 0, ws + wo[j], d));               // G2 = Q1^T Q1
+    gg2.push_back(sym_group(plain_group(d, d, m, qo[j], d, 1, qo[j], d, 0, ws + wo[j], d)));    // G2 = Q1^T Q1
     gq2.push_back(plain_group(m, d, d, qo[j], d, 0, 4 * ws + wo[j], d, 0, qs + qo[j], d));      // Q2 = Q1 M2
-    gg3.push_back(plain_group(d, d, m, qs + qo[j], d, 1, qs + qo[j], d, 0, 2 * ws + wo[j], d)); // G3 = Q2^T Q2
+    gg3.push_back(sym_group(plain_group(d, d, m, qs + qo[j], d, 1, qs + qo[j], d, 0, 2 * ws + wo[j], d)));  // G3
     gt.push_back(plain_group(d, d, d, 2 * ws + wo[j], d, 0, ws + wo[j], d, 0, 5 * ws + wo[j], d));  // T = R3 R2
     gr.push_back(plain_group(d, d, d, 5 * ws + wo[j], d, 0, wo[j], d, 0, J[j].goff, d));         // R = T R1
   }
@@ -995,8 +1002,8 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
     const int64_t rA = S[g].rA, rB = S[g].rB, go = (int64_t)t * p * p;
     gxt.push_back(plain_group(rB, p, rA, xoff[g], rB, 1, qo[t], p, 0, zo[t], p));  // Z = X^T Q
     gx.push_back(plain_group(rA, p, rB, xoff[g], rB, 0, zo[t], p, 0, qo[t], p));   // Q = X Z
-    ggq.push_back(plain_group(p, p, rA, qo[t], p, 1, qo[t], p, 0, go, p));         // Q^T Q
-    ggz.push_back(plain_group(p, p, rB, zo[t], p, 1, zo[t], p, 0, go, p));         // Z^T Z
+    ggq.push_back(sym_group(plain_group(p, p, rA, qo[t], p, 1, qo[t], p, 0, go, p)));  // Q^T Q
+    ggz.push_back(sym_group(plain_group(p, p, rB, zo[t], p, 1, zo[t], p, 0, go, p)));  // Z^T Z
     gaq.push_back(plain_group(rA, p, p, qo[t], p, 0, go, p, 0, qo[t], p));         // Q M
     gaz.push_back(plain_group(rB, p, p, zo[t], p, 0, go, p, 0, zo[t], p));         // Z M
     ge.push_back(plain_group(rA, p, p, qo[t], p, 0, go, p, 0, eoff[g], p));        // E = Q Zs
@@ -1091,6 +1098,32 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   run_gemm(Pe, FTN_F64, q, Zs.p, Em, nullptr, s);
 }
 
+// number of K slices of the Gram products G_A = A~^T A~ (one launch over
+// all sectors and slices; G_B likewise): each slice multiplies the upper
+// triangle of tiles (128 x 128 when every sector has d >= 128, else 64 x 64)
+// over K / slices, so the launch takes ceil(slices * tiles / CUs) waves of
+// tiles of duration ~ 1 / slices. The count with the fewest waves per slice
+// is taken (the smallest one within 3% of the best, since every slice adds
+// a partial matrix to sum).
+static int gram_split(const std::vector<Sect>& S, int64_t maxk) {
+  int64_t dmin = INT64_MAX, tri = 0;
+  for (auto& x : S) dmin = std::min(dmin, x.d);
+  const int64_t bt = dmin >= 128 ? 128 : 64;
+  for (auto& x : S) {
+    const int64_t t = cdiv(x.d, bt);
+    tri += t * (t + 1) / 2;
+  }
+  const int cap = (int)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(maxk, 256)));
+  if (tri == 0) return 1;
+  const int ncu = 256;
+  auto cost = [&](int k) { return (double)cdiv((int64_t)k * tri, ncu) / k; };
+  double best = 1e300;
+  for (int k = 1; k <= cap; ++k) best = std::min(best, cost(k));
+  for (int k = 1; k <= cap; ++k)
+    if (cost(k) <= 1.03 * best) return k;
+  return 1;
+}
+
 CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi, double cutoff,
                                 int conv, hipStream_t s) {
   CompressResult res;
@@ -1171,11 +1204,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   }
   DBuf<double> Gm(std::max<int64_t>(gsz, 1), s);
   {
-    int64_t tiles = 0;
-    for (auto& x : S) tiles += 2 * cdiv(x.d, 64) * cdiv(x.d, 64);
     int64_t maxk = 1;
     for (auto& x : S) maxk = std::max(maxk, std::max(x.M, x.N));
-    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, std::max<int64_t>(tiles, 1)), cdiv(maxk, 256)));
+    const int nsplit = gram_split(S, maxk);
     DBuf<double> part((int64_t)nsplit * std::max<int64_t>(gsz, 1), s);
     std::vector<GemmGroup> gA, gB;
     for (int k = 0; k < nsplit; ++k)
@@ -1183,12 +1214,12 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         const Sect& x = S[g];
         int64_t ca = cdiv(x.M, nsplit), k0 = std::min<int64_t>(k * ca, x.M), k1 = std::min<int64_t>(k0 + ca, x.M);
         // G_A = A~^T A~ : op(A) = A~^T (transA, lda = d), op(B) = A~ (ldb = d)
-        gA.push_back(plain_group(x.d, x.d, k1 - k0, x.a_off + k0 * x.d, x.d, 1, x.a_off + k0 * x.d, x.d, 0,
-                                 (int64_t)k * gsz + goffA[g], x.d));
+        gA.push_back(sym_group(plain_group(x.d, x.d, k1 - k0, x.a_off + k0 * x.d, x.d, 1, x.a_off + k0 * x.d, x.d,
+                                           0, (int64_t)k * gsz + goffA[g], x.d)));
         int64_t cb = cdiv(x.N, nsplit), j0 = std::min<int64_t>(k * cb, x.N), j1 = std::min<int64_t>(j0 + cb, x.N);
         // G_B = B~ B~^T : op(A) = B~ (lda = N), op(B) = B~^T (transB, ldb = N)
-        gB.push_back(plain_group(x.d, x.d, j1 - j0, x.b_off + j0, x.N, 0, x.b_off + j0, x.N, 1,
-                                 (int64_t)k * gsz + goffB[g], x.d));
+        gB.push_back(sym_group(plain_group(x.d, x.d, j1 - j0, x.b_off + j0, x.N, 0, x.b_off + j0, x.N, 1,
+                                           (int64_t)k * gsz + goffB[g], x.d)));
       }
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gA, At.p, At.p, part.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gB, Bt.p, Bt.p, part.p, nullptr, s);
@@ -1308,7 +1339,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         // accurate factors: X = R R_o^T (r x r_o), H = X X^T
         const int64_t r = x.ns, r_o = x.sideA ? x.rB : x.rA;
         gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
-        gxh.push_back(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r));
+        gxh.push_back(sym_group(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r)));
         continue;
       }
       // U1 = G_o R^T (d x r), H = R U1 (r x r)
@@ -1782,8 +1813,8 @@ void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb,
     std::vector<GemmGroup> ga, gb;
     for (int i = 0; i < ns; ++i) {
       const BS& x = S[i];
-      ga.push_back(plain_group(x.d, x.d, x.M, x.a_off, x.d, 1, x.a_off, x.d, 0, go[i], x.d));
-      gb.push_back(plain_group(x.d, x.d, x.N, x.b_off, x.N, 0, x.b_off, x.N, 1, go[i], x.d));
+      ga.push_back(sym_group(plain_group(x.d, x.d, x.M, x.a_off, x.d, 1, x.a_off, x.d, 0, go[i], x.d)));
+      gb.push_back(sym_group(plain_group(x.d, x.d, x.N, x.b_off, x.N, 0, x.b_off, x.N, 1, go[i], x.d)));
     }
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ga, At.p, At.p, GA.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gb, Bt.p, Bt.p, GB.p, nullptr, s);
@@ -1819,7 +1850,7 @@ void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb,
     for (int i = 0; i < ns; ++i) {
       const int64_t d = S[i].d;
       gx.push_back(plain_group(d, d, d, go[i], d, 0, go[i], d, 1, go[i], d));
-      gh.push_back(plain_group(d, d, d, go[i], d, 0, go[i], d, 1, go[i], d));
+      gh.push_back(sym_group(plain_group(d, d, d, go[i], d, 0, go[i], d, 1, go[i], d)));
     }
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, RA.p, RB.p, X.p, nullptr, s);
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, X.p, X.p, Hm.p, nullptr, s);
