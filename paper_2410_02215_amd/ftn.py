@@ -95,6 +95,9 @@ def load_library(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (the one that owns the device memory and streams it is handed)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError("libftn.so is not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(path)
