@@ -44,7 +44,11 @@
  *     data-dependent size (block counts of a new structure, the dims kept by
  *     a truncation) synchronise that stream before returning. A tensor's
  *     memory is released in the order of the stream that created it, so that
- *     stream must outlive the tensor.
+ *     stream must outlive the tensor, and a tensor read by work on another
+ *     stream must not be freed before that work has completed (synchronise
+ *     the other stream, or make the creating stream wait on it, first). The
+ *     library's own shared state (block structures, cached plans) may be
+ *     used from several streams at once.
  *   - Threads: a handle must not be used by two threads at once.
  */
 #ifndef FTN_H

@@ -397,6 +397,8 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
     }
   }
   if (!J.M) return;
+  // every wave has read R before the inversion below overwrites it in place
+  __syncthreads();
   // 16 x 16 diagonal blocks: lane c of wave w solves column c of block w
   if (w < JMAX / 16 && lane < 16) {
     const int o = 16 * w, c = lane;

@@ -419,10 +419,13 @@ std::shared_ptr<const Structure> get_structure(int sym, const std::vector<Leg>& 
     HIPC(hipStreamSynchronize(s));
     st->nblocks = nb;
     Structure* w = st.get();
-    w->d_keys = DBuf<int32_t>(nb * n, nullptr);
-    w->d_offsets = DBuf<int64_t>(nb + 1, nullptr);
-    w->d_shapes = DBuf<int32_t>(nb * n, nullptr);
-    w->d_parmask = DBuf<uint32_t>(nb, nullptr);
+    // a cached structure's tables are read by kernels of every stream; they
+    // are released (on eviction) by hipFree, which waits for all streams,
+    // never through the stream-ordered cache
+    w->d_keys = DBuf<int32_t>(nb * n, nullptr, true);
+    w->d_offsets = DBuf<int64_t>(nb + 1, nullptr, true);
+    w->d_shapes = DBuf<int32_t>(nb * n, nullptr, true);
+    w->d_parmask = DBuf<uint32_t>(nb, nullptr, true);
     if (nb) {
       LAUNCH(k_enum_write, dim3((unsigned)cdiv(P, T)), dim3(T), 0, s, dl.tab, dl.q.p,
                          dl.d.p, P, last.p, flag.p, w->d_keys.p, w->d_offsets.p, w->d_shapes.p,
@@ -446,10 +449,10 @@ std::shared_ptr<const Structure> get_structure(int sym, const std::vector<Leg>& 
   }
   if (st->d_offsets.p == nullptr) {  // scalar / empty structures: small uploads
     Structure* w = st.get();
-    w->d_offsets = DBuf<int64_t>(w->offsets.size(), nullptr);
+    w->d_offsets = DBuf<int64_t>(w->offsets.size(), nullptr, true);
     HIPC(hipMemcpy(w->d_offsets.p, w->offsets.data(), w->offsets.size() * 8, hipMemcpyHostToDevice));
     if (w->nblocks) {
-      w->d_parmask = DBuf<uint32_t>(w->nblocks, nullptr);
+      w->d_parmask = DBuf<uint32_t>(w->nblocks, nullptr, true);
       HIPC(hipMemcpy(w->d_parmask.p, w->parmask.data(), w->nblocks * 4, hipMemcpyHostToDevice));
     }
   }

@@ -283,6 +283,47 @@ def test_concurrent_contractions_on_two_streams(P):
     assert out == serial
 
 
+def test_c2_repeated_and_concurrent_contractions_are_bitwise_identical(P):
+    # Repeating the 40-site contractions, one after the other and then the
+    # norm and the hopping term at the same time on two streams from two host
+    # threads, must reproduce the first results bit for bit: no kernel may
+    # depend on wave timing, and no buffer may be reused by one stream while
+    # another still reads it.
+    import json, os, threading
+    from paper_2410_02215_amd import peps as GP
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    paths = json.load(open(os.path.join(root, "synth", "data", "paths.json")))
+    cfg = W.c2()
+    spec = cfg["spec"]
+    kets = GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
+    op = GP.operator_tensor(spec, operator_dense("hop", "Z2"))
+    nets = [GP.norm_network(spec, kets), GP.norm_network(spec, kets, op=op, op_sites=cfg["op_sites"])]
+    pth = [paths["c2_norm"]["path"], paths["c2_hop"]["path"]]
+    torch.cuda.synchronize()
+
+    def one(k):
+        m, e, _ = nets[k].contract(pth[k], chi=cfg["chi"])
+        return (m, e)
+
+    ref = [one(0), one(1)]
+    for _ in range(3):
+        assert [one(0), one(1)] == ref
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for _ in range(4):
+        out = [None, None]
+
+        def run(k):
+            with torch.cuda.stream(streams[k]):
+                out[k] = one(k)
+
+        th = threading.Thread(target=run, args=(1,))
+        th.start()
+        run(0)
+        th.join()
+        torch.cuda.synchronize()
+        assert out == ref
+
+
 def test_c2_full_size_norm_and_hopping(P):
     # the full 40-site workload against the stored oracle values
     import json, os
