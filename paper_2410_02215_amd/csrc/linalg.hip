@@ -298,9 +298,11 @@ __global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const EigJob* 
 // directions are dropped instead of amplified. R itself (rows of dropped
 // columns zero) can be written as well or instead.
 // Blocked in LDS, upper triangle only, panels of 16: one wave factors the
-// 16 x 16 diagonal block (no workgroup barrier inside), the panel row
-// R12 = R11^-T A12 is solved one column per thread, and the trailing
-// update A22 -= R12^T R12 runs on FP64 MFMA tiles. R is padded with the
+// 16 x 16 diagonal block in registers (four entries per lane, rows
+// broadcast by cross-lane reads; pivots by a reciprocal square root with
+// two Newton steps), the panel row R12 = R11^-T A12 is solved one column per
+// thread with the stored reciprocals of the pivots, and the trailing update
+// A22 -= R12^T R12 runs on FP64 MFMA tiles. R is padded with the
 // identity to order 128 and inverted in place: 16 x 16 diagonal blocks by
 // back substitution, then three doubling levels
 // [U11 U12; 0 U22]^-1 = [U11^-1, -U11^-1 U12 U22^-1; 0, U22^-1] on MFMA
@@ -318,6 +320,7 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   const int p = J.p;
   __shared__ double A[JMAX][JMAX + 1];
   __shared__ int dr[JMAX];
+  __shared__ double rinv[JMAX];  // 1 / R_jj, 0 for a dropped column
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int e = tid; e < JMAX * JMAX; e += LT) {
@@ -330,39 +333,55 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   mx = wave_max(mx);
   const double thr = J.thr ? *J.thr : tol * mx;
   for (int j0 = 0; j0 < JMAX; j0 += 16) {
-    if (w == 0) {  // 16 x 16 diagonal block, one wave
+    if (w == 0) {  // 16 x 16 diagonal block in registers of wave 0
+      // lane: column b = lane & 15, rows a0 + t (t < 4), a0 = 4 (lane >> 4)
+      const int b = lane & 15, a0 = 4 * (lane >> 4);
+      double x[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) x[t] = A[j0 + a0 + t][j0 + b];
+#pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
-        const int j = j0 + jj;
-        const double d = A[j][j];
+        const int j = j0 + jj, tj = jj & 3, lb = 16 * (jj >> 2);
+        const double d = __shfl(x[tj], lb + jj);
         const bool drop = (j < p) && !(d > thr);
-        const double r = drop ? 1.0 : sqrt(d), inv = 1.0 / r;
-        double v = 0.0;
-        if (lane > jj && lane < 16) v = drop ? 0.0 : A[j][j0 + lane] * inv;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (lane > jj && lane < 16) A[j][j0 + lane] = v;
+        // 1 / sqrt(d): hardware estimate and two Newton steps
+        double y = __builtin_amdgcn_rsq(d);
+        const double h = 0.5 * d;
+        y = y * (1.5 - h * y * y);
+        y = y * (1.5 - h * y * y);
+        const double r = drop ? 1.0 : d * y, inv = drop ? 1.0 : y;
+        if (lane >= lb && lane < lb + 16) {  // these lanes hold row jj in x[tj]
+          if (b > jj) x[tj] = drop ? 0.0 : x[tj] * inv;
+          else if (b == jj) x[tj] = r;
+        }
+        const double rbv = __shfl(x[tj], lb + b);
+        double ra[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ra[t] = __shfl(x[tj], lb + a0 + t);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (a0 + t > jj && b >= a0 + t) x[t] -= ra[t] * rbv;
         if (lane == 0) {
-          A[j][j] = r;
           dr[j] = drop ? 1 : 0;
+          rinv[j] = drop ? 0.0 : inv;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int e = lane; e < 256; e += 64) {
-          const int a = e >> 4, b = e & 15;
-          if (a > jj && b >= a) A[j0 + a][j0 + b] -= A[j][j0 + a] * A[j][j0 + b];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (a0 + t <= b) A[j0 + a0 + t][j0 + b] = x[t];
     }
     __syncthreads();
     const int rest = JMAX - j0 - 16;
-    if (tid < rest) {  // R12 = R11^-T A12, column c
+    if (tid < rest) {  // R12 = R11^-T A12, column c (right-looking: independent updates per step)
       const int c = j0 + 16 + tid;
       double x[16];
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        double sacc = A[j0 + jj][c];
+      for (int jj = 0; jj < 16; ++jj) x[jj] = A[j0 + jj][c];
 #pragma unroll
-        for (int l = 0; l < jj; ++l) sacc -= A[j0 + l][j0 + jj] * x[l];
-        x[jj] = dr[j0 + jj] ? 0.0 : sacc / A[j0 + jj][j0 + jj];
+      for (int l = 0; l < 16; ++l) {
+        x[l] *= rinv[j0 + l];
+#pragma unroll
+        for (int jj = l + 1; jj < 16; ++jj) x[jj] -= A[j0 + l][j0 + jj] * x[l];
       }
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) A[j0 + jj][c] = x[jj];
