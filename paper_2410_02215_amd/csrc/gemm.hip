@@ -510,12 +510,14 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   };
   int64_t tiles = 0;
   for (auto& g : gs) tiles += ntiles_of(g);
-  // split-K for plain outputs when the tiles alone cannot fill the chip
+  // split-K for plain outputs when the tiles alone give fewer than four
+  // workgroups per compute unit: more resident workgroups hide the latency
+  // of the K loop, and the partial sums cost one extra pass over C
   int64_t split = 1;
-  if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < NCU) split = std::max<int64_t>(1, cdiv(2 * NCU, tiles));
+  if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < 4 * NCU) split = std::max<int64_t>(1, cdiv(8 * NCU, tiles));
   int64_t t = 0;
   for (auto g : gs) {
-    const int64_t S = g.scatter ? 1 : std::min<int64_t>(split, std::min<int64_t>(64, g.K / 128));
+    const int64_t S = g.scatter ? 1 : std::min<int64_t>(split, std::min<int64_t>(256, g.K / 128));
     g.ntm = cdiv(g.M, bm);
     g.ntn = cdiv(g.N, bn);
     if (S <= 1) {
