@@ -166,17 +166,18 @@ void dfree(void* p, hipStream_t s, bool persistent) {
 
 // ---------------------------------------------------------------------------
 // pinned staging ring for small host-to-device copies: 16 chunks of 4 MiB;
-// a copy never spans chunks, and a chunk is reused only after the event
-// recorded behind its last copy has completed
+// a copy never spans chunks, copies from any streams share a chunk (they
+// never share bytes), and a chunk is reused only after the events recorded
+// behind the last copy of every stream that used it have completed
 namespace {
 constexpr size_t RING_CH = 4u << 20, RING_N = 16;
 std::mutex g_ring_mu;
 char* g_ring = nullptr;
 bool g_ring_failed = false;
 size_t g_ring_cur = 0, g_ring_off = 0;  // current chunk, offset inside it
-hipEvent_t g_ring_ev[RING_N];
-hipStream_t g_ring_st[RING_N];
-bool g_ring_used[RING_N];
+// per chunk: (stream, event behind that stream's last copy from the chunk)
+std::vector<std::pair<hipStream_t, hipEvent_t>> g_ring_use[RING_N];
+std::vector<hipEvent_t> g_ring_pool;
 }  // namespace
 
 void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -187,32 +188,38 @@ void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
       (void)hipGetLastError();
       g_ring = nullptr;
       g_ring_failed = true;
-    } else {
-      for (size_t c = 0; c < RING_N; ++c) {
-        HIPC(hipEventCreateWithFlags(&g_ring_ev[c], hipEventDisableTiming));
-        g_ring_used[c] = false;
-        g_ring_st[c] = nullptr;
-      }
     }
   }
   if (!g_ring || bytes > RING_CH) {
     HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     return;
   }
-  if (g_ring_off + bytes > RING_CH) {  // move to the next chunk once its copies are done
+  if (g_ring_off + bytes > RING_CH) {  // move to the next chunk once every copy from it is done
     g_ring_cur = (g_ring_cur + 1) % RING_N;
     g_ring_off = 0;
-    if (g_ring_used[g_ring_cur]) HIPC(hipEventSynchronize(g_ring_ev[g_ring_cur]));
-    g_ring_used[g_ring_cur] = false;
+    for (auto& u : g_ring_use[g_ring_cur]) {
+      HIPC(hipEventSynchronize(u.second));
+      g_ring_pool.push_back(u.second);
+    }
+    g_ring_use[g_ring_cur].clear();
   }
   const size_t c = g_ring_cur;
-  if (g_ring_used[c] && g_ring_st[c] != s) HIPC(hipEventSynchronize(g_ring_ev[c]));
   char* stage = g_ring + c * RING_CH + g_ring_off;
   std::memcpy(stage, src, bytes);
   HIPC(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, s));
-  HIPC(hipEventRecord(g_ring_ev[c], s));
-  g_ring_used[c] = true;
-  g_ring_st[c] = s;
+  hipEvent_t ev = nullptr;
+  for (auto& u : g_ring_use[c])
+    if (u.first == s) ev = u.second;
+  if (!ev) {
+    if (!g_ring_pool.empty()) {
+      ev = g_ring_pool.back();
+      g_ring_pool.pop_back();
+    } else {
+      HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    g_ring_use[c].emplace_back(s, ev);
+  }
+  HIPC(hipEventRecord(ev, s));
   g_ring_off = (g_ring_off + bytes + 255) & ~(size_t)255;
 }
 
