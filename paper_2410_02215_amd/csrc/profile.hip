@@ -31,18 +31,47 @@ hipEvent_t take() {
   return e;
 }
 
-void drain_locked() {
-  for (auto& r : g_recs) {
-    HIPC(hipEventSynchronize(r.b));
-    float ms = 0;
-    HIPC(hipEventElapsedTime(&ms, r.a, r.b));
-    g_ms[r.cls] += ms;
+// durations of a batch of records, taken outside the lock (waiting for the
+// events must not hold up the other threads' launches). Without `block`,
+// only records whose end event has completed are taken; the others go back.
+void settle(std::vector<Rec>& recs, bool block) {
+  std::vector<float> ms(recs.size(), -1.0f);
+  for (size_t i = 0; i < recs.size(); ++i) {
+    if (block) {
+      HIPC(hipEventSynchronize(recs[i].b));
+    } else {
+      const hipError_t q = hipEventQuery(recs[i].b);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();
+        continue;
+      }
+      HIPC(q);
+    }
+    HIPC(hipEventElapsedTime(&ms[i], recs[i].a, recs[i].b));
+  }
+  std::lock_guard<std::mutex> g(g_mu);
+  for (size_t i = 0; i < recs.size(); ++i) {
+    const Rec& r = recs[i];
+    if (ms[i] < 0.0f) {
+      g_recs.push_back(r);
+      continue;
+    }
+    g_ms[r.cls] += ms[i];
     g_cnt[r.cls] += 1;
     g_work[r.cls] += r.work;
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }
-  g_recs.clear();
+  recs.clear();
+}
+
+void drain() {
+  std::vector<Rec> recs;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    recs.swap(g_recs);
+  }
+  settle(recs, true);
 }
 }  // namespace
 
@@ -61,24 +90,28 @@ void* prof_begin(hipStream_t s) {
 void prof_end(void* tok, hipStream_t s, int cls, double work) {
   if (!tok) return;
   Rec* r = (Rec*)tok;
-  std::lock_guard<std::mutex> g(g_mu);
   HIPC(hipEventRecord(r->b, s));
   r->cls = cls;
   r->work = work;
-  g_recs.push_back(*r);
+  std::vector<Rec> full;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_recs.push_back(*r);
+    if (g_recs.size() > 4096) full.swap(g_recs);
+  }
   delete r;
-  if (g_recs.size() > 4096) drain_locked();
+  if (!full.empty()) settle(full, false);
 }
 
 void prof_enable(int on) {
+  drain();
   std::lock_guard<std::mutex> g(g_mu);
-  drain_locked();
   g_on = on != 0;
 }
 
 void prof_collect(double* ms, double* count, double* work) {
+  drain();
   std::lock_guard<std::mutex> g(g_mu);
-  drain_locked();
   for (int c = 0; c < FTN_PROF_NCLASS; ++c) {
     if (ms) ms[c] = g_ms[c];
     if (count) count[c] = g_cnt[c];
