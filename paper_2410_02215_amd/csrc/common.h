@@ -189,6 +189,9 @@ int64_t block_index(const Structure& t, const int32_t* key);  // -1 if absent (h
 // a tensor sharing t's data under another structure of the same layout
 std::unique_ptr<Tensor> share_tensor(const Tensor& t, std::shared_ptr<const Structure> st);
 void scale_inplace(Tensor& t, double alpha, hipStream_t s);
+// t <- 2^-e t, e the binary exponent of max |t| (when positive and finite),
+// e added to the device counter *e2; no host synchronisation
+void normalise_pow2(Tensor& t, int64_t* e2, hipStream_t s);
 
 // leg tables passed by value to kernels
 struct LegTab {

@@ -194,6 +194,9 @@ static void contract_net(const ftn_net* net, int nsteps, const int32_t* ssa_path
   int sgn = 0;
   int next_bond = net->nbonds;
   int64_t e2 = 0;
+  // binary exponents taken out of the intermediates, summed on the device
+  DBuf<int64_t> de2(1, s);
+  HIPC(hipMemsetAsync(de2.p, 0, sizeof(int64_t), s));
   const bool trace = std::getenv("FTN_TRACE") != nullptr;
   double st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = 0; k < nsteps; ++k) {
@@ -284,13 +287,7 @@ static void contract_net(const ftn_net* net, int nsteps, const int32_t* ssa_path
       std::fprintf(stderr, "[ftn] step %d: (%d,%d) -> %d legs [%s] size %lld\n", k, i, j, T[z]->ndim(),
                    d.c_str(), (long long)T[z]->size());
     }
-    double m = op_max_abs(*T[z], s);
-    if (m > 0 && std::isfinite(m)) {
-      int e;
-      std::frexp(m, &e);
-      scale_inplace(*T[z], std::ldexp(1.0, -e), s);
-      e2 += e;
-    }
+    normalise_pow2(*T[z], de2.p, s);
   }
   int fin = -1;
   for (int t = 0; t < (int)T.size(); ++t)
@@ -306,6 +303,12 @@ static void contract_net(const ftn_net* net, int nsteps, const int32_t* ssa_path
   if (((m * (m - 1) / 2) & 1) ^ sgn) F = op_scale(*F, -1.0, s);
   if (stats)
     for (int q = 0; q < 8; ++q) stats[q] = st[q];
+  {
+    int64_t de = 0;
+    HIPC(hipMemcpyAsync(&de, de2.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    e2 += de;
+  }
   if (exp2) *exp2 = e2;
   if (F->ndim() == 0) {
     double v = 0.0;

@@ -713,6 +713,38 @@ double op_max_abs(const Tensor& a, hipStream_t s) {
   return m;
 }
 
+// t <- 2^-e t with e the binary exponent of m = *mx (m = f 2^e, f in
+// [1/2, 1)) when m is positive and finite; e is added to *e2
+template <typename T>
+__global__ void k_scale_pow2(T* __restrict__ x, int64_t n, const double* __restrict__ mx, int64_t* e2) {
+  const double m = *mx;
+  if (!(m > 0.0) || !isfinite(m)) return;
+  int e;
+  (void)frexp(m, &e);
+  const T a = (T)ldexp(1.0, -e);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) *e2 += e;
+  if (i < n) x[i] = a * x[i];
+}
+
+void normalise_pow2(Tensor& t, int64_t* e2, hipStream_t s) {
+  const int64_t n = t.size();
+  if (!n) return;
+  const int nb = (int)std::min<int64_t>(1024, cdiv(n, 256));
+  DBuf<double> part(nb + 1, s);
+  if (t.dtype == FTN_F64)
+    LAUNCH(k_absmax<double>, dim3(nb), dim3(256), 0, s, (const double*)t.data, n, part.p);
+  else
+    LAUNCH(k_absmax<float>, dim3(nb), dim3(256), 0, s, (const float*)t.data, n, part.p);
+  LAUNCH(k_max_reduce, dim3(1), dim3(256), 0, s, part.p, nb, part.p + nb);
+  const dim3 g((unsigned)cdiv(n, 256));
+  if (t.dtype == FTN_F64)
+    LAUNCH(k_scale_pow2<double>, g, dim3(256), 0, s, (double*)t.data, n, part.p + nb, e2);
+  else
+    LAUNCH(k_scale_pow2<float>, g, dim3(256), 0, s, (float*)t.data, n, part.p + nb, e2);
+  HIPC(hipGetLastError());
+}
+
 void scale_inplace(Tensor& t, double alpha, hipStream_t s) {
   int64_t n = t.size();
   if (!n) return;
