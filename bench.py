@@ -334,7 +334,7 @@ def main():
                     help="c2: the 40-site norm and hopping contractions (default); amplitudes: <n|psi> of the "
                          "8x8 lattice at chi = 36; gradient: Hubbard energy gradient on the 6x6 lattice")
     ap.add_argument("--batch", type=int, default=64, help="amplitudes per step (amplitude workload)")
-    ap.add_argument("--workers", type=int, default=4, help="host worker threads (amplitude workload)")
+    ap.add_argument("--workers", type=int, default=8, help="host worker threads (amplitude workload)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
