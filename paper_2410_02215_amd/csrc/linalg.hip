@@ -233,6 +233,220 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep(const EigJob* jobs) {
   }
 }
 
+constexpr int NPAIR_LA = 3;  // off-diagonal blocks per thread of waves 1..15: 64 * 63 / 2 <= 3 * 960
+
+// partner of index x in round r (round-robin on n2 players, fixed player n2-1)
+__device__ inline int rr_partner(int n2, int r, int x) {
+  const int m = n2 - 1;
+  if (x == m) return r;
+  int y = 2 * r - x;
+  if (y < 0) y += m;
+  if (y >= m) y -= m;
+  return y == x ? m : y;
+}
+// index of the pair that holds x in round r
+__device__ inline int rr_slot(int n2, int r, int x) {
+  const int m = n2 - 1, np = n2 / 2;
+  if (x == m || x == r) return 0;
+  int d = x - r;
+  if (d < 0) d += m;
+  return d <= np - 1 ? d : m - d;
+}
+
+__device__ inline void jac_rotation(double app, double aqq, double apq, double& c, double& sn, double& t) {
+  c = 1.0;
+  sn = 0.0;
+  if (apq != 0.0) {
+    const double tau = (aqq - app) / (2.0 * apq);
+    const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    c = 1.0 / sqrt(1.0 + tt * tt);
+    sn = tt * c;
+  }
+  t = sn / c;
+}
+
+// The same sweeps with one barrier per round (for n2 >= 6, where no 2 x 2
+// block of a round holds two pivots of the next round, and no pivot of the
+// next round lies in a diagonal block of this one): wave 0 updates the
+// diagonal blocks and, for every pair of the next round, the block that
+// holds its pivot, and computes the next round's rotations from those fresh
+// values (cross-lane reads for the new diagonal entries) into the other LDS
+// buffer; waves 1..15 update the remaining blocks meanwhile. Every entry gets
+// the same operations in the same order as in k_jacobi_sweep, so the results
+// are bitwise the same.
+__global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
+  const EigJob J = jobs[blockIdx.x];
+  const int n = J.n;
+  if (n <= 0) return;
+  __shared__ double A[JMAX][JMAX + 1];
+  __shared__ double ev[JMAX];
+  __shared__ double red[2][LT / 64];
+  __shared__ double2 rcs[2][JMAX / 2];
+  __shared__ double rt[2][JMAX / 2];
+  __shared__ int rpq_s[2][JMAX / 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n2 = n + (n & 1), np = n2 / 2, m = n2 - 1;
+  for (int e = tid; e < n2 * n2; e += LT) {
+    const int i = e / n2, j = e % n2;
+    if (i <= j) A[i][j] = (j < n) ? J.H[(int64_t)i * n + j] : 0.0;
+  }
+  __syncthreads();
+  int pk1[NPAIR_LA], pk2[NPAIR_LA];
+  bool pact[NPAIR_LA];
+  {
+    const int nb = np * (np - 1) / 2;  // off-diagonal blocks k1 < k2
+#pragma unroll
+    for (int u = 0; u < NPAIR_LA; ++u) {
+      const int e = (tid - 64) + u * (LT - 64);
+      pact[u] = w > 0 && e < nb;
+      int k1 = 0, rem = pact[u] ? e : 0;
+      while (rem >= np - 1 - k1) {
+        rem -= np - 1 - k1;
+        ++k1;
+      }
+      pk1[u] = k1;
+      pk2[u] = k1 + 1 + rem;
+    }
+  }
+  int cur = 0;
+  if (w == 0 && lane < np) {  // rotations of round 0
+    int p, q;
+    rr_pair(n2, 0, lane, p, q);
+    double c, sn, t;
+    jac_rotation(A[p][p], A[q][q], A[p][q], c, sn, t);
+    rcs[0][lane] = make_double2(c, sn);
+    rt[0][lane] = t;
+    rpq_s[0][lane] = p | (q << 16);
+  }
+  __syncthreads();
+  int nr = 0;
+  for (int sweep = 0; sweep < JAC_SWEEPS; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n2 * n2; e += LT) {
+      const int i = e / n2, j = e % n2;
+      if (i < j)
+        off += A[i][j] * A[i][j];
+      else if (i == j)
+        tot += A[i][i] * A[i][i];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
+    }
+    if (lane == 0) {
+      red[0][w] = off;
+      red[1][w] = tot;
+    }
+    __syncthreads();
+    off = 0.0;
+    tot = 0.0;
+    for (int i = 0; i < LT / 64; ++i) {
+      off += red[0][i];
+      tot += red[1][i];
+    }
+    __syncthreads();
+    if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
+    for (int r = 0; r < m; ++r, ++nr) {
+      const int r2 = r + 1 == m ? 0 : r + 1;
+      double* Af = &A[0][0];
+      if (w > 0) {
+#pragma unroll
+        for (int u = 0; u < NPAIR_LA; ++u) {
+          if (!pact[u]) continue;
+          const int v1 = rpq_s[cur][pk1[u]], v2 = rpq_s[cur][pk2[u]];
+          const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
+          const int x1 = rr_partner(n2, r2, p1), y1 = rr_partner(n2, r2, q1);
+          if (x1 == p2 || x1 == q2 || y1 == p2 || y1 == q2) continue;  // wave 0 updates it
+          const double2 ra = rcs[cur][pk1[u]], rb = rcs[cur][pk2[u]];
+          const int a0 = min(p1, p2) * (JMAX + 1) + max(p1, p2);
+          const int a1 = min(p1, q2) * (JMAX + 1) + max(p1, q2);
+          const int a2 = min(q1, p2) * (JMAX + 1) + max(q1, p2);
+          const int a3 = min(q1, q2) * (JMAX + 1) + max(q1, q2);
+          const double b0 = Af[a0], b1 = Af[a1], b2 = Af[a2], b3 = Af[a3];
+          const double r00 = ra.x * b0 - ra.y * b2, r01 = ra.x * b1 - ra.y * b3;
+          const double r10 = ra.y * b0 + ra.x * b2, r11 = ra.y * b1 + ra.x * b3;
+          Af[a0] = rb.x * r00 - rb.y * r01;
+          Af[a1] = rb.y * r00 + rb.x * r01;
+          Af[a2] = rb.x * r10 - rb.y * r11;
+          Af[a3] = rb.y * r10 + rb.x * r11;
+        }
+      } else {
+        // the round being applied goes to the log
+        int pl = 0, ql = 0;
+        double dpp = 0.0, dqq = 0.0;
+        if (lane < np) {
+          const int v = rpq_s[cur][lane];
+          pl = v & 0xffff;
+          ql = v >> 16;
+          J.rot[(int64_t)nr * np + lane] = rcs[cur][lane];
+          J.rpq[(int64_t)nr * np + lane] = v;
+          // diagonal block of pair lane: a_pq is annihilated
+          const double b0 = A[pl][pl], b1 = A[pl][ql], b2 = A[ql][ql], t = rt[cur][lane];
+          dpp = b0 - t * b1;
+          dqq = b2 + t * b1;
+          A[pl][pl] = dpp;
+          A[ql][ql] = dqq;
+          A[pl][ql] = 0.0;
+        }
+        // next round's pair `lane`: its pivot block in this round
+        int pn = 0, qn = 0, ka = 0, kb = 0;
+        double apq_n = 0.0;
+        if (lane < np) {
+          rr_pair(n2, r2, lane, pn, qn);
+          const int sa = rr_slot(n2, r, pn), sb = rr_slot(n2, r, qn);
+          ka = sa;
+          kb = sb;
+          const int k1 = min(sa, sb), k2 = max(sa, sb);
+          const int v1 = rpq_s[cur][k1], v2 = rpq_s[cur][k2];
+          const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
+          const double2 ra = rcs[cur][k1], rb = rcs[cur][k2];
+          const int a0 = min(p1, p2) * (JMAX + 1) + max(p1, p2);
+          const int a1 = min(p1, q2) * (JMAX + 1) + max(p1, q2);
+          const int a2 = min(q1, p2) * (JMAX + 1) + max(q1, p2);
+          const int a3 = min(q1, q2) * (JMAX + 1) + max(q1, q2);
+          const double b0 = Af[a0], b1 = Af[a1], b2 = Af[a2], b3 = Af[a3];
+          const double r00 = ra.x * b0 - ra.y * b2, r01 = ra.x * b1 - ra.y * b3;
+          const double r10 = ra.y * b0 + ra.x * b2, r11 = ra.y * b1 + ra.x * b3;
+          const double n0 = rb.x * r00 - rb.y * r01, n1 = rb.y * r00 + rb.x * r01;
+          const double n2v = rb.x * r10 - rb.y * r11, n3 = rb.y * r10 + rb.x * r11;
+          Af[a0] = n0;
+          Af[a1] = n1;
+          Af[a2] = n2v;
+          Af[a3] = n3;
+          const int at = pn * (JMAX + 1) + qn;  // pn < qn
+          apq_n = at == a0 ? n0 : at == a1 ? n1 : at == a2 ? n2v : n3;
+        }
+        // the new diagonal entries of pn and qn, from the lanes that own them
+        const double dpa = __shfl(dpp, ka), dqa = __shfl(dqq, ka), dpb = __shfl(dpp, kb), dqb = __shfl(dqq, kb);
+        const int pa = __shfl(pl, ka), pb = __shfl(pl, kb);
+        if (lane < np) {
+          const double app = pn == pa ? dpa : dqa;
+          const double aqq = qn == pb ? dpb : dqb;
+          double c, sn, t;
+          jac_rotation(app, aqq, apq_n, c, sn, t);
+          rcs[cur ^ 1][lane] = make_double2(c, sn);
+          rt[cur ^ 1][lane] = t;
+          rpq_s[cur ^ 1][lane] = pn | (qn << 16);
+        }
+      }
+      sync_lds();
+      cur ^= 1;
+    }
+  }
+  for (int i = tid; i < n; i += LT) ev[i] = A[i][i];
+  if (tid == 0) J.rounds[0] = nr;
+  __syncthreads();
+  for (int i = tid; i < n; i += LT) {
+    const double v = ev[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double u = ev[j];
+      rank += (u > v) || (u == v && j < i);
+    }
+    J.rk[i] = rank;
+    J.W[rank] = v;
+  }
+}
 // grid (jobs, ceil(n / JV_WAVES)), JV_WAVES waves: wave w owns row
 // blockIdx.y * JV_WAVES + w of V and lane k applies rotation k of every
 // round; the log is read PF rounds ahead, double-buffered in registers.
@@ -651,9 +865,16 @@ static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>*
     e.rk = e.rounds + 1;
     e.pad = 0;
   }
-  DBuf<EigJob> dj = to_device(ej, s);
+  // orders of 63 and up take the sweep with one barrier per round (faster
+  // there); the jobs are ordered so that each kernel gets a contiguous range
+  std::vector<EigJob> ord(ej);
+  std::stable_partition(ord.begin(), ord.end(), [](const EigJob& e) { return e.n < 63; });
+  int nsmall = 0;
+  while (nsmall < nj && ord[nsmall].n < 63) ++nsmall;
+  DBuf<EigJob> dj = to_device(ord, s);
   void* tok = prof_begin(s);
-  LAUNCH(k_jacobi_sweep, dim3((unsigned)nj), dim3(LT), 0, s, dj.p);
+  if (nsmall > 0) LAUNCH(k_jacobi_sweep, dim3((unsigned)nsmall), dim3(LT), 0, s, dj.p);
+  if (nsmall < nj) LAUNCH(k_jacobi_sweep_la, dim3((unsigned)(nj - nsmall)), dim3(LT), 0, s, dj.p + nsmall);
   if (nmax > 0)
     LAUNCH(k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(nmax, JV_WAVES)), dim3(64 * JV_WAVES), 0, s, dj.p);
   prof_end(tok, s, FTN_PROF_FACTOR, eig_flops(ej));
