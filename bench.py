@@ -253,8 +253,13 @@ def main_gradient(args):
     print("[bench] workload %s at chi %d: %d networks per gradient" % (cfg["name"], chi, nnet), file=sys.stderr,
           flush=True)
 
+    # recomputation checkpoints: by default one absorbed layer of the boundary
+    # contraction per segment, so the stored tensors are the boundaries
+    # between layers (the environments)
+    ck = ly if args.checkpoint is None else (args.checkpoint or None)
+
     def step():
-        E = AG.expectation_ratio(spec, kets, gterms, paths, chi=chi)
+        E = AG.expectation_ratio(spec, kets, gterms, paths, chi=chi, checkpoint=ck)
         gs = torch.autograd.grad(E, [k.data for k in kets])
         return float(E.detach()), gs
 
@@ -262,6 +267,8 @@ def main_gradient(args):
         E, _ = step()
         print("[bench] warmup gradient done: E = %.10f" % E, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    P.ftn.memory_stats(torch.cuda.current_device(), reset_peak=True)
+    torch.cuda.reset_peak_memory_stats()
     P.ftn.profile_collect()
     P.ftn.profile_enable(True)
     t0 = time.perf_counter()
@@ -280,7 +287,10 @@ def main_gradient(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"].replace("chi%d" % cfg["chi"], "chi%d" % chi), "sites": spec.n_sites,
-                   "chi": chi, "networks_per_gradient": nnet, "gradients_per_s": args.steps / el},
+                   "chi": chi, "networks_per_gradient": nnet, "gradients_per_s": args.steps / el,
+                   "checkpoint_steps": ck or 0},
+        "peak_memory_gb": {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
+                           "torch": torch.cuda.max_memory_allocated() / 1e9},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
         "result": {"energy": E, "grad_norm": gnorm},
         "roofline": roofline(prof, cfg["name"]),
@@ -335,6 +345,9 @@ def main():
                          "8x8 lattice at chi = 36; gradient: Hubbard energy gradient on the 6x6 lattice")
     ap.add_argument("--batch", type=int, default=64, help="amplitudes per step (amplitude workload)")
     ap.add_argument("--workers", type=int, default=8, help="host worker threads (amplitude workload)")
+    ap.add_argument("--checkpoint", type=int, default=None,
+                    help="path steps per recomputation segment (gradient workload; default: one lattice "
+                         "layer, 0: keep every intermediate)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -296,7 +296,149 @@ def network_value(tensors, bonds, path, order=None, gemm=ftn.GEMM_F64):
     return Z.data.sum()
 
 
-def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64):
+class _NetState:
+    """Host bookkeeping of a network contraction plus its live DTensors.
+
+    ``T``: DTensors by id (consumed ids stay in the list); ``L``: labels of
+    every leg (("o", tensor, leg) for open legs, ("b", bond) for bonds);
+    ``D``: the dummy ranks each tensor carries; ``sgn``: the sign exponent of
+    moving and merging them; ``e2``: binary exponent taken out so far.
+    Steps replace list entries and never modify a DTensor or a label list in
+    place, so a shallow copy of the lists is an independent state.
+    """
+
+    def __init__(self, tensors, bonds, pos):
+        n = len(tensors)
+        self.T = list(tensors)
+        self.L = [[("o", t, l) for l in range(x.ndim)] for t, x in enumerate(tensors)]
+        for bi, (t1, l1, t2, l2) in enumerate(bonds):
+            self.L[t1][l1] = ("b", bi)
+            self.L[t2][l2] = ("b", bi)
+        odd = sorted([t for t in range(n) if self.T[t].parity], key=lambda t: pos[t])
+        self.D = [[] for _ in range(n)]
+        for r, t in enumerate(odd):
+            self.D[t] = [r]
+        self.sgn = 0
+        self.alive = [True] * n
+        self.ssa = list(range(n))
+        self.next_bond = len(bonds)
+        self.e2 = 0
+
+    def copy(self):
+        c = _NetState.__new__(_NetState)
+        c.T, c.L, c.D, c.alive, c.ssa = list(self.T), list(self.L), list(self.D), list(self.alive), list(self.ssa)
+        c.sgn, c.next_bond, c.e2 = self.sgn, self.next_bond, self.e2
+        return c
+
+    def shared(self, x, y):
+        L = self.L
+        pairs = [(L[x][k][1], k, L[y].index(l)) for k, l in enumerate(L[x]) if l[0] == "b" and l in L[y]]
+        pairs.sort()
+        return [p[1] for p in pairs], [p[2] for p in pairs]
+
+    def step(self, i, j, chi, gemm):
+        """One path step: dot, then fusion and compression of every bond of
+        the new tensor, then the power-of-two rescaling."""
+        import math
+        T, L, D = self.T, self.L, self.D
+        x, y = self.ssa[i], self.ssa[j]
+        lx, ly = self.shared(x, y)
+        Z = dot(T[x], T[y], lx, ly, ftn.LOCAL, gemm)
+        e = (len(D[x]) & 1) & (len(D[y]) & 1)
+        for a in D[x]:
+            for b in D[y]:
+                e ^= int(a > b)
+        self.sgn ^= e
+        D.append(sorted(D[x] + D[y]))
+        L.append([l for k, l in enumerate(L[x]) if k not in lx] + [l for k, l in enumerate(L[y]) if k not in ly])
+        T.append(Z)
+        self.alive.append(True)
+        self.alive[x] = self.alive[y] = False
+        z = len(T) - 1
+        self.ssa.append(z)
+        if chi:
+            nbs = [w for w in range(len(T)) if w != z and self.alive[w] and self.shared(z, w)[0]]
+            for w in nbs:
+                lz, lw = self.shared(z, w)
+                if len(lz) > 1:
+                    Tz, Tw = fuse(T[z], lz, ftn.LOCAL, 0), fuse(T[w], lw, ftn.LOCAL, 0)
+                    nb = ("b", self.next_bond)
+                    self.next_bond += 1
+                    for t_, ls, X in ((z, lz, Tz), (w, lw, Tw)):
+                        rest = [l for k, l in enumerate(L[t_]) if k not in ls]
+                        p_ = sum(1 for k in range(len(L[t_])) if k not in ls and k < ls[0])
+                        L[t_] = rest[:p_] + [nb] + rest[p_:]
+                        T[t_] = X
+                    lz, lw = self.shared(z, w)
+                dim = sum(T[z].legs[lz[0]][1])
+                if dim > chi and T[z].data.numel() and T[w].data.numel():
+                    T[z], T[w] = compress(T[z], T[w], lz[0], lw[0], chi, 1e-6, ftn.LOCAL)
+        m = float(T[z].data.detach().abs().max()) if T[z].data.numel() else 0.0
+        if m > 0 and math.isfinite(m):
+            ex = math.frexp(m)[1]
+            T[z] = DTensor(T[z].sym, T[z].legs, T[z].total, T[z].data * (2.0 ** -ex))
+            self.e2 += ex
+
+
+class _Segment(torch.autograd.Function):
+    """Recomputation checkpoint over consecutive path steps.
+
+    The forward pass receives the outputs already computed without a graph
+    and keeps only the segment's input data; the backward pass replays the
+    segment from them with the graph recorded and back-propagates through
+    it. The replay calls the same deterministic kernels on the same inputs,
+    so it rebuilds the same block structures and values.
+    """
+
+    @staticmethod
+    def forward(ctx, replay, outs, *ins):
+        ctx.replay = replay
+        ctx.save_for_backward(*ins)
+        return tuple(o.detach() for o in outs)
+
+    @staticmethod
+    def backward(ctx, *gouts):
+        ins = [x.detach().requires_grad_(True) for x in ctx.saved_tensors]
+        with torch.enable_grad():
+            outs = ctx.replay(ins)
+        os_, gs_ = [], []
+        for o, g in zip(outs, gouts):
+            if g is not None and o.requires_grad:
+                os_.append(o)
+                gs_.append(g)
+        if os_:
+            torch.autograd.backward(os_, gs_)
+        return (None, None) + tuple(x.grad for x in ins)
+
+
+def _run_segment(st, steps, chi, gemm):
+    """Advance ``st`` over ``steps`` (SSA pairs) under a recomputation
+    checkpoint and return the new state."""
+    with torch.no_grad():
+        s1 = st.copy()
+        for (i, j) in steps:
+            s1.step(i, j, chi, gemm)
+    n0 = len(st.T)
+    ins = [t for t in range(n0) if st.alive[t] and (not s1.alive[t] or s1.T[t] is not st.T[t])]
+    outs = [t for t in range(len(s1.T)) if s1.alive[t] and (t >= n0 or s1.T[t] is not st.T[t])]
+
+    def replay(datas):
+        s2 = st.copy()
+        for t, d in zip(ins, datas):
+            x = st.T[t]
+            s2.T[t] = DTensor(x.sym, x.legs, x.total, d)
+        for (i, j) in steps:
+            s2.step(i, j, chi, gemm)
+        return [s2.T[t].data for t in outs]
+
+    datas = _Segment.apply(replay, [s1.T[t].data for t in outs], *[st.T[t].data for t in ins])
+    for t, d in zip(outs, datas):
+        x = s1.T[t]
+        s1.T[t] = DTensor(x.sym, x.legs, x.total, d)
+    return s1
+
+
+def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64, checkpoint=None):
     """Approximate (chi) or exact contraction, differentiable.
 
     The same steps as ``ftn_contract_network`` in the local convention, each
@@ -307,77 +449,33 @@ def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64):
     dummy ranks (by ``order``) whose moves and final sort are a sign.
     Returns ``(T, labels, exp2)``: the final DTensor scaled by 2^-exp2 and
     the (tensor, leg) of each open leg.
+
+    ``checkpoint=s`` (s >= 1) runs the path in segments of s steps whose
+    intermediates are not kept for the backward pass: only the tensors
+    entering each segment (the environments at its boundary) are stored,
+    and the backward pass recomputes one segment at a time. The gradient is
+    the same; the cost is one more forward pass.
     """
-    import math
     n = len(tensors)
     pos = list(range(n)) if order is None else [int(x) for x in order]
-    T = list(tensors)
-    L = [[("o", t, l) for l in range(x.ndim)] for t, x in enumerate(tensors)]
-    for bi, (t1, l1, t2, l2) in enumerate(bonds):
-        L[t1][l1] = ("b", bi)
-        L[t2][l2] = ("b", bi)
-    odd = sorted([t for t in range(n) if T[t].parity], key=lambda t: pos[t])
-    D = [[] for _ in range(n)]
-    for r, t in enumerate(odd):
-        D[t] = [r]
-    sgn = 0
-    alive = [True] * n
-    ssa = list(range(n))
-    next_bond = len(bonds)
-    e2 = 0
-
-    def shared(x, y):
-        pairs = [(L[x][k][1], k, L[y].index(l)) for k, l in enumerate(L[x]) if l[0] == "b" and l in L[y]]
-        pairs.sort()
-        return [p[1] for p in pairs], [p[2] for p in pairs]
-
-    for (i, j) in path:
-        x, y = ssa[i], ssa[j]
-        lx, ly = shared(x, y)
-        Z = dot(T[x], T[y], lx, ly, ftn.LOCAL, gemm)
-        e = (len(D[x]) & 1) & (len(D[y]) & 1)
-        for a in D[x]:
-            for b in D[y]:
-                e ^= int(a > b)
-        sgn ^= e
-        D.append(sorted(D[x] + D[y]))
-        L.append([l for k, l in enumerate(L[x]) if k not in lx] + [l for k, l in enumerate(L[y]) if k not in ly])
-        T.append(Z)
-        alive.append(True)
-        alive[x] = alive[y] = False
-        z = len(T) - 1
-        ssa.append(z)
-        if chi:
-            nbs = [w for w in range(len(T)) if w != z and alive[w] and shared(z, w)[0]]
-            for w in nbs:
-                lz, lw = shared(z, w)
-                if len(lz) > 1:
-                    Tz, Tw = fuse(T[z], lz, ftn.LOCAL, 0), fuse(T[w], lw, ftn.LOCAL, 0)
-                    nb = ("b", next_bond)
-                    next_bond += 1
-                    for t_, ls, X in ((z, lz, Tz), (w, lw, Tw)):
-                        rest = [l for k, l in enumerate(L[t_]) if k not in ls]
-                        p_ = sum(1 for k in range(len(L[t_])) if k not in ls and k < ls[0])
-                        L[t_] = rest[:p_] + [nb] + rest[p_:]
-                        T[t_] = X
-                    lz, lw = shared(z, w)
-                dim = sum(T[z].legs[lz[0]][1])
-                if dim > chi and T[z].data.numel() and T[w].data.numel():
-                    T[z], T[w] = compress(T[z], T[w], lz[0], lw[0], chi, 1e-6, ftn.LOCAL)
-        m = float(T[z].data.detach().abs().max()) if T[z].data.numel() else 0.0
-        if m > 0 and math.isfinite(m):
-            ex = math.frexp(m)[1]
-            T[z] = DTensor(T[z].sym, T[z].legs, T[z].total, T[z].data * (2.0 ** -ex))
-            e2 += ex
-    fin = [t for t in range(len(T)) if alive[t]]
+    st = _NetState(tensors, bonds, pos)
+    path = [(int(i), int(j)) for (i, j) in path]
+    if checkpoint is not None and int(checkpoint) >= 1 and torch.is_grad_enabled():
+        s = int(checkpoint)
+        for k0 in range(0, len(path), s):
+            st = _run_segment(st, path[k0:k0 + s], chi, gemm)
+    else:
+        for (i, j) in path:
+            st.step(i, j, chi, gemm)
+    fin = [t for t in range(len(st.T)) if st.alive[t]]
     if len(fin) != 1:
         raise ValueError("path does not contract the network to one tensor")
-    F = T[fin[0]]
-    m = len(D[fin[0]])
-    if ((m * (m - 1) // 2) & 1) ^ sgn:
+    F = st.T[fin[0]]
+    m = len(st.D[fin[0]])
+    if ((m * (m - 1) // 2) & 1) ^ st.sgn:
         F = DTensor(F.sym, F.legs, F.total, -F.data)
-    labs = [(l[1], l[2]) if l[0] == "o" else l for l in L[fin[0]]]
-    return F, labs, e2
+    labs = [(l[1], l[2]) if l[0] == "o" else l for l in st.L[fin[0]]]
+    return F, labs, st.e2
 
 
 def norm_tensors(spec, kets, op=None, op_sites=None):
@@ -395,19 +493,20 @@ def norm_tensors(spec, kets, op=None, op_sites=None):
     return tensors, bonds, norm_network_positions(n, op is not None)
 
 
-def expectation_ratio(spec, kets, terms, paths, chi=None, gemm=ftn.GEMM_F64):
+def expectation_ratio(spec, kets, terms, paths, chi=None, gemm=ftn.GEMM_F64, checkpoint=None):
     """sum_t <psi|G_t|psi> / <psi|psi> as a 0-d torch tensor (differentiable).
 
     ``terms``: list of (G DTensor, (u, v)); ``paths``: {None: norm path,
     (u, v): path of that term}. Every network is contracted approximately
-    with compression to chi (exact when chi is None).
+    with compression to chi (exact when chi is None), with recomputation
+    checkpoints every ``checkpoint`` steps when given (see ``contract``).
     """
     t, b, p = norm_tensors(spec, kets)
-    N, _, eN = contract(t, b, paths[None], chi, p, gemm)
+    N, _, eN = contract(t, b, paths[None], chi, p, gemm, checkpoint)
     nval = N.data.sum()
     tot = 0.0
     for G, sites in terms:
         t, b, p = norm_tensors(spec, kets, G, sites)
-        X, _, eX = contract(t, b, paths[tuple(sites)], chi, p, gemm)
+        X, _, eX = contract(t, b, paths[tuple(sites)], chi, p, gemm, checkpoint)
         tot = tot + X.data.sum() * (2.0 ** (eX - eN))
     return tot / nval

@@ -8,6 +8,7 @@
 namespace ftn {
 const char* last_error_cstr();
 void set_allocator(void* (*a)(size_t, ftn_stream_t, void*), void (*f)(void*, ftn_stream_t, void*), void* ctx);
+void memory_stats(int dev, int64_t* in_use, int64_t* peak, int64_t* reserved, bool reset_peak);
 }  // namespace ftn
 
 struct ftn_tensor {
@@ -77,6 +78,15 @@ int ftn_set_allocator(void* (*alloc_fn)(size_t, ftn_stream_t, void*), void (*fre
   return guarded([&] {
     if ((alloc_fn == nullptr) != (free_fn == nullptr)) fail(FTN_EINVAL, "give both allocator functions or neither");
     set_allocator(alloc_fn, free_fn, ctx);
+  });
+}
+
+int ftn_memory_stats(int device, int64_t* in_use, int64_t* peak, int64_t* reserved, int reset_peak) {
+  return guarded([&] {
+    int n = 0;
+    HIPC(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(FTN_EINVAL, "no such device");
+    memory_stats(device, in_use, peak, reserved, reset_peak != 0);
   });
 }
 

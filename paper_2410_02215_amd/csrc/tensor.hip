@@ -67,6 +67,14 @@ struct DevCache {
   std::multimap<size_t, Block> free_;      // by size
   std::unordered_map<void*, size_t> live;  // pointer -> rounded size
   std::vector<hipEvent_t> events;          // idle events for reuse
+  // bytes handed out (rounded sizes), their high-water mark, and bytes held
+  // from hipMalloc (handed out + cached)
+  size_t in_use = 0, peak = 0, reserved = 0;
+  void take(void* p, size_t sz) {
+    live[p] = sz;
+    in_use += sz;
+    peak = std::max(peak, in_use);
+  }
 };
 std::mutex g_cache_mu;
 std::unordered_map<int, DevCache>* g_cache = new std::unordered_map<int, DevCache>();
@@ -81,6 +89,7 @@ void release_cached(DevCache& c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c.free_) {
     (void)hipFree(kv.second.p);
+    c.reserved -= kv.first;
     if (kv.second.ev) c.events.push_back(kv.second.ev);
   }
   c.free_.clear();
@@ -111,7 +120,7 @@ void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
       continue;
     }
     p = b.p;
-    c.live[p] = it->first;
+    c.take(p, it->first);
     if (b.ev) c.events.push_back(b.ev);
     c.free_.erase(it);
     return p;
@@ -127,7 +136,8 @@ void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
     fail(e == hipErrorOutOfMemory ? FTN_ENOMEM : FTN_EHIP,
          "hipMalloc(" + std::to_string(sz) + "): " + hipGetErrorString(e));
   }
-  c.live[p] = sz;
+  c.reserved += sz;
+  c.take(p, sz);
   return p;
 }
 
@@ -148,6 +158,7 @@ void dfree(void* p, hipStream_t s, bool persistent) {
   auto it = c.live.find(p);
   if (it == c.live.end()) return;  // not from this cache
   Block b{p, it->second, s, nullptr};
+  c.in_use -= it->second;
   c.live.erase(it);
   if (!c.events.empty()) {
     b.ev = c.events.back();
@@ -162,6 +173,15 @@ void dfree(void* p, hipStream_t s, bool persistent) {
     b.ev = nullptr;
   }
   c.free_.emplace(b.size, b);
+}
+
+void memory_stats(int dev, int64_t* in_use, int64_t* peak, int64_t* reserved, bool reset_peak) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  DevCache& c = (*g_cache)[dev];
+  if (in_use) *in_use = (int64_t)c.in_use;
+  if (peak) *peak = (int64_t)c.peak;
+  if (reserved) *reserved = (int64_t)c.reserved;
+  if (reset_peak) c.peak = c.in_use;
 }
 
 // ---------------------------------------------------------------------------

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("ftn_amplitudes", _I, [_I, _PP, _I, _PI32, _I, _PI32, _I64, _I, _I64, _PI32, _I, _P, _PD, _PI64]),
     ("ftn_profile_enable", _I, [_I]),
     ("ftn_profile_collect", _I, [_PD, _PD, _PD]),
+    ("ftn_memory_stats", _I, [_I, _PI64, _PI64, _PI64, _I]),
 ]
 
 PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_bf16x3", "permute", "factor", "other"]
@@ -82,6 +83,16 @@ def profile_collect():
     ms, cnt, wk = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
     _check(_lib.ftn_profile_collect(ms, cnt, wk))
     return {c: (ms[i], cnt[i], wk[i]) for i, c in enumerate(PROF_CLASSES)}
+
+
+def memory_stats(device=0, reset_peak=False):
+    """{"in_use", "peak", "reserved"}: bytes of the library's caching
+    allocator on ``device`` (see ``ftn_memory_stats``)."""
+    load_library()
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.ftn_memory_stats(int(device), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                 1 if reset_peak else 0))
+    return {"in_use": a.value, "peak": b.value, "reserved": c.value}
 
 
 class FtnError(RuntimeError):

@@ -347,3 +347,58 @@ def test_hubbard_energy_gradient_matches_oracle(P, shape, d, chi):
         r = flat_blocks(grads[s])
         err = np.abs(gs[s].double().cpu().numpy() - r).max(initial=0)
         assert err <= 1e-7 * max(1e-300, np.abs(r).max(initial=0)), (s, err)
+
+
+@pytest.mark.parametrize("ck", [1, 4])
+def test_checkpointed_energy_gradient_matches_the_stored_one(P, ck):
+    # recomputation checkpoints change what is stored, not what is computed:
+    # the same value (bitwise: the forward kernels see the same inputs) and
+    # the same gradient up to the order in which contributions are summed
+    from paper_2410_02215_amd import autograd as AG
+    from paper_2410_02215_amd import peps as GP
+    from synth import workloads as W
+    from synth.operators import operator_dense
+    from tests.test_oracle_adjoint import _hubbard_setup
+    spec, kets, terms, paths = _hubbard_setup((2, 3), (2, 2), 35)
+    gterms = [(AG.DTensor.from_tensor(GP.operator_tensor(spec, operator_dense(kind, "Z2"))), sites)
+              for kind, sites in W.hubbard_terms(spec)]
+    D0 = [_dtensor(k) for k in kets]
+    E0 = AG.expectation_ratio(spec, D0, gterms, paths, chi=6)
+    g0 = torch.autograd.grad(E0, [x.data for x in D0])
+    D1 = [_dtensor(k) for k in kets]
+    E1 = AG.expectation_ratio(spec, D1, gterms, paths, chi=6, checkpoint=ck)
+    assert float(E1.detach()) == float(E0.detach())
+    g1 = torch.autograd.grad(E1, [x.data for x in D1])
+    for s in range(len(kets)):
+        a, b = g0[s].double().cpu().numpy(), g1[s].double().cpu().numpy()
+        assert np.abs(a - b).max(initial=0) <= 1e-12 * max(1e-300, np.abs(a).max(initial=0)), s
+
+
+def test_checkpointed_network_gradient_keeps_only_segment_inputs(P):
+    # a compressed norm network: with one checkpoint per step the graph holds
+    # the segment functions only, and the gradient equals the stored one
+    from paper_2410_02215_amd import autograd as AG
+    from tests.test_oracle_adjoint import _hubbard_setup
+    spec, kets, terms, paths = _hubbard_setup((2, 3), (2, 2), 36)
+    outs = []
+    for ck in (None, 1):
+        D = [_dtensor(k) for k in kets]
+        t, b, p = AG.norm_tensors(spec, D)
+        F, _, e2 = AG.contract(t, b, paths[None], 6, p, checkpoint=ck)
+        v = F.data.sum()
+        names = set()
+        stack = [v.grad_fn]
+        while stack:
+            fn = stack.pop()
+            if fn is None:
+                continue
+            names.add(type(fn).__name__)
+            stack.extend(f for f, _ in fn.next_functions)
+        outs.append((float(v.detach()), e2, torch.autograd.grad(v, [x.data for x in D]), names))
+    (v0, e0, g0, n0), (v1, e1, g1, n1) = outs
+    assert (v1, e1) == (v0, e0)
+    assert any("_Dot" in n for n in n0) and any("_Compress" in n for n in n0)
+    assert not any("_Dot" in n or "_Compress" in n for n in n1) and any("_Segment" in n for n in n1)
+    for a, b in zip(g0, g1):
+        a, b = a.double().cpu().numpy(), b.double().cpu().numpy()
+        assert np.abs(a - b).max(initial=0) <= 1e-12 * max(1e-300, np.abs(a).max(initial=0))
