@@ -357,7 +357,8 @@ int ftn_profile_collect(double* ms, double* count, double* work);
    index), in bytes: `in_use` held by live buffers (tensor data, plans,
    temporaries; sizes rounded as allocated), `peak` the largest in_use since
    the last reset, `reserved` obtained from hipMalloc (in use + cached). Any
-   pointer may be NULL. reset_peak != 0 sets peak to the current in_use.
+   pointer may be NULL. reset_peak != 0 then sets peak to the current in_use
+   (the values returned are those before the reset).
    Memory from an external allocator and persistent tables (hipMalloc
    directly) are not counted. FTN_EINVAL for a device index out of range. */
 int ftn_memory_stats(int device, int64_t* in_use, int64_t* peak, int64_t* reserved, int reset_peak);

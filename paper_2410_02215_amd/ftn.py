@@ -87,7 +87,9 @@ def profile_collect():
 
 def memory_stats(device=0, reset_peak=False):
     """{"in_use", "peak", "reserved"}: bytes of the library's caching
-    allocator on ``device`` (see ``ftn_memory_stats``)."""
+    allocator on ``device`` (see ``ftn_memory_stats``); with ``reset_peak``
+    the peak is then reset to the current use (the values returned are
+    those before the reset)."""
     load_library()
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.ftn_memory_stats(int(device), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),

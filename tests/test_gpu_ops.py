@@ -179,3 +179,28 @@ def test_errors_are_reported(P):
     with pytest.raises(P.FtnError) as e:
         P.ftranspose(to_gpu(A), [0, 0])
     assert e.value.code == -1
+
+
+def test_memory_statistics_follow_allocations(P):
+    # one Z2 tensor of 2 x (1024 x 1024) FP64 entries: 16 MiB of block data
+    dev = torch.cuda.current_device()
+    torch.cuda.synchronize()
+    s0 = P.ftn.memory_stats(dev, reset_peak=True)  # values before the reset
+    assert s0["peak"] >= s0["in_use"] and s0["reserved"] >= s0["in_use"] >= 0
+    assert P.ftn.memory_stats(dev)["peak"] == s0["in_use"]
+    legs = [([(0, 0), (1, 0)], [1024, 1024], 0), ([(0, 0), (1, 0)], [1024, 1024], 1)]
+    G = P.Tensor.create(0, legs, (0, 0))
+    s1 = P.ftn.memory_stats(dev)
+    assert s1["in_use"] - s0["in_use"] >= 2 * 1024 * 1024 * 8
+    assert s1["peak"] >= s1["in_use"] and s1["reserved"] >= s1["in_use"]
+    del G
+    torch.cuda.synchronize()
+    s2 = P.ftn.memory_stats(dev)
+    assert s2["in_use"] <= s1["in_use"] - 2 * 1024 * 1024 * 8
+    assert s2["peak"] == s1["peak"]
+    s3 = P.ftn.memory_stats(dev, reset_peak=True)
+    assert s3["peak"] == s1["peak"]
+    assert P.ftn.memory_stats(dev)["peak"] == s3["in_use"]
+    with pytest.raises(P.FtnError) as e:
+        P.ftn.memory_stats(-1)
+    assert e.value.code == -1
