@@ -345,3 +345,32 @@ def test_c2_full_size_norm_and_hopping(P):
     ref2 = gold["c2_hop"]["mantissa"] * 2.0 ** gold["c2_hop"]["exp2"]
     print("c2 hop gpu %.15g ref %.15g" % (_val(m2, e2), ref2))
     assert abs(_val(m2, e2) - ref2) <= 1e-8 * abs(ref)
+
+
+def test_precision_forms_on_a_u1u1_diamond_cluster(P):
+    # the precision workload's structure (U(1)xU(1) diamond lattice, bond
+    # (0,0):4 and four charged sectors of 1) on a 2x2x1-cell cluster: the
+    # FP64 path against the oracle, then FP32 tensors with FP32 and split-BF16
+    # block GEMMs (compression in FP64) against the same oracle value
+    from paper_2410_02215_amd import peps as GP
+    cfg = W.c3(cells=(2, 2, 1), chi=16)
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"])
+    okets = OP.ket_tensors(spec, vals)
+    path = W.norm_path(spec, chi=16, seed=1)
+    ref = _val(*network_value(OP.norm_network(spec, okets, conv="local"), path, chi=16))
+    gk = GP.ket_tensors(spec, vals)
+    m, e, st = GP.norm_network(spec, gk).contract(path, chi=16)
+    assert st["compressions"] > 0
+    err64 = abs(_val(m, e) - ref) / abs(ref)
+    assert err64 <= 1e-9, err64
+    gk32 = []
+    for k in gk:
+        inf = k.info()
+        gk32.append(P.Tensor.create(inf["sym"], k.legs(), inf["total"], P.F32, data=k.data().float()))
+    errs = {}
+    for name, gemm, tol in (("f32", P.GEMM_F32, 1e-5), ("bf16x3", P.GEMM_BF16X3, 1e-4)):
+        m3, e3, _ = GP.norm_network(spec, gk32).contract(path, chi=16, gemm=gemm)
+        errs[name] = abs(_val(m3, e3) - ref) / abs(ref)
+        assert errs[name] <= tol, (name, errs[name])
+    print("relative error vs the FP64 oracle: fp64 %.3g, fp32 %.3g, bf16x3 %.3g" % (err64, errs["f32"], errs["bf16x3"]))
