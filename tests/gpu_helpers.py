@@ -56,3 +56,15 @@ def assert_same_structure(T, G):
 def flat_blocks(T):
     parts = [T.block(k).detach().numpy().ravel() for k in T.keys()]
     return np.concatenate(parts) if parts else np.zeros(0)
+
+
+def rounded_f32(T):
+    """Copy of an oracle tensor with every entry rounded to FP32 and back.
+
+    An FP32 path starts from these values, so comparing it with the oracle
+    on them isolates the arithmetic of the path from the input rounding.
+    """
+    out = FTensor(T.sym, T.legs, T.total)
+    for k in T.keys():
+        out.blocks[k] = T.block(k).to(torch.float32).to(torch.float64)
+    return out

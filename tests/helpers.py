@@ -116,3 +116,69 @@ def random_ssa_path(rng, tensors, bonds):
         gid.append(nxt)
         nxt += 1
     return path
+
+
+def slater_amplitude(phi, config):
+    """Closed form of a Slater determinant's Jordan-Wigner coefficient.
+
+    |psi> = b+_1 ... b+_M |0> with b+_k = sum_m phi[m, k] c+_m: expanding the
+    product and sorting each term's creation operators into ascending mode
+    order gives <n|psi> = det phi[occupied modes ascending, :]. Modes of site
+    i: 2i (up), 2i+1 (down); physical index 0 = |0>, 1 = |up,dn>, 2 = |up>,
+    3 = |dn>.
+    """
+    modes = {0: (), 1: (0, 1), 2: (0,), 3: (1,)}
+    occ = []
+    for i, p in enumerate(config):
+        occ += [2 * i + loc for loc in modes[int(p)]]
+    if len(occ) != phi.shape[1]:
+        return 0.0
+    return float(np.linalg.det(phi[occ, :])) if occ else 1.0
+
+
+def slater_sites(lx, ly, phi):
+    """Site structures of the Slater fPEPS on a snake-labelled lattice.
+
+    Per site: (legs in the chain layout (left, phys, right, other bonds),
+    total charge, dense array, perm) where ``perm`` is the fermionic
+    transposition to the PEPS layout (phys, neighbours ascending); bonds
+    ``(t1, l1, t2, l2)`` in PEPS legs; the snake label of every site. Chain
+    bonds carry the orbital subsets (Z2 sectors 2^(M-1) | 2^(M-1)), the
+    other lattice bonds one even state; the bond between i < j is '-' on i.
+    """
+    from synth import slater as SL
+    n, edges, label = SL.snake_square_lattice(lx, ly)
+    m = phi.shape[1]
+    arrs = SL.chain_arrays(phi)
+    nbrs = [sorted([b for a, b in edges if a == s] + [a for a, b in edges if b == s]) for s in range(n)]
+    phys = make_leg(S.Z2, [(0,), (1,)], [2, 2], 0)
+    half = 1 << (m - 1)
+    out = []
+    for j in range(n):
+        def bond(nb):
+            dual = 1 if j < nb else 0
+            if abs(nb - j) == 1:
+                return make_leg(S.Z2, [(0,), (1,)], [half, half], dual)
+            return make_leg(S.Z2, [(0,)], [1], dual)
+        chain = ([j - 1] if j > 0 else []) + ([j + 1] if j < n - 1 else [])
+        rungs = [nb for nb in nbrs[j] if nb not in chain]
+        legs = ([bond(j - 1)] if j > 0 else []) + [phys] + ([bond(j + 1)] if j < n - 1 else [])
+        legs += [bond(nb) for nb in rungs]
+        arr = arrs[j].reshape(arrs[j].shape + (1,) * len(rungs))
+        total = (m % 2,) if j == n - 1 else (0,)
+        where, k = {}, 0
+        if j > 0:
+            where[j - 1] = 0
+            k = 1
+        pphys = k
+        k += 1
+        if j < n - 1:
+            where[j + 1] = k
+            k += 1
+        for nb in rungs:
+            where[nb] = k
+            k += 1
+        perm = [pphys] + [where[nb] for nb in nbrs[j]]
+        out.append((legs, total, arr, perm))
+    bonds = [(a, 1 + nbrs[a].index(b), b, 1 + nbrs[b].index(a)) for a, b in edges]
+    return out, bonds, label

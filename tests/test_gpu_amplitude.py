@@ -128,3 +128,44 @@ def test_bad_arguments_are_reported(P):
     with pytest.raises(P.FtnError) as e:
         P.amplitudes(sites, [(0, 0, 1, 1)] + bonds[1:], W.boundary_path(2, 2), [(0, 0, 0, 0)])
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("shape,m_up,m_dn,chi", [((4, 4), 2, 2, 16), ((6, 6), 2, 1, 8), ((8, 8), 2, 2, 36)])
+def test_slater_amplitudes_are_the_determinant(P, shape, m_up, m_dn, chi):
+    # free-fermion fPEPS (a Slater determinant laid along a row snake, the
+    # chain bonds 2^M wide): the library's amplitudes against the closed form
+    # det Phi[occupied modes, :], with chi at or above the bond dimension;
+    # site tensors are built in the chain layout and brought to the PEPS
+    # layout by the library's own fermionic transposition
+    from synth import slater as SL
+    from tests.gpu_helpers import legs_abi
+    from tests.helpers import slater_amplitude, slater_sites
+    lx, ly = shape
+    n = lx * ly
+    phi = SL.orbitals(n, m_up, m_dn, seed=130 + n)
+    sites, bonds, label = slater_sites(lx, ly, phi)
+    gsites = []
+    for legs, total, arr, perm in sites:
+        dense = torch.from_numpy(np.ascontiguousarray(arr)).to(device="cuda", dtype=torch.float64)
+        T = P.Tensor.from_dense(0, legs_abi(legs), (total[0], 0), dense)
+        gsites.append(P.ftranspose(T, perm))
+    path = [tuple(int(label[t]) if t < n else t for t in step) for step in W.boundary_path(lx, ly)]
+    rng = np.random.default_rng(131)
+    cfgs = []
+    for mu, md, cnt in ((m_up, m_dn, 24), (m_up + 1, m_dn + 1, 2), (m_up + 1, m_dn, 2)):
+        for _ in range(cnt):
+            up = set(rng.choice(n, mu, replace=False).tolist())
+            dn = set(rng.choice(n, md, replace=False).tolist())
+            cfgs.append([1 if (i in up and i in dn) else 2 if i in up else 3 if i in dn else 0 for i in range(n)])
+    cfgs = np.array(cfgs)
+    refs = np.array([slater_amplitude(phi, c) for c in cfgs])
+    m, e = P.amplitudes(gsites, bonds, path, cfgs, chi=chi, nworkers=4)
+    got = m * np.exp2(e.astype(np.float64))
+    scale = np.abs(refs).max()
+    err = np.abs(got - refs).max() / scale
+    print("slater %dx%d M=%d+%d chi=%d: max error %.3g of the largest amplitude" % (lx, ly, m_up, m_dn, chi, err))
+    # the bonds are compressed wherever they exceed chi (every cut of the
+    # state has rank at most 2^M <= chi, so only zero directions are cut)
+    assert err <= 1e-9, err
+    # wrong parity: exactly zero
+    assert np.all(got[-2:] == 0.0)

@@ -16,7 +16,7 @@ from oracle import symmetry as S
 from oracle.ops import ftranspose, ftensordot, flip_dual, fuse
 from oracle.tensor import FTensor, make_leg
 from tests.helpers import rand_leg, partner, rand_tensor
-from tests.gpu_helpers import to_gpu, from_gpu, assert_same_structure, flat_blocks
+from tests.gpu_helpers import to_gpu, from_gpu, assert_same_structure, flat_blocks, rounded_f32
 
 pytestmark = pytest.mark.gpu
 
@@ -151,20 +151,27 @@ def test_ftensordot_tiles_and_ragged_tails(P):
 
 @pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
 def test_ftensordot_fp32_forms(P, gemm):
+    # FP32 tensors hold the FP64 inputs rounded to nearest; the oracle runs on
+    # the same rounded values (promoted to FP64), so the error measured is that
+    # of the FP32 or split-BF16 arithmetic, relative to the largest entry
     rng = np.random.default_rng(8)
     sym = S.U1U1
-    tol = {"f32": 1e-5, "bf16x3": 1e-4}[gemm]
+    tol = {"f32": 1e-6, "bf16x3": 1e-4}[gemm]
+    worst = 0.0
     for trial in range(6):
         k = int(rng.integers(1, 3))
         A, B, ax_a, ax_b = _rand_pair(rng, sym, k, 2, 2, 4)
-        ref = ftensordot(A, B, ax_a, ax_b, conv="local")
+        A32, B32 = rounded_f32(A), rounded_f32(B)
+        ref = ftensordot(A32, B32, ax_a, ax_b, conv="local")
         Ga = to_gpu(A, torch.float32)
         Gb = to_gpu(B, torch.float32)
         G = P.ftensordot(Ga, Gb, ax_a, ax_b, gemm=P.GEMM_F32 if gemm == "f32" else P.GEMM_BF16X3)
         assert_same_structure(ref, G)
         r = flat_blocks(ref)
         err = np.abs(_data(G) - r).max(initial=0) / max(np.abs(r).max(initial=0), 1e-30)
+        worst = max(worst, err)
         assert err < tol, err
+    print("%s ftensordot: max error %.3g of the largest entry" % (gemm, worst))
 
 
 def test_errors_are_reported(P):

@@ -86,3 +86,46 @@ def test_compress_bond_eckart_young(conv, sym):
         # chi >= rank: exact
         A3, B3, _ = compress_bond(A, B, pa, pb, rank + 5, conv=conv)
         np.testing.assert_allclose(ftensordot(A3, B3, [pa], [pb], conv).to_dense(), Cd, atol=1e-10)
+
+
+def test_select_top_exact_ties_across_charges():
+    # the paper keeps the chi largest values over all blocks and is silent on
+    # ties; the reading is: larger value first, then lower charge, then lower
+    # index inside the sector; values not above cutoff * s_max are dropped
+    from oracle.linalg import select_top
+    sv = [(-1.0, (1,), 0), (-1.0, (0,), 0), (-0.5, (1,), 1), (-0.5, (0,), 1), (-0.25, (0,), 2)]
+    assert select_top(sv, 1, 0.0) == {(0,): 1}
+    assert select_top(sv, 2, 0.0) == {(0,): 1, (1,): 1}
+    assert select_top(sv, 3, 0.0) == {(0,): 2, (1,): 1}
+    assert select_top(sv, 4, 0.0) == {(0,): 2, (1,): 2}
+    assert select_top(sv, None, 0.0) == {(0,): 3, (1,): 2}
+    assert select_top(sv, None, 0.25) == {(0,): 2, (1,): 2}       # 0.25 is not above 0.25
+    assert select_top(sv, None, 0.2499) == {(0,): 3, (1,): 2}
+    # U(1)xU(1): charges compare lexicographically
+    sv2 = [(-2.0, (0, 1), 0), (-2.0, (-1, 0), 0), (-2.0, (0, -1), 0), (-1.0, (-1, 0), 1)]
+    assert select_top(sv2, 1, 0.0) == {(-1, 0): 1}
+    assert select_top(sv2, 2, 0.0) == {(-1, 0): 1, (0, -1): 1}
+    assert select_top(sv2, 3, 0.0) == {(-1, 0): 1, (0, -1): 1, (0, 1): 1}
+
+
+def test_compress_bond_breaks_exact_ties_by_charge():
+    # A~ = diag per sector, B~ = identity: the bond matrix of each Z2 sector
+    # has singular values (3, 1) exactly, so the two sectors tie value by
+    # value and the kept dims follow the tie-break alone
+    from oracle.tensor import make_leg, FTensor
+    import torch
+    sym = S.Z2
+    phys = make_leg(sym, [(0,), (1,)], [2, 2], 0)
+    bond = make_leg(sym, [(0,), (1,)], [2, 2], 1)
+    A = FTensor.zeros(sym, [phys, bond], (0,))
+    B = FTensor.zeros(sym, [partner(bond), partner(phys)], (0,))
+    for q in (0, 1):
+        A.blocks[(q, q)] = torch.diag(torch.tensor([3.0, 1.0], dtype=torch.float64))
+        B.blocks[(q, q)] = torch.eye(2, dtype=torch.float64)
+    for chi, dims in ((1, ((0,),)), (2, ((0,), (1,))), (3, ((0,), (1,)))):
+        A2, B2, info = compress_bond(A, B, 1, 0, chi)
+        assert A2.legs[1].charges == dims
+        kept = {q: len(v) for q, v in info["svals"].items()}
+        want = {1: {(0,): 1}, 2: {(0,): 1, (1,): 1}, 3: {(0,): 2, (1,): 1}}[chi]
+        assert kept == want
+        assert abs(info["discarded"] - {1: 11.0, 2: 2.0, 3: 1.0}[chi]) <= 1e-12

@@ -137,3 +137,58 @@ def test_approximate_limit_is_exact():
     a_loc = _val(net, path, chi=64)
     a_glo = _val(P.norm_network(spec, kets, conv="global"), path, chi=64)
     assert abs(a_loc - a_glo) <= 1e-10 * abs(a_loc)
+
+
+def _padded_site_values(spec, spec_big, vals, rng):
+    """Site values of the same state with every bond sector widened.
+
+    For each bond (i, j), i < j, a random per-sector map E (d x d') with a
+    right inverse E+ (E E+ = 1) is applied to the bond leg of site i (E) and
+    of site j (E+). Sectors keep their parity, so every fermionic sign of the
+    contraction over the bond is unchanged and the network value is that of
+    the unpadded state; the bond dimension grows but the rank across it does
+    not.
+    """
+    out = [v.copy() for v in vals]
+    for (i, j) in spec.edges:
+        li, lj = spec.bond_leg(i, j), spec.bond_leg(j, i)
+        small = spec.sites[i].legs[li]
+        big = spec_big.sites[i].legs[li]
+        E = np.zeros((small.size, big.size))
+        o_s = o_b = 0
+        for d, db in zip(small.dims, big.dims):
+            E[o_s:o_s + d, o_b:o_b + db] = rng.standard_normal((d, db))
+            o_s += d
+            o_b += db
+        Ep = np.linalg.pinv(E)                      # E @ Ep = 1 (full row rank)
+        out[i] = np.moveaxis(np.tensordot(out[i], E, axes=([li], [0])), -1, li)
+        out[j] = np.moveaxis(np.tensordot(out[j], Ep.T, axes=([lj], [0])), -1, lj)
+    return out
+
+
+def test_approximate_limit_with_compression_is_exact():
+    # bonds (1|1) widened to (2|2): a fused bra-ket bond is 16 wide but of
+    # rank 4 (the unpadded 2 x 2), so with chi = 8 every such bond is
+    # compressed while chi stays at or above the exact rank across every cut
+    # the path meets: the approximate contraction must reproduce the exact
+    # value, through compress_bond, with nothing but zeros discarded
+    n, edges = square_lattice(2, 3)
+    spec = W.z2_peps(n, edges, 1, 1)
+    big = W.z2_peps(n, edges, 2, 2)
+    rng = np.random.default_rng(140)
+    vals = [rng.standard_normal(s.dense_shape) for s in spec.sites]
+    pv = _padded_site_values(spec, big, vals, rng)
+    exact = _val(P.norm_network(spec, P.ket_tensors(spec, vals), conv="local"), W.norm_path(spec, seed=0))
+    net = P.norm_network(big, P.ket_tensors(big, pv), conv="local")
+    path = W.norm_path(big, seed=0)
+    assert abs(_val(net, path) - exact) <= 1e-12 * abs(exact)
+    T, _, e, infos = contract_network(net, path, chi=8)
+    truncating = [i for i in infos if len(i["all_svals"]) > sum(len(v) for v in i["svals"].values())]
+    assert len(truncating) >= 3                            # compression ran and cut
+    for i in truncating:
+        assert i["discarded"] <= 1e-24 * i["total"]        # only zero values dropped
+    approx = float(T.blocks[()]) * 2.0 ** e
+    assert abs(approx - exact) <= 1e-12 * abs(exact), (approx, exact)
+    # a chi below the exact rank is no longer exact
+    T2, _, e2, _ = contract_network(net, path, chi=2)
+    assert abs(float(T2.blocks[()]) * 2.0 ** e2 - exact) > 1e-6 * abs(exact)
