@@ -235,9 +235,15 @@ int ftn_ftensordot_backward(ftn_tensor_t a, ftn_tensor_t b, ftn_tensor_t dc, int
    is the best rank-chi approximation of F(AB) across that bond, keeping the
    chi largest singular values over all charge sectors (ties: larger value,
    then lower charge, then lower index). Values not above cutoff * s_max are
-   dropped and empty sectors removed; the decomposition goes through Gram
-   matrices, which resolve singular values to about 1e-8 * s_max, so cutoffs
-   below 1e-6 are raised to 1e-6. The bond keeps its leg positions,
+   dropped (cutoff >= 0, FTN_EINVAL otherwise) and empty sectors removed.
+   Bond sectors of dimension up to 128 take exact triangular factors of both
+   sides (shifted Cholesky QR, three passes) and a one-sided Jacobi SVD of
+   their product, which resolves singular values to about 1e-15 of the
+   largest; larger sectors reach their values through Gram matrices, which
+   resolve them only to ~1e-7 of the sector's largest, and there values below
+   1e-6 of it count as zero. If no charge of the bond carries blocks on both
+   sides, F(AB) is zero across the bond: nothing is kept and the bond leg
+   of both outputs has no sector. The bond keeps its leg positions,
    duals and charge labels; only sector dims shrink. conv selects how F(AB)
    is read (as in ftn_ftensordot). FP64 arithmetic is used for the
    decomposition whatever the tensors' dtype. discarded_weight (may be NULL)
@@ -292,7 +298,7 @@ int ftn_net_free(ftn_net_t net);
    shares. With chi > 0 (approximate contraction, compression as early as
    possible, Sec. III): after each step the bonds the new tensor shares with
    one neighbour are fused into one (Sec. IV.A) and every such bond larger
-   than chi is compressed with ftn_compress_bond (cutoff 1e-6). chi <= 0
+   than chi is compressed with ftn_compress_bond (cutoff 1e-12). chi <= 0
    means exact. Every intermediate is rescaled by a power of two; the value
    is mantissa * 2^exp2. For a closed network the result is a scalar and
    open_out may be NULL; otherwise *open_out receives the final tensor (its
@@ -300,7 +306,10 @@ int ftn_net_free(ftn_net_t net);
    the (tensor, leg) each came from) scaled by 2^-exp2.
    stats (may be NULL, 8 doubles): [0] useful GEMM flops, [1] compressions,
    [2] total discarded weight, [3] near ties flagged at truncation cuts,
-   [4] max intermediate entries, [5..7] reserved. */
+   [4] max intermediate entries, [5] textbook flops of the compressions
+   (per bond sector: QR and LQ of the two sides with thin factors,
+   4 m n^2 - 4 n^3 / 3 each, m >= n; thin SVD of the core, 14 m n^2 + 8 n^3;
+   absorbing the kept vectors, 2 m r k per side), [6..7] reserved. */
 int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int64_t chi,
                          ftn_gemm gemm, ftn_stream_t stream, double* mantissa, int64_t* exp2,
                          ftn_tensor_t* open_out, int32_t* leg_src, double* stats);
@@ -330,6 +339,30 @@ int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds, const int3
                    int64_t* exp2);
 
 /* ---------------------------------------------------------------------------
+ * Tile autotuner of the grouped GEMM (the block-pair products of every
+ * contraction and the products of bond compression)
+ * ------------------------------------------------------------------------ */
+
+/* mode 0: tile shapes from the built-in heuristic (default); 1: from the
+   tuning table where it has an entry for the plan's shape key (the GEMM
+   form, the binary orders of the largest M, N, K and of the group count,
+   symmetric and scatter flags), else the heuristic; 2: as 1, and a plan
+   whose key has no entry is tuned first: every tile configuration whose
+   padded tiles stay within four times the useful area, with and without
+   split-K, is timed on scratch operands of the plan's extents (one warm-up,
+   median of three) and the fastest is stored. Tuning allocates and
+   synchronises the stream; results of different tile shapes differ only by
+   rounding. The table is process-wide. */
+int ftn_autotune(int mode);
+/* Merge entries from / write the table to a JSON file
+   ({"entries": {"<key>": [config, split, microseconds], ...}}). */
+int ftn_autotune_load(const char* path);
+int ftn_autotune_save(const char* path);
+/* Entries in the table, keys tuned by this process, plans that took a
+   stored choice (any pointer may be NULL). */
+int ftn_autotune_stats(int64_t* entries, int64_t* tuned, int64_t* hits);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (measurement support)
  * ------------------------------------------------------------------------ */
 
@@ -349,9 +382,11 @@ enum {
    (adds a little launch overhead); 0: stop. Accumulated figures are kept. */
 int ftn_profile_enable(int on);
 /* Per class (FTN_PROF_NCLASS entries each, any may be NULL): summed kernel
-   milliseconds, launch counts and attributed work since the last collect.
-   Synchronises the recorded events and resets the accumulators. */
-int ftn_profile_collect(double* ms, double* count, double* work);
+   milliseconds, launch counts, attributed work and algorithmic bytes (GEMM:
+   every entry of A, B and C once; permute: bytes read + written) since the
+   last collect. Synchronises the recorded events and resets the
+   accumulators. */
+int ftn_profile_collect(double* ms, double* count, double* work, double* bytes);
 
 /* Device memory of the built-in caching allocator on `device` (a HIP device
    index), in bytes: `in_use` held by live buffers (tensor data, plans,

@@ -18,7 +18,7 @@ Approximate contraction (Fig. 1b, Sec. III, compression as early as
 possible): after each pairwise contraction the bonds the new tensor shares
 with one neighbour are fused into one bond (Sec. IV.A), and every such bond
 larger than chi is compressed with ``compress_bond`` (singular values not
-above 1e-6 of the largest count as zero). Each intermediate is
+above 1e-12 of the largest count as zero). Each intermediate is
 rescaled by a power of two, accumulated in an integer exponent (exact in
 binary floating point).
 """
@@ -93,7 +93,11 @@ def _neighbours(st, z):
     return out
 
 
-CUTOFF = 1e-6  # relative singular-value cutoff of network compression
+# relative singular-value cutoff of network compression: values not above
+# 1e-12 of the largest are numerically zero (the FP64 round-off of an SVD is
+# ~1e-15 of the largest); the paper keeps the chi largest values and names
+# no cutoff
+CUTOFF = 1e-12
 
 
 def _fuse_and_compress(st, z, chi, conv, order, cutoff=CUTOFF):

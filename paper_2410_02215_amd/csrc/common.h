@@ -338,12 +338,25 @@ struct GemmPlan {
   double flops = 0;
   int kind = FTN_GEMM_F64;
   int cfg = 0;
+  int64_t split = 1;
+  double abytes = 0;  // algorithmic bytes per run: entries of A, B and C once (FP64 count)
 };
 void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
                bool persistent = false);
+// the same with the tile configuration (0 .. gemm_ncfg()-1) and the split-K
+// factor given (-1: the built-in heuristic)
+void gemm_plan_with(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
+                    bool persistent, int cfg, int split);
+int gemm_ncfg();
+// tile autotuner: the (cfg, split) for these groups from the tuning cache, or
+// tuned now (tuning mode), or -1 / -1 (the built-in heuristic)
+void tune_choice(const std::vector<GemmGroup>& gs, int kind, hipStream_t s, int* cfg, int* split);
 // C[g] = alpha * op(A[g]) op(B[g]) (+ beta C for plain outputs). No host sync.
+// ws (may be null): caller-owned split-K workspace of p.ws_elems entries;
+// without it the workspace is taken from the caching allocator
 void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
-              const GemmScatter* sc, hipStream_t s, double alpha = 1.0, double beta = 0.0);
+              const GemmScatter* sc, hipStream_t s, double alpha = 1.0, double beta = 0.0,
+              void* ws = nullptr);
 // one-off convenience: plan + run (the plan's table is freed stream-ordered)
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,
                       const void* B, void* C, const GemmScatter* sc, hipStream_t s,
@@ -370,6 +383,11 @@ struct CompressResult {
   double discarded = 0.0;
   std::vector<double> svals;
   bool near_tie = false;
+  // textbook flops of the decomposition per bond sector (m >= n): QR of A~
+  // and LQ of B~ with thin Q, 4 m n^2 - 4 n^3 / 3 each; thin SVD of the
+  // r_A x r_B core, 14 m n^2 + 8 n^3; absorbing the kept k vectors into both
+  // tall factors, 2 M r_A k + 2 N r_B k
+  double textbook_flops = 0.0;
 };
 CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb, int64_t chi,
                                 double cutoff, int conv, hipStream_t s);
@@ -392,6 +410,15 @@ struct DotPlanView {
 std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
                                   const std::vector<int>& axb, int conv, int gemm, hipStream_t s);
 DotPlanView dot_plan_view(const DotPlan& p);
+// the cached plan of a contraction, or null if none was built (no allocation)
+std::shared_ptr<DotPlan> dot_plan_lookup(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                                         const std::vector<int>& axb, int conv, int gemm);
+// op_ftensordot with a cached plan, every temporary in `scratch` (device,
+// `scratch_bytes`) and the output blocks written to `out` (device, out_elems
+// entries in the output structure's block layout); allocates nothing
+void op_ftensordot_into(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                        const std::vector<int>& axb, int conv, int gemm, hipStream_t s, void* out,
+                        int64_t out_elems, char* scratch, size_t scratch_bytes);
 // the fused per-group matrices (group g: M_g x N_g row-major at f_off[g], the
 // GEMM output layout before the block scatter) of a tensor c that has the
 // plan's output structure; F may be null to get only the size
@@ -411,6 +438,9 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // event timing of instrumented launches (profile.hip)
 bool prof_on();
 void* prof_begin(hipStream_t s);
-void prof_end(void* tok, hipStream_t s, int cls, double work);
+// bytes: algorithmic bytes of the launch (operands read once, results written once)
+void prof_end(void* tok, hipStream_t s, int cls, double work, double bytes = 0.0);
+// suppress instrumentation on the calling thread (library worker threads)
+void prof_quiet(bool on);
 
 }  // namespace ftn

@@ -409,13 +409,27 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   return P;
 }
 
-std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
-                                  const std::vector<int>& axb, int conv, int gemm, hipStream_t s) {
+static std::string plan_key(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                            const std::vector<int>& axb, int conv, int gemm) {
   std::string key = a.st->skey + "|" + b.st->skey + "|";
   for (int x : axa) key += std::to_string(x) + ",";
   key += "|";
   for (int x : axb) key += std::to_string(x) + ",";
   key += "|" + std::to_string(conv) + "|" + std::to_string(gemm);
+  return key;
+}
+
+std::shared_ptr<DotPlan> dot_plan_lookup(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                                         const std::vector<int>& axb, int conv, int gemm) {
+  const std::string key = plan_key(a, b, axa, axb, conv, gemm);
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  auto it = g_plans.find(key);
+  return it == g_plans.end() ? nullptr : it->second;
+}
+
+std::shared_ptr<DotPlan> dot_plan(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                                  const std::vector<int>& axb, int conv, int gemm, hipStream_t s) {
+  const std::string key = plan_key(a, b, axa, axb, conv, gemm);
   {
     std::lock_guard<std::mutex> g(g_plan_mu);
     auto it = g_plans.find(key);
@@ -467,6 +481,39 @@ std::unique_ptr<Tensor> op_ftensordot(const Tensor& a, const Tensor& b, const st
   dfree(At, s);
   dfree(Bt, s);
   return out;
+}
+
+void op_ftensordot_into(const Tensor& a, const Tensor& b, const std::vector<int>& axa,
+                        const std::vector<int>& axb, int conv, int gemm, hipStream_t s, void* out,
+                        int64_t out_elems, char* scratch, size_t scratch_bytes) {
+  if (a.sym() != b.sym()) fail(FTN_EINVAL, "symmetry mismatch");
+  if (a.dtype != b.dtype) fail(FTN_ENOTSUP, "operands must have the same dtype");
+  if (axa.size() != axb.size()) fail(FTN_EINVAL, "axes length mismatch");
+  if (conv != FTN_LOCAL && conv != FTN_GLOBAL) fail(FTN_EINVAL, "unknown convention");
+  if (gemm == FTN_GEMM_F64 && a.dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
+  if (gemm != FTN_GEMM_F64 && a.dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 / split-BF16 GEMM needs FP32 tensors");
+  std::shared_ptr<DotPlan> P = dot_plan_lookup(a, b, axa, axb, conv, gemm);
+  if (!P)
+    fail(FTN_ENOTSUP,
+         "no cached plan for this contraction: call ftn_ftensordot once with operands of the same structures, "
+         "axes, convention and GEMM form");
+  if (out_elems != P->cst->size)
+    fail(FTN_EINVAL, "output buffer holds " + std::to_string(out_elems) + " entries, the contraction gives " +
+                         std::to_string(P->cst->size));
+  if (P->cst->size == 0) return;
+  if (!out) fail(FTN_EINVAL, "null output buffer");
+  const size_t es = a.esize();
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t ba = up(P->asz * es), bb = up(P->bsz * es), bw = up(P->gp.ws_elems * es);
+  if (ba + bb + bw > scratch_bytes)
+    fail(FTN_EINVAL, "contraction needs " + std::to_string(ba + bb + bw) + " bytes of temporaries, the scratch buffer holds " +
+                         std::to_string(scratch_bytes));
+  char* At = scratch;
+  char* Bt = scratch + ba;
+  char* W = scratch + ba + bb;
+  run_perm(0, a.S(), a.dtype, P->pa, a.data, At, s);
+  run_perm(0, b.S(), b.dtype, P->pb, b.data, Bt, s);
+  run_gemm(P->gp, a.dtype, At, Bt, out, &P->sc, s, 1.0, 0.0, W);
 }
 
 // ---------------------------------------------------------------------------

@@ -488,7 +488,19 @@ static int choose_cfg(const std::vector<GemmGroup>& gs) {
   return CFG_64;
 }
 
+int gemm_ncfg() { return 6; }
+
 void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s, bool persistent) {
+  std::vector<GemmGroup> gs;
+  for (auto& g : groups)
+    if (g.M > 0 && g.N > 0) gs.push_back(g);
+  int cfg = -1, split = -1;
+  if (kind != FTN_GEMM_BF16X3 && !gs.empty()) tune_choice(gs, kind, s, &cfg, &split);
+  gemm_plan_with(p, gs, kind, s, persistent, cfg, split);
+}
+
+void gemm_plan_with(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
+                    bool persistent, int cfg_override, int split_override) {
   p.host.clear();
   p.red_host.clear();
   p.kind = kind;
@@ -498,7 +510,9 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   for (auto& g : groups)
     if (g.M > 0 && g.N > 0) gs.push_back(g);
   p.flops = gemm_flops(gs);
-  p.cfg = kind == FTN_GEMM_BF16X3 ? CFG_64 : choose_cfg(gs);
+  p.abytes = 0;
+  for (auto& g : gs) p.abytes += (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+  p.cfg = kind == FTN_GEMM_BF16X3 ? CFG_64 : (cfg_override >= 0 ? cfg_override : choose_cfg(gs));
   const int bm = kind == FTN_GEMM_BF16X3 ? TBM : CFG_BM[p.cfg], bn = kind == FTN_GEMM_BF16X3 ? TBN : CFG_BN[p.cfg];
   // the triangle of tiles needs square tiles, a square product and a plain
   // output (the split-BF16 kernel multiplies the full grid)
@@ -515,6 +529,8 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   // of the K loop, and the partial sums cost one extra pass over C
   int64_t split = 1;
   if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < 4 * NCU) split = std::max<int64_t>(1, cdiv(8 * NCU, tiles));
+  if (kind != FTN_GEMM_BF16X3 && split_override >= 1) split = split_override;
+  p.split = split;
   int64_t t = 0;
   for (auto g : gs) {
     const int64_t S = g.scatter ? 1 : std::min<int64_t>(split, std::min<int64_t>(256, g.K / 128));
@@ -594,7 +610,7 @@ static void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmLaunch& L, c
 }
 
 void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* C,
-              const GemmScatter* sc, hipStream_t s, double alpha, double beta) {
+              const GemmScatter* sc, hipStream_t s, double alpha, double beta, void* ws_ext) {
   if (p.ntiles == 0) return;
   GemmLaunch L;
   L.groups = p.groups.p;
@@ -618,20 +634,21 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
                  p.host[0].transA, p.host[0].transB, p.host[0].scatter, p.cfg, p.red_host.size());
   }
   const size_t es = dtype == FTN_F64 ? 8 : 4;
-  DBuf<char> ws(p.ws_elems * es, s);
+  DBuf<char> ws_own(ws_ext ? 0 : p.ws_elems * es, s);
+  char* wsp = ws_ext ? (char*)ws_ext : ws_own.p;
   void* tok = prof_begin(s);
   if (p.kind == FTN_GEMM_F64) {
     if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
-    launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)ws.p);
+    launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)wsp);
     if (p.red_elems)
       LAUNCH((k_splitk_reduce<double>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
-             (int)p.red_host.size(), p.red_elems, (const double*)ws.p, (double*)C, alpha, beta);
+             (int)p.red_host.size(), p.red_elems, (const double*)wsp, (double*)C, alpha, beta);
   } else if (p.kind == FTN_GEMM_F32) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 GEMM needs FP32 tensors");
-    launch_cfg<float>(p.cfg, grid, s, L, (const float*)A, (const float*)B, (float*)C, (float*)ws.p);
+    launch_cfg<float>(p.cfg, grid, s, L, (const float*)A, (const float*)B, (float*)C, (float*)wsp);
     if (p.red_elems)
       LAUNCH((k_splitk_reduce<float>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
-             (int)p.red_host.size(), p.red_elems, (const float*)ws.p, (float*)C, alpha, beta);
+             (int)p.red_host.size(), p.red_elems, (const float*)wsp, (float*)C, alpha, beta);
   } else if (p.kind == FTN_GEMM_BF16X3) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "split-BF16 GEMM needs FP32 tensors");
     LAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, dim3(GT), 0, s, L, (const float*)A,
@@ -641,7 +658,7 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   }
   HIPC(hipGetLastError());
   prof_end(tok, s, p.kind == FTN_GEMM_F64 ? FTN_PROF_GEMM_F64 : (p.kind == FTN_GEMM_F32 ? FTN_PROF_GEMM_F32 : FTN_PROF_GEMM_BF16X3),
-           p.flops);
+           p.flops, p.abytes * (double)es);
 }
 
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,

@@ -768,6 +768,22 @@ __global__ void k_proj_out(const double* F, const double* GF, int64_t d, int k, 
   Pb[(int64_t)c * d + r] = sideA ? F[e] * h : GF[e] * h3;
 }
 
+// W[i, j] = V[i, j] * sv[j] for j < cols (V row-major with ld ldv, W ld cols)
+struct ScaleColsJob {
+  const double* V;
+  const double* sv;
+  double* W;
+  int64_t rows, cols, ldv;
+};
+__global__ void k_scale_cols(const ScaleColsJob* jobs) {
+  const ScaleColsJob J = jobs[blockIdx.y];
+  const int64_t n = J.rows * J.cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / J.cols, j = e % J.cols;
+    J.W[e] = J.V[i * J.ldv + j] * J.sv[j];
+  }
+}
+
 __global__ void k_sqrt_inplace(double* w, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) w[i] = sqrt(fmax(w[i], 0.0));
@@ -884,6 +900,163 @@ static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>*
       HIPC(hipMemcpyAsync(rounds->data() + t, aux.p + (int64_t)t * (JMAX + 1), sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
   }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of a small matrix X (r x c, r, c <= 128),
+// one workgroup per matrix. The columns of X are rotated in pairs until they
+// are mutually orthogonal: X V = W, W = U S with S the column norms. The
+// singular values come from the columns themselves, not from a Gram matrix,
+// so they are accurate to about eps * |X| (a Gram matrix X X^T holds s^2
+// only to eps * |X|^2, which loses every s below ~1e-8 |X|).
+// The c columns live in LDS (column-major, padded); a round applies the c/2
+// disjoint rotations of a round-robin tournament, one column pair per wave
+// at a time (the three inner products are wave reductions); a pair is
+// rotated when |x_p . x_q| > tol sqrt(|x_p|^2 |x_q|^2). Sweeps stop after one
+// without rotation (at most JAC_SWEEPS). Outputs: the m = min(r, c) largest
+// s^2 in descending order (ties: lower column first) and U (r x m, ld ldu),
+// column k = the k-th column of W divided by its norm (zero if the norm is);
+// every rotation (c, s) with its column pair is logged per round in the
+// format of the two-sided sweeps, with the rank of every column, so that
+// k_jacobi_vectors replays them onto the identity and returns V (c x c,
+// columns in rank order) as the product of the rotations: V is orthogonal
+// to working precision however small a singular value is, which X^T U / s
+// is not (its error grows like eps |X| / s).
+struct SvdJob {
+  const double* X;  // r x c row-major, leading dimension ldx
+  double* U;        // r x m, leading dimension ldu
+  double* W;        // m values s^2, descending
+  double2* rot;     // rotation log (c, s), np per round
+  int* rpq;         // rotation log: p | q << 16
+  int* rounds;      // rounds done
+  int* rk;          // c: rank of every column by its final norm
+  int r, c, ldx, ldu;
+};
+
+__global__ void __launch_bounds__(LT) k_svd_cols(const SvdJob* jobs, double tol) {
+  const SvdJob J = jobs[blockIdx.x];
+  const int r = J.r, c = J.c;
+  if (r <= 0 || c <= 0) return;
+  __shared__ double Xc[JMAX][JMAX + 1];
+  __shared__ double nrm[JMAX];
+  __shared__ int rot_any;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = LT / 64;
+  for (int e = tid; e < r * c; e += LT) {
+    const int i = e / c, j = e % c;
+    Xc[j][i] = J.X[(int64_t)i * J.ldx + j];
+  }
+  const int n2 = c + (c & 1);  // an odd count gets a zero column
+  if (c & 1)
+    for (int i = tid; i < r; i += LT) Xc[c][i] = 0.0;
+  const int np = n2 / 2;
+  const bool l0 = lane < r, l1 = lane + 64 < r;
+  int nr = 0;
+  for (int sweep = 0; sweep < JAC_SWEEPS; ++sweep) {
+    if (tid == 0) rot_any = 0;
+    __syncthreads();
+    for (int rd = 0; rd < n2 - 1; ++rd, ++nr) {
+      for (int k = w; k < np; k += nw) {
+        int p, q;
+        rr_pair(n2, rd, k, p, q);
+        double lc = 1.0, ls = 0.0;
+        const double xp0 = l0 ? Xc[p][lane] : 0.0, xp1 = l1 ? Xc[p][lane + 64] : 0.0;
+        const double xq0 = l0 ? Xc[q][lane] : 0.0, xq1 = l1 ? Xc[q][lane + 64] : 0.0;
+        double a = xp0 * xp0 + xp1 * xp1, b = xq0 * xq0 + xq1 * xq1, g = xp0 * xq0 + xp1 * xq1;
+        for (int o = 32; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o);
+          b += __shfl_xor(b, o);
+          g += __shfl_xor(g, o);
+        }
+        if (g != 0.0 && fabs(g) > tol * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          if (l0) {
+            Xc[p][lane] = cs * xp0 - sn * xq0;
+            Xc[q][lane] = sn * xp0 + cs * xq0;
+          }
+          if (l1) {
+            Xc[p][lane + 64] = cs * xp1 - sn * xq1;
+            Xc[q][lane + 64] = sn * xp1 + cs * xq1;
+          }
+          if (lane == 0) rot_any = 1;
+          lc = cs;
+          ls = sn;
+        }
+        if (lane == 0) {
+          J.rot[(int64_t)nr * np + k] = make_double2(lc, ls);
+          J.rpq[(int64_t)nr * np + k] = p | (q << 16);
+        }
+      }
+      __syncthreads();
+    }
+    if (!rot_any) break;
+    __syncthreads();
+  }
+  if (tid == 0) J.rounds[0] = nr;
+  // column norms, ranks by (larger norm, lower index), sorted outputs
+  for (int j = w; j < c; j += nw) {
+    const double v0 = l0 ? Xc[j][lane] : 0.0, v1 = l1 ? Xc[j][lane + 64] : 0.0;
+    double t = v0 * v0 + v1 * v1;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) nrm[j] = t;
+  }
+  __syncthreads();
+  const int m = r < c ? r : c;
+  for (int j = w; j < c; j += nw) {
+    const double sj = nrm[j];
+    int rank = 0;
+    for (int k = 0; k < c; ++k) rank += (nrm[k] > sj || (nrm[k] == sj && k < j)) ? 1 : 0;
+    if (lane == 0) J.rk[j] = rank;
+    if (rank >= m) continue;
+    const double inv = sj > 0.0 ? 1.0 / sqrt(sj) : 0.0;
+    if (l0) J.U[(int64_t)lane * J.ldu + rank] = Xc[j][lane] * inv;
+    if (l1) J.U[(int64_t)(lane + 64) * J.ldu + rank] = Xc[j][lane + 64] * inv;
+    if (lane == 0) J.W[rank] = sj;
+  }
+}
+
+// thin SVD of every listed X (textbook thin-SVD flops 14 m n^2 + 8 n^3, m >= n):
+// U, s^2 and V[t] (c x c, columns in rank order, ld c) of job t
+static void svd_cols(std::vector<SvdJob>& sj, const std::vector<double*>& V, hipStream_t s) {
+  if (sj.empty()) return;
+  const int nj = (int)sj.size();
+  double f = 0;
+  int64_t log_n = 0;
+  int cmax = 0;
+  for (const SvdJob& j : sj) {
+    if (j.r > JMAX || j.c > JMAX) fail(FTN_ENOTSUP, "one-sided Jacobi order above 128");
+    const double m = std::max(j.r, j.c), n = std::min(j.r, j.c);
+    f += 14.0 * m * n * n + 8.0 * n * n * n;
+    log_n += jacobi_log_len(j.c);
+    cmax = std::max(cmax, j.c);
+  }
+  DBuf<double2> lrot(std::max<int64_t>(log_n, 1), s);
+  DBuf<int> lpq(std::max<int64_t>(log_n, 1), s), aux((int64_t)nj * (JMAX + 1), s);
+  std::vector<EigJob> ej(nj);
+  int64_t o = 0;
+  for (int t = 0; t < nj; ++t) {
+    SvdJob& j = sj[t];
+    j.rot = lrot.p + o;
+    j.rpq = lpq.p + o;
+    o += jacobi_log_len(j.c);
+    j.rounds = aux.p + (int64_t)t * (JMAX + 1);
+    j.rk = j.rounds + 1;
+    EigJob& e = ej[t];
+    e = EigJob{};
+    e.V = V[t];
+    e.rot = j.rot;
+    e.rpq = j.rpq;
+    e.rounds = j.rounds;
+    e.rk = j.rk;
+    e.n = j.c;
+  }
+  DBuf<SvdJob> d = to_device(sj, s);
+  DBuf<EigJob> de = to_device(ej, s);
+  void* tok = prof_begin(s);
+  LAUNCH(k_svd_cols, dim3((unsigned)nj), dim3(LT), 0, s, d.p, 1e-15);
+  LAUNCH(k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(cmax, JV_WAVES)), dim3(64 * JV_WAVES), 0, s, de.p);
+  prof_end(tok, s, FTN_PROF_FACTOR, f);
 }
 
 // per bond sector q
@@ -1197,13 +1370,39 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
 //   <= 1e-14 of the largest) or 96 iterations.
 static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
                        const double* Xm, const std::vector<int64_t>& xoff, double* Em, const std::vector<int64_t>& eoff,
-                       double* Lm, const std::vector<int64_t>& loff, hipStream_t s) {
+                       double* Lm, const std::vector<int64_t>& loff, double* Vm, const std::vector<int64_t>& voff,
+                       hipStream_t s) {
   const int ng = (int)S.size();
   const double tol = 1e-13;
   std::vector<int> dir, it;
   for (int g = 0; g < ng; ++g)
     if (S[g].ns > 0) (S[g].iterate ? it : dir).push_back(g);
   static const bool trace = std::getenv("FTN_TRACE") != nullptr;
+  {
+    // sectors with exact factors and X formed: one-sided Jacobi on X itself
+    std::vector<SvdJob> sj;
+    std::vector<double*> vv;
+    std::vector<int> rest;
+    for (int g : dir) {
+      if (!S[g].acc) {
+        rest.push_back(g);
+        continue;
+      }
+      const int r = S[g].ns, c = S[g].sideA ? S[g].rB : S[g].rA;
+      SvdJob j{};
+      j.X = Xm + xoff[g];
+      j.U = Em + eoff[g];
+      j.W = Lm + loff[g];
+      j.r = r;
+      j.c = c;
+      j.ldx = c;
+      j.ldu = S[g].p;
+      sj.push_back(j);
+      vv.push_back(Vm + voff[g]);
+    }
+    svd_cols(sj, vv, s);
+    dir.swap(rest);
+  }
   if (!dir.empty()) {
     const int nd = (int)dir.size();
     std::vector<EigJob> ej;
@@ -1414,20 +1613,17 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   }
   const int ng = (int)S.size();
   if (ng == 0) {
-    auto leg_str = [](const Leg& l) {
-      std::string r = "dual " + std::to_string(l.dual) + " [";
-      for (int k = 0; k < l.nsect(); ++k)
-        r += "(" + std::to_string(l.q[k].a) + "," + std::to_string(l.q[k].b) + "):" + std::to_string(l.d[k]) + " ";
-      return r + "]";
-    };
-    std::string g;
-    for (size_t gi = 0; gi < pv.groups.size(); ++gi)
-      g += " {M " + std::to_string(pv.groups[gi].M) + " N " + std::to_string(pv.groups[gi].N) + " K " +
-           std::to_string(pv.groups[gi].K) + "}";
-    fail(FTN_EINVAL, "compress_bond: no charge sector common to both bond legs: A leg " + std::to_string(la) +
-                         " of " + std::to_string(a.ndim()) + " " + leg_str(LA) + ", B leg " + std::to_string(lb) +
-                         " of " + std::to_string(b.ndim()) + " " + leg_str(LB) + ", sizes " +
-                         std::to_string(a.size()) + " / " + std::to_string(b.size()) + ", groups" + g);
+    // no bond charge carries blocks on both sides: F(AB) is exactly zero
+    // across this bond, no singular value is kept and the bond leg is left
+    // with no sector on both tensors (which then hold no block)
+    std::vector<Leg> la_legs = a.legs(), lb_legs = b.legs();
+    la_legs[la].q.clear();
+    la_legs[la].d.clear();
+    lb_legs[lb].q.clear();
+    lb_legs[lb].d.clear();
+    res.a = make_tensor(sym, a.dtype, la_legs, a.total(), s, true);
+    res.b = make_tensor(sym, b.dtype, lb_legs, b.total(), s, true);
+    return res;
   }
   {
     std::vector<int> order(ng);
@@ -1555,7 +1751,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     xoff[g] = xs;
     xs += (x.iterate || x.acc) ? (int64_t)x.rA * x.rB : 0;
     hoff[g] = hs;
-    hs += x.iterate ? 0 : (int64_t)x.ns * x.ns;
+    hs += (x.iterate || x.acc) ? 0 : (int64_t)x.ns * x.ns;
     u1off[g] = u1s;
     u1s += x.iterate ? 0 : x.d * x.ns;
     eoff[g] = es;
@@ -1563,12 +1759,23 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     loff[g] = ls;
     ls += std::max(x.p, 1);
   }
+  // right singular vectors (r_o x r_o) of the sectors with exact factors
+  std::vector<int64_t> voff(ng, 0);
+  int64_t vs = 0;
+  for (int g = 0; g < ng; ++g) {
+    const Sect& x = S[g];
+    voff[g] = vs;
+    if (x.acc && x.ns && !x.iterate) {
+      const int64_t r_o = x.sideA ? x.rB : x.rA;
+      vs += r_o * r_o;
+    }
+  }
   DBuf<double> Xm(std::max<int64_t>(xs, 1), s), Hm(std::max<int64_t>(hs, 1), s), Em(std::max<int64_t>(es, 1), s),
-      Lm(std::max<int64_t>(ls, 1), s);
+      Lm(std::max<int64_t>(ls, 1), s), Vm(std::max<int64_t>(vs, 1), s);
   HIPC(hipMemsetAsync(Lm.p, 0, std::max<int64_t>(ls, 1) * 8, s));
   {
     DBuf<double> U1(std::max<int64_t>(u1s, 1), s);
-    std::vector<GemmGroup> gx, gu, gh, gxs, gxh;
+    std::vector<GemmGroup> gx, gu, gh, gxs;
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.ns) continue;
@@ -1581,7 +1788,6 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         // accurate factors: X = R R_o^T (r x r_o), H = X X^T
         const int64_t r = x.ns, r_o = x.sideA ? x.rB : x.rA;
         gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
-        gxh.push_back(sym_group(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r)));
         continue;
       }
       // U1 = G_o R^T (d x r), H = R U1 (r x r)
@@ -1589,16 +1795,13 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       gh.push_back(plain_group(x.ns, x.ns, x.d, ro, x.d, 0, u1off[g], x.ns, 0, hoff[g], x.ns));
     }
     if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rc.p, Rc.p, Xm.p, nullptr, s);
-    if (!gxs.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxh, Xm.p, Xm.p, Hm.p, nullptr, s);
-    }
+    if (!gxs.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
     if (!gu.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Rc.p, U1.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Rc.p, U1.p, Hm.p, nullptr, s);
     }
   }
-  x_spectrum(S, chi, Hm.p, hoff, Xm.p, xoff, Em.p, eoff, Lm.p, loff, s);
+  x_spectrum(S, chi, Hm.p, hoff, Xm.p, xoff, Em.p, eoff, Lm.p, loff, Vm.p, voff, s);
   // singular values = sqrt(eigenvalues); selection
   launch_1d(std::max<int64_t>(ls, 1), s, k_sqrt_inplace, Lm.p, (int)std::max<int64_t>(ls, 1));
   {
@@ -1621,6 +1824,15 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       vals[i] = hw[pos[i]];
       if (!std::isfinite(vals[i])) fail(FTN_ENOCONV, "compress_bond: non-finite singular value");
     }
+    // sectors without exact factors (bond sector above 128) reach their
+    // values through Gram matrices, which resolve a singular value only down
+    // to ~1e-7 of the sector's largest: values below 1e-6 of it are zero
+    {
+      std::vector<double> smax(ng, 0.0);
+      for (int i = 0; i < n; ++i) smax[grp[i]] = std::max(smax[grp[i]], vals[i]);
+      for (int i = 0; i < n; ++i)
+        if (!S[grp[i]].acc && vals[i] < 1e-6 * smax[grp[i]]) vals[i] = 0.0;
+    }
     DBuf<double> dv = to_device(vals, s);
     DBuf<int> dg = to_device(grp, s), di = to_device(idx, s), dc = to_device(crank, s);
     DBuf<int> dk(std::max(ng, 1), s);
@@ -1628,9 +1840,8 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     std::vector<double> st(4, 0.0);
     HIPC(hipMemsetAsync(dst.p, 0, 32, s));
     if (ng > 1024) fail(FTN_ENOTSUP, "more than 1024 bond sectors");
-    // the Gram route resolves singular values to ~1e-8 of the largest, so a
-    // relative cutoff below 1e-6 is raised to 1e-6 (values under it are zero)
-    const double eff_cut = std::max(cutoff, 1e-6);
+    if (cutoff < 0 || !std::isfinite(cutoff)) fail(FTN_EINVAL, "cutoff must be finite and >= 0");
+    const double eff_cut = cutoff;
     if (n)
       LAUNCH(k_select, dim3(1), dim3(LT), 0, s, dv.p, dg.p, di.p, dc.p, n, ng, chi, eff_cut, dk.p, dst.p);
     HIPC(hipGetLastError());
@@ -1650,6 +1861,19 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       std::fprintf(stderr, "[ftn] compress: sectors %s chi-th %.17g next %.17g max %.17g\n", d.c_str(), a1, a2, smax);
     }
     for (int g = 0; g < ng; ++g) S[g].kept = kept[g];
+    {
+      auto qr = [](double m, double n) {
+        const double a = std::max(m, n), b = std::min(m, n);
+        return 4.0 * a * b * b - 4.0 * b * b * b / 3.0;
+      };
+      for (int g = 0; g < ng; ++g) {
+        const double M = (double)S[g].M, N = (double)S[g].N, d = (double)S[g].d;
+        const double ra = std::min(M, d), rb = std::min(N, d);
+        const double hi = std::max(ra, rb), lo = std::min(ra, rb);
+        res.textbook_flops += qr(M, d) + qr(N, d) + 14.0 * hi * lo * lo + 8.0 * lo * lo * lo +
+                              2.0 * (M * ra + N * rb) * S[g].kept;
+      }
+    }
     for (int g = 0; g < ng; ++g)
       for (int i = 0; i < S[g].kept; ++i) res.svals.push_back(hw[loff[g] + i]);
     std::sort(res.svals.begin(), res.svals.end(), std::greater<double>());
@@ -1674,7 +1898,8 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   DBuf<double> PAB(std::max<int64_t>(pas, 1), s), Fk(std::max<int64_t>(fs, 1), s), GF(std::max<int64_t>(fs, 1), s);
   {
     // with accurate factors GF = R_o^T (X^T E_k) replaces G_o F
-    std::vector<GemmGroup> gf, ggf, gw, gwf;
+    std::vector<GemmGroup> gf, ggf, gwf;
+    std::vector<ScaleColsJob> scols;
     std::vector<int64_t> wo(ng);
     int64_t wsz = 0;
     for (int g = 0; g < ng; ++g) {
@@ -1690,8 +1915,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
       gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
       if (x.acc) {
+        // W_k = V_k S_k from the accumulated rotations (not X^T E_k)
         const int64_t r_o = x.sideA ? x.rB : x.rA;
-        gw.push_back(plain_group(r_o, x.kept, r, xoff[g], r_o, 1, eoff[g], x.p, 0, wo[g], x.kept));
+        scols.push_back(ScaleColsJob{Vm.p + voff[g], Lm.p + loff[g], Wk.p + wo[g], r_o, x.kept, r_o});
         gwf.push_back(plain_group(x.d, x.kept, r_o, go, x.d, 1, wo[g], x.kept, 0, fo[g], x.kept));
       } else {
         ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
@@ -1700,8 +1926,12 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     if (!gf.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gf, Rc.p, Em.p, Fk.p, nullptr, s);
       if (!ggf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggf, Gm.p, Fk.p, GF.p, nullptr, s);
-      if (!gw.empty()) {
-        run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gw, Xm.p, Em.p, Wk.p, nullptr, s);
+      if (!scols.empty()) {
+        int64_t mx = 1;
+        for (auto& j : scols) mx = std::max<int64_t>(mx, j.rows * j.cols);
+        DBuf<ScaleColsJob> dj = to_device(scols, s);
+        LAUNCH(k_scale_cols, dim3((unsigned)std::min<int64_t>(cdiv(mx, 256), 1024), (unsigned)scols.size()), dim3(256),
+               0, s, dj.p);
         run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);
       }
       for (int g = 0; g < ng; ++g) {

@@ -42,6 +42,11 @@ ftn_tensor_t make_handle(std::unique_ptr<Tensor> t);
 
 using namespace ftn;
 
+// relative singular-value cutoff of the compressions of a network: values
+// not above 1e-12 of the largest are numerically zero (FP64 round-off of the
+// decomposition is ~1e-15 of the largest)
+constexpr double NET_CUTOFF = 1e-12;
+
 namespace {
 struct Label {
   int kind;  // 0 bond (a = bond id), 1 open (a = tensor, b = leg)
@@ -271,12 +276,13 @@ static void contract_net(const ftn_net* net, int nsteps, const int32_t* ssa_path
         const int64_t dim = T[z]->legs()[lzs[0]].size();
         // a tensor with no allowed block is exactly zero: nothing to truncate
         if (dim > chi && T[z]->size() > 0 && T[w]->size() > 0) {
-          CompressResult r = op_compress_bond(*T[z], *T[w], lzs[0], lw[0], chi, 1e-6, FTN_LOCAL, s);
+          CompressResult r = op_compress_bond(*T[z], *T[w], lzs[0], lw[0], chi, NET_CUTOFF, FTN_LOCAL, s);
           T[z] = std::move(r.a);
           T[w] = std::move(r.b);
           st[1] += 1;
           st[2] += r.discarded;
           st[3] += r.near_tie ? 1 : 0;
+          st[5] += r.textbook_flops;
         }
       }
     }
@@ -449,6 +455,8 @@ extern "C" int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds,
     const std::vector<hipStream_t> wss = worker_streams(dev, nw);
     auto work = [&](int w) {
       hipStream_t ws = wss[w];
+      // the calling thread keeps its instrumentation when it works alone
+      prof_quiet(nw > 1);
       try {
         HIPC(hipSetDevice(dev));
         std::vector<const Tensor*> P(nsites);
@@ -488,6 +496,7 @@ extern "C" int ftn_amplitudes(int nsites, const ftn_tensor_t* sites, int nbonds,
         stop = true;
       }
       (void)hipStreamSynchronize(ws);
+      prof_quiet(false);
     };
     std::vector<std::thread> th;
     for (int w = 1; w < nw; ++w) th.emplace_back(work, w);

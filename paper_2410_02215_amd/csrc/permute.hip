@@ -343,7 +343,8 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
            (float)alpha);
   }
   HIPC(hipGetLastError());
-  prof_end(tok, s, FTN_PROF_PERMUTE, 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4));
+  const double pb = 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4);
+  prof_end(tok, s, FTN_PROF_PERMUTE, pb, pb);
 }
 
 // ---------------------------------------------------------------------------

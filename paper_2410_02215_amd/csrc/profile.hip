@@ -13,12 +13,13 @@ struct Rec {
   hipEvent_t a, b;
   int cls;
   double work;
+  double bytes;
 };
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
-double g_ms[FTN_PROF_NCLASS], g_cnt[FTN_PROF_NCLASS], g_work[FTN_PROF_NCLASS];
+double g_ms[FTN_PROF_NCLASS], g_cnt[FTN_PROF_NCLASS], g_work[FTN_PROF_NCLASS], g_bytes[FTN_PROF_NCLASS];
 
 hipEvent_t take() {
   if (!g_pool.empty()) {
@@ -59,6 +60,7 @@ void settle(std::vector<Rec>& recs, bool block) {
     g_ms[r.cls] += ms[i];
     g_cnt[r.cls] += 1;
     g_work[r.cls] += r.work;
+    g_bytes[r.cls] += r.bytes;
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }
@@ -75,10 +77,17 @@ void drain() {
 }
 }  // namespace
 
-bool prof_on() { return g_on; }
+// Launches made from library worker threads (several host threads submitting
+// at once) are never instrumented: every event record of this timer happens
+// on a thread that called into the library, under the timer's lock.
+thread_local bool t_quiet = false;
+
+bool prof_on() { return g_on && !t_quiet; }
+
+void prof_quiet(bool on) { t_quiet = on; }
 
 void* prof_begin(hipStream_t s) {
-  if (!g_on) return nullptr;
+  if (!g_on || t_quiet) return nullptr;
   std::lock_guard<std::mutex> g(g_mu);
   Rec* r = new Rec;
   r->a = take();
@@ -87,15 +96,16 @@ void* prof_begin(hipStream_t s) {
   return r;
 }
 
-void prof_end(void* tok, hipStream_t s, int cls, double work) {
+void prof_end(void* tok, hipStream_t s, int cls, double work, double bytes) {
   if (!tok) return;
   Rec* r = (Rec*)tok;
-  HIPC(hipEventRecord(r->b, s));
   r->cls = cls;
   r->work = work;
+  r->bytes = bytes;
   std::vector<Rec> full;
   {
     std::lock_guard<std::mutex> g(g_mu);
+    HIPC(hipEventRecord(r->b, s));
     g_recs.push_back(*r);
     if (g_recs.size() > 4096) full.swap(g_recs);
   }
@@ -109,14 +119,15 @@ void prof_enable(int on) {
   g_on = on != 0;
 }
 
-void prof_collect(double* ms, double* count, double* work) {
+void prof_collect(double* ms, double* count, double* work, double* bytes) {
   drain();
   std::lock_guard<std::mutex> g(g_mu);
   for (int c = 0; c < FTN_PROF_NCLASS; ++c) {
     if (ms) ms[c] = g_ms[c];
     if (count) count[c] = g_cnt[c];
     if (work) work[c] = g_work[c];
-    g_ms[c] = g_cnt[c] = g_work[c] = 0;
+    if (bytes) bytes[c] = g_bytes[c];
+    g_ms[c] = g_cnt[c] = g_work[c] = g_bytes[c] = 0;
   }
 }
 
@@ -132,9 +143,9 @@ extern "C" int ftn_profile_enable(int on) {
   }
 }
 
-extern "C" int ftn_profile_collect(double* ms, double* count, double* work) {
+extern "C" int ftn_profile_collect(double* ms, double* count, double* work, double* bytes) {
   try {
-    ftn::prof_collect(ms, count, work);
+    ftn::prof_collect(ms, count, work, bytes);
     return FTN_OK;
   } catch (const ftn::Error& e) {
     ftn::set_last_error(e.msg);

@@ -78,6 +78,12 @@ struct DevCache {
 };
 std::mutex g_cache_mu;
 std::unordered_map<int, DevCache>* g_cache = new std::unordered_map<int, DevCache>();
+// blocks of external allocators, with the free function that owns each
+struct ExtOwner {
+  void (*free_fn)(void*, ftn_stream_t, void*);
+  void* ctx;
+};
+std::unordered_map<void*, ExtOwner>* g_ext = new std::unordered_map<void*, ExtOwner>();
 
 size_t round_size(size_t b) {
   const size_t big = 2u << 20;
@@ -100,8 +106,14 @@ void* dmalloc(size_t bytes, hipStream_t s, bool persistent) {
   if (bytes == 0) return nullptr;
   void* p = nullptr;
   if (g_alloc && !persistent) {
-    p = g_alloc(bytes, (ftn_stream_t)s, g_alloc_ctx);
+    auto fr = g_free;
+    void* ctx = g_alloc_ctx;
+    p = g_alloc(bytes, (ftn_stream_t)s, ctx);
     if (!p) fail(FTN_ENOMEM, "external allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    // remembered with the allocator that made it: a block is always returned
+    // to its own allocator, even after another one has been registered
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    (*g_ext)[p] = ExtOwner{fr, ctx};
     return p;
   }
   if (persistent) {
@@ -147,9 +159,20 @@ void dfree(void* p, hipStream_t s, bool persistent) {
     (void)hipFree(p);
     return;
   }
-  if (g_free) {
-    g_free(p, (ftn_stream_t)s, g_alloc_ctx);
-    return;
+  {
+    ExtOwner o{nullptr, nullptr};
+    {
+      std::lock_guard<std::mutex> g(g_cache_mu);
+      auto it = g_ext->find(p);
+      if (it != g_ext->end()) {
+        o = it->second;
+        g_ext->erase(it);
+      }
+    }
+    if (o.free_fn) {
+      o.free_fn(p, (ftn_stream_t)s, o.ctx);
+      return;
+    }
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;

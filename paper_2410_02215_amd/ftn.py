@@ -64,8 +64,12 @@ SIGNATURES = [
     ("ftn_net_free", _I, [_P]),
     ("ftn_contract_network", _I, [_P, _I, _PI32, _I64, _I, _P, _PD, _PI64, _PP, _PI32, _PD]),
     ("ftn_amplitudes", _I, [_I, _PP, _I, _PI32, _I, _PI32, _I64, _I, _I64, _PI32, _I, _P, _PD, _PI64]),
+    ("ftn_autotune", _I, [_I]),
+    ("ftn_autotune_load", _I, [ctypes.c_char_p]),
+    ("ftn_autotune_save", _I, [ctypes.c_char_p]),
+    ("ftn_autotune_stats", _I, [_PI64, _PI64, _PI64]),
     ("ftn_profile_enable", _I, [_I]),
-    ("ftn_profile_collect", _I, [_PD, _PD, _PD]),
+    ("ftn_profile_collect", _I, [_PD, _PD, _PD, _PD]),
     ("ftn_memory_stats", _I, [_I, _PI64, _PI64, _PI64, _I]),
 ]
 
@@ -78,11 +82,64 @@ def profile_enable(on=True):
 
 
 def profile_collect():
-    """{class: (ms, launches, work)} since the last collect."""
+    """{class: (ms, launches, work, algorithmic bytes)} since the last collect."""
     n = len(PROF_CLASSES)
-    ms, cnt, wk = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
-    _check(_lib.ftn_profile_collect(ms, cnt, wk))
-    return {c: (ms[i], cnt[i], wk[i]) for i, c in enumerate(PROF_CLASSES)}
+    ms, cnt, wk, by = [(ctypes.c_double * n)() for _ in range(4)]
+    _check(_lib.ftn_profile_collect(ms, cnt, wk, by))
+    return {c: (ms[i], cnt[i], wk[i], by[i]) for i, c in enumerate(PROF_CLASSES)}
+
+
+def autotune(mode):
+    """GEMM tile autotuner: 0 heuristic, 1 stored choices, 2 tune unseen shapes."""
+    load_library()
+    _check(_lib.ftn_autotune(int(mode)))
+
+
+def autotune_load(path):
+    load_library()
+    _check(_lib.ftn_autotune_load(str(path).encode()))
+
+
+def autotune_save(path):
+    load_library()
+    _check(_lib.ftn_autotune_save(str(path).encode()))
+
+
+def autotune_stats():
+    load_library()
+    e, t, h = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.ftn_autotune_stats(ctypes.byref(e), ctypes.byref(t), ctypes.byref(h)))
+    return dict(entries=e.value, tuned=t.value, hits=h.value)
+
+
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_torch_hooks = None
+
+
+def use_torch_allocator(on=True):
+    """Route the library's device allocations through torch's caching allocator
+    (on=True) or back to the library's own (on=False). Blocks are always
+    returned to the allocator that made them."""
+    global _torch_hooks
+    load_library()
+    if not on:
+        _check(_lib.ftn_set_allocator(None, None, None))
+        return
+    import torch
+
+    def _alloc(size, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+        except Exception:  # reported by the library as FTN_ENOMEM
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    hooks = (_ALLOC_T(_alloc), _FREE_T(_free))
+    _check(_lib.ftn_set_allocator(ctypes.cast(hooks[0], ctypes.c_void_p), ctypes.cast(hooks[1], ctypes.c_void_p), None))
+    _torch_hooks = hooks  # keep the callbacks alive
 
 
 def memory_stats(device=0, reset_peak=False):
@@ -373,7 +430,7 @@ class Network:
                                          _stream(), ctypes.byref(m), ctypes.byref(e),
                                          ctypes.byref(out) if open_legs else None, src, st))
         stats = dict(flops=st[0], compressions=int(st[1]), discarded=st[2], near_ties=int(st[3]),
-                     max_entries=st[4])
+                     max_entries=st[4], compress_textbook_flops=st[5])
         if open_legs and out.value:
             t = Tensor(out)
             n = t.ndim

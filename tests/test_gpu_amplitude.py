@@ -166,6 +166,6 @@ def test_slater_amplitudes_are_the_determinant(P, shape, m_up, m_dn, chi):
     print("slater %dx%d M=%d+%d chi=%d: max error %.3g of the largest amplitude" % (lx, ly, m_up, m_dn, chi, err))
     # the bonds are compressed wherever they exceed chi (every cut of the
     # state has rank at most 2^M <= chi, so only zero directions are cut)
-    assert err <= 1e-9, err
+    assert err <= 1e-12, err
     # wrong parity: exactly zero
     assert np.all(got[-2:] == 0.0)

@@ -107,16 +107,49 @@ def test_compress_bond_matches_oracle(P, sym, conv):
         A = rand_tensor(rng, sym, la[:pa] + [bond] + la[pa:], total=S.zero(sym))
         B = rand_tensor(rng, sym, lb[:pb] + [partner(bond)] + lb[pb:], total=S.zero(sym))
         chi = int(rng.integers(2, 8))
-        A2, B2, info = o_compress(A, B, pa, pb, chi, conv=conv, cutoff=1e-6)
+        A2, B2, info = o_compress(A, B, pa, pb, chi, conv=conv, cutoff=1e-12)
         ref = ftensordot(A2, B2, [pa], [pb], conv).to_dense()
         cv = P.LOCAL if conv == "local" else P.GLOBAL
-        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), pa, pb, chi, 1e-6, cv)
+        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), pa, pb, chi, 1e-12, cv)
         assert GA.legs()[pa][1] == list(A2.legs[pa].dims)       # kept dims, bit-exact
         GC = P.ftensordot(GA, GB, [pa], [pb], conv=cv)
         got = GC.to_dense().cpu().numpy()
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()))
         kept = sorted(np.concatenate([v.numpy() for v in info["svals"].values()]), reverse=True)
         np.testing.assert_allclose(ginfo["svals"], kept, rtol=1e-9)
+
+
+@pytest.mark.parametrize("chi,kept", [(100, {(0,): 7, (1,): 6}), (10, {(0,): 6, (1,): 4})])
+def test_compress_bond_resolves_a_graded_spectrum(P, chi, kept):
+    # bond matrices with singular values from 1 down to 1e-15 per Z2 sector:
+    # with cutoff 1e-12 the kept dims are fixed by values down to 4e-11, so
+    # the library must resolve singular values far below the ~1e-8 of a Gram
+    # matrix; kept dims bit-exact, kept values to 1e-14 of the largest
+    rng = np.random.default_rng(830)
+    sym = S.Z2
+    from oracle.tensor import make_leg, FTensor
+    sig = {0: [1.0, 3e-2, 1e-3, 3e-5, 1e-6, 3e-8, 1e-9, 1e-14],
+           1: [0.5, 2e-3, 4e-6, 8e-9, 2e-10, 4e-11, 3e-13, 1e-15]}
+    la = make_leg(sym, [(0,), (1,)], [20, 20], 0)
+    bond = make_leg(sym, [(0,), (1,)], [8, 8], 1)
+    lb = make_leg(sym, [(0,), (1,)], [12, 12], 1)
+    A = FTensor.zeros(sym, [la, bond], (0,))
+    B = FTensor.zeros(sym, [partner(bond), lb], (0,))
+    for q in (0, 1):
+        ua = np.linalg.qr(rng.standard_normal((20, 8)))[0]
+        va = np.linalg.qr(rng.standard_normal((8, 8)))[0]
+        wb = np.linalg.qr(rng.standard_normal((12, 8)))[0].T
+        A.blocks[(q, q)] = torch.from_numpy(ua @ np.diag(sig[q]) @ va.T)
+        B.blocks[(q, q)] = torch.from_numpy(wb.copy())
+    A2, B2, info = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-12)
+    assert {q: len(v) for q, v in info["svals"].items()} == kept
+    GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-12, P.LOCAL)
+    assert GA.legs()[1][1] == [kept[(0,)], kept[(1,)]]
+    ref_sv = sorted(np.concatenate([v.numpy() for v in info["svals"].values()]), reverse=True)
+    np.testing.assert_allclose(ginfo["svals"], ref_sv, rtol=0, atol=1e-14)
+    ref = ftensordot(A2, B2, [1], [0], "local").to_dense()
+    got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
 
 
 @pytest.mark.parametrize("sym", [S.Z2, S.U1])
@@ -128,9 +161,9 @@ def test_compress_bond_odd_tensors(P, sym):
         A = rand_tensor(rng, sym, [rand_leg(rng, sym, maxd=3), bond, rand_leg(rng, sym, maxd=3)], total=ta)
         B = rand_tensor(rng, sym, [partner(bond), rand_leg(rng, sym, maxd=3)], total=tb)
         chi = int(rng.integers(2, 8))
-        A2, B2, info = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-6)
+        A2, B2, info = o_compress(A, B, 1, 0, chi, conv="local", cutoff=1e-12)
         ref = ftensordot(A2, B2, [1], [0], "local").to_dense()
-        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-6, P.LOCAL)
+        GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-12, P.LOCAL)
         assert GA.legs()[1][1] == list(A2.legs[1].dims)
         got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * max(1.0, np.abs(ref).max()))

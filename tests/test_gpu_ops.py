@@ -211,3 +211,60 @@ def test_memory_statistics_follow_allocations(P):
     with pytest.raises(P.FtnError) as e:
         P.ftn.memory_stats(-1)
     assert e.value.code == -1
+
+
+def test_compress_bond_with_no_common_sector(P):
+    # the two ends share no charge that carries blocks on both sides: F(AB)
+    # is zero across the bond, nothing is kept and the bond leg is emptied on
+    # both tensors (the oracle's compress_bond gives the same structure)
+    from oracle.linalg import compress_bond
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    rng = np.random.default_rng(11)
+    A = rand_tensor(rng, sym, [l(3, 2, 0), l(4, 5, 1)], total=(0,))
+    A.blocks = {k: v for k, v in A.blocks.items() if k[1] == 0}   # even bond sector only
+    B = rand_tensor(rng, sym, [l(4, 5, 0)], total=(1,))           # odd bond sector only
+    A2, B2, info = compress_bond(A, B, 1, 0, 3)
+    assert A2.legs[1].charges == () and B2.legs[0].charges == ()
+    Ga = P.Tensor.from_dense(0, [([(0, 0), (1, 0)], [3, 2], 0), ([(0, 0)], [4], 1)], (0, 0),
+                             torch.from_numpy(A.to_dense()[:, :4].copy()).cuda())
+    Gb = P.Tensor.from_dense(0, [([(1, 0)], [5], 0)], (1, 0), torch.from_numpy(B.to_dense()[4:].copy()).cuda())
+    ga, gb, info = P.compress_bond(Ga, Gb, 1, 0, 3)
+    assert ga.leg(1)[0] == [] and gb.leg(0)[0] == []
+    assert ga.size == 0 and gb.size == 0 and len(info["svals"]) == 0
+
+
+def test_torch_owns_the_library_memory(P):
+    # with torch's caching allocator registered, tensor data and temporaries
+    # of a contraction come from torch (its allocated bytes grow while the
+    # library's own cache does not), results are unchanged, and blocks made
+    # by either allocator go back to it after the other is registered
+    from tests.helpers import rand_tensor as rt
+    rng = np.random.default_rng(12)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rt(rng, sym, [l(64, 48, 0), l(40, 30, 1)], total=(0,))
+    B = rt(rng, sym, [l(40, 30, 0), l(50, 20, 1)], total=(0,))
+    ref = flat_blocks(ftensordot(A, B, [1], [0], conv="local"))
+    dev = torch.cuda.current_device()
+    G0 = to_gpu(A)                                   # built-in allocator
+    torch.cuda.synchronize()
+    lib0 = P.ftn.memory_stats(dev)["in_use"]
+    t0 = torch.cuda.memory_allocated()
+    try:
+        P.ftn.use_torch_allocator(True)
+        Ga, Gb = to_gpu(A), to_gpu(B)
+        C = P.ftensordot(Ga, Gb, [1], [0])
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - t0 >= 8 * (Ga.size + Gb.size + C.size)
+        assert P.ftn.memory_stats(dev)["in_use"] == lib0
+        np.testing.assert_allclose(C.data().cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        C2 = P.ftensordot(G0, Gb, [1], [0])          # a built-in block used beside torch's
+        np.testing.assert_allclose(C2.data().cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        del G0                                       # back to the built-in cache
+    finally:
+        P.ftn.use_torch_allocator(False)
+    torch.cuda.synchronize()
+    del Ga, Gb, C, C2                                # back to torch
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= t0

@@ -36,3 +36,28 @@ def test_binding_declares_every_symbol():
     assert set(header_symbols()) == declared
     lib = ftn.load_library()
     assert lib.ftn_version().startswith(b"ftn")
+
+
+def test_autotune_table_host_logic(tmp_path):
+    # mode checks and the JSON table round trip need no device
+    from paper_2410_02215_amd import ftn
+    ftn.load_library()
+    with pytest.raises(ftn.FtnError):
+        ftn.autotune(3)
+    p = os.path.join(str(tmp_path), "t.json")
+    with open(p, "w") as f:
+        f.write('{\n "version": 1,\n "entries": {\n  "k0-m9-n9-k9-g1-s0-x1": [1, 1, 12.5],\n'
+                '  "k1-m4-n8-k12-g2-s0-x0": [4, 3, 7.25]\n }\n}\n')
+    before = ftn.autotune_stats()["entries"]
+    ftn.autotune_load(p)
+    q = os.path.join(str(tmp_path), "u.json")
+    ftn.autotune_save(q)
+    import json
+    ent = json.load(open(q))["entries"]
+    assert ent["k0-m9-n9-k9-g1-s0-x1"] == [1, 1, 12.5] and ent["k1-m4-n8-k12-g2-s0-x0"] == [4, 3, 7.25]
+    assert ftn.autotune_stats()["entries"] >= max(before, 2)
+    with open(p, "w") as f:
+        f.write('{"entries": {\n  "bad": [9, 1, 1.0]\n}}\n')
+    with pytest.raises(ftn.FtnError):
+        ftn.autotune_load(p)
+    ftn.autotune(0)
