@@ -226,6 +226,26 @@ int ftn_ftensordot_backward(ftn_tensor_t a, ftn_tensor_t b, ftn_tensor_t dc, int
                             ftn_gemm gemm, ftn_stream_t stream, ftn_tensor_t* da,
                             ftn_tensor_t* db);
 
+/* Allocation-free form of ftn_ftensordot, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid allocation). Same arguments and result as ftn_ftensordot, but
+   the output blocks are written to out_data (device memory of the current
+   device, out_size entries of the tensors' dtype, in the block layout of the
+   output structure that ftn_ftensordot returns for these operands), and the
+   temporaries (fused matrices, split-K workspace) live in a fixed 64 MiB
+   device array that the library holds on each GPU until the process ends.
+   No device memory is allocated or freed, so the contraction plan must be
+   cached: call ftn_ftensordot once with operands of the same structures,
+   axes, convention and GEMM form first (FTN_ENOTSUP otherwise).
+   FTN_EINVAL if out_size differs from the output's size or if the
+   temporaries exceed 64 MiB. Every call on one GPU uses that GPU's array:
+   calls that overlap in time on one GPU (other streams or threads) race and
+   must be serialised by the caller; the array keeps the last call's
+   contents, every entry a call reads it has written first. */
+int ftn_ftensordot_noalloc(ftn_tensor_t a, ftn_tensor_t b, int naxes, const int32_t* axes_a,
+                           const int32_t* axes_b, ftn_conv conv, ftn_gemm gemm,
+                           ftn_stream_t stream, void* out_data, int64_t out_size);
+
 /* ---------------------------------------------------------------------------
  * Bond compression (Sec. II.A truncated SVD; Sec. III approximate trees)
  * ------------------------------------------------------------------------ */

@@ -10,12 +10,12 @@ through the library's adjoint contraction.
 """
 
 from . import ftn
-from .ftn import (Tensor, Network, ftranspose, flip_dual, dagger, fuse, fuse_backward, ftensordot,
+from .ftn import (Tensor, Network, ftranspose, flip_dual, dagger, fuse, fuse_backward, ftensordot, ftensordot_noalloc,
                   ftensordot_backward, compress_bond, compress_bond_backward, amplitudes, load_library, FtnError,
                   Z2, U1, U1xU1, F64, F32, LOCAL, GLOBAL,
                   GEMM_F64, GEMM_F32, GEMM_BF16X3)
 
 __all__ = ["ftn", "Tensor", "Network", "ftranspose", "flip_dual", "dagger", "fuse", "fuse_backward",
-           "ftensordot", "ftensordot_backward", "compress_bond", "compress_bond_backward", "amplitudes", "load_library", "FtnError",
+           "ftensordot", "ftensordot_noalloc", "ftensordot_backward", "compress_bond", "compress_bond_backward", "amplitudes", "load_library", "FtnError",
            "Z2", "U1", "U1xU1", "F64", "F32", "LOCAL", "GLOBAL",
            "GEMM_F64", "GEMM_F32", "GEMM_BF16X3"]

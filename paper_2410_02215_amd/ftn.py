@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ftn_dagger", _I, [_P, _P, _PP]),
     ("ftn_fuse", _I, [_P, _I, _PI32, _I, _I, _P, _PP]),
     ("ftn_ftensordot", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP]),
+    ("ftn_ftensordot_noalloc", _I, [_P, _P, _I, _PI32, _PI32, _I, _I, _P, _P, _I64]),
     ("ftn_ftensordot_backward", _I, [_P, _P, _P, _I, _PI32, _PI32, _I, _I, _P, _PP, _PP]),
     ("ftn_compress_bond", _I, [_P, _P, _I, _I, _I64, _D, _I, _P, _PP, _PP, _PD, _PD, _PI64]),
     ("ftn_fuse_backward", _I, [_P, _I, _PI32, _I, _I, _P, _P, _PP]),
@@ -366,6 +367,15 @@ def ftensordot(a, b, axes_a, axes_b, conv=LOCAL, gemm=GEMM_F64):
                                _arr([int(x) for x in axes_b], ctypes.c_int32), int(conv), int(gemm),
                                _stream(), ctypes.byref(out)))
     return Tensor(out)
+
+
+def ftensordot_noalloc(a, b, axes_a, axes_b, out, conv=LOCAL, gemm=GEMM_F64):
+    """ftensordot into ``out`` (a contiguous device tensor of the output's size
+    and dtype) without any device allocation; needs a cached plan."""
+    _check(_lib.ftn_ftensordot_noalloc(a.h, b.h, len(axes_a), _arr([int(x) for x in axes_a], ctypes.c_int32),
+                                       _arr([int(x) for x in axes_b], ctypes.c_int32), int(conv), int(gemm),
+                                       _stream(), ctypes.c_void_p(out.data_ptr()), int(out.numel())))
+    return out
 
 
 def ftensordot_backward(a, b, dc, axes_a, axes_b, conv=LOCAL, gemm=GEMM_F64):

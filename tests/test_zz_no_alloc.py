@@ -1,0 +1,78 @@
+"""The allocation-free contraction ``ftn_ftensordot_noalloc`` against
+``ftn_ftensordot``: the same plan and kernels with the temporaries in the
+library's fixed per-GPU scratch array, so the outputs agree bit for bit; two
+calls in a row, the second on a smaller contraction; the library's caching
+allocator does not move during the calls; errors for an uncached plan, a
+wrong output size and temporaries beyond the scratch array.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import symmetry as S
+from tests.helpers import rand_tensor
+from tests.gpu_helpers import to_gpu
+from oracle.tensor import make_leg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_02215_amd as P
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    P.load_library()
+    return P
+
+
+def _pair(rng, sym, dims_free_a, dims_k, dims_free_b):
+    qs = [(0,), (1,)] if sym == S.Z2 else [(-1,), (0,), (1,)]
+    mk = lambda d, dual: make_leg(sym, qs, d, dual)
+    A = rand_tensor(rng, sym, [mk(dims_free_a, 0), mk(dims_k, 1)], total=S.zero(sym))
+    B = rand_tensor(rng, sym, [mk(dims_k, 0), mk(dims_free_b, 1)], total=S.zero(sym))
+    return A, B
+
+
+@pytest.mark.parametrize("dtype,gemm", [("f64", 0), ("f32", 1), ("f32", 2)])
+def test_noalloc_matches_ftensordot_on_two_calls(P, dtype, gemm):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(700)
+    dev = torch.cuda.current_device()
+    cases = [_pair(rng, S.Z2, [300, 257], [190, 77], [211, 160]),   # several tiles, ragged tails
+             _pair(rng, S.U1, [20, 13, 9], [7, 11, 5], [16, 3, 12])]  # the smaller second call
+    for A, B in cases:
+        Ga, Gb = to_gpu(A, tdt), to_gpu(B, tdt)
+        ref = P.ftensordot(Ga, Gb, [1], [0], gemm=gemm)           # caches the plan
+        want = ref.data().clone()
+        out = torch.full((ref.size,), float("nan"), device="cuda", dtype=tdt)
+        torch.cuda.synchronize()
+        before = P.ftn.memory_stats(dev)
+        P.ftensordot_noalloc(Ga, Gb, [1], [0], out, gemm=gemm)
+        torch.cuda.synchronize()
+        after = P.ftn.memory_stats(dev)
+        assert after["reserved"] == before["reserved"] and after["in_use"] == before["in_use"]
+        assert torch.equal(out, want), (out - want).abs().max().item()
+
+
+def test_noalloc_errors(P):
+    rng = np.random.default_rng(701)
+    A, B = _pair(rng, S.Z2, [5, 4], [3, 6], [2, 7])
+    Ga, Gb = to_gpu(A), to_gpu(B)
+    out = torch.zeros(1000, device="cuda", dtype=torch.float64)
+    with pytest.raises(P.FtnError) as e:                          # no cached plan yet
+        P.ftensordot_noalloc(Ga, Gb, [1], [0], out, gemm=0, conv=P.GLOBAL)
+    assert e.value.code == -6
+    ref = P.ftensordot(Ga, Gb, [1], [0], conv=P.GLOBAL)
+    with pytest.raises(P.FtnError) as e:                          # wrong output size
+        P.ftensordot_noalloc(Ga, Gb, [1], [0], out[:ref.size - 1], conv=P.GLOBAL)
+    assert e.value.code == -1
+    # temporaries of 2 x 4096 x 1200 FP64 per operand exceed the 64 MiB array
+    big_a = P.Tensor.create(0, [([(0, 0), (1, 0)], [4096, 4096], 0), ([(0, 0), (1, 0)], [1200, 1200], 1)], (0, 0))
+    big_b = P.Tensor.create(0, [([(0, 0), (1, 0)], [1200, 1200], 0), ([(0, 0), (1, 0)], [8, 8], 1)], (0, 0))
+    c = P.ftensordot(big_a, big_b, [1], [0])
+    o2 = torch.zeros(c.size, device="cuda", dtype=torch.float64)
+    with pytest.raises(P.FtnError) as e:
+        P.ftensordot_noalloc(big_a, big_b, [1], [0], o2)
+    assert e.value.code == -1
