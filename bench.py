@@ -122,11 +122,13 @@ def gpu_step(g, chi, concurrent=True):
     return (m1, e1, m2, e2), (s1, s2)
 
 
-def cpu_baseline(cfg, paths):
-    """The oracle on the host cores: one full <psi|psi> contraction, timed.
+def cpu_baseline(cfg, paths, runs=3):
+    """The oracle on the host cores: full <psi|psi> contractions, timed.
 
-    The hopping term costs several times more on the CPU, so the rate of
-    norm contractions alone is an upper bound on the oracle's rate for the
+    One untimed warm-up contraction, then ``runs`` timed ones; the rate is
+    that of the median. The hopping term costs about six times a norm
+    contraction on the CPU, so it is left out of the bounded sample: the rate
+    of norm contractions alone is an upper bound on the oracle's rate for the
     benchmark's mix of contractions.
     """
     import torch
@@ -138,13 +140,47 @@ def cpu_baseline(cfg, paths):
     torch.set_num_threads(cores)
     kets = OP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
     net = OP.norm_network(spec, kets, conv="local")
-    t0 = time.time()
     m, e = network_value(net, paths["c2_norm"]["path"], chi=cfg["chi"])
-    el = time.time() - t0
+    ts = []
+    for _ in range(runs):
+        t0 = time.time()
+        network_value(net, paths["c2_norm"]["path"], chi=cfg["chi"])
+        ts.append(time.time() - t0)
+    el = sorted(ts)[len(ts) // 2]
     return dict(value=1.0 / el, unit="contractions/s", cores=cores, kind="oracle",
-                sample="one full <psi|psi> contraction of the same workload (%.1f s, FP64, torch CPU "
-                       "with %d threads); the hopping-term contraction is not included" % (el, cores),
+                sample="full <psi|psi> contractions of the same workload: one warm-up, then the median of %d "
+                       "(%s s; FP64, torch CPU with %d threads); the hopping-term contraction is not included"
+                       % (runs, ", ".join("%.1f" % t for t in ts), cores),
                 log2_norm=math.log2(abs(m)) + e if m else None)
+
+
+def golden_errors(norm, hop):
+    """Relative errors of the step's results against the stored oracle values.
+
+    tests/golden/values.json is written by tests/golden/make_golden.py, which
+    calls only the oracle, with the same seeded inputs, paths and chi.
+    """
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "values.json")) as f:
+            gold = json.load(f)
+        rn = gold["c2_norm"]["mantissa"] * 2.0 ** gold["c2_norm"]["exp2"]
+        rh = gold["c2_hop"]["mantissa"] * 2.0 ** gold["c2_hop"]["exp2"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return {"norm": abs(norm / rn - 1.0), "hop_term": abs(hop * norm / rh - 1.0)}
+
+
+TUNING = os.path.join(ROOT, "paper_2410_02215_amd", "tuning", "gfx950.json")
+
+
+def autotune_setup(P, args):
+    """GEMM tile autotuner: stored choices, unseen shapes tuned during warm-up."""
+    if args.no_autotune:
+        P.ftn.autotune(0)
+        return
+    if os.path.exists(TUNING):
+        P.ftn.autotune_load(TUNING)
+    P.ftn.autotune(2)
 
 
 def amplitude_setup(cfg):
@@ -217,7 +253,9 @@ def main_amplitudes(args):
         "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": cfg["chi"],
                    "amplitudes_per_step": B, "workers": args.workers},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
-        "roofline": roofline(prof, cfg["name"]),
+        # launches of the library's worker threads are not instrumented: with
+        # more than one worker the line carries wall-clock rates only
+        "roofline": roofline(prof, cfg["name"]) if any(prof[c][0] > 0 for c in prof) else None,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, %d amplitudes)" % args.cpu_samples, file=sys.stderr, flush=True)
@@ -324,13 +362,14 @@ def gradient_cpu_baseline(cfg, chi, paths):
 def roofline(prof, workload):
     """Roofline entry of the dominant kernel class by time."""
     dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
-    ms, cnt, work = prof[dom]
+    ms, cnt, work = prof[dom][:3]
     peak, unit, bound = PEAK[dom]
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     achieved = work / (ms * 1e-3) / scale if ms > 0 else 0.0
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": measured_traffic(dom, workload), "kernel": dom, "launches": cnt,
-            "avg_launch_ms": ms / max(cnt, 1), "work_per_launch": work / max(cnt, 1)}
+            "avg_launch_ms": ms / max(cnt, 1), "work_per_launch": work / max(cnt, 1),
+            "algorithmic_bytes_per_launch": prof[dom][3] / max(cnt, 1)}
 
 
 def main():
@@ -349,6 +388,8 @@ def main():
                     help="path steps per recomputation segment (gradient workload; default: one lattice "
                          "layer, 0: keep every intermediate)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
+    ap.add_argument("--no-autotune", action="store_true", help="tile shapes from the built-in heuristic only")
+    ap.add_argument("--save-tuning", default=None, help="write the autotuner's table to this JSON file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a single approximate contraction does not shard "
@@ -369,19 +410,27 @@ def main():
     chi = cfg["chi"]
     paths = load_paths()
     g = gpu_setup(cfg, paths)
+    autotune_setup(P, args)
     print("[bench] workload %s: warmup %d" % (cfg["name"], args.warmup), file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         res, st = gpu_step(g, chi, not args.serial)
         print("[bench] warmup step done: norm mantissa %.6g exp %d" % (res[0], res[1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    if not args.no_autotune:
+        P.ftn.autotune(1)  # the timed steps use the stored choices only
+        if args.save_tuning:
+            P.ftn.autotune_save(args.save_tuning)
+    tune_stats = P.ftn.autotune_stats()
     P.ftn.profile_collect()
     P.ftn.profile_enable(True)
     t0 = time.perf_counter()
     flops = 0.0
+    tb_flops = 0.0
     for k in range(args.steps):
         ts = time.perf_counter()
         res, st = gpu_step(g, chi, not args.serial)
         flops += st[0]["flops"] + st[1]["flops"]
+        tb_flops += st[0]["compress_textbook_flops"] + st[1]["compress_textbook_flops"]
         print("[bench] step %d done (%.1f ms host)" % (k, 1000 * (time.perf_counter() - ts)), file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
@@ -404,15 +453,20 @@ def main():
                    "contractions_per_step": 2, "terms": ["norm", "hopping(first edge)"],
                    "streams": 1 if args.serial else 2},
         "ftensordot_useful_tflops": flops / el / 1e12,
+        "textbook_tflops": {"ftensordot": flops / el / 1e12, "compression": tb_flops / el / 1e12,
+                            "note": "useful block-pair GEMM flops plus the textbook QR/LQ/SVD/absorb counts of "
+                                    "the compressions, per second of the timed steps"},
+        "autotune": dict(tune_stats, enabled=not args.no_autotune),
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
         "kernel_rate": {c: "%.4g %s" % (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
                                         PEAK[c][1])
                         for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
+        "rel_err_vs_oracle": golden_errors(norm, hop),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle, one norm contraction)", file=sys.stderr, flush=True)
+        print("[bench] cpu baseline (oracle, norm contractions: warm-up + 3)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, paths)
     print(json.dumps(out), flush=True)
 

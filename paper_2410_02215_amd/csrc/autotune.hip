@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -38,6 +39,7 @@ std::map<std::string, Choice> g_table;
 int g_mode = 0;  // 0 off, 1 use stored choices, 2 also tune unseen keys
 int64_t g_tuned = 0, g_hits = 0;
 
+constexpr double TUNE_MAX_BYTES = 2.0 * (1 << 30);
 const int TILE_BM[] = {64, 128, 256, 256, 16, 32};
 const int TILE_BN[] = {64, 128, 16, 32, 256, 256};
 
@@ -91,6 +93,15 @@ Choice tune_now(const std::vector<GemmGroup>& gs0, int kind, hipStream_t s) {
   extents(gs, ea, eb, ec);
   const size_t es = kind == FTN_GEMM_F64 ? 8 : 4;
   const int dtype = kind == FTN_GEMM_F64 ? FTN_F64 : FTN_F32;
+  Choice best;
+  // plans whose operands span more than TUNE_MAX_BYTES are left to the
+  // heuristic (their large tiles fill the chip anyway)
+  const double need = (double)(ea + eb + ec) * es;
+  static const bool trace = std::getenv("FTN_TRACE_TUNE") != nullptr;
+  if (trace)
+    std::fprintf(stderr, "[tune] %s extents %lld %lld %lld (%.3g GB)\n", shape_key(gs0, kind).c_str(), (long long)ea,
+                 (long long)eb, (long long)ec, need / 1e9);
+  if (need > TUNE_MAX_BYTES) return best;
   DBuf<char> A(ea * es, s), B(eb * es, s), C(ec * es, s);
   HIPC(hipMemsetAsync(A.p, 0, ea * es, s));
   HIPC(hipMemsetAsync(B.p, 0, eb * es, s));
@@ -99,7 +110,6 @@ Choice tune_now(const std::vector<GemmGroup>& gs0, int kind, hipStream_t s) {
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
-  Choice best;
   best.us = 1e300;
   prof_quiet(true);
   try {
@@ -113,6 +123,7 @@ Choice tune_now(const std::vector<GemmGroup>& gs0, int kind, hipStream_t s) {
         gemm_plan_with(p, gs, kind, s, false, cfg, sp);
         if (p.split == last_split) continue;
         last_split = p.split;
+        if ((double)p.ws_elems * es > TUNE_MAX_BYTES) continue;
         DBuf<char> ws(p.ws_elems * es, s);
         run_gemm(p, dtype, A.p, B.p, C.p, nullptr, s, 1.0, 0.0, ws.p);
         float t[3];

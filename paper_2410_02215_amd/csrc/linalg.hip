@@ -938,7 +938,7 @@ __global__ void __launch_bounds__(LT) k_svd_cols(const SvdJob* jobs, double tol)
   const int r = J.r, c = J.c;
   if (r <= 0 || c <= 0) return;
   __shared__ double Xc[JMAX][JMAX + 1];
-  __shared__ double nrm[JMAX];
+  __shared__ double nrm[JMAX + 1];
   __shared__ int rot_any;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = LT / 64;
   for (int e = tid; e < r * c; e += LT) {
@@ -950,40 +950,86 @@ __global__ void __launch_bounds__(LT) k_svd_cols(const SvdJob* jobs, double tol)
     for (int i = tid; i < r; i += LT) Xc[c][i] = 0.0;
   const int np = n2 / 2;
   const bool l0 = lane < r, l1 = lane + 64 < r;
+  // |X|_F^2 for the absolute noise floor of a pair's inner product
+  __shared__ double fro_part[LT / 64];
+  __syncthreads();
+  {
+    double t = 0.0;
+    for (int e = tid; e < r * c; e += LT) {
+      const double x = Xc[e % c][e / c];
+      t += x * x;
+    }
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) fro_part[w] = t;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int k = 0; k < nw; ++k) fro2 += fro_part[k];
+  // a pair is rotated when its inner product is above tol * sqrt(a b) (tol =
+  // rows * eps, the rounding level of a length-r inner product) and above the
+  // rounding level of the whole matrix, 4 r eps^2 |X|_F^2: below it the two
+  // columns are round-off of zero directions and rotating them changes
+  // nothing but would keep the sweeps from ending
+  const double rtol = fmax(tol, (double)r * 2.220446049250313e-16);
+  const double floor_g = 4.0 * (double)r * 4.930380657631324e-32 * fro2;
+  // Each half-wave (32 lanes, four entries of a column each) takes one
+  // pair at a time, so a wave rotates two pairs at once. Only the cross
+  // product x_p . x_q needs a reduction: the squared column norms are exact
+  // at the start of a sweep and carried through its rotations by
+  // |x_p'|^2 = |x_p|^2 - t g, |x_q'|^2 = |x_q|^2 + t g.
+  const int hl = lane & 31, hw = lane >> 5;
+  const int nh = 2 * nw;  // half-waves
   int nr = 0;
   for (int sweep = 0; sweep < JAC_SWEEPS; ++sweep) {
     if (tid == 0) rot_any = 0;
     __syncthreads();
+    for (int j = w; j < n2; j += nw) {
+      double t = 0.0;
+      if (j < c) {
+        const double v0 = l0 ? Xc[j][lane] : 0.0, v1 = l1 ? Xc[j][lane + 64] : 0.0;
+        t = v0 * v0 + v1 * v1;
+      }
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      if (lane == 0) nrm[j] = t;
+    }
+    __syncthreads();
     for (int rd = 0; rd < n2 - 1; ++rd, ++nr) {
-      for (int k = w; k < np; k += nw) {
+      for (int k = 2 * w + hw; k < np; k += nh) {
         int p, q;
         rr_pair(n2, rd, k, p, q);
         double lc = 1.0, ls = 0.0;
-        const double xp0 = l0 ? Xc[p][lane] : 0.0, xp1 = l1 ? Xc[p][lane + 64] : 0.0;
-        const double xq0 = l0 ? Xc[q][lane] : 0.0, xq1 = l1 ? Xc[q][lane + 64] : 0.0;
-        double a = xp0 * xp0 + xp1 * xp1, b = xq0 * xq0 + xq1 * xq1, g = xp0 * xq0 + xp1 * xq1;
-        for (int o = 32; o > 0; o >>= 1) {
-          a += __shfl_xor(a, o);
-          b += __shfl_xor(b, o);
-          g += __shfl_xor(g, o);
+        double xp[4], xq[4];
+        double g = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = hl + 32 * u;
+          xp[u] = i < r ? Xc[p][i] : 0.0;
+          xq[u] = i < r ? Xc[q][i] : 0.0;
+          g += xp[u] * xq[u];
         }
-        if (g != 0.0 && fabs(g) > tol * sqrt(a * b)) {
+        for (int o = 16; o > 0; o >>= 1) g += __shfl_xor(g, o);
+        const double a = fmax(nrm[p], 0.0), b = fmax(nrm[q], 0.0);
+        if (fabs(g) > floor_g && fabs(g) > rtol * sqrt(a * b)) {
           const double zeta = (b - a) / (2.0 * g);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          if (l0) {
-            Xc[p][lane] = cs * xp0 - sn * xq0;
-            Xc[q][lane] = sn * xp0 + cs * xq0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = hl + 32 * u;
+            if (i < r) {
+              Xc[p][i] = cs * xp[u] - sn * xq[u];
+              Xc[q][i] = sn * xp[u] + cs * xq[u];
+            }
           }
-          if (l1) {
-            Xc[p][lane + 64] = cs * xp1 - sn * xq1;
-            Xc[q][lane + 64] = sn * xp1 + cs * xq1;
+          if (hl == 0) {
+            nrm[p] = a - t * g;
+            nrm[q] = b + t * g;
+            rot_any = 1;
           }
-          if (lane == 0) rot_any = 1;
           lc = cs;
           ls = sn;
         }
-        if (lane == 0) {
+        if (hl == 0) {
           J.rot[(int64_t)nr * np + k] = make_double2(lc, ls);
           J.rpq[(int64_t)nr * np + k] = p | (q << 16);
         }
@@ -1069,6 +1115,7 @@ struct Sect {
   bool iterate = false;
   bool sideA = true;     // eigenvectors live on the A side (U) or the B side (V)
   bool acc = false;      // d <= 128: accurate factors, X formed explicitly
+  bool svd = false;      // spectrum redone by the one-sided Jacobi SVD of X (V available)
   int kept = 0;
   Q charge;
   int crank = 0;
@@ -1370,39 +1417,13 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
 //   <= 1e-14 of the largest) or 96 iterations.
 static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
                        const double* Xm, const std::vector<int64_t>& xoff, double* Em, const std::vector<int64_t>& eoff,
-                       double* Lm, const std::vector<int64_t>& loff, double* Vm, const std::vector<int64_t>& voff,
-                       hipStream_t s) {
+                       double* Lm, const std::vector<int64_t>& loff, hipStream_t s) {
   const int ng = (int)S.size();
   const double tol = 1e-13;
   std::vector<int> dir, it;
   for (int g = 0; g < ng; ++g)
     if (S[g].ns > 0) (S[g].iterate ? it : dir).push_back(g);
   static const bool trace = std::getenv("FTN_TRACE") != nullptr;
-  {
-    // sectors with exact factors and X formed: one-sided Jacobi on X itself
-    std::vector<SvdJob> sj;
-    std::vector<double*> vv;
-    std::vector<int> rest;
-    for (int g : dir) {
-      if (!S[g].acc) {
-        rest.push_back(g);
-        continue;
-      }
-      const int r = S[g].ns, c = S[g].sideA ? S[g].rB : S[g].rA;
-      SvdJob j{};
-      j.X = Xm + xoff[g];
-      j.U = Em + eoff[g];
-      j.W = Lm + loff[g];
-      j.r = r;
-      j.c = c;
-      j.ldx = c;
-      j.ldu = S[g].p;
-      sj.push_back(j);
-      vv.push_back(Vm + voff[g]);
-    }
-    svd_cols(sj, vv, s);
-    dir.swap(rest);
-  }
   if (!dir.empty()) {
     const int nd = (int)dir.size();
     std::vector<EigJob> ej;
@@ -1751,7 +1772,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     xoff[g] = xs;
     xs += (x.iterate || x.acc) ? (int64_t)x.rA * x.rB : 0;
     hoff[g] = hs;
-    hs += (x.iterate || x.acc) ? 0 : (int64_t)x.ns * x.ns;
+    hs += x.iterate ? 0 : (int64_t)x.ns * x.ns;
     u1off[g] = u1s;
     u1s += x.iterate ? 0 : x.d * x.ns;
     eoff[g] = es;
@@ -1775,7 +1796,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   HIPC(hipMemsetAsync(Lm.p, 0, std::max<int64_t>(ls, 1) * 8, s));
   {
     DBuf<double> U1(std::max<int64_t>(u1s, 1), s);
-    std::vector<GemmGroup> gx, gu, gh, gxs;
+    std::vector<GemmGroup> gx, gu, gh, gxs, gxh;
     for (int g = 0; g < ng; ++g) {
       const Sect& x = S[g];
       if (!x.ns) continue;
@@ -1788,6 +1809,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         // accurate factors: X = R R_o^T (r x r_o), H = X X^T
         const int64_t r = x.ns, r_o = x.sideA ? x.rB : x.rA;
         gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
+        gxh.push_back(sym_group(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r)));
         continue;
       }
       // U1 = G_o R^T (d x r), H = R U1 (r x r)
@@ -1795,13 +1817,16 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       gh.push_back(plain_group(x.ns, x.ns, x.d, ro, x.d, 0, u1off[g], x.ns, 0, hoff[g], x.ns));
     }
     if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rc.p, Rc.p, Xm.p, nullptr, s);
-    if (!gxs.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
+    if (!gxs.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxh, Xm.p, Xm.p, Hm.p, nullptr, s);
+    }
     if (!gu.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Rc.p, U1.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Rc.p, U1.p, Hm.p, nullptr, s);
     }
   }
-  x_spectrum(S, chi, Hm.p, hoff, Xm.p, xoff, Em.p, eoff, Lm.p, loff, Vm.p, voff, s);
+  x_spectrum(S, chi, Hm.p, hoff, Xm.p, xoff, Em.p, eoff, Lm.p, loff, s);
   // singular values = sqrt(eigenvalues); selection
   launch_1d(std::max<int64_t>(ls, 1), s, k_sqrt_inplace, Lm.p, (int)std::max<int64_t>(ls, 1));
   {
@@ -1819,6 +1844,50 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     std::vector<double> hw(std::max<int64_t>(ls, 1));
     HIPC(hipMemcpyAsync(hw.data(), Lm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    // The eigenvalues of H = X X^T hold a singular value s only to about
+    // eps s_max^2 / s. A sector with exact factors whose values that matter
+    // (kept, or among the chi + 1 largest overall that decide the cut) reach
+    // below 1e-4 of its largest is redone by the one-sided Jacobi SVD of X
+    // itself, which resolves s to ~eps s_max; its projectors then use the V
+    // of that SVD.
+    {
+      std::vector<std::pair<double, int>> cand;
+      for (int i = 0; i < n; ++i) cand.push_back({hw[pos[i]], grp[i]});
+      const size_t top = std::min<size_t>(cand.size(), (size_t)std::max<int64_t>(chi, 0) + 1);
+      std::partial_sort(cand.begin(), cand.begin() + top, cand.end(),
+                        [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+      std::vector<double> smax(ng, 0.0);
+      for (int i = 0; i < n; ++i) smax[grp[i]] = std::max(smax[grp[i]], hw[pos[i]]);
+      std::vector<int> redo(ng, 0);
+      for (size_t t = 0; t < top; ++t) {
+        const int g = cand[t].second;
+        if (S[g].acc && !S[g].iterate && cand[t].first < 1e-4 * smax[g]) redo[g] = 1;
+      }
+      std::vector<SvdJob> sj;
+      std::vector<double*> vv;
+      for (int g = 0; g < ng; ++g) {
+        if (!redo[g]) continue;
+        S[g].svd = true;
+        const int r = S[g].ns, c = S[g].sideA ? S[g].rB : S[g].rA;
+        SvdJob j{};
+        j.X = Xm.p + xoff[g];
+        j.U = Em.p + eoff[g];
+        j.W = Lm.p + loff[g];
+        j.r = r;
+        j.c = c;
+        j.ldx = c;
+        j.ldu = S[g].p;
+        sj.push_back(j);
+        vv.push_back(Vm.p + voff[g]);
+      }
+      if (!sj.empty()) {
+        svd_cols(sj, vv, s);
+        for (int g = 0; g < ng; ++g)
+          if (redo[g]) launch_1d(S[g].p, s, k_sqrt_inplace, Lm.p + loff[g], S[g].p);
+        HIPC(hipMemcpyAsync(hw.data(), Lm.p, hw.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+      }
+    }
     std::vector<double> vals(n);
     for (int i = 0; i < n; ++i) {
       vals[i] = hw[pos[i]];
@@ -1898,7 +1967,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   DBuf<double> PAB(std::max<int64_t>(pas, 1), s), Fk(std::max<int64_t>(fs, 1), s), GF(std::max<int64_t>(fs, 1), s);
   {
     // with accurate factors GF = R_o^T (X^T E_k) replaces G_o F
-    std::vector<GemmGroup> gf, ggf, gwf;
+    std::vector<GemmGroup> gf, ggf, gw, gwf;
     std::vector<ScaleColsJob> scols;
     std::vector<int64_t> wo(ng);
     int64_t wsz = 0;
@@ -1915,9 +1984,13 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
       gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
       if (x.acc) {
-        // W_k = V_k S_k from the accumulated rotations (not X^T E_k)
+        // W_k = V_k S_k: from the accumulated rotations of the one-sided SVD,
+        // else X^T E_k (accurate while the kept values stay above 1e-4 s_max)
         const int64_t r_o = x.sideA ? x.rB : x.rA;
-        scols.push_back(ScaleColsJob{Vm.p + voff[g], Lm.p + loff[g], Wk.p + wo[g], r_o, x.kept, r_o});
+        if (x.svd)
+          scols.push_back(ScaleColsJob{Vm.p + voff[g], Lm.p + loff[g], Wk.p + wo[g], r_o, x.kept, r_o});
+        else
+          gw.push_back(plain_group(r_o, x.kept, r, xoff[g], r_o, 1, eoff[g], x.p, 0, wo[g], x.kept));
         gwf.push_back(plain_group(x.d, x.kept, r_o, go, x.d, 1, wo[g], x.kept, 0, fo[g], x.kept));
       } else {
         ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
@@ -1932,8 +2005,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         DBuf<ScaleColsJob> dj = to_device(scols, s);
         LAUNCH(k_scale_cols, dim3((unsigned)std::min<int64_t>(cdiv(mx, 256), 1024), (unsigned)scols.size()), dim3(256),
                0, s, dj.p);
-        run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);
       }
+      if (!gw.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gw, Xm.p, Em.p, Wk.p, nullptr, s);
+      if (!gwf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
         if (!x.kept) continue;

@@ -174,6 +174,17 @@ __global__ void k_tile_task(const int64_t* __restrict__ tile_start, int64_t ntas
   tile_task[tl] = (int32_t)lo;
 }
 
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double2 type;
+};
+template <>
+struct Pair<float> {
+  typedef float2 type;
+};
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(PM_THREADS)
     k_block_perm(const PermDesc* __restrict__ desc, const int64_t* __restrict__ tile_start,
@@ -215,15 +226,27 @@ __global__ void __launch_bounds__(PM_THREADS)
         rbase[r] = a;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < PM_TILE; e += PM_THREADS) {
+      // two neighbouring entries of a row per thread (ta is an even power of
+      // two, so a pair never straddles rows): one 2-wide load and store when
+      // both addresses are aligned to the pair, else two single entries
+      typedef typename Pair<T>::type T2;
+      for (int e = 2 * threadIdx.x; e < PM_TILE; e += 2 * PM_THREADS) {
         const int r = e >> lta, i = e & (ta - 1);
         const int64_t row = r0 + r, x = x0 + i;
         if (row >= D.rows || x >= dx) continue;
         const int64_t bi = D.boff + row * dx + x, si = D.moff + rbase[r] + x;
-        if (DIR == 0)
-          dst[si] = v * src[bi];
-        else
-          dst[bi] = v * src[si];
+        const T* sp = DIR == 0 ? src + bi : src + si;
+        T* dp = DIR == 0 ? dst + si : dst + bi;
+        if (x + 1 < dx && ((((uintptr_t)sp) | ((uintptr_t)dp)) & (sizeof(T2) - 1)) == 0) {
+          const T2 a = *(const T2*)sp;
+          T2 b;
+          b.x = v * a.x;
+          b.y = v * a.y;
+          *(T2*)dp = b;
+        } else {
+          dp[0] = v * sp[0];
+          if (x + 1 < dx) dp[1] = v * sp[1];
+        }
       }
     } else if (D.mode == 1) {
       const int y = D.y;

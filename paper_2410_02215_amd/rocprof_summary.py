@@ -33,7 +33,7 @@ CLASSES = [
     ("gemm_f32", re.compile(r"k_splitk_reduce<float"), False),
     ("gemm_bf16x3", re.compile(r"k_gemm_bf16x3"), True),
     ("permute", re.compile(r"k_block_perm<"), True),
-    ("factor", re.compile(r"k_jacobi_sweep|k_orth_factor"), True),
+    ("factor", re.compile(r"k_jacobi_sweep|k_orth_factor|k_svd_cols"), True),
     ("factor", re.compile(r"k_jacobi_vectors"), False),
     ("copy", re.compile(r"__amd_rocclr_copyBuffer"), True),
 ]

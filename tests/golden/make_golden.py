@@ -52,6 +52,18 @@ def main():
                          chi=cfg["chi"])
     out["c2_hop"] = dict(mantissa=m, exp2=e, path_sha=_hash(ph), chi=cfg["chi"], op_sites=list(cfg["op_sites"]),
                          seconds=time.time() - t0)
+    # the precision workload's structure on a 16-site (2 x 2 x 2 cells) diamond
+    # cluster at chi = 32: the largest cluster the oracle contracts in minutes
+    # (the 64-site chi = 128 workload is beyond it); bonds reach 700 per sector
+    # before compression
+    cfg = W.c3(cells=(2, 2, 2), chi=32)
+    spec = cfg["spec"]
+    kets = OP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"]))
+    p3 = W.norm_path(spec, chi=32, seed=0)
+    t0 = time.time()
+    m, e = network_value(OP.norm_network(spec, kets, conv="local"), p3, chi=32)
+    out["c3_222_norm"] = dict(mantissa=m, exp2=e, path_sha=_hash(p3), chi=32, cells=[2, 2, 2],
+                              seconds=time.time() - t0)
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({k: {kk: vv for kk, vv in v.items() if kk != "path"} for k, v in out.items()}, indent=1))

@@ -417,3 +417,45 @@ def test_precision_forms_on_a_u1u1_diamond_cluster(P):
     print("relative error vs the FP64 oracle on the rounded inputs: fp64 %.3g, fp32 %.3g, bf16x3 %.3g; "
           "vs the unrounded inputs: fp32 %.3g, bf16x3 %.3g"
           % (err64, errs["f32"], errs["bf16x3"], errs_in["f32"], errs_in["bf16x3"]))
+
+
+def test_precision_workload_on_a_16_site_cluster(P):
+    # the precision workload's structure (U(1)xU(1) diamond cluster, bond
+    # (0,0):4 plus four charged sectors of 1, compression as early as
+    # possible) on 2 x 2 x 2 cells (16 sites) at chi = 32, the largest cluster
+    # the oracle contracts in minutes (tests/golden/make_golden.py): FP64 path,
+    # then FP32 tensors with FP32 and split-BF16 block GEMMs (compression in
+    # FP64), each against the FP64 oracle value
+    import json, os, time
+    from paper_2410_02215_amd import peps as GP
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    gold = json.load(open(os.path.join(root, "tests", "golden", "values.json")))["c3_222_norm"]
+    ref = gold["mantissa"] * 2.0 ** gold["exp2"]
+    cfg = W.c3(cells=(2, 2, 2), chi=32)
+    spec = cfg["spec"]
+    vals = W.all_site_values(spec, cfg["seed"])
+    path = W.norm_path(spec, chi=32, seed=0)
+    gk = GP.ket_tensors(spec, vals)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    m, e, st = GP.norm_network(spec, gk).contract(path, chi=32)
+    t64 = time.time() - t0
+    assert st["compressions"] > 0
+    err64 = abs(_val(m, e) - ref) / abs(ref)
+    gk32 = []
+    for k in gk:
+        inf = k.info()
+        gk32.append(P.Tensor.create(inf["sym"], k.legs(), inf["total"], P.F32, data=k.data().float()))
+    errs, secs = {}, {}
+    for name, gemm in (("f32", P.GEMM_F32), ("bf16x3", P.GEMM_BF16X3)):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        m3, e3, _ = GP.norm_network(spec, gk32).contract(path, chi=32, gemm=gemm)
+        secs[name] = time.time() - t0
+        errs[name] = abs(_val(m3, e3) - ref) / abs(ref)
+    print("16-site U1xU1 cluster chi 32: relative error vs the FP64 oracle fp64 %.3g (%.2f s), fp32 %.3g (%.2f s), "
+          "bf16x3 %.3g (%.2f s); %d compressions" % (err64, t64, errs["f32"], secs["f32"], errs["bf16x3"],
+                                                     secs["bf16x3"], st["compressions"]))
+    assert err64 <= 1e-10, err64
+    assert errs["f32"] <= 1e-5, errs
+    assert errs["bf16x3"] <= 1e-3, errs
