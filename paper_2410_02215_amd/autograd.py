@@ -139,7 +139,7 @@ class _Compress(torch.autograd.Function):
         return da.data(), db.data(), None, None, None, None, None, None, None, None
 
 
-def compress(a, b, la, lb, chi, cutoff=1e-6, conv=ftn.LOCAL):
+def compress(a, b, la, lb, chi, cutoff=1e-12, conv=ftn.LOCAL):
     """Differentiable compress_bond of two FP64 DTensors (kept counts fixed).
 
     The backward pass is ``ftn_compress_bond_backward``, the derivative of
@@ -372,7 +372,7 @@ class _NetState:
                     lz, lw = self.shared(z, w)
                 dim = sum(T[z].legs[lz[0]][1])
                 if dim > chi and T[z].data.numel() and T[w].data.numel():
-                    T[z], T[w] = compress(T[z], T[w], lz[0], lw[0], chi, 1e-6, ftn.LOCAL)
+                    T[z], T[w] = compress(T[z], T[w], lz[0], lw[0], chi, 1e-12, ftn.LOCAL)
         m = float(T[z].data.detach().abs().max()) if T[z].data.numel() else 0.0
         if m > 0 and math.isfinite(m):
             ex = math.frexp(m)[1]
@@ -445,7 +445,7 @@ def contract(tensors, bonds, path, chi=None, order=None, gemm=ftn.GEMM_F64, chec
     a differentiable library call: pairwise ``dot`` over all shared bonds
     (paired in bond order), then for every neighbour (in creation order)
     the shared bonds fused into one and a bond larger than chi compressed
-    (cutoff 1e-6), then a rescaling by a power of two. Odd tensors carry
+    (cutoff 1e-12, as the library's network driver), then a rescaling by a power of two. Odd tensors carry
     dummy ranks (by ``order``) whose moves and final sort are a sign.
     Returns ``(T, labels, exp2)``: the final DTensor scaled by 2^-exp2 and
     the (tensor, leg) of each open leg.

@@ -1413,7 +1413,8 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
 //   iteration applying X^T and X alternately to a JMAX-column basis (each
 //   product scales the columns by s, not s^2), with one dropping
 //   Cholesky-QR after each product (two before each Rayleigh-Ritz step,
-//   every 8 iterations) until the leading Ritz values are stable (change
+//   every 4 iterations) until the Ritz values that can be kept (those among
+//   the chi + 8 largest over all sectors) are stable (change
 //   <= 1e-14 of the largest) or 96 iterations.
 static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, const std::vector<int64_t>& hoff,
                        const double* Xm, const std::vector<int64_t>& xoff, double* Em, const std::vector<int64_t>& eoff,
@@ -1511,7 +1512,36 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   orth(Pgq, Paq, q, qt);
   orth(Pgq, Paq, q, qt);
   std::vector<double> prev, cur(ni * p);
-  const int max_iter = 96, check = 8;
+  // values of the directly solved sectors (final): with the current Ritz
+  // values they decide which values can be kept, and only those (plus a
+  // margin of 8) have to converge
+  std::vector<double> dvals;
+  {
+    std::vector<double> hw;
+    for (int g : dir) {
+      hw.resize(S[g].p);
+      HIPC(hipMemcpyAsync(hw.data(), Lm + loff[g], S[g].p * 8, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      dvals.insert(dvals.end(), hw.begin(), hw.end());
+    }
+  }
+  auto needed = [&](const std::vector<double>& rv) {
+    // rv: Ritz values of the iterated sectors (p each, descending); returns
+    // per iterated sector how many of its leading values are within the
+    // chi + 8 largest of all sectors
+    std::vector<std::pair<double, int>> all;
+    for (double v : dvals) all.push_back({v, -1});
+    for (int t = 0; t < ni; ++t)
+      for (int j = 0; j < p; ++j) all.push_back({rv[t * p + j], t});
+    const size_t top = std::min<size_t>(all.size(), (size_t)std::max<int64_t>(chi, 0) + 8);
+    std::partial_sort(all.begin(), all.begin() + top, all.end(),
+                      [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+    std::vector<int> kk(ni, 0);
+    for (size_t i = 0; i < top; ++i)
+      if (all[i].second >= 0) ++kk[all[i].second];
+    return kk;
+  };
+  const int max_iter = 96, check = 4;
   int iters = 0;
   bool have_next = false;  // z already holds X^T q (computed for the last check)
   for (int k = 1; k <= max_iter; ++k) {
@@ -1533,8 +1563,9 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
       HIPC(hipStreamSynchronize(s));
       if (trace) rr_trace += " " + std::to_string(rr[0]);
       bool done = !prev.empty();
+      const std::vector<int> kks = needed(cur);
       for (int t = 0; t < ni && done; ++t) {
-        const int kk = (int)std::min<int64_t>(chi, p);
+        const int kk = std::min(kks[t], (int)p);
         const double top = std::max(cur[t * p], 1e-300);
         for (int j = 0; j < kk; ++j)
           if (std::fabs(cur[t * p + j] - prev[t * p + j]) > 1e-14 * top) done = false;

@@ -271,30 +271,66 @@ __global__ void __launch_bounds__(PM_THREADS)
       const int64_t bbase = D.boff + s_bb, sbase = D.moff + s_sb;
       const int64_t sby = D.sb[y], tsx = D.ts[0];
       const int ld = ta + 1, n = ta * tr;
-      // the block side is walked with leg 0 fastest, the strided side with leg y
+      // the block side is walked with leg 0 fastest, the strided side with leg y;
+      // each thread moves two neighbours along the contiguous direction of the
+      // side it touches (ta and tr are powers of two >= 2), with one 2-wide
+      // access when the pair is aligned
+      typedef typename Pair<T>::type T2;
+      auto ld2 = [](const T* p, bool two, T& a0, T& a1) {
+        if (two && (((uintptr_t)p) & (sizeof(T2) - 1)) == 0) {
+          const T2 t = *(const T2*)p;
+          a0 = t.x;
+          a1 = t.y;
+        } else {
+          a0 = p[0];
+          a1 = two ? p[1] : T(0);
+        }
+      };
+      auto st2 = [](T* p, bool two, T b0, T b1) {
+        if (two && (((uintptr_t)p) & (sizeof(T2) - 1)) == 0) {
+          T2 t;
+          t.x = b0;
+          t.y = b1;
+          *(T2*)p = t;
+        } else {
+          p[0] = b0;
+          if (two) p[1] = b1;
+        }
+      };
       if (DIR == 0) {
-        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
           const int r = e >> lta, i = e & (ta - 1);
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) tile[r * ld + i] = v * src[bbase + yy * sby + x];
+          if (yy < dy && x < dx) {
+            T a0, a1;
+            ld2(src + bbase + yy * sby + x, x + 1 < dx, a0, a1);
+            tile[r * ld + i] = v * a0;
+            tile[r * ld + i + 1] = v * a1;
+          }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
           const int r = e & (tr - 1), i = e >> ltr;
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) dst[sbase + yy + x * tsx] = tile[r * ld + i];
+          if (yy < dy && x < dx)
+            st2(dst + sbase + yy + x * tsx, yy + 1 < dy, tile[r * ld + i], tile[(r + 1) * ld + i]);
         }
       } else {
-        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
           const int r = e & (tr - 1), i = e >> ltr;
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) tile[r * ld + i] = v * src[sbase + yy + x * tsx];
+          if (yy < dy && x < dx) {
+            T a0, a1;
+            ld2(src + sbase + yy + x * tsx, yy + 1 < dy, a0, a1);
+            tile[r * ld + i] = v * a0;
+            tile[(r + 1) * ld + i] = v * a1;
+          }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < n; e += PM_THREADS) {
+        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
           const int r = e >> lta, i = e & (ta - 1);
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) dst[bbase + yy * sby + x] = tile[r * ld + i];
+          if (yy < dy && x < dx) st2(dst + bbase + yy * sby + x, x + 1 < dx, tile[r * ld + i], tile[r * ld + i + 1]);
         }
       }
     } else if (D.mode == 2) {
@@ -352,8 +388,18 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
     std::string sh, pm;
     for (int j = 0; j < S.ndim; ++j) sh += std::to_string(S.shapes[big * S.ndim + j]) + " ";
     for (int j = 0; j < p.op.ndim; ++j) pm += std::to_string(p.op.perm[j]) + " ";
-    std::fprintf(stderr, "[perm] dir %d nel %lld nblocks %lld nA %d nG %d perm [%s] biggest [%s]\n", dir,
-                 (long long)p.nelem, (long long)S.nblocks, p.op.nA, p.op.nG, pm.c_str(), sh.c_str());
+    // entries moved per copy mode (descriptors read back: trace runs only)
+    std::vector<PermDesc> hd(p.ntasks);
+    HIPC(hipMemcpyAsync(hd.data(), p.desc.p, p.ntasks * sizeof(PermDesc), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    int64_t em[4] = {0, 0, 0, 0}, dxs = 0;
+    for (auto& d : hd) {
+      em[d.mode & 3] += d.nel;
+      if (d.mode == 0) dxs += d.nel * d.dim[0];
+    }
+    std::fprintf(stderr, "[perm] dir %d nel %lld nblocks %lld nA %d nG %d perm [%s] biggest [%s] modes %lld %lld %lld "
+                 "row0 %.1f\n", dir, (long long)p.nelem, (long long)S.nblocks, p.op.nA, p.op.nG, pm.c_str(), sh.c_str(),
+                 (long long)em[0], (long long)em[1], (long long)em[2], em[0] ? (double)dxs / em[0] : 0.0);
   }
   void* tok = prof_begin(s);
   const dim3 grid((unsigned)p.ntiles), block(PM_THREADS);
