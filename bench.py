@@ -288,18 +288,25 @@ def main_gradient(args):
     gterms = [(AG.DTensor.from_tensor(GP.operator_tensor(spec, operator_dense(kind, "Z2"))), sites)
               for kind, sites in terms]
     nnet = len(terms) + 1
-    print("[bench] workload %s at chi %d: %d networks per gradient" % (cfg["name"], chi, nnet), file=sys.stderr,
-          flush=True)
+    wname = cfg["name"].replace("chi%d" % cfg["chi"], "chi%d" % chi)
+    print("[bench] workload %s: %d networks per gradient" % (wname, nnet), file=sys.stderr, flush=True)
 
     # recomputation checkpoints: by default one absorbed layer of the boundary
     # contraction per segment, so the stored tensors are the boundaries
     # between layers (the environments)
     ck = ly if args.checkpoint is None else (args.checkpoint or None)
 
+    gkets = GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"], std=cfg["std"]))
+    gops = [(GP.operator_tensor(spec, operator_dense(kind, "Z2")), sites) for kind, sites in terms]
+
     def step():
-        E = AG.expectation_ratio(spec, kets, gterms, paths, chi=chi, checkpoint=ck)
-        gs = torch.autograd.grad(E, [k.data for k in kets])
-        return float(E.detach()), gs
+        if args.autograd:
+            E = AG.expectation_ratio(spec, kets, gterms, paths, chi=chi, checkpoint=ck)
+            gs = torch.autograd.grad(E, [k.data for k in kets])
+            return float(E.detach()), gs
+        # the library's backward pass per network (ftn_contract_network_grad)
+        E, gt = GP.energy_gradient(spec, gkets, gops, paths, chi=chi, checkpoint=ck or 0)
+        return E, [g.data() for g in gt]
 
     for _ in range(args.warmup):
         E, _ = step()
@@ -324,9 +331,11 @@ def main_gradient(args):
         "value": nnet * args.steps / el, "unit": "contractions/s (forward + backward)", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg["name"].replace("chi%d" % cfg["chi"], "chi%d" % chi), "sites": spec.n_sites,
+        "config": {"workload": wname, "sites": spec.n_sites,
                    "chi": chi, "networks_per_gradient": nnet, "gradients_per_s": args.steps / el,
-                   "checkpoint_steps": ck or 0},
+                   "checkpoint_steps": ck or 0,
+                   "backward": "torch.autograd over the library's adjoints" if args.autograd
+                   else "library network backward (ftn_contract_network_grad)"},
         "peak_memory_gb": {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
                            "torch": torch.cuda.max_memory_allocated() / 1e9},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
@@ -389,6 +398,9 @@ def main():
                          "layer, 0: keep every intermediate)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
     ap.add_argument("--no-autotune", action="store_true", help="tile shapes from the built-in heuristic only")
+    ap.add_argument("--autograd", action="store_true",
+                    help="gradient workload: torch.autograd over the library's adjoints instead of the library's "
+                         "network backward pass")
     ap.add_argument("--save-tuning", default=None, help="write the autotuner's table to this JSON file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -115,6 +115,16 @@ int ftn_tensor_create(ftn_sym sym, ftn_dtype dtype, int ndim, const int32_t* nse
                       const uint8_t* dual, const int32_t* total_charge,
                       const void* src, ftn_stream_t stream, ftn_tensor_t* out);
 
+/* Same structure arguments; the tensor's block data are the caller's device
+   buffer dev_data (the documented layout, as many entries as the tensor
+   has), used in place without a copy: the buffer is borrowed, must stay
+   alive and unchanged while the handle or any tensor sharing its data (a
+   network built from it) is in use, and is never freed by the library. */
+int ftn_tensor_wrap(ftn_sym sym, ftn_dtype dtype, int ndim, const int32_t* nsect,
+                    const int32_t* charges, const int64_t* sect_dims, const uint8_t* dual,
+                    const int32_t* total_charge, void* dev_data, ftn_stream_t stream,
+                    ftn_tensor_t* out);
+
 /* Same structure arguments; the data are gathered on the device from a
    dense row-major array `dense` (device memory, same dtype as the tensor)
    whose leg index spaces are the leg's sectors concatenated in order.
@@ -146,6 +156,9 @@ int ftn_tensor_copy_data(ftn_tensor_t t, void* dst, ftn_stream_t stream);
 int ftn_tensor_cast(ftn_tensor_t t, ftn_dtype dtype, ftn_stream_t stream, ftn_tensor_t* out);
 /* out = alpha * t (alpha applied in the tensor's dtype). */
 int ftn_tensor_scale(ftn_tensor_t t, double alpha, ftn_stream_t stream, ftn_tensor_t* out);
+/* out = alpha * x + y (x and y of one structure and dtype), e.g. to combine
+   the gradients of several networks. */
+int ftn_tensor_axpy(double alpha, ftn_tensor_t x, ftn_tensor_t y, ftn_stream_t stream, ftn_tensor_t* out);
 int ftn_tensor_free(ftn_tensor_t t);
 
 /* ---------------------------------------------------------------------------
@@ -333,6 +346,24 @@ int ftn_net_free(ftn_net_t net);
 int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int64_t chi,
                          ftn_gemm gemm, ftn_stream_t stream, double* mantissa, int64_t* exp2,
                          ftn_tensor_t* open_out, int32_t* leg_src, double* stats);
+
+/* Value and reverse-mode derivative of a closed network in the local
+   convention (FP64 tensors, FTN_GEMM_F64; FTN_ENOTSUP otherwise): the same
+   steps as ftn_contract_network (contraction, fusion, compression as early as
+   possible with cutoff 1e-12, power-of-two rescaling), recorded and run
+   backwards through the adjoints of contraction (Eq. standardcontract is
+   bilinear), fusion (a signed permutation) and compression (the truncated-SVD
+   derivative of ftn_compress_bond_backward, kept counts fixed; bond sectors up
+   to 128), each rescaling by its own power of two, and the sign of the dummy
+   legs of odd tensors as a constant factor. value = mantissa * 2^exp2;
+   grads[t] (ntensors new handles, structure of tensor t) holds
+   d(value)/d(tensor t) * 2^-exp2. checkpoint = 0 keeps every intermediate for
+   the backward pass; checkpoint = s >= 1 keeps only the tensors alive at the
+   start of every s-th path step (the environments at the segment boundaries)
+   and recomputes one segment at a time during the backward pass. */
+int ftn_contract_network_grad(ftn_net_t net, int nsteps, const int32_t* ssa_path, int64_t chi,
+                              ftn_gemm gemm, int checkpoint, ftn_stream_t stream, double* mantissa,
+                              int64_t* exp2, ftn_tensor_t* grads);
 
 /* Amplitudes <n|psi> of a fermionic tensor network state (the coefficient
    tensor of the ket network, Secs. II.D-II.E): for every sample k,

@@ -67,9 +67,10 @@ class DTensor:
         return _parity(self.sym, self.total)
 
     def handle(self, data=None):
-        """An ftn.Tensor holding a copy of ``data`` (default: the current data)."""
+        """An ftn.Tensor over ``data`` (default: the current data) without a
+        copy (ftn_tensor_wrap); the wrapper keeps the torch tensor alive."""
         d = (self.data if data is None else data).detach().contiguous()
-        return ftn.Tensor.create(self.sym, self.legs, self.total, self.dtype, data=d)
+        return ftn.Tensor.wrap(self.sym, self.legs, self.total, d)
 
     @classmethod
     def from_tensor(cls, t, requires_grad=False):
@@ -89,14 +90,14 @@ class _Dot(torch.autograd.Function):
         out.append((C.legs(), inf["total"]))
         ctx.A, ctx.B = A, B
         ctx.args = (axes_a, axes_b, conv, gemm, a.sym, C.legs(), inf["total"], a.dtype)
-        return C.data()
+        return C.data_view()
 
     @staticmethod
     def backward(ctx, dc):
         axes_a, axes_b, conv, gemm, sym, legs, total, dtype = ctx.args
         DC = ftn.Tensor.create(sym, legs, total, dtype, data=dc.detach().contiguous())
         dA, dB = ftn.ftensordot_backward(ctx.A, ctx.B, DC, axes_a, axes_b, conv, gemm)
-        return dA.data(), dB.data(), None, None, None, None, None, None, None
+        return dA.data_view(), dB.data_view(), None, None, None, None, None, None, None
 
 
 class _Transpose(torch.autograd.Function):
@@ -105,7 +106,7 @@ class _Transpose(torch.autograd.Function):
         T = ftn.ftranspose(a.handle(data), perm)
         out.append(T.legs())
         ctx.a, ctx.perm = a, perm
-        return T.data()
+        return T.data_view()
 
     @staticmethod
     def backward(ctx, dt):
@@ -115,7 +116,7 @@ class _Transpose(torch.autograd.Function):
             inv[p] = i
         legs = [a.legs[p] for p in perm]
         D = ftn.Tensor.create(a.sym, legs, a.total, a.dtype, data=dt.detach().contiguous())
-        return ftn.ftranspose(D, inv).data(), None, None, None
+        return ftn.ftranspose(D, inv).data_view(), None, None, None
 
 
 class _Compress(torch.autograd.Function):
@@ -128,7 +129,7 @@ class _Compress(torch.autograd.Function):
         out.append((sa, sb))
         ctx.A, ctx.B = A, B
         ctx.args = (a.sym, la, lb, chi, cutoff, conv, sa, sb)
-        return A2.data(), B2.data()
+        return A2.data_view(), B2.data_view()
 
     @staticmethod
     def backward(ctx, dA2, dB2):

@@ -104,6 +104,25 @@ int ftn_tensor_create(ftn_sym sym, ftn_dtype dtype, int ndim, const int32_t* nse
   });
 }
 
+int ftn_tensor_wrap(ftn_sym sym, ftn_dtype dtype, int ndim, const int32_t* nsect, const int32_t* charges,
+                    const int64_t* sect_dims, const uint8_t* dual, const int32_t* total_charge, void* dev_data,
+                    ftn_stream_t stream, ftn_tensor_t* out) {
+  return guarded([&] {
+    if (!out || !total_charge) fail(FTN_EINVAL, "null argument");
+    auto legs = parse_legs(sym, ndim, nsect, charges, sect_dims, dual);
+    hipStream_t s = (hipStream_t)stream;
+    auto st = get_structure(sym, legs, Q{total_charge[0], total_charge[1]}, s);
+    if (st->size && !dev_data) fail(FTN_EINVAL, "null data for a tensor with entries");
+    if (dtype != FTN_F64 && dtype != FTN_F32) fail(FTN_EINVAL, "unknown dtype");
+    auto t = std::make_unique<Tensor>();
+    t->st = st;
+    t->dtype = dtype;
+    t->buf = std::shared_ptr<void>(dev_data, [](void*) {});  // borrowed: the caller keeps it alive
+    t->data = dev_data;
+    *out = wrap(std::move(t));
+  });
+}
+
 int ftn_tensor_from_dense(ftn_sym sym, ftn_dtype dtype, int ndim, const int32_t* nsect, const int32_t* charges,
                           const int64_t* sect_dims, const uint8_t* dual, const int32_t* total_charge,
                           const void* dense, ftn_stream_t stream, ftn_tensor_t* out) {
@@ -189,6 +208,13 @@ int ftn_tensor_scale(ftn_tensor_t t, double alpha, ftn_stream_t stream, ftn_tens
   return guarded([&] {
     if (!out) fail(FTN_EINVAL, "null out");
     *out = wrap(op_scale(T(t), alpha, (hipStream_t)stream));
+  });
+}
+
+int ftn_tensor_axpy(double alpha, ftn_tensor_t x, ftn_tensor_t y, ftn_stream_t stream, ftn_tensor_t* out) {
+  return guarded([&] {
+    if (!out) fail(FTN_EINVAL, "null out");
+    *out = wrap(op_axpy(alpha, T(x), T(y), (hipStream_t)stream));
   });
 }
 

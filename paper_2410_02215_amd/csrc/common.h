@@ -373,6 +373,8 @@ std::unique_ptr<Tensor> op_fuse(const Tensor& a, const std::vector<int>& legs, i
 std::unique_ptr<Tensor> op_fuse_backward(const Tensor& a, const std::vector<int>& glegs, int conv, int rev,
                                          const Tensor& dout, hipStream_t s);
 std::unique_ptr<Tensor> op_scale(const Tensor& a, double alpha, hipStream_t s);
+// alpha * x + y (same structure and dtype) as a new tensor
+std::unique_ptr<Tensor> op_axpy(double alpha, const Tensor& x, const Tensor& y, hipStream_t s);
 std::unique_ptr<Tensor> op_cast(const Tensor& a, int dtype, hipStream_t s);
 std::unique_ptr<Tensor> op_leg_sign(const Tensor& a, int leg, hipStream_t s);
 std::unique_ptr<Tensor> op_ftensordot(const Tensor& a, const Tensor& b, const std::vector<int>& axa,

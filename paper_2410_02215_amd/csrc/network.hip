@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <thread>
 
@@ -341,6 +342,328 @@ static void contract_net(const ftn_net* net, int nsteps, const int32_t* ssa_path
       }
     *open_out = make_handle(std::move(F));
   }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-mode derivative of a closed network's value (local convention).
+// The forward pass is the driver above, step for step, on reference-counted
+// tensors; with a tape it records every operation with its inputs: the
+// contraction, each fusion, each compression and the power-of-two rescaling
+// of the new tensor (its exponent kept on the device). The backward pass
+// walks the tape in reverse and maps cotangents through the adjoints of the
+// library: ftn_ftensordot_backward, ftn_fuse_backward,
+// ftn_compress_bond_backward (kept counts fixed), and the rescaling itself.
+// The signs of the dummy legs of odd tensors are a constant factor of the
+// value, applied to the seed. With recomputation checkpoints every
+// `checkpoint` path steps, the first pass keeps only the tensors alive at the
+// start of each segment (the environments at its boundary); the backward pass
+// recomputes one segment at a time with the tape on and passes the
+// cotangents of its boundary tensors to the segment before it. The kernels are
+// deterministic, so a recomputed segment reproduces the first pass.
+
+namespace {
+struct GState {
+  std::vector<std::shared_ptr<Tensor>> T;
+  std::vector<std::vector<Label>> L;
+  std::vector<std::vector<int>> D;
+  std::vector<int> alive, ssa;
+  int sgn = 0;
+  int next_bond = 0;
+};
+struct GOp {
+  int kind = 0;  // 0 contraction, 1 fusion, 2 compression, 3 rescaling
+  std::shared_ptr<Tensor> a, b, c, d;
+  std::vector<int> xa, xb;     // contracted axes (xa also: fused legs)
+  int la = 0, lb = 0;          // compressed bond legs
+  const int64_t* e = nullptr;  // rescaling: device exponent
+};
+
+template <typename T>
+__global__ void k_axpy_inplace(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+__global__ void k_scale_pow2_by(double* __restrict__ x, int64_t n, const int64_t* __restrict__ e) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = ldexp(x[i], (int)-*e);
+}
+}  // namespace
+
+static void gstep(GState& G, int k, int i, int j, int64_t chi, int gemm, hipStream_t s, int64_t* edev,
+                  std::vector<GOp>* tape) {
+  if (i < 0 || j < 0 || i >= (int)G.ssa.size() || j >= (int)G.ssa.size() || i == j)
+    fail(FTN_EINVAL, "bad SSA id in path step " + std::to_string(k));
+  const int x = G.ssa[i], y = G.ssa[j];
+  if (x < 0 || y < 0 || !G.alive[x] || !G.alive[y]) fail(FTN_EINVAL, "path uses a consumed tensor");
+  std::vector<int> ly;
+  std::vector<int> lx = shared_legs(G.L[x], G.L[y], ly);
+  std::shared_ptr<Tensor> Z(op_ftensordot(*G.T[x], *G.T[y], lx, ly, FTN_LOCAL, gemm, s, nullptr).release());
+  if (tape) {
+    GOp o;
+    o.kind = 0;
+    o.a = G.T[x];
+    o.b = G.T[y];
+    o.c = Z;
+    o.xa = lx;
+    o.xb = ly;
+    tape->push_back(o);
+  }
+  {
+    const std::vector<int>&dx = G.D[x], &dy = G.D[y];
+    int e = (int)((dx.size() & 1) & (dy.size() & 1));
+    for (int a : dx)
+      for (int b : dy) e ^= a > b ? 1 : 0;
+    G.sgn ^= e;
+    std::vector<int> dz(dx.size() + dy.size());
+    std::merge(dx.begin(), dx.end(), dy.begin(), dy.end(), dz.begin());
+    G.D.push_back(dz);
+    G.D[x].clear();
+    G.D[y].clear();
+  }
+  std::vector<Label> lz;
+  for (int q = 0; q < (int)G.L[x].size(); ++q)
+    if (std::find(lx.begin(), lx.end(), q) == lx.end()) lz.push_back(G.L[x][q]);
+  for (int q = 0; q < (int)G.L[y].size(); ++q)
+    if (std::find(ly.begin(), ly.end(), q) == ly.end()) lz.push_back(G.L[y][q]);
+  const int z = (int)G.T.size();
+  G.T.push_back(Z);
+  G.L.push_back(lz);
+  G.alive.push_back(1);
+  G.alive[x] = G.alive[y] = 0;
+  G.T[x].reset();
+  G.T[y].reset();
+  G.ssa[i] = G.ssa[j] = -1;
+  G.ssa.push_back(z);
+  if (chi > 0) {
+    std::vector<int> nbs;
+    for (int w = 0; w < (int)G.T.size(); ++w) {
+      if (w == z || !G.alive[w]) continue;
+      std::vector<int> tmp;
+      if (!shared_legs(G.L[z], G.L[w], tmp).empty()) nbs.push_back(w);
+    }
+    for (int w : nbs) {
+      std::vector<int> lw;
+      std::vector<int> lzs = shared_legs(G.L[z], G.L[w], lw);
+      if (lzs.size() > 1) {
+        std::shared_ptr<Tensor> Zf(op_fuse(*G.T[z], lzs, FTN_LOCAL, 0, s).release());
+        std::shared_ptr<Tensor> Wf(op_fuse(*G.T[w], lw, FTN_LOCAL, 0, s).release());
+        if (tape) {
+          GOp o;
+          o.kind = 1;
+          o.a = G.T[z];
+          o.c = Zf;
+          o.xa = lzs;
+          tape->push_back(o);
+          o.a = G.T[w];
+          o.c = Wf;
+          o.xa = lw;
+          tape->push_back(o);
+        }
+        Label nb{0, G.next_bond++, 0};
+        auto relabel = [&](std::vector<Label>& lab, const std::vector<int>& legs) {
+          std::vector<Label> rest;
+          int pos = 0;
+          for (int q = 0; q < (int)lab.size(); ++q) {
+            if (std::find(legs.begin(), legs.end(), q) != legs.end()) continue;
+            if (q < legs[0]) ++pos;
+            rest.push_back(lab[q]);
+          }
+          rest.insert(rest.begin() + pos, nb);
+          lab = rest;
+        };
+        relabel(G.L[z], lzs);
+        relabel(G.L[w], lw);
+        G.T[z] = Zf;
+        G.T[w] = Wf;
+        lzs = shared_legs(G.L[z], G.L[w], lw);
+      }
+      const int64_t dim = G.T[z]->legs()[lzs[0]].size();
+      if (dim > chi && G.T[z]->size() > 0 && G.T[w]->size() > 0) {
+        CompressResult r = op_compress_bond(*G.T[z], *G.T[w], lzs[0], lw[0], chi, NET_CUTOFF, FTN_LOCAL, s);
+        std::shared_ptr<Tensor> Zc(r.a.release()), Wc(r.b.release());
+        if (tape) {
+          GOp o;
+          o.kind = 2;
+          o.a = G.T[z];
+          o.b = G.T[w];
+          o.c = Zc;
+          o.d = Wc;
+          o.la = lzs[0];
+          o.lb = lw[0];
+          tape->push_back(o);
+        }
+        G.T[z] = Zc;
+        G.T[w] = Wc;
+      }
+    }
+  }
+  normalise_pow2(*G.T[z], edev, s);
+  if (tape) {
+    GOp o;
+    o.kind = 3;
+    o.a = G.T[z];
+    o.e = edev;
+    tape->push_back(o);
+  }
+}
+
+static void add_into(std::unordered_map<const Tensor*, std::shared_ptr<Tensor>>& cot, const Tensor* key,
+                     std::unique_ptr<Tensor> v, hipStream_t s) {
+  auto it = cot.find(key);
+  if (it == cot.end()) {
+    cot.emplace(key, std::shared_ptr<Tensor>(v.release()));
+    return;
+  }
+  Tensor& y = *it->second;
+  if (y.st->skey != v->st->skey) fail(FTN_EINVAL, "internal: cotangent structures differ");
+  const int64_t n = y.size();
+  if (n)
+    LAUNCH(k_axpy_inplace<double>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, (double*)y.data,
+           (const double*)v->data, n);
+  HIPC(hipGetLastError());
+}
+
+// cotangents of the tape's inputs from those of its outputs (in cot)
+static void backprop(const std::vector<GOp>& tape, std::unordered_map<const Tensor*, std::shared_ptr<Tensor>>& cot,
+                     int64_t chi, int gemm, hipStream_t s) {
+  for (auto it = tape.rbegin(); it != tape.rend(); ++it) {
+    const GOp& o = *it;
+    if (o.kind == 3) {
+      auto f = cot.find(o.a.get());
+      if (f != cot.end() && f->second->size())
+        LAUNCH(k_scale_pow2_by, dim3((unsigned)cdiv(f->second->size(), 256)), dim3(256), 0, s,
+               (double*)f->second->data, f->second->size(), o.e);
+      HIPC(hipGetLastError());
+      continue;
+    }
+    auto fc = cot.find(o.c.get());
+    std::shared_ptr<Tensor> dc = fc == cot.end() ? nullptr : fc->second;
+    std::shared_ptr<Tensor> dd;
+    if (o.kind == 2) {
+      auto fd = cot.find(o.d.get());
+      if (fd != cot.end()) dd = fd->second;
+    }
+    if (!dc && !dd) continue;
+    if (o.kind == 0) {
+      std::unique_ptr<Tensor> da, db;
+      op_ftensordot_backward(*o.a, *o.b, *dc, o.xa, o.xb, FTN_LOCAL, gemm, s, da, db);
+      add_into(cot, o.a.get(), std::move(da), s);
+      add_into(cot, o.b.get(), std::move(db), s);
+    } else if (o.kind == 1) {
+      add_into(cot, o.a.get(), op_fuse_backward(*o.a, o.xa, FTN_LOCAL, 0, *dc, s), s);
+    } else {
+      if (!dc) dc.reset(make_tensor(o.c->st, FTN_F64, s, true).release());
+      if (!dd) dd.reset(make_tensor(o.d->st, FTN_F64, s, true).release());
+      std::unique_ptr<Tensor> da, db;
+      op_compress_bond_backward(*o.a, *o.b, o.la, o.lb, chi, NET_CUTOFF, FTN_LOCAL, *dc, *dd, s, da, db);
+      add_into(cot, o.a.get(), std::move(da), s);
+      add_into(cot, o.b.get(), std::move(db), s);
+      cot.erase(o.d.get());
+    }
+    cot.erase(o.c.get());
+  }
+}
+
+static void net_grad(const ftn_net* net, int nsteps, const int32_t* ssa_path, int64_t chi, int gemm, int checkpoint,
+                     hipStream_t s, double* mantissa, int64_t* exp2, std::vector<std::unique_ptr<Tensor>>& grads) {
+  if (!net || (nsteps && !ssa_path)) fail(FTN_EINVAL, "bad arguments");
+  const int n = net->n;
+  if (nsteps != n - 1) fail(FTN_EINVAL, "a path over n tensors has n-1 steps");
+  if (gemm != FTN_GEMM_F64) fail(FTN_ENOTSUP, "network gradients need the FP64 GEMM form");
+  if (checkpoint < 0) fail(FTN_EINVAL, "checkpoint must be >= 0");
+  GState G;
+  for (int t = 0; t < n; ++t) {
+    if (net->T[t]->dtype != FTN_F64) fail(FTN_ENOTSUP, "network gradients need FP64 tensors");
+    G.T.push_back(std::shared_ptr<Tensor>(share_tensor(*net->T[t], net->T[t]->st).release()));
+    G.L.push_back(net->lab[t]);
+    G.D.push_back(net->dummy_rank[t] >= 0 ? std::vector<int>{net->dummy_rank[t]} : std::vector<int>{});
+    G.alive.push_back(1);
+    G.ssa.push_back(t);
+  }
+  G.next_bond = net->nbonds;
+  const int seg = (checkpoint > 0 && checkpoint < nsteps) ? checkpoint : std::max(nsteps, 1);
+  const bool recompute = seg < nsteps;
+  DBuf<int64_t> edev(std::max(nsteps, 1), s);
+  HIPC(hipMemsetAsync(edev.p, 0, std::max(nsteps, 1) * sizeof(int64_t), s));
+  std::vector<GState> starts;
+  std::vector<GOp> tape;
+  for (int k = 0; k < nsteps; ++k) {
+    if (k % seg == 0) starts.push_back(G);
+    gstep(G, k, ssa_path[2 * k], ssa_path[2 * k + 1], chi, gemm, s, edev.p + k, recompute ? nullptr : &tape);
+  }
+  if (nsteps == 0) starts.push_back(G);
+  int fin = -1;
+  for (int t = 0; t < (int)G.T.size(); ++t)
+    if (G.alive[t]) {
+      if (fin >= 0) fail(FTN_EINVAL, "path does not contract the network to one tensor");
+      fin = t;
+    }
+  const Tensor& F = *G.T[fin];
+  if (F.ndim() != 0) fail(FTN_ENOTSUP, "network gradients need a closed network (a scalar value)");
+  const int64_t m = (int64_t)G.D[fin].size();
+  const double sign = (((m * (m - 1) / 2) & 1) ^ G.sgn) ? -1.0 : 1.0;
+  std::vector<int64_t> eh(std::max(nsteps, 1), 0);
+  double v = 0.0;
+  HIPC(hipMemcpyAsync(eh.data(), edev.p, eh.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  if (F.size()) HIPC(hipMemcpyAsync(&v, F.data, 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  int64_t e2 = 0;
+  for (int k = 0; k < nsteps; ++k) e2 += eh[k];
+  if (mantissa) *mantissa = sign * v;
+  if (exp2) *exp2 = e2;
+  // cotangents of the tensors alive at a segment boundary, by slot
+  std::map<int, std::shared_ptr<Tensor>> bcot;
+  if (F.size()) {
+    std::shared_ptr<Tensor> seed(make_tensor(F.st, FTN_F64, s, false).release());
+    h2d(seed->data, &sign, 8, s);
+    bcot[fin] = seed;
+  }
+  const int nseg = (int)starts.size();
+  DBuf<int64_t> edev2(recompute ? std::max(nsteps, 1) : 1, s);
+  for (int g = nseg - 1; g >= 0 && !bcot.empty(); --g) {
+    const int k0 = g * seg, k1 = std::min(nsteps, k0 + seg);
+    const GState* end = &G;
+    GState G2;
+    if (recompute) {
+      G2 = starts[g];
+      tape.clear();
+      HIPC(hipMemsetAsync(edev2.p + k0, 0, (k1 - k0) * sizeof(int64_t), s));
+      for (int k = k0; k < k1; ++k)
+        gstep(G2, k, ssa_path[2 * k], ssa_path[2 * k + 1], chi, gemm, s, edev2.p + k, &tape);
+      end = &G2;
+    }
+    std::unordered_map<const Tensor*, std::shared_ptr<Tensor>> cot;
+    for (auto& kv : bcot) cot[end->T[kv.first].get()] = kv.second;
+    bcot.clear();
+    backprop(tape, cot, chi, gemm, s);
+    tape.clear();
+    const GState& S0 = starts[g];
+    for (int t = 0; t < (int)S0.T.size(); ++t) {
+      if (!S0.alive[t] || !S0.T[t]) continue;
+      auto f = cot.find(S0.T[t].get());
+      if (f != cot.end()) bcot[t] = f->second;
+    }
+  }
+  grads.clear();
+  for (int t = 0; t < n; ++t) {
+    auto f = bcot.find(t);
+    if (f != bcot.end() && f->second->st->skey == net->T[t]->st->skey) {
+      grads.push_back(share_tensor(*f->second, f->second->st));
+    } else {
+      grads.push_back(make_tensor(net->T[t]->st, FTN_F64, s, true));
+    }
+  }
+}
+
+extern "C" int ftn_contract_network_grad(ftn_net_t net, int nsteps, const int32_t* ssa_path, int64_t chi,
+                                         ftn_gemm gemm, int checkpoint, ftn_stream_t stream, double* mantissa,
+                                         int64_t* exp2, ftn_tensor_t* grads) {
+  return guarded_net([&] {
+    if (!net || !grads) fail(FTN_EINVAL, "null argument");
+    std::vector<std::unique_ptr<Tensor>> g;
+    net_grad(net, nsteps, ssa_path, chi, gemm, checkpoint, (hipStream_t)stream, mantissa, exp2, g);
+    for (size_t t = 0; t < g.size(); ++t) grads[t] = make_handle(std::move(g[t]));
+  });
 }
 
 extern "C" int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int64_t chi,

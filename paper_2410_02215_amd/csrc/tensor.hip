@@ -788,6 +788,28 @@ void normalise_pow2(Tensor& t, int64_t* e2, hipStream_t s) {
   HIPC(hipGetLastError());
 }
 
+template <typename T>
+__global__ void k_axpy(T* __restrict__ y, const T* __restrict__ x, int64_t n, T alpha) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += alpha * x[i];
+}
+
+std::unique_ptr<Tensor> op_axpy(double alpha, const Tensor& x, const Tensor& y, hipStream_t s) {
+  if (x.st->skey != y.st->skey) fail(FTN_EINVAL, "axpy: the tensors must have the same structure");
+  if (x.dtype != y.dtype) fail(FTN_ENOTSUP, "axpy: the tensors must have the same dtype");
+  auto out = make_tensor(y.st, y.dtype, s, false);
+  const int64_t n = y.size();
+  if (!n) return out;
+  HIPC(hipMemcpyAsync(out->data, y.data, n * y.esize(), hipMemcpyDeviceToDevice, s));
+  const dim3 g((unsigned)cdiv(n, 256));
+  if (y.dtype == FTN_F64)
+    LAUNCH(k_axpy<double>, g, dim3(256), 0, s, (double*)out->data, (const double*)x.data, n, alpha);
+  else
+    LAUNCH(k_axpy<float>, g, dim3(256), 0, s, (float*)out->data, (const float*)x.data, n, (float)alpha);
+  HIPC(hipGetLastError());
+  return out;
+}
+
 void scale_inplace(Tensor& t, double alpha, hipStream_t s) {
   int64_t n = t.size();
   if (!n) return;

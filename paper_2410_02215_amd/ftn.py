@@ -41,6 +41,7 @@ SIGNATURES = [
     ("ftn_version", ctypes.c_char_p, []),
     ("ftn_set_allocator", _I, [_P, _P, _P]),
     ("ftn_tensor_create", _I, [_I, _I, _I, _PI32, _PI32, _PI64, _PU8, _PI32, _P, _P, _PP]),
+    ("ftn_tensor_wrap", _I, [_I, _I, _I, _PI32, _PI32, _PI64, _PU8, _PI32, _P, _P, _PP]),
     ("ftn_tensor_from_dense", _I, [_I, _I, _I, _PI32, _PI32, _PI64, _PU8, _PI32, _P, _P, _PP]),
     ("ftn_tensor_to_dense", _I, [_P, _P, _P]),
     ("ftn_tensor_info", _I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), _PI64, _PI64, _PI32]),
@@ -50,6 +51,7 @@ SIGNATURES = [
     ("ftn_tensor_copy_data", _I, [_P, _P, _P]),
     ("ftn_tensor_cast", _I, [_P, _I, _P, _PP]),
     ("ftn_tensor_scale", _I, [_P, _D, _P, _PP]),
+    ("ftn_tensor_axpy", _I, [_D, _P, _P, _P, _PP]),
     ("ftn_tensor_free", _I, [_P]),
     ("ftn_ftranspose", _I, [_P, _PI32, _P, _PP]),
     ("ftn_flip_dual", _I, [_P, _I, _I, _P, _PP]),
@@ -64,6 +66,7 @@ SIGNATURES = [
     ("ftn_net_create", _I, [_I, _PP, _I, _PI32, _I, _PI32, _PP]),
     ("ftn_net_free", _I, [_P]),
     ("ftn_contract_network", _I, [_P, _I, _PI32, _I64, _I, _P, _PD, _PI64, _PP, _PI32, _PD]),
+    ("ftn_contract_network_grad", _I, [_P, _I, _PI32, _I64, _I, _I, _P, _PD, _PI64, _PP]),
     ("ftn_amplitudes", _I, [_I, _PP, _I, _PI32, _I, _PI32, _I64, _I, _I64, _PI32, _I, _P, _PD, _PI64]),
     ("ftn_autotune", _I, [_I]),
     ("ftn_autotune_load", _I, [ctypes.c_char_p]),
@@ -213,6 +216,16 @@ def _total(total):
     return _arr([t[0], t[1] if len(t) > 1 else 0], ctypes.c_int32)
 
 
+class _DeviceArray:
+    """A library buffer exposed through the CUDA array interface; holds the
+    tensor wrapper that owns the buffer."""
+
+    def __init__(self, owner, ptr, n, typestr):
+        self.owner = owner
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
 class Tensor:
     """Owning wrapper of an ftn_tensor_t handle."""
 
@@ -255,6 +268,23 @@ class Tensor:
         _check(_lib.ftn_tensor_create(sym, dtype, len(legs), ns, ch, dm, du, _total(total), src,
                                       _stream(), ctypes.byref(out)))
         return cls(out)
+
+    @classmethod
+    def wrap(cls, sym, legs, total, data):
+        """A tensor whose block data are ``data`` (a contiguous device torch
+        tensor, float64 or float32), without a copy; ``data`` is kept alive by
+        the returned wrapper."""
+        load_library()
+        if not data.is_contiguous():
+            raise ValueError("wrap needs contiguous data")
+        ns, ch, dm, du = _legs_args(sym, legs)
+        out = ctypes.c_void_p()
+        dtype = F64 if data.dtype == __import__("torch").float64 else F32
+        _check(_lib.ftn_tensor_wrap(sym, dtype, len(legs), ns, ch, dm, du, _total(total),
+                                    ctypes.c_void_p(data.data_ptr()), _stream(), ctypes.byref(out)))
+        t = cls(out)
+        t._keep = data
+        return t
 
     # --- queries ---------------------------------------------------------
     def info(self):
@@ -308,6 +338,19 @@ class Tensor:
             _check(_lib.ftn_tensor_copy_data(self.h, ctypes.c_void_p(out.data_ptr()), _stream()))
         return out
 
+    def data_view(self):
+        """The block data as a torch device tensor without a copy (the
+        library's buffer, kept alive by the returned tensor)."""
+        import torch
+        inf = self.info()
+        dt = torch.float64 if inf["dtype"] == F64 else torch.float32
+        if inf["size"] == 0:
+            return torch.empty(0, dtype=dt, device="cuda")
+        p = ctypes.c_void_p()
+        _check(_lib.ftn_tensor_data(self.h, ctypes.byref(p)))
+        return torch.as_tensor(_DeviceArray(self, p.value, inf["size"], "<f8" if inf["dtype"] == F64 else "<f4"),
+                               device="cuda")
+
     def to_dense(self):
         import torch
         inf = self.info()
@@ -326,6 +369,13 @@ class Tensor:
         out = ctypes.c_void_p()
         _check(_lib.ftn_tensor_scale(self.h, float(alpha), _stream(), ctypes.byref(out)))
         return Tensor(out)
+
+
+def axpy(alpha, x, y):
+    """alpha * x + y as a new tensor (same structure and dtype)."""
+    out = ctypes.c_void_p()
+    _check(_lib.ftn_tensor_axpy(float(alpha), x.h, y.h, _stream(), ctypes.byref(out)))
+    return Tensor(out)
 
 
 def ftranspose(a, perm):
@@ -446,6 +496,26 @@ class Network:
             n = t.ndim
             return t, e.value, [(src[2 * k], src[2 * k + 1]) for k in range(n)], stats
         return m.value, e.value, stats
+
+
+def _network_grad(self, path, chi=0, checkpoint=0):
+    """(mantissa, exp2, grads) of a closed network: value = m * 2**e and
+    grads[t] = d(value)/d(tensor t) * 2**-e, computed by the library's
+    backward pass (checkpoint: path steps per recomputation segment, 0 keeps
+    every intermediate)."""
+    flat = []
+    for (i, j) in path:
+        flat += [int(i), int(j)]
+    m = ctypes.c_double()
+    e = ctypes.c_int64()
+    n = len(self.tensors)
+    gh = (ctypes.c_void_p * n)()
+    _check(_lib.ftn_contract_network_grad(self.h, len(path), _arr(flat, ctypes.c_int32), int(chi or 0), GEMM_F64,
+                                          int(checkpoint), _stream(), ctypes.byref(m), ctypes.byref(e), gh))
+    return m.value, e.value, [Tensor(ctypes.c_void_p(gh[t])) for t in range(n)]
+
+
+Network.contract_grad = _network_grad
 
 
 def amplitudes(sites, bonds, path, configs, chi=0, gemm=GEMM_F64, nworkers=8):

@@ -53,3 +53,45 @@ def norm_network(spec, kets, op=None, op_sites=None, conv=ftn.LOCAL):
              norm_network_bonds(spec, op_sites if op is not None else None)]
     pos = norm_network_positions(n, op is not None)
     return Network(tensors, bonds, conv=conv, positions=pos)
+
+
+def energy_gradient(spec, kets, terms, paths, chi=0, checkpoint=0):
+    """E = sum_t <psi|G_t|psi> / <psi|psi> and dE/d(ket tensors), by the
+    library's network backward pass (ftn_contract_network_grad).
+
+    ``terms``: list of (G Tensor, (u, v)); ``paths``: {None: norm path,
+    (u, v): path of that term}. Each network is <psi|psi> or <psi|G_t|psi>
+    with the bras made by ftn_dagger from the kets; the gradient of a network
+    with respect to a ket collects its ket slot and, through the adjoint of
+    the Hermitian conjugate (the same relabelling: ftn_dagger), its bra slot.
+    With N = <psi|psi> and X_t the terms, dE = sum_t dX_t / N - E dN / N; the
+    combination is a sequence of ftn_tensor_axpy calls with scalar weights.
+    Returns (E, [gradient Tensor per ket]).
+    """
+    n = spec.n_sites
+
+    def value_and_ket_grads(op, sites):
+        net = norm_network(spec, kets, op=op, op_sites=sites)
+        m, e, g = net.contract_grad(paths[tuple(sites) if sites is not None else None], chi=chi,
+                                    checkpoint=checkpoint)
+        # slots: bra s -> s, ket s -> n + s
+        return m, e, [ftn.axpy(1.0, dagger(g[s]), g[n + s]) for s in range(n)]
+
+    mN, eN, gN = value_and_ket_grads(None, None)
+    if mN == 0.0:
+        raise ValueError("the norm network is zero")
+    E = 0.0
+    acc = [ftn.axpy(-1.0, gN[s], gN[s]) for s in range(n)]  # zero tensors of the ket structures
+    parts = []
+    for G, sites in terms:
+        m, e, g = value_and_ket_grads(G, tuple(sites))
+        w = 2.0 ** (e - eN) / mN            # dX_t / N in units of the returned gradients
+        E += m * 2.0 ** (e - eN) / mN
+        parts.append((w, g))
+    for w, g in parts:
+        for s in range(n):
+            acc[s] = ftn.axpy(w, g[s], acc[s])
+    # - E dN / N
+    for s in range(n):
+        acc[s] = ftn.axpy(-E / mN, gN[s], acc[s])
+    return E, acc

@@ -145,6 +145,15 @@ def test_network_gradient_matches_oracle(P, sym):
             r = flat_blocks(grads[t])
             err = np.abs(gs[t].double().cpu().numpy() - r).max(initial=0)
             assert err <= 1e-11 * max(1.0, np.abs(r).max(initial=0)), (t, err)
+        # exact contraction through the library's backward pass (odd tensors:
+        # the dummy-leg sign is part of the seed)
+        gnet = P.Network([to_gpu(tensors[t]) for t in range(n)], bonds, conv=P.LOCAL, positions=order)
+        m2, e2n, ng = gnet.contract_grad(path, chi=0, checkpoint=1)
+        assert abs(m2 * 2.0 ** e2n - v) <= 1e-11 * max(1.0, abs(v))
+        for t in range(n):
+            r = flat_blocks(grads[t])
+            err = np.abs(ng[t].data().cpu().numpy() * 2.0 ** e2n - r).max(initial=0)
+            assert err <= 1e-11 * max(1.0, np.abs(r).max(initial=0)), (t, err)
         done += 1
 
 
@@ -250,6 +259,17 @@ def _net_grad_case(P, tensors, bonds, path, pos, chi, tol):
         g = gs[t].double().cpu().numpy() * 2.0 ** e2
         err = np.abs(g - r).max(initial=0)
         assert err <= tol * max(1e-300, np.abs(r).max(initial=0)), (t, err, np.abs(r).max(initial=0))
+    # the library's own backward pass, keeping every intermediate and with
+    # recomputation segments of two path steps
+    gnet = P.Network([to_gpu(tensors[t]) for t in range(n)], bonds, conv=P.LOCAL, positions=pos)
+    for ck in (0, 2):
+        m2, e2n, ng = gnet.contract_grad(path, chi=chi or 0, checkpoint=ck)
+        assert abs(m2 * 2.0 ** e2n - v) <= tol * max(abs(v), 1e-300), (ck, m2 * 2.0 ** e2n, v)
+        for t in range(n):
+            r = flat_blocks(grads[t])
+            g = ng[t].data().cpu().numpy() * 2.0 ** e2n
+            err = np.abs(g - r).max(initial=0)
+            assert err <= tol * max(1e-300, np.abs(r).max(initial=0)), (ck, t, err, np.abs(r).max(initial=0))
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -347,6 +367,17 @@ def test_hubbard_energy_gradient_matches_oracle(P, shape, d, chi):
         r = flat_blocks(grads[s])
         err = np.abs(gs[s].double().cpu().numpy() - r).max(initial=0)
         assert err <= 1e-7 * max(1e-300, np.abs(r).max(initial=0)), (s, err)
+    # the library's backward pass per network, combined by ftn_tensor_axpy,
+    # with every intermediate kept and with recomputation segments of 3 steps
+    gk = [to_gpu(k) for k in kets]
+    gops = [(GP.operator_tensor(spec, operator_dense(kind, "Z2")), sites) for kind, sites in W.hubbard_terms(spec)]
+    for ck in (0, 3):
+        En, gn = GP.energy_gradient(spec, gk, gops, paths, chi=chi or 0, checkpoint=ck)
+        assert abs(En - E) <= 1e-9 * abs(E), (ck, En, E)
+        for s in range(len(kets)):
+            r = flat_blocks(grads[s])
+            err = np.abs(gn[s].data().cpu().numpy() - r).max(initial=0)
+            assert err <= 1e-7 * max(1e-300, np.abs(r).max(initial=0)), (ck, s, err)
 
 
 @pytest.mark.parametrize("ck", [1, 4])
