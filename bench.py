@@ -263,9 +263,6 @@ def main_amplitudes(args):
     print(json.dumps(out), flush=True)
 
 
-GRAD_CHI = 16  # bond sectors of the operator terms stay within the 128 the compression adjoint handles
-
-
 def main_gradient(args):
     """Energy-gradient workload: a step is one gradient of
     E = sum_t <psi|h_t|psi> / <psi|psi> (Hubbard, t = 1, U = 8) with respect
@@ -277,7 +274,7 @@ def main_gradient(args):
     from synth.operators import operator_dense
     cfg = W.c5()
     spec = cfg["spec"]
-    chi = GRAD_CHI
+    chi = args.chi or cfg["chi"]
     lx, ly = cfg["lx"], cfg["ly"]
     kets = [AG.DTensor.from_tensor(k, requires_grad=True)
             for k in GP.ket_tensors(spec, W.all_site_values(spec, cfg["seed"], std=cfg["std"]))]
@@ -396,6 +393,7 @@ def main():
     ap.add_argument("--checkpoint", type=int, default=None,
                     help="path steps per recomputation segment (gradient workload; default: one lattice "
                          "layer, 0: keep every intermediate)")
+    ap.add_argument("--chi", type=int, default=0, help="bond dimension of the gradient workload (default: 32)")
     ap.add_argument("--cpu-samples", type=int, default=12, help="oracle amplitudes timed (amplitude workload)")
     ap.add_argument("--no-autotune", action="store_true", help="tile shapes from the built-in heuristic only")
     ap.add_argument("--autograd", action="store_true",

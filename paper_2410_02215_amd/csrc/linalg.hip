@@ -903,6 +903,273 @@ static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>*
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric eigendecomposition of orders 129 to 1024 by block Jacobi. The
+// indices are cut into nb = 2 ceil(n / 128) contiguous blocks of near-equal
+// size (at most 64 each), and a sweep meets every two blocks once (a
+// round-robin tournament over the blocks: nb / 2 disjoint pairs per round).
+// In a round the principal submatrix of every pair (order at most 128) is
+// diagonalised completely by the LDS eigensolver above; the pairs'
+// eigenvector matrices, embedded in one orthogonal Q, then rotate the whole
+// matrix, H <- Q^T H Q, and the accumulated vectors, V <- V Q (dense FP64
+// GEMMs). Sweeps repeat until the off-diagonal Frobenius norm is at most
+// 8 n u of the matrix's (each rotation of the whole matrix rounds every entry
+// by about u |H|, so smaller targets are out of reach), at most 40 sweeps.
+// Outputs as jacobi_eig's: values descending (ties: lower index first) and
+// the matching eigenvectors as columns.
+constexpr int EIG_BIG_MAX = 1024;
+constexpr int BLK_SWEEPS = 40;
+
+struct BlkPair {
+  const double* H;  // n x n matrix being diagonalised
+  double* sub;      // ns x ns principal submatrix of the pair (rows of block i, then block j)
+  const double* vs; // ns x ns eigenvectors of sub (columns)
+  double* Q;        // n x n rotation of this round
+  int n, i0, i1, j0, j1;
+};
+
+__device__ inline int blk_index(const BlkPair& P, int a) {
+  const int ni = P.i1 - P.i0;
+  return a < ni ? P.i0 + a : P.j0 + a - ni;
+}
+
+// grid (chunks, pairs)
+__global__ void k_blk_gather(const BlkPair* pairs) {
+  const BlkPair P = pairs[blockIdx.y];
+  const int ns = (P.i1 - P.i0) + (P.j1 - P.j0);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ns * ns; e += gridDim.x * blockDim.x) {
+    const int a = e / ns, b = e % ns;
+    P.sub[e] = P.H[(int64_t)blk_index(P, a) * P.n + blk_index(P, b)];
+  }
+}
+
+// rows of Q that belong to the pair, written in full (zero outside the
+// pair's columns), so that the pairs of a round cover all of Q
+__global__ void k_blk_scatter(const BlkPair* pairs) {
+  const BlkPair P = pairs[blockIdx.y];
+  const int ni = P.i1 - P.i0, ns = ni + (P.j1 - P.j0), n = P.n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)ns * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / n), c = (int)(e % n);
+    int b = -1;
+    if (c >= P.i0 && c < P.i1) b = c - P.i0;
+    else if (c >= P.j0 && c < P.j1) b = ni + c - P.j0;
+    P.Q[(int64_t)blk_index(P, a) * n + c] = b >= 0 ? P.vs[(int64_t)a * ns + b] : 0.0;
+  }
+}
+
+struct BlkMat {
+  const double* H;  // n x n
+  const double* V;  // n x n accumulated vectors
+  double* Vout;     // n x n eigenvectors by rank (EigJob.V)
+  double* W;        // n values by rank (EigJob.W)
+  double* norms;    // 2: off-diagonal and total sums of squares
+  int n;
+};
+
+// one workgroup per matrix: sums of squares off the diagonal and in total
+__global__ void __launch_bounds__(1024) k_blk_offnorm(const BlkMat* mats) {
+  const BlkMat M = mats[blockIdx.x];
+  __shared__ double red[2][16];
+  double off = 0.0, tot = 0.0;
+  const int64_t nn = (int64_t)M.n * M.n;
+  for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const double v = M.H[e];
+    tot += v * v;
+    if (e / M.n != e % M.n) off += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_xor(off, o);
+    tot += __shfl_xor(tot, o);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = off;
+    red[1][w] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      a += red[0][i];
+      b += red[1][i];
+    }
+    M.norms[0] = a;
+    M.norms[1] = b;
+  }
+}
+
+// one workgroup per matrix: values by rank and the vectors' columns moved to
+// their ranks
+__global__ void __launch_bounds__(1024) k_blk_finish(const BlkMat* mats) {
+  const BlkMat M = mats[blockIdx.x];
+  const int n = M.n;
+  __shared__ double dg[EIG_BIG_MAX];
+  __shared__ int rk[EIG_BIG_MAX];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dg[i] = M.H[(int64_t)i * n + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = dg[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += (dg[j] > v) || (dg[j] == v && j < i);
+    rk[i] = r;
+    M.W[r] = v;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const int64_t row = e / n;
+    const int c = (int)(e % n);
+    M.Vout[row * n + rk[c]] = M.V[e];
+  }
+}
+
+__global__ void k_set_identity(double* X, const int64_t* off, const int* dim) {
+  const int m = blockIdx.y, n = dim[m];
+  double* Y = X + off[m];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    Y[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// round-robin tournament on nb (even) players: pair i of round r
+static void rr_pair_host(int nb, int r, int i, int& p, int& q) {
+  const int m = nb - 1;
+  if (i == 0) {
+    p = r;
+    q = m;
+  } else {
+    p = (r + i) % m;
+    q = ((r - i) % m + m) % m;
+  }
+  if (p > q) std::swap(p, q);
+}
+
+static void block_jacobi_eig(std::vector<EigJob>& ej, hipStream_t s) {
+  const int nj = (int)ej.size();
+  if (!nj) return;
+  std::vector<int64_t> off(nj);
+  std::vector<int> dim(nj), nb(nj);
+  int64_t tot = 0;
+  int nbmax = 0;
+  for (int j = 0; j < nj; ++j) {
+    const int n = ej[j].n;
+    if (n <= JMAX || n > EIG_BIG_MAX) fail(FTN_EINVAL, "internal: block Jacobi order out of range");
+    off[j] = tot;
+    tot += (int64_t)n * n;
+    dim[j] = n;
+    nb[j] = 2 * (int)cdiv(n, JMAX);
+    nbmax = std::max(nbmax, nb[j]);
+  }
+  // H (working copy) | V0 | V1 | Q | T, each `tot`
+  DBuf<double> Wk(5 * tot, s), nrm(2 * nj, s), sub((int64_t)nbmax / 2 * nj * JMAX * JMAX, s),
+      vs((int64_t)nbmax / 2 * nj * JMAX * JMAX, s), wv((int64_t)nbmax / 2 * nj * JMAX, s);
+  double *Hw = Wk.p, *Qw = Wk.p + 3 * tot;
+  for (int j = 0; j < nj; ++j)
+    HIPC(hipMemcpyAsync(Hw + off[j], ej[j].H, (size_t)dim[j] * dim[j] * 8, hipMemcpyDeviceToDevice, s));
+  DBuf<int64_t> doff = to_device(std::vector<int64_t>(off), s);
+  DBuf<int> ddim = to_device(dim, s);
+  LAUNCH(k_set_identity, dim3(64, (unsigned)nj), dim3(256), 0, s, Wk.p + tot, doff.p, ddim.p);
+  std::vector<int> vcur(nj, 1);  // which V slot (1 or 2) holds the accumulated vectors
+  std::vector<char> done(nj, 0);
+  std::vector<double> hn(2 * nj);
+  for (int sweep = 0; sweep < BLK_SWEEPS; ++sweep) {
+    for (int r = 0; r < nbmax - 1; ++r) {
+      std::vector<BlkPair> pr;
+      std::vector<EigJob> inner;
+      std::vector<int> owner;
+      for (int j = 0; j < nj; ++j) {
+        if (done[j] || r >= nb[j] - 1) continue;
+        const int n = dim[j];
+        for (int i = 0; i < nb[j] / 2; ++i) {
+          int p, q;
+          rr_pair_host(nb[j], r, i, p, q);
+          BlkPair P;
+          P.H = Hw + off[j];
+          P.n = n;
+          P.i0 = (int)((int64_t)p * n / nb[j]);
+          P.i1 = (int)((int64_t)(p + 1) * n / nb[j]);
+          P.j0 = (int)((int64_t)q * n / nb[j]);
+          P.j1 = (int)((int64_t)(q + 1) * n / nb[j]);
+          const int64_t slot = (int64_t)pr.size();
+          P.sub = sub.p + slot * JMAX * JMAX;
+          P.vs = vs.p + slot * JMAX * JMAX;
+          P.Q = Qw + off[j];
+          EigJob e{};
+          e.H = P.sub;
+          e.V = vs.p + slot * JMAX * JMAX;
+          e.W = wv.p + slot * JMAX;
+          e.n = (P.i1 - P.i0) + (P.j1 - P.j0);
+          pr.push_back(P);
+          inner.push_back(e);
+        }
+        owner.push_back(j);
+      }
+      if (owner.empty()) continue;
+      DBuf<BlkPair> dp = to_device(pr, s);
+      LAUNCH(k_blk_gather, dim3(16, (unsigned)pr.size()), dim3(256), 0, s, dp.p);
+      jacobi_eig(inner, s);
+      LAUNCH(k_blk_scatter, dim3(32, (unsigned)pr.size()), dim3(256), 0, s, dp.p);
+      // T = H Q, H = Q^T T, V' = V Q
+      std::vector<GemmGroup> g1, g2, g3;
+      for (int j : owner) {
+        const int64_t n = dim[j];
+        g1.push_back(plain_group(n, n, n, off[j], n, 0, 3 * tot + off[j], n, 0, 4 * tot + off[j], n));
+        g2.push_back(plain_group(n, n, n, 3 * tot + off[j], n, 1, 4 * tot + off[j], n, 0, off[j], n));
+        g3.push_back(plain_group(n, n, n, vcur[j] * tot + off[j], n, 0, 3 * tot + off[j], n, 0,
+                                 (3 - vcur[j]) * tot + off[j], n));
+      }
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g1, Wk.p, Wk.p, Wk.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g2, Wk.p, Wk.p, Wk.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g3, Wk.p, Wk.p, Wk.p, nullptr, s);
+      for (int j : owner) vcur[j] = 3 - vcur[j];
+    }
+    // convergence of every matrix still running
+    std::vector<BlkMat> bm;
+    std::vector<int> idx;
+    for (int j = 0; j < nj; ++j) {
+      if (done[j]) continue;
+      BlkMat b{};
+      b.H = Hw + off[j];
+      b.norms = nrm.p + 2 * j;
+      b.n = dim[j];
+      bm.push_back(b);
+      idx.push_back(j);
+    }
+    if (bm.empty()) break;
+    DBuf<BlkMat> db = to_device(bm, s);
+    LAUNCH(k_blk_offnorm, dim3((unsigned)bm.size()), dim3(1024), 0, s, db.p);
+    HIPC(hipMemcpyAsync(hn.data(), nrm.p, 2 * nj * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    bool all = true;
+    for (int j : idx) {
+      const double lim = 8.0 * dim[j] * 0x1p-53;
+      if (hn[2 * j] <= lim * lim * hn[2 * j + 1]) done[j] = 1;
+      all = all && done[j];
+    }
+    if (all) break;
+  }
+  std::vector<BlkMat> fin(nj);
+  for (int j = 0; j < nj; ++j) {
+    fin[j] = BlkMat{};
+    fin[j].H = Hw + off[j];
+    fin[j].V = Wk.p + vcur[j] * tot + off[j];
+    fin[j].Vout = ej[j].V;
+    fin[j].W = ej[j].W;
+    fin[j].n = dim[j];
+  }
+  DBuf<BlkMat> df = to_device(fin, s);
+  LAUNCH(k_blk_finish, dim3((unsigned)nj), dim3(1024), 0, s, df.p);
+}
+
+// eigendecompositions of any order up to 1024: LDS sweeps up to 128, block
+// Jacobi above
+static void sym_eig(const std::vector<EigJob>& ej, hipStream_t s) {
+  std::vector<EigJob> small, big;
+  for (const EigJob& e : ej) (e.n <= JMAX ? small : big).push_back(e);
+  if (!small.empty()) jacobi_eig(small, s);
+  if (!big.empty()) block_jacobi_eig(big, s);
+}
+
+// ---------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of a small matrix X (r x c, r, c <= 128),
 // one workgroup per matrix. The columns of X are rotated in pairs until they
 // are mutually orthogonal: X V = W, W = U S with S the column norms. The
@@ -1199,9 +1466,13 @@ __global__ void __launch_bounds__(1024) k_pack_rows(const double* G, const int64
 // LDS (k_orth_factor, which also returns its inverse), the panel row is
 // R12 = R11^-T A12 (a GEMM with the inverse), and the trailing matrix is
 // updated by G22 -= R12^T R12 (GEMM). A column is dropped when its pivot is
-// not above tol * (largest diagonal of G).
+// not above tol * (largest diagonal of G). With Mout, also the inverse in the
+// convention of k_orth_factor (R with ones on the dropped diagonal, inverted,
+// dropped columns cleared) at the same offsets of Mout: the diagonal blocks
+// come from the LDS factorisations and block column j above them is
+// -M[0:j, 0:j] R[0:j, j] M_jj (two GEMMs per panel, left to right).
 static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::vector<int64_t>& dim, double tol,
-                      hipStream_t s) {
+                      hipStream_t s, double* Mout = nullptr) {
   const int nm = (int)off.size();
   if (!nm) return;
   const int64_t NB = JMAX;
@@ -1219,7 +1490,9 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
     r12off[m] = r12n;
     r12n += NB * std::max<int64_t>(dim[m] - NB, 0);
   }
-  DBuf<double> Minv(nm * NB * NB, s), R12(std::max<int64_t>(r12n, 1), s);
+  DBuf<double> Minv(Mout ? 1 : nm * NB * NB, s), R12(std::max<int64_t>(r12n, 1), s);
+  if (Mout)
+    for (int m = 0; m < nm; ++m) HIPC(hipMemsetAsync(Mout + off[m], 0, (size_t)dim[m] * dim[m] * 8, s));
   for (int64_t j0 = 0; j0 < dmax; j0 += NB) {
     std::vector<OrthJob> oj;
     std::vector<GemmGroup> gt, gs;
@@ -1231,14 +1504,19 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
       OrthJob o;
       o.G = blk;
       o.R = blk;
-      o.M = rest > 0 ? Minv.p + m * NB * NB : nullptr;
+      o.M = Mout ? Mout + off[m] + j0 * d + j0 : rest > 0 ? Minv.p + m * NB * NB : nullptr;
       o.thr = thr.p + m;
       o.p = (int)nb;
       o.ldg = o.ldr = (int)d;
-      o.ldm = (int)NB;
+      o.ldm = Mout ? (int)d : (int)NB;
       oj.push_back(o);
       if (rest > 0) {
-        gt.push_back(plain_group(nb, rest, nb, m * NB * NB, NB, 1, off[m] + j0 * d + j0 + nb, d, 0, r12off[m], rest));
+        if (Mout)
+          gt.push_back(plain_group(nb, rest, nb, off[m] + j0 * d + j0, d, 1, off[m] + j0 * d + j0 + nb, d, 0,
+                                   r12off[m], rest));
+        else
+          gt.push_back(
+              plain_group(nb, rest, nb, m * NB * NB, NB, 1, off[m] + j0 * d + j0 + nb, d, 0, r12off[m], rest));
         gs.push_back(sym_group(plain_group(rest, rest, nb, r12off[m], rest, 1, r12off[m], rest, 0,
                                            off[m] + (j0 + nb) * d + j0 + nb, d)));
       }
@@ -1246,7 +1524,7 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
     DBuf<OrthJob> doj = to_device(oj, s);
     FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
     if (!gt.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Minv.p, Gm, R12.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Mout ? Mout : Minv.p, Gm, R12.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
       for (int m = 0; m < nm; ++m) {
         const int64_t d = dim[m];
@@ -1260,21 +1538,37 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
   DBuf<int64_t> doff = to_device(off, s), ddim = to_device(dim, s);
   LAUNCH(k_zero_lower, dim3((unsigned)std::min<int64_t>(cdiv(dmax * dmax, 256), 4096), nm), dim3(256), 0, s, Gm,
          doff.p, ddim.p, nm);
+  if (!Mout || dmax <= NB) return;
+  DBuf<double> T((int64_t)nm * dmax * NB, s);
+  for (int64_t j0 = NB; j0 < dmax; j0 += NB) {
+    std::vector<GemmGroup> g1, g2;
+    for (int m = 0; m < nm; ++m) {
+      const int64_t d = dim[m];
+      if (d <= j0) continue;
+      const int64_t nb = std::min(NB, d - j0), to = (int64_t)m * dmax * NB;
+      g1.push_back(plain_group(j0, nb, j0, off[m], d, 0, off[m] + j0, d, 0, to, nb));  // M[0:j,0:j] R[0:j,j]
+      g2.push_back(plain_group(j0, nb, nb, to, nb, 0, off[m] + j0 * d + j0, d, 0, off[m] + j0, d));  // (..) M_jj
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g1, Mout, Gm, T.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g2, T.p, Mout, Mout, nullptr, s, -1.0, 0.0);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Accurate triangular factors of small sectors (d <= 128). The Gram matrix
+// Accurate triangular factors of sectors up to order 1024. The Gram matrix
 // G = A^T A of a factor A (m x d) holds a direction of A with singular value
 // s only to about eps * |A|^2 / s^2, so directions below ~1e-8 of |A| are
 // lost, although the product X = R_A R_B^T can need them when the leading
-// directions of the two sides are nearly orthogonal. For d <= 128 the factor
-// is therefore taken as A itself when m <= d (R = A, rank m), and otherwise
+// directions of the two sides are nearly orthogonal. The factor is therefore
+// taken as A itself when m <= d (R = A, rank m), and otherwise
 // by shifted Cholesky QR applied three times: R1 = chol(G + sigma I) with
 // sigma = 11 (m d + d (d + 1)) u |A|_F^2 (u = 2^-53), Q1 = A R1^-1, then two
 // dropping Cholesky QR passes on Q1, R = R3 R2 R1. The shift keeps the
 // first factorisation defined for any conditioning and the later passes
 // recover the small directions from A itself; rows whose pivot is not above
 // 1e-13 of the largest in a later pass (exact dependencies) are dropped.
+// Each Cholesky factorisation runs in LDS (k_orth_factor) for d <= 128 and
+// as the blocked chol_drop with its inverse above.
 
 struct ShiftJob {
   const double* G;  // d x d Gram matrix (ld d)
@@ -1355,17 +1649,27 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
     LAUNCH(k_shift_diag, dim3(nj), dim3(256), 0, s, d.p);
   }
   auto factor = [&](double* R, double* M, double tol) {
-    std::vector<OrthJob> oj(nj);
+    std::vector<OrthJob> oj;
+    std::vector<int64_t> boff, bdim;
     for (int j = 0; j < nj; ++j) {
-      OrthJob& o = oj[j];
+      if (J[j].d > JMAX) {
+        boff.push_back(wo[j]);
+        bdim.push_back(J[j].d);
+        continue;
+      }
+      OrthJob o;
       o.G = R + wo[j];
       o.R = R + wo[j];
       o.M = M ? M + wo[j] : nullptr;
       o.thr = nullptr;
       o.p = o.ldg = o.ldr = o.ldm = J[j].d;
+      oj.push_back(o);
     }
-    DBuf<OrthJob> d = to_device(oj, s);
-    FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)nj), dim3(LT), 0, s, d.p, tol);
+    if (!oj.empty()) {
+      DBuf<OrthJob> d = to_device(oj, s);
+      FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, d.p, tol);
+    }
+    if (!boff.empty()) chol_drop(R, boff, bdim, tol, s, M);
   };
   // pass 1: no column is dropped (G + sigma I is positive definite)
   factor(R1, M1, 0.0);
@@ -2151,7 +2455,7 @@ __device__ inline void adj_sync() { __syncthreads(); }
 __global__ void __launch_bounds__(1024) k_svd_adjoint(const AdjJob* jobs) {
   const AdjJob J = jobs[blockIdx.x];
   const int d = J.d, k = J.k, tid = threadIdx.x;
-  __shared__ double sv[JMAX], sg[JMAX];
+  __shared__ double sv[EIG_BIG_MAX], sg[EIG_BIG_MAX];
   __shared__ int rho_s;
   const int64_t dd = (int64_t)d * d;
   double *Us = J.ws, *V = J.ws + dd, *al = J.ws + 2 * dd, *be = J.ws + 3 * dd, *Y = J.ws + 4 * dd,
@@ -2355,7 +2659,8 @@ void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb,
     if (h < 0) fail(FTN_EINVAL, "internal: compress backward sector without a partner");
     const GemmGroup& H = vb.groups[h];
     if (H.K != G.K || H.M != G.N) fail(FTN_EINVAL, "internal: compress backward sector mismatch");
-    if (G.K > JMAX) fail(FTN_ENOTSUP, "compress_bond_backward: bond sectors larger than 128 are not supported");
+    if (G.K > EIG_BIG_MAX)
+      fail(FTN_ENOTSUP, "compress_bond_backward: bond sectors larger than 1024 are not supported");
     BS x;
     x.ga = (int)g;
     x.gb = h;
@@ -2440,7 +2745,7 @@ void op_compress_bond_backward(const Tensor& a, const Tensor& b, int la, int lb,
       j.W = lam.p + go[i];
       j.n = (int)S[i].d;
     }
-    jacobi_eig(ej, s);
+    sym_eig(ej, s);
   }
   // qa = Q_A^T dA', qb = Q_B^T dB'^T, qf = Q_A^T A'   (d x k)
   DBuf<double> qa(std::max<int64_t>(ks, 1), s), qb(std::max<int64_t>(ks, 1), s), qf(std::max<int64_t>(ks, 1), s);
