@@ -621,8 +621,18 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   std::memset(&L.sc, 0, sizeof(L.sc));
   if (sc) L.sc = *sc;
   dim3 grid((unsigned)p.ntiles);
-  static const bool trace = std::getenv("FTN_TRACE_GEMM") != nullptr;
-  if (trace) {
+  // FTN_TRACE_GEMM: one line per launch; FTN_TRACE_GEMM=2 also times it
+  // (synchronising the stream around the launch)
+  static const char* trace_env = std::getenv("FTN_TRACE_GEMM");
+  static const bool trace = trace_env != nullptr;
+  static const bool trace_time = trace && trace_env[0] == '2';
+  hipEvent_t te0 = nullptr, te1 = nullptr;
+  if (trace_time) {
+    HIPC(hipEventCreate(&te0));
+    HIPC(hipEventCreate(&te1));
+    HIPC(hipEventRecord(te0, s));
+  }
+  if (trace && !trace_time) {
     int64_t mm = 0, mn = 0, mk = 0;
     for (auto& g : p.host) {
       mm = std::max(mm, g.M);
@@ -659,6 +669,24 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   HIPC(hipGetLastError());
   prof_end(tok, s, p.kind == FTN_GEMM_F64 ? FTN_PROF_GEMM_F64 : (p.kind == FTN_GEMM_F32 ? FTN_PROF_GEMM_F32 : FTN_PROF_GEMM_BF16X3),
            p.flops, p.abytes * (double)es);
+  if (trace_time) {
+    HIPC(hipEventRecord(te1, s));
+    HIPC(hipEventSynchronize(te1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, te0, te1));
+    int64_t mm = 0, mn = 0, mk = 0;
+    for (auto& g : p.host) {
+      mm = std::max(mm, g.M);
+      mn = std::max(mn, g.N);
+      mk = std::max(mk, g.K);
+    }
+    std::fprintf(stderr, "[gemm] us %.1f tflops %.2f tiles %lld groups %zu flops %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sym %d sc %d cfg %d split %lld\n",
+                 1000.0 * ms, ms > 0 ? p.flops / (ms * 1e-3) / 1e12 : 0.0, (long long)p.ntiles, p.host.size(), p.flops,
+                 (long long)mm, (long long)mn, (long long)mk, p.host[0].transA, p.host[0].transB, p.host[0].sym,
+                 p.host[0].scatter, p.cfg, (long long)p.split);
+    (void)hipEventDestroy(te0);
+    (void)hipEventDestroy(te1);
+  }
 }
 
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,

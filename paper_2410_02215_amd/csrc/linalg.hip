@@ -54,7 +54,8 @@ __device__ inline double wave_max(double v) {
 // every element belongs to exactly one block of a round, so reads and
 // writes of a round need no barrier between them); a second barrier ends
 // the round. The rotations are logged to global memory. Sweeps stop when the
-// off-diagonal norm^2 is <= 1e-30 of the diagonal norm^2. The eigenvalues
+// off-diagonal norm^2 is <= max(1e-30, (4 n u)^2) of the diagonal norm^2
+// (jacobi_stop). The eigenvalues
 // are written sorted, with the rank of each diagonal position.
 // k_jacobi_vectors replays the log onto V = I: rows of V are independent, so
 // each wave owns one row, the log is read ahead in blocks of rounds, and no
@@ -104,6 +105,35 @@ __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
 // workgroup barrier that orders LDS only (the rotation log stores to global
 // memory stay in flight)
 __device__ inline void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Rotation annihilating a_pq: t = tan(theta) = sign(tau) / (|tau| + sqrt(1 +
+// tau^2)) with tau = (a_qq - a_pp) / (2 a_pq) (|t| <= 1; a huge tau gives
+// t = 0), c = 1 / sqrt(1 + t^2) by the hardware reciprocal square root and
+// two Newton steps, s = t c.
+__device__ inline void jac_rotation(double app, double aqq, double apq, double& c, double& sn, double& t) {
+  c = 1.0;
+  sn = 0.0;
+  t = 0.0;
+  if (apq != 0.0) {
+    const double tau = (aqq - app) / (2.0 * apq);
+    t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double q = 1.0 + t * t, h = 0.5 * q;
+    double y = __builtin_amdgcn_rsq(q);
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    c = y;
+    sn = t * y;
+  }
+}
+
+// Sweeps stop when the off-diagonal sum of squares is at most this fraction
+// of the diagonal's: 1e-30, or (4 n u)^2 when that is larger, since every
+// rotation rounds the entries it touches by about u times the largest ones
+// and the off-diagonal part settles near (n u)^2 of the diagonal's.
+__host__ __device__ inline double jacobi_stop(int n) {
+  const double f = 4.0 * n * 0x1p-53;
+  return fmax(1e-30, f * f);
+}
 
 __global__ void __launch_bounds__(LT) k_jacobi_sweep(const EigJob* jobs) {
   const EigJob J = jobs[blockIdx.x];
@@ -167,21 +197,15 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep(const EigJob* jobs) {
       tot += red[1][i];
     }
     __syncthreads();
-    if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
+    if (off == 0.0 || 2.0 * off <= jacobi_stop(n) * tot) break;
     for (int r = 0; r < n2 - 1; ++r, ++nr) {
       if (w == 0 && lane < np) {
         int p, q;
         rr_pair(n2, r, lane, p, q);
-        double c = 1.0, sn = 0.0;
-        const double apq = A[p][q];
-        if (apq != 0.0) {
-          const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = t * c;
-        }
+        double c, sn, t;
+        jac_rotation(A[p][p], A[q][q], A[p][q], c, sn, t);
         rcs[lane] = make_double2(c, sn);
-        rt[lane] = sn / c;
+        rt[lane] = t;
         rpq_s[lane] = p | (q << 16);
         J.rot[(int64_t)nr * np + lane] = make_double2(c, sn);
         J.rpq[(int64_t)nr * np + lane] = p | (q << 16);
@@ -253,17 +277,6 @@ __device__ inline int rr_slot(int n2, int r, int x) {
   return d <= np - 1 ? d : m - d;
 }
 
-__device__ inline void jac_rotation(double app, double aqq, double apq, double& c, double& sn, double& t) {
-  c = 1.0;
-  sn = 0.0;
-  if (apq != 0.0) {
-    const double tau = (aqq - app) / (2.0 * apq);
-    const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    c = 1.0 / sqrt(1.0 + tt * tt);
-    sn = tt * c;
-  }
-  t = sn / c;
-}
 
 // The same sweeps with one barrier per round (for n2 >= 6, where no 2 x 2
 // block of a round holds two pivots of the next round, and no pivot of the
@@ -291,10 +304,14 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
     if (i <= j) A[i][j] = (j < n) ? J.H[(int64_t)i * n + j] : 0.0;
   }
   __syncthreads();
+  // the off-diagonal blocks (k1 < k2) of this thread; a block that holds a
+  // pivot of the next round is wave 0's. Which blocks those are does not
+  // depend on the round (partners in round r + 1 of the pair in slot k of
+  // round r sit in fixed slots), so they are found once, from round 0.
   int pk1[NPAIR_LA], pk2[NPAIR_LA];
   bool pact[NPAIR_LA];
   {
-    const int nb = np * (np - 1) / 2;  // off-diagonal blocks k1 < k2
+    const int nb = np * (np - 1) / 2;
 #pragma unroll
     for (int u = 0; u < NPAIR_LA; ++u) {
       const int e = (tid - 64) + u * (LT - 64);
@@ -306,6 +323,14 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
       }
       pk1[u] = k1;
       pk2[u] = k1 + 1 + rem;
+      if (pact[u]) {
+        int p1, q1, p2, q2;
+        rr_pair(n2, 0, pk1[u], p1, q1);
+        rr_pair(n2, 0, pk2[u], p2, q2);
+        const int r1 = m > 1 ? 1 : 0;
+        const int x1 = rr_partner(n2, r1, p1), y1 = rr_partner(n2, r1, q1);
+        if (x1 == p2 || x1 == q2 || y1 == p2 || y1 == q2) pact[u] = false;
+      }
     }
   }
   int cur = 0;
@@ -345,7 +370,7 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
       tot += red[1][i];
     }
     __syncthreads();
-    if (off == 0.0 || 2.0 * off <= 1e-30 * tot) break;
+    if (off == 0.0 || 2.0 * off <= jacobi_stop(n) * tot) break;
     for (int r = 0; r < m; ++r, ++nr) {
       const int r2 = r + 1 == m ? 0 : r + 1;
       double* Af = &A[0][0];
@@ -355,8 +380,6 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
           if (!pact[u]) continue;
           const int v1 = rpq_s[cur][pk1[u]], v2 = rpq_s[cur][pk2[u]];
           const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
-          const int x1 = rr_partner(n2, r2, p1), y1 = rr_partner(n2, r2, q1);
-          if (x1 == p2 || x1 == q2 || y1 == p2 || y1 == q2) continue;  // wave 0 updates it
           const double2 ra = rcs[cur][pk1[u]], rb = rcs[cur][pk2[u]];
           const int a0 = min(p1, p2) * (JMAX + 1) + max(p1, p2);
           const int a1 = min(p1, q2) * (JMAX + 1) + max(p1, q2);

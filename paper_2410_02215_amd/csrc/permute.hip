@@ -132,6 +132,8 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
       D.mode = 0;
       D.rows = D.nel / dx;
       D.ta = max(2, min(pow2ceil(dx), 256));
+      // few rows: longer row pieces, so that the tile's rows are all used
+      if (D.rows * D.ta < PM_TILE) D.ta = max(2, min(pow2ceil(dx), PM_TILE / pow2ceil(D.rows)));
       D.tr = PM_TILE / D.ta;
       D.nx = (dx + D.ta - 1) / D.ta;
       D.nr = (D.rows + D.tr - 1) / D.tr;
@@ -228,24 +230,51 @@ __global__ void __launch_bounds__(PM_THREADS)
       __syncthreads();
       // two neighbouring entries of a row per thread (ta is an even power of
       // two, so a pair never straddles rows): one 2-wide load and store when
-      // both addresses are aligned to the pair, else two single entries
+      // both addresses are aligned to the pair, else two single entries. The
+      // PPT pairs of a thread are all loaded before any is stored, so that
+      // each thread keeps several loads in flight.
       typedef typename Pair<T>::type T2;
-      for (int e = 2 * threadIdx.x; e < PM_TILE; e += 2 * PM_THREADS) {
+      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
+      T2 buf[PPT];
+      int64_t bis[PPT], sis[PPT];
+      unsigned okm = 0, twom = 0, vecm = 0;
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
         const int r = e >> lta, i = e & (ta - 1);
         const int64_t row = r0 + r, x = x0 + i;
-        if (row >= D.rows || x >= dx) continue;
-        const int64_t bi = D.boff + row * dx + x, si = D.moff + rbase[r] + x;
+        const bool ok = row < D.rows && x < dx;
+        const int64_t bi = D.boff + row * dx + x, si = D.moff + (ok ? rbase[r] : 0) + x;
+        bis[u] = bi;
+        sis[u] = si;
         const T* sp = DIR == 0 ? src + bi : src + si;
         T* dp = DIR == 0 ? dst + si : dst + bi;
-        if (x + 1 < dx && ((((uintptr_t)sp) | ((uintptr_t)dp)) & (sizeof(T2) - 1)) == 0) {
-          const T2 a = *(const T2*)sp;
-          T2 b;
-          b.x = v * a.x;
-          b.y = v * a.y;
+        const bool two = x + 1 < dx;
+        const bool vec = two && ((((uintptr_t)sp) | ((uintptr_t)dp)) & (sizeof(T2) - 1)) == 0;
+        okm |= ok ? 1u << u : 0u;
+        twom |= two ? 1u << u : 0u;
+        vecm |= vec ? 1u << u : 0u;
+        if (ok) {
+          if (vec) {
+            buf[u] = *(const T2*)sp;
+          } else {
+            buf[u].x = sp[0];
+            buf[u].y = two ? sp[1] : T(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        if (!((okm >> u) & 1u)) continue;
+        T* dp = DIR == 0 ? dst + sis[u] : dst + bis[u];
+        T2 b;
+        b.x = v * buf[u].x;
+        b.y = v * buf[u].y;
+        if ((vecm >> u) & 1u) {
           *(T2*)dp = b;
         } else {
-          dp[0] = v * sp[0];
-          if (x + 1 < dx) dp[1] = v * sp[1];
+          dp[0] = b.x;
+          if ((twom >> u) & 1u) dp[1] = b.y;
         }
       }
     } else if (D.mode == 1) {
@@ -297,15 +326,27 @@ __global__ void __launch_bounds__(PM_THREADS)
           if (two) p[1] = b1;
         }
       };
+      // the loads of a thread are issued together (PPT pairs at most) before
+      // the staging writes, so that several are in flight
+      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
       if (DIR == 0) {
-        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
+        T la0[PPT], la1[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
           const int r = e >> lta, i = e & (ta - 1);
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) {
-            T a0, a1;
-            ld2(src + bbase + yy * sby + x, x + 1 < dx, a0, a1);
-            tile[r * ld + i] = v * a0;
-            tile[r * ld + i + 1] = v * a1;
+          la0[u] = la1[u] = T(0);
+          if (e < n && yy < dy && x < dx) ld2(src + bbase + yy * sby + x, x + 1 < dx, la0[u], la1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
+          const int r = e >> lta, i = e & (ta - 1);
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (e < n && yy < dy && x < dx) {
+            tile[r * ld + i] = v * la0[u];
+            tile[r * ld + i + 1] = v * la1[u];
           }
         }
         __syncthreads();
@@ -316,14 +357,23 @@ __global__ void __launch_bounds__(PM_THREADS)
             st2(dst + sbase + yy + x * tsx, yy + 1 < dy, tile[r * ld + i], tile[(r + 1) * ld + i]);
         }
       } else {
-        for (int e = 2 * threadIdx.x; e < n; e += 2 * PM_THREADS) {
+        T la0[PPT], la1[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
           const int r = e & (tr - 1), i = e >> ltr;
           const int64_t yy = y0 + r, x = x0 + i;
-          if (yy < dy && x < dx) {
-            T a0, a1;
-            ld2(src + sbase + yy + x * tsx, yy + 1 < dy, a0, a1);
-            tile[r * ld + i] = v * a0;
-            tile[(r + 1) * ld + i] = v * a1;
+          la0[u] = la1[u] = T(0);
+          if (e < n && yy < dy && x < dx) ld2(src + sbase + yy + x * tsx, yy + 1 < dy, la0[u], la1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
+          const int r = e & (tr - 1), i = e >> ltr;
+          const int64_t yy = y0 + r, x = x0 + i;
+          if (e < n && yy < dy && x < dx) {
+            tile[r * ld + i] = v * la0[u];
+            tile[(r + 1) * ld + i] = v * la1[u];
           }
         }
         __syncthreads();
@@ -380,7 +430,12 @@ void perm_plan_build(PermPlan& p, const Structure& S, hipStream_t s) {
 void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const void* src, void* dst,
               hipStream_t s, double alpha) {
   if (p.ntiles == 0) return;
-  static const bool trace = std::getenv("FTN_TRACE_PERM") != nullptr;
+  // FTN_TRACE_PERM: one line per launch; FTN_TRACE_PERM=2 also times it
+  // (synchronising the stream around the launch)
+  static const char* trace_env = std::getenv("FTN_TRACE_PERM");
+  static const bool trace = trace_env != nullptr;
+  static const bool trace_time = trace && trace_env[0] == '2';
+  hipEvent_t te0 = nullptr, te1 = nullptr;
   if (trace) {
     int64_t big = 0;
     for (int64_t b = 1; b < S.nblocks; ++b)
@@ -401,6 +456,11 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
                  "row0 %.1f\n", dir, (long long)p.nelem, (long long)S.nblocks, p.op.nA, p.op.nG, pm.c_str(), sh.c_str(),
                  (long long)em[0], (long long)em[1], (long long)em[2], em[0] ? (double)dxs / em[0] : 0.0);
   }
+  if (trace_time) {
+    HIPC(hipEventCreate(&te0));
+    HIPC(hipEventCreate(&te1));
+    HIPC(hipEventRecord(te0, s));
+  }
   void* tok = prof_begin(s);
   const dim3 grid((unsigned)p.ntiles), block(PM_THREADS);
   if (dtype == FTN_F64) {
@@ -414,6 +474,15 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
   HIPC(hipGetLastError());
   const double pb = 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4);
   prof_end(tok, s, FTN_PROF_PERMUTE, pb, pb);
+  if (trace_time) {
+    HIPC(hipEventRecord(te1, s));
+    HIPC(hipEventSynchronize(te1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, te0, te1));
+    std::fprintf(stderr, "[perm-time] us %.1f GB/s %.0f\n", 1000.0 * ms, ms > 0 ? pb / (ms * 1e-3) / 1e9 : 0.0);
+    (void)hipEventDestroy(te0);
+    (void)hipEventDestroy(te1);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -176,22 +176,35 @@ void dfree(void* p, hipStream_t s, bool persistent) {
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
-  std::lock_guard<std::mutex> g(g_cache_mu);
-  DevCache& c = (*g_cache)[dev];
-  auto it = c.live.find(p);
-  if (it == c.live.end()) return;  // not from this cache
-  Block b{p, it->second, s, nullptr};
-  c.in_use -= it->second;
-  c.live.erase(it);
-  if (!c.events.empty()) {
-    b.ev = c.events.back();
-    c.events.pop_back();
-  } else if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+  // the block leaves the live set under the lock, its release event is
+  // recorded outside it (the block is nobody else's until it is listed as
+  // free again), so threads on other streams do not wait behind the call
+  Block b{p, 0, s, nullptr};
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    DevCache& c = (*g_cache)[dev];
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;  // not from this cache
+    b.size = it->second;
+    c.in_use -= it->second;
+    c.live.erase(it);
+    if (!c.events.empty()) {
+      b.ev = c.events.back();
+      c.events.pop_back();
+    }
+  }
+  if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     b.ev = nullptr;
   }
+  bool idle_ev = false;
   if (b.ev && hipEventRecord(b.ev, s) != hipSuccess) {
     (void)hipGetLastError();
+    idle_ev = true;
+  }
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  DevCache& c = (*g_cache)[dev];
+  if (idle_ev) {
     c.events.push_back(b.ev);
     b.ev = nullptr;
   }
@@ -208,62 +221,64 @@ void memory_stats(int dev, int64_t* in_use, int64_t* peak, int64_t* reserved, bo
 }
 
 // ---------------------------------------------------------------------------
-// pinned staging ring for small host-to-device copies: 16 chunks of 4 MiB;
-// a copy never spans chunks, copies from any streams share a chunk (they
-// never share bytes), and a chunk is reused only after the events recorded
-// behind the last copy of every stream that used it have completed
+// pinned staging rings for small host-to-device copies, one per stream, so
+// that threads driving different streams never wait for one another (a
+// shared ring serialised every upload of every worker thread behind one
+// lock): 4 chunks of 2 MiB per stream; a copy never spans chunks; when the
+// ring moves on from a chunk an event is recorded behind the copies
+// enqueued so far, and a chunk is written again only after its event has
+// completed. Rings live as long as the process (one per stream handle seen).
 namespace {
-constexpr size_t RING_CH = 4u << 20, RING_N = 16;
-std::mutex g_ring_mu;
-char* g_ring = nullptr;
-bool g_ring_failed = false;
-size_t g_ring_cur = 0, g_ring_off = 0;  // current chunk, offset inside it
-// per chunk: (stream, event behind that stream's last copy from the chunk)
-std::vector<std::pair<hipStream_t, hipEvent_t>> g_ring_use[RING_N];
-std::vector<hipEvent_t> g_ring_pool;
+constexpr size_t RING_CH = 2u << 20, RING_N = 4;
+struct Ring {
+  std::mutex mu;
+  char* buf = nullptr;
+  bool failed = false;
+  size_t cur = 0, off = 0;
+  hipEvent_t ev[RING_N] = {};
+  bool pending[RING_N] = {};
+};
+std::mutex g_rings_mu;
+std::unordered_map<hipStream_t, Ring*>* g_rings = new std::unordered_map<hipStream_t, Ring*>();
+
+Ring* ring_of(hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_rings_mu);
+  Ring*& r = (*g_rings)[s];
+  if (!r) r = new Ring();
+  return r;
+}
 }  // namespace
 
 void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return;
-  std::lock_guard<std::mutex> g(g_ring_mu);
-  if (!g_ring && !g_ring_failed) {
-    if (hipHostMalloc((void**)&g_ring, RING_CH * RING_N, hipHostMallocDefault) != hipSuccess) {
+  Ring* r = ring_of(s);
+  std::lock_guard<std::mutex> g(r->mu);
+  if (!r->buf && !r->failed) {
+    if (hipHostMalloc((void**)&r->buf, RING_CH * RING_N, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
-      g_ring = nullptr;
-      g_ring_failed = true;
+      r->buf = nullptr;
+      r->failed = true;
     }
   }
-  if (!g_ring || bytes > RING_CH) {
+  if (!r->buf || bytes > RING_CH) {
     HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     return;
   }
-  if (g_ring_off + bytes > RING_CH) {  // move to the next chunk once every copy from it is done
-    g_ring_cur = (g_ring_cur + 1) % RING_N;
-    g_ring_off = 0;
-    for (auto& u : g_ring_use[g_ring_cur]) {
-      HIPC(hipEventSynchronize(u.second));
-      g_ring_pool.push_back(u.second);
+  if (r->off + bytes > RING_CH) {
+    if (!r->ev[r->cur]) HIPC(hipEventCreateWithFlags(&r->ev[r->cur], hipEventDisableTiming));
+    HIPC(hipEventRecord(r->ev[r->cur], s));
+    r->pending[r->cur] = true;
+    r->cur = (r->cur + 1) % RING_N;
+    r->off = 0;
+    if (r->pending[r->cur]) {
+      HIPC(hipEventSynchronize(r->ev[r->cur]));
+      r->pending[r->cur] = false;
     }
-    g_ring_use[g_ring_cur].clear();
   }
-  const size_t c = g_ring_cur;
-  char* stage = g_ring + c * RING_CH + g_ring_off;
+  char* stage = r->buf + r->cur * RING_CH + r->off;
   std::memcpy(stage, src, bytes);
   HIPC(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, s));
-  hipEvent_t ev = nullptr;
-  for (auto& u : g_ring_use[c])
-    if (u.first == s) ev = u.second;
-  if (!ev) {
-    if (!g_ring_pool.empty()) {
-      ev = g_ring_pool.back();
-      g_ring_pool.pop_back();
-    } else {
-      HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    }
-    g_ring_use[c].emplace_back(s, ev);
-  }
-  HIPC(hipEventRecord(ev, s));
-  g_ring_off = (g_ring_off + bytes + 255) & ~(size_t)255;
+  r->off = (r->off + bytes + 255) & ~(size_t)255;
 }
 
 // ---------------------------------------------------------------------------
