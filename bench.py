@@ -30,7 +30,15 @@ if ROOT not in sys.path:
 # (256 CUs x 2.4 GHz x 128 FP64 flops per CU per clock = 78.6 TFLOP/s).
 PEAK = {"gemm_f64": (78.6, "TFLOP/s", "mfma"), "gemm_f32": (157.3, "TFLOP/s", "mfma"),
         "gemm_bf16x3": (2500.0, "TFLOP/s", "mfma"), "permute": (8000.0, "GB/s", "hbm"),
-        "factor": (78.6, "TFLOP/s", "alu")}
+        "factor": (78.6, "TFLOP/s", "alu"), "k_splitk_reduce_f64": (8000.0, "GB/s", "hbm")}
+for _k in ("64x64", "128x128", "256x16", "256x32", "16x256", "32x256"):
+    PEAK["k_gemm_f64_" + _k] = (78.6, "TFLOP/s", "mfma")
+for _k in ("k_orth_factor", "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"):
+    PEAK[_k] = (78.6, "TFLOP/s", "alu")
+# single kernels (the classes gemm_f64 and factor are families of kernels)
+KERNELS = ["gemm_f32", "gemm_bf16x3", "permute", "k_splitk_reduce_f64", "k_gemm_f64_64x64", "k_gemm_f64_128x128",
+           "k_gemm_f64_256x16", "k_gemm_f64_256x32", "k_gemm_f64_16x256", "k_gemm_f64_32x256", "k_orth_factor",
+           "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -252,7 +260,7 @@ def main_amplitudes(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": cfg["chi"],
                    "amplitudes_per_step": B, "workers": args.workers},
-        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         # launches of the library's worker threads are not instrumented: with
         # more than one worker the line carries wall-clock rates only
         "roofline": roofline(prof, cfg["name"]) if any(prof[c][0] > 0 for c in prof) else None,
@@ -335,7 +343,7 @@ def main_gradient(args):
                    else "library network backward (ftn_contract_network_grad)"},
         "peak_memory_gb": {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
                            "torch": torch.cuda.max_memory_allocated() / 1e9},
-        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "result": {"energy": E, "grad_norm": gnorm},
         "roofline": roofline(prof, cfg["name"]),
     }
@@ -366,8 +374,10 @@ def gradient_cpu_baseline(cfg, chi, paths):
 
 
 def roofline(prof, workload):
-    """Roofline entry of the dominant kernel class by time."""
-    dom = max((c for c in prof if c in PEAK), key=lambda c: prof[c][0])
+    """Roofline entry of the dominant kernel (the single kernel with the most
+    time; the permute class is one kernel template, the GEMM and factor
+    classes are split into their kernels)."""
+    dom = max((c for c in prof if c in KERNELS), key=lambda c: prof[c][0])
     ms, cnt, work = prof[dom][:3]
     peak, unit, bound = PEAK[dom]
     scale = 1e12 if unit == "TFLOP/s" else 1e9
@@ -433,6 +443,7 @@ def main():
     tune_stats = P.ftn.autotune_stats()
     P.ftn.profile_collect()
     P.ftn.profile_enable(True)
+    w0 = time.monotonic_ns()
     t0 = time.perf_counter()
     flops = 0.0
     tb_flops = 0.0
@@ -445,6 +456,7 @@ def main():
               flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    w1 = time.monotonic_ns()
     P.ftn.profile_enable(False)
     prof = P.ftn.profile_collect()
     el = t1 - t0
@@ -467,12 +479,15 @@ def main():
                             "note": "useful block-pair GEMM flops plus the textbook QR/LQ/SVD/absorb counts of "
                                     "the compressions, per second of the timed steps"},
         "autotune": dict(tune_stats, enabled=not args.no_autotune),
-        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof},
+        "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_rate": {c: "%.4g %s" % (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
                                         PEAK[c][1])
                         for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
         "rel_err_vs_oracle": golden_errors(norm, hop),
+        # CLOCK_MONOTONIC bounds of the timed steps: a rocprofv3 kernel trace of
+        # the same run can be cut to them (rocprof_summary stats <dir> <this line>)
+        "timed_window_ns": [w0, w1],
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -426,7 +426,25 @@ enum {
   FTN_PROF_FACTOR = 4,      /* Cholesky / Jacobi kernels; work = textbook flops
                                (Cholesky p^3/3, triangular inverse p^3/3,
                                symmetric eigensolver with vectors 9 n^3) */
-  FTN_PROF_NCLASS = 6
+  FTN_PROF_OTHER = 5,
+  /* single kernels inside classes 0 and 4, for per-kernel rooflines. Their
+     time, launches and work are also counted in the class they belong to,
+     except that the split-K reduction and the eigenvector kernel add time
+     only (a grouped GEMM is one launch of class 0, its reduction included;
+     an eigensolve's launch is its sweep kernel). */
+  FTN_PROF_K_GEMM_F64_64x64 = 6,   /* k_gemm FP64, 64 x 64 tiles; work = useful flops */
+  FTN_PROF_K_GEMM_F64_128x128 = 7, /* 128 x 128 tiles */
+  FTN_PROF_K_GEMM_F64_256x16 = 8,  /* 256 x 16 tiles */
+  FTN_PROF_K_GEMM_F64_256x32 = 9,  /* 256 x 32 tiles */
+  FTN_PROF_K_GEMM_F64_16x256 = 10, /* 16 x 256 tiles */
+  FTN_PROF_K_GEMM_F64_32x256 = 11, /* 32 x 256 tiles */
+  FTN_PROF_K_SPLITK_F64 = 12,      /* split-K reduction, FP64; work = bytes read + written */
+  FTN_PROF_K_ORTH = 13,            /* Cholesky with triangular inverse (k_orth_factor) */
+  FTN_PROF_K_JACOBI = 14,          /* Jacobi sweeps, orders below 63 */
+  FTN_PROF_K_JACOBI_LA = 15,       /* Jacobi sweeps, one barrier per round (orders 63..128) */
+  FTN_PROF_K_JACOBI_VEC = 16,      /* eigenvector accumulation (work counted with the sweeps) */
+  FTN_PROF_K_SVD_COLS = 17,        /* one-sided Jacobi SVD */
+  FTN_PROF_NCLASS = 18
 };
 
 /* on != 0: bracket every instrumented launch with HIP events on its stream

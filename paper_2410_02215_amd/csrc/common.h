@@ -1,6 +1,7 @@
 // Internal declarations of the fermionic tensor library (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,6 +33,15 @@ void check_launch(const char* name, dim3 grid, dim3 block);
     ::ftn::check_launch(#kern, (grid), (block));                                      \
     hipLaunchKernelGGL(kern, (grid), (block), (shm), (stream), __VA_ARGS__);          \
     ::ftn::hip_check(hipGetLastError(), #kern);                                       \
+  } while (0)
+// the same with HIP events attached to the dispatch itself (either may be
+// null): the start event takes the time the kernel starts, the stop event
+// the time it ends, so an event pair times exactly one kernel
+#define ELAUNCH(kern, grid, block, shm, stream, ev0, ev1, ...)                               \
+  do {                                                                                       \
+    ::ftn::check_launch(#kern, (grid), (block));                                             \
+    hipExtLaunchKernelGGL(kern, (grid), (block), (shm), (stream), (ev0), (ev1), 0, __VA_ARGS__); \
+    ::ftn::hip_check(hipGetLastError(), #kern);                                              \
   } while (0)
 void set_last_error(const std::string& msg);
 
@@ -440,6 +450,9 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // event timing of instrumented launches (profile.hip)
 bool prof_on();
 void* prof_begin(hipStream_t s);
+// the start (which = 0) or stop (1) event of a timing token, null without one;
+// the launch being timed takes them (ELAUNCH)
+hipEvent_t prof_ev(void* tok, int which);
 // bytes: algorithmic bytes of the launch (operands read once, results written once)
 void prof_end(void* tok, hipStream_t s, int cls, double work, double bytes = 0.0);
 // suppress instrumentation on the calling thread (library worker threads)

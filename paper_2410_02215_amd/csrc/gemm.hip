@@ -586,25 +586,26 @@ void gemm_plan_with(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind,
 }
 
 template <typename T>
-static void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmLaunch& L, const T* A, const T* B, T* C, T* W) {
+static void launch_cfg(int cfg, dim3 grid, hipStream_t s, const GemmLaunch& L, const T* A, const T* B, T* C, T* W,
+                       hipEvent_t e0, hipEvent_t e1) {
   switch (cfg) {
     case CFG_128:
-      LAUNCH((k_gemm<T, 128, 128, 2, 4>), grid, dim3(512), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 128, 128, 2, 4>), grid, dim3(512), 0, s, e0, e1, L, A, B, C, W);
       break;
     case CFG_256x16:
-      LAUNCH((k_gemm<T, 256, 16, 4, 1>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 256, 16, 4, 1>), grid, dim3(GT), 0, s, e0, e1, L, A, B, C, W);
       break;
     case CFG_256x32:
-      LAUNCH((k_gemm<T, 256, 32, 4, 1>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 256, 32, 4, 1>), grid, dim3(GT), 0, s, e0, e1, L, A, B, C, W);
       break;
     case CFG_16x256:
-      LAUNCH((k_gemm<T, 16, 256, 1, 4>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 16, 256, 1, 4>), grid, dim3(GT), 0, s, e0, e1, L, A, B, C, W);
       break;
     case CFG_32x256:
-      LAUNCH((k_gemm<T, 32, 256, 1, 4>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 32, 256, 1, 4>), grid, dim3(GT), 0, s, e0, e1, L, A, B, C, W);
       break;
     default:
-      LAUNCH((k_gemm<T, 64, 64, 2, 2>), grid, dim3(GT), 0, s, L, A, B, C, W);
+      ELAUNCH((k_gemm<T, 64, 64, 2, 2>), grid, dim3(GT), 0, s, e0, e1, L, A, B, C, W);
       break;
   }
 }
@@ -649,26 +650,40 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   void* tok = prof_begin(s);
   if (p.kind == FTN_GEMM_F64) {
     if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
-    launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)wsp);
-    if (p.red_elems)
-      LAUNCH((k_splitk_reduce<double>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
-             (int)p.red_host.size(), p.red_elems, (const double*)wsp, (double*)C, alpha, beta);
+    launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)wsp,
+                       prof_ev(tok, 0), prof_ev(tok, 1));
+    HIPC(hipGetLastError());
+    // the GEMM kernel and the reduction are timed apart (per-kernel classes)
+    prof_end(tok, s, FTN_PROF_K_GEMM_F64_64x64 + p.cfg, p.flops, p.abytes * (double)es);
+    tok = nullptr;
+    if (p.red_elems) {
+      double rb = 0;  // partials read, output written (and read when accumulating)
+      for (auto& r : p.red_host) rb += (double)r.M * r.N * (r.S + 1 + (beta != 0.0 ? 1 : 0)) * es;
+      void* tr = prof_begin(s);
+      ELAUNCH((k_splitk_reduce<double>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, prof_ev(tr, 0),
+              prof_ev(tr, 1), p.red.p, (int)p.red_host.size(), p.red_elems, (const double*)wsp, (double*)C, alpha,
+              beta);
+      prof_end(tr, s, FTN_PROF_K_SPLITK_F64, rb, rb);
+    }
   } else if (p.kind == FTN_GEMM_F32) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 GEMM needs FP32 tensors");
-    launch_cfg<float>(p.cfg, grid, s, L, (const float*)A, (const float*)B, (float*)C, (float*)wsp);
+    // one timed call: the GEMM kernel's start to the reduction's end
+    launch_cfg<float>(p.cfg, grid, s, L, (const float*)A, (const float*)B, (float*)C, (float*)wsp, prof_ev(tok, 0),
+                      p.red_elems ? nullptr : prof_ev(tok, 1));
     if (p.red_elems)
-      LAUNCH((k_splitk_reduce<float>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, p.red.p,
-             (int)p.red_host.size(), p.red_elems, (const float*)wsp, (float*)C, alpha, beta);
+      ELAUNCH((k_splitk_reduce<float>), dim3((unsigned)cdiv(p.red_elems, 256)), dim3(256), 0, s, nullptr,
+              prof_ev(tok, 1), p.red.p, (int)p.red_host.size(), p.red_elems, (const float*)wsp, (float*)C, alpha,
+              beta);
   } else if (p.kind == FTN_GEMM_BF16X3) {
     if (dtype != FTN_F32) fail(FTN_ENOTSUP, "split-BF16 GEMM needs FP32 tensors");
-    LAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, dim3(GT), 0, s, L, (const float*)A,
-                       (const float*)B, (float*)C);
+    ELAUNCH((k_gemm_bf16x3<TBM, TBN, 32>), grid, dim3(GT), 0, s, prof_ev(tok, 0), prof_ev(tok, 1), L,
+            (const float*)A, (const float*)B, (float*)C);
   } else {
     fail(FTN_EINVAL, "unknown GEMM kind");
   }
   HIPC(hipGetLastError());
-  prof_end(tok, s, p.kind == FTN_GEMM_F64 ? FTN_PROF_GEMM_F64 : (p.kind == FTN_GEMM_F32 ? FTN_PROF_GEMM_F32 : FTN_PROF_GEMM_BF16X3),
-           p.flops, p.abytes * (double)es);
+  if (tok) prof_end(tok, s, p.kind == FTN_GEMM_F32 ? FTN_PROF_GEMM_F32 : FTN_PROF_GEMM_BF16X3, p.flops,
+                    p.abytes * (double)es);
   if (trace_time) {
     HIPC(hipEventRecord(te1, s));
     HIPC(hipEventSynchronize(te1));

@@ -855,11 +855,11 @@ static GemmGroup sym_group(GemmGroup g) {
 // Cholesky of a p x p matrix p^3/3, a triangular inverse p^3/3, and a
 // symmetric eigendecomposition with eigenvectors 9 n^3 (tridiagonal
 // reduction plus implicit QR), whatever the algorithm actually runs
-#define FACTOR_LAUNCH(work, ...)                 \
-  do {                                           \
-    void* tok_ = prof_begin(s);                  \
-    LAUNCH(__VA_ARGS__);                         \
-    prof_end(tok_, s, FTN_PROF_FACTOR, (work));  \
+#define FACTOR_LAUNCH(cls, work, kern, grid, block, shm, stream, ...)                          \
+  do {                                                                                       \
+    void* tok_ = prof_begin(s);                                                              \
+    ELAUNCH(kern, grid, block, shm, stream, prof_ev(tok_, 0), prof_ev(tok_, 1), __VA_ARGS__); \
+    prof_end(tok_, s, (cls), (work));                                                        \
   } while (0)
 
 static double orth_flops(const std::vector<OrthJob>& oj) {
@@ -911,12 +911,18 @@ static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>*
   int nsmall = 0;
   while (nsmall < nj && ord[nsmall].n < 63) ++nsmall;
   DBuf<EigJob> dj = to_device(ord, s);
-  void* tok = prof_begin(s);
-  if (nsmall > 0) LAUNCH(k_jacobi_sweep, dim3((unsigned)nsmall), dim3(LT), 0, s, dj.p);
-  if (nsmall < nj) LAUNCH(k_jacobi_sweep_la, dim3((unsigned)(nj - nsmall)), dim3(LT), 0, s, dj.p + nsmall);
+  if (nsmall > 0) {
+    const std::vector<EigJob> part(ord.begin(), ord.begin() + nsmall);
+    FACTOR_LAUNCH(FTN_PROF_K_JACOBI, eig_flops(part), k_jacobi_sweep, dim3((unsigned)nsmall), dim3(LT), 0, s, dj.p);
+  }
+  if (nsmall < nj) {
+    const std::vector<EigJob> part(ord.begin() + nsmall, ord.end());
+    FACTOR_LAUNCH(FTN_PROF_K_JACOBI_LA, eig_flops(part), k_jacobi_sweep_la, dim3((unsigned)(nj - nsmall)), dim3(LT), 0,
+                  s, dj.p + nsmall);
+  }
   if (nmax > 0)
-    LAUNCH(k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(nmax, JV_WAVES)), dim3(64 * JV_WAVES), 0, s, dj.p);
-  prof_end(tok, s, FTN_PROF_FACTOR, eig_flops(ej));
+    FACTOR_LAUNCH(FTN_PROF_K_JACOBI_VEC, 0.0, k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(nmax, JV_WAVES)),
+                  dim3(64 * JV_WAVES), 0, s, dj.p);
   if (rounds) {
     rounds->assign(nj, 0);
     for (int t = 0; t < nj; ++t)
@@ -1389,10 +1395,9 @@ static void svd_cols(std::vector<SvdJob>& sj, const std::vector<double*>& V, hip
   }
   DBuf<SvdJob> d = to_device(sj, s);
   DBuf<EigJob> de = to_device(ej, s);
-  void* tok = prof_begin(s);
-  LAUNCH(k_svd_cols, dim3((unsigned)nj), dim3(LT), 0, s, d.p, 1e-15);
-  LAUNCH(k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(cmax, JV_WAVES)), dim3(64 * JV_WAVES), 0, s, de.p);
-  prof_end(tok, s, FTN_PROF_FACTOR, f);
+  FACTOR_LAUNCH(FTN_PROF_K_SVD_COLS, f, k_svd_cols, dim3((unsigned)nj), dim3(LT), 0, s, d.p, 1e-15);
+  FACTOR_LAUNCH(FTN_PROF_K_JACOBI_VEC, 0.0, k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(cmax, JV_WAVES)),
+                dim3(64 * JV_WAVES), 0, s, de.p);
 }
 
 // per bond sector q
@@ -1545,7 +1550,7 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
       }
     }
     DBuf<OrthJob> doj = to_device(oj, s);
-    FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
     if (!gt.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Mout ? Mout : Minv.p, Gm, R12.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
@@ -1690,7 +1695,7 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
     }
     if (!oj.empty()) {
       DBuf<OrthJob> d = to_device(oj, s);
-      FACTOR_LAUNCH(orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, d.p, tol);
+      FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, d.p, tol);
     }
     if (!boff.empty()) chol_drop(R, boff, bdim, tol, s, M);
   };
@@ -1831,7 +1836,7 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
   // y <- orthonormal basis of span(y), dependent columns zeroed
   auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
     run_gemm(gram, FTN_F64, y, y, Gy.p, nullptr, s);
-    FACTOR_LAUNCH(of_it, k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(FTN_PROF_K_ORTH, of_it, k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
     run_gemm(app, FTN_F64, y, Mm.p, yt, nullptr, s);
     std::swap(y, yt);
   };

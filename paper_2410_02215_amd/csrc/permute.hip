@@ -465,11 +465,12 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
   const dim3 grid((unsigned)p.ntiles), block(PM_THREADS);
   if (dtype == FTN_F64) {
     auto k = dir == 0 ? k_block_perm<double, 0> : k_block_perm<double, 1>;
-    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.tile_task.p, (const double*)src, (double*)dst, alpha);
+    ELAUNCH(k, grid, block, 0, s, prof_ev(tok, 0), prof_ev(tok, 1), p.desc.p, p.tile_start.p, p.tile_task.p,
+            (const double*)src, (double*)dst, alpha);
   } else {
     auto k = dir == 0 ? k_block_perm<float, 0> : k_block_perm<float, 1>;
-    LAUNCH(k, grid, block, 0, s, p.desc.p, p.tile_start.p, p.tile_task.p, (const float*)src, (float*)dst,
-           (float)alpha);
+    ELAUNCH(k, grid, block, 0, s, prof_ev(tok, 0), prof_ev(tok, 1), p.desc.p, p.tile_start.p, p.tile_task.p,
+            (const float*)src, (float*)dst, (float)alpha);
   }
   HIPC(hipGetLastError());
   const double pb = 2.0 * (double)p.nelem * (dtype == FTN_F64 ? 8 : 4);

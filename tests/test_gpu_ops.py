@@ -268,3 +268,32 @@ def test_torch_owns_the_library_memory(P):
     del Ga, Gb, C, C2                                # back to torch
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() <= t0
+
+
+def test_profiler_kernel_classes_add_up_to_their_families(P):
+    # the per-kernel classes of the grouped GEMM and of the factorisation
+    # kernels partition their families' time, launches and work
+    from paper_2410_02215_amd import ftn
+    rng = np.random.default_rng(33)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(90, 70, 0), l(150, 130, 1)], total=(0,))
+    B = rand_tensor(rng, sym, [l(150, 130, 0), l(200, 180, 1)], total=(0,))
+    ga, gb = to_gpu(A), to_gpu(B)
+    torch.cuda.synchronize()
+    ftn.profile_collect()
+    ftn.profile_enable(True)
+    P.ftensordot(ga, gb, [1], [0])
+    P.compress_bond(ga, gb, 1, 0, 40)
+    torch.cuda.synchronize()
+    ftn.profile_enable(False)
+    pr = ftn.profile_collect()
+    gk = [k for k in ftn.PROF_CLASSES if k.startswith("k_gemm_f64_")]
+    fk = ["k_orth_factor", "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"]
+    assert pr["gemm_f64"][1] > 0 and pr["factor"][1] > 0
+    ms = sum(pr[k][0] for k in gk) + pr["k_splitk_reduce_f64"][0]
+    assert abs(ms - pr["gemm_f64"][0]) <= 1e-6 * pr["gemm_f64"][0] + 1e-9
+    assert sum(pr[k][1] for k in gk) == pr["gemm_f64"][1]
+    assert abs(sum(pr[k][2] for k in gk) - pr["gemm_f64"][2]) <= 1e-9 * pr["gemm_f64"][2]
+    assert abs(sum(pr[k][0] for k in fk) - pr["factor"][0]) <= 1e-6 * pr["factor"][0] + 1e-9
+    assert sum(pr[k][1] for k in fk if k != "k_jacobi_vectors") == pr["factor"][1]
