@@ -94,7 +94,7 @@ def gpu_setup(cfg, paths):
                 streams=streams)
 
 
-def gpu_step(g, chi, concurrent=True):
+def gpu_step(g, chi, concurrent=True, gemm=None):
     """One step: the norm and the hopping-term contraction.
 
     The two contractions are independent. By default they run at the same
@@ -111,7 +111,10 @@ def gpu_step(g, chi, concurrent=True):
     def run(k):
         try:
             with torch.cuda.stream(g["streams"][k]):
-                out[k] = jobs[k][0].contract(jobs[k][1], chi=chi)
+                if gemm is None:
+                    out[k] = jobs[k][0].contract(jobs[k][1], chi=chi)
+                else:
+                    out[k] = jobs[k][0].contract(jobs[k][1], chi=chi, gemm=gemm)
         except Exception as ex:  # re-raised in the caller
             err[k] = ex
 
@@ -128,6 +131,55 @@ def gpu_step(g, chi, concurrent=True):
             raise ex
     (m1, e1, s1), (m2, e2, s2) = out
     return (m1, e1, m2, e2), (s1, s2)
+
+
+def to_f32(P, t):
+    """FP32 copy of a library tensor (entries rounded to nearest)."""
+    inf = t.info()
+    return P.Tensor.create(inf["sym"], t.legs(), inf["total"], P.F32, data=t.data().float())
+
+
+def to_f64(P, t):
+    """FP64 copy of a library tensor."""
+    inf = t.info()
+    return P.Tensor.create(inf["sym"], t.legs(), inf["total"], P.F64, data=t.data().double())
+
+
+def c2_forms(P, cfg, g, chi, steps, golden):
+    """The same workload with FP32 tensors and FP32 or split-BF16 block GEMMs
+    (compression and the final reduction in FP64), measured after the timed
+    FP64 region: contractions/s and error against the oracle."""
+    import torch
+    from paper_2410_02215_amd import peps as GP
+    spec = cfg["spec"]
+    k32 = [to_f32(P, k) for k in g["kets"]]
+    op32 = to_f32(P, g["op"])
+    g32 = dict(g, nn=GP.norm_network(spec, k32), nh=GP.norm_network(spec, k32, op=op32, op_sites=cfg["op_sites"]))
+    # the FP64 path on the FP32-rounded inputs: the reference that isolates
+    # the error of the FP32 arithmetic from the rounding of the inputs
+    k64r = [to_f64(P, k) for k in k32]
+    g64r = dict(g, nn=GP.norm_network(spec, k64r),
+                nh=GP.norm_network(spec, k64r, op=to_f64(P, op32), op_sites=cfg["op_sites"]))
+    r64, _ = gpu_step(g64r, chi, True)
+    n64 = r64[0] * 2.0 ** r64[1]
+    h64 = (r64[2] / r64[0]) * 2.0 ** (r64[3] - r64[1])
+    out = {}
+    for name, gemm in (("f32", P.GEMM_F32), ("bf16x3", P.GEMM_BF16X3)):
+        gpu_step(g32, chi, True, gemm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, _ = gpu_step(g32, chi, True, gemm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        norm = res[0] * 2.0 ** res[1]
+        hop = (res[2] / res[0]) * 2.0 ** (res[3] - res[1])
+        out[name] = {"value": 2.0 * steps / el, "ms_per_step": 1000.0 * el / steps, "steps": steps,
+                     "rel_err_vs_oracle": golden(norm, hop),
+                     "rel_err_vs_f64_same_inputs": {"norm": abs(norm - n64) / abs(n64),
+                                                    "hop_term": abs(hop - h64) / abs(h64)}}
+        print("[bench] form %s: %.3f contractions/s" % (name, out[name]["value"]), file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(cfg, paths, runs=3):
@@ -265,10 +317,48 @@ def main_amplitudes(args):
         # more than one worker the line carries wall-clock rates only
         "roofline": roofline(prof, cfg["name"]) if any(prof[c][0] > 0 for c in prof) else None,
     }
+    if not args.no_forms:
+        out["forms"] = amplitude_forms(P, cfg, g, g["samples"][k - B:k], args.workers, m, e)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, %d amplitudes)" % args.cpu_samples, file=sys.stderr, flush=True)
         out["cpu_baseline"] = amplitude_cpu_baseline(cfg, g, args.cpu_samples)
     print(json.dumps(out), flush=True)
+
+
+def amplitude_forms(P, cfg, g, samples, workers, m64, e64):
+    """After the timed batches: the last batch again as the plain FP64 loop
+    (one worker, one sample after the other; a subset of 16) and with FP32 site
+    tensors and FP32 block GEMMs (compression in FP64) over the same workers,
+    with the error of every amplitude against the FP64 result."""
+    import numpy as np
+    import torch
+    out = {}
+    sub = samples[:16]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.amplitudes(g["kets"], g["bonds"], g["path"], sub, chi=cfg["chi"], nworkers=1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["plain_f64"] = {"value": len(sub) / el, "samples": len(sub), "workers": 1}
+    k32 = [to_f32(P, k) for k in g["kets"]]
+    P.amplitudes(k32, g["bonds"], g["path"], samples[:4], chi=cfg["chi"], gemm=P.GEMM_F32, nworkers=workers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m32, e32 = P.amplitudes(k32, g["bonds"], g["path"], samples, chi=cfg["chi"], gemm=P.GEMM_F32, nworkers=workers)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m64, e64 = np.asarray(m64, dtype=np.float64), np.asarray(e64, dtype=np.int64)
+    ok = m64 != 0
+    rel = np.abs(np.asarray(m32)[ok] * np.exp2((np.asarray(e32)[ok] - e64[ok]).astype(np.float64)) - m64[ok]) \
+        / np.abs(m64[ok])
+    out["f32"] = {"value": len(samples) / el, "samples": len(samples), "workers": workers,
+                  "rel_err_vs_f64": {"max": float(rel.max()) if rel.size else None,
+                                     "median": float(np.median(rel)) if rel.size else None}}
+    out["note"] = ("plain_f64: the same amplitudes one after the other on one worker; f32: FP32 site tensors and "
+                   "block GEMMs, compression in FP64, error against the FP64 amplitudes of the timed batch")
+    print("[bench] forms: plain %.2f/s, f32 %.2f/s" % (out["plain_f64"]["value"], out["f32"]["value"]),
+          file=sys.stderr, flush=True)
+    return out
 
 
 def main_gradient(args):
@@ -394,6 +484,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32 / split-BF16 forms measured after the FP64 timed region")
     ap.add_argument("--serial", action="store_true", help="run the two contractions of a step one after the other")
     ap.add_argument("--workload", choices=["c2", "amplitudes", "gradient"], default="c2",
                     help="c2: the 40-site norm and hopping contractions (default); amplitudes: <n|psi> of the "
@@ -490,6 +582,15 @@ def main():
         "timed_window_ns": [w0, w1],
         "roofline": roof,
     }
+    if not args.no_forms:
+        out["forms"] = c2_forms(P, cfg, g, chi, min(args.steps, 3), golden_errors)
+        out["forms"]["f64"] = {"value": value, "ms_per_step": ms_step, "steps": args.steps,
+                               "rel_err_vs_oracle": out["rel_err_vs_oracle"]}
+        out["forms"]["note"] = ("FP32 tensors with FP32 or split-BF16 (three BF16 products, FP32 accumulation) "
+                                "block GEMMs, compression and final reduction in FP64; measured after the FP64 "
+                                "timed region on the same workload and streams. rel_err_vs_oracle includes the "
+                                "rounding of the inputs to FP32; rel_err_vs_f64_same_inputs compares with the FP64 "
+                                "path run on the rounded inputs (the error of the reduced-precision arithmetic)")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, norm contractions: warm-up + 3)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, paths)

@@ -301,8 +301,12 @@ int ftn_compress_bond(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int6
    Valid for losses unchanged by a_out -> a_out D, b_out -> D b_out with D
    diagonal +-1 (sign of each kept singular vector pair); couplings of
    singular values closer than 1e-13 s_max^2 are dropped. FP64 only
-   (FTN_ENOTSUP otherwise); bond sectors of dimension up to 128 (FTN_ENOTSUP
-   for larger ones). Synchronises the stream. */
+   (FTN_ENOTSUP otherwise); bond sectors of dimension up to 1024 (FTN_ENOTSUP
+   for larger ones): the eigenpairs of X X^T come from Jacobi sweeps in LDS up
+   to order 128 and from block Jacobi above (pairs of blocks of at most 64
+   diagonalised in LDS, the whole matrix rotated by GEMMs, until the
+   off-diagonal norm is at most 8 n u of the matrix's). Synchronises the
+   stream. */
 int ftn_compress_bond_backward(ftn_tensor_t a, ftn_tensor_t b, int leg_a, int leg_b, int64_t chi,
                                double cutoff, ftn_conv conv, ftn_tensor_t da_out, ftn_tensor_t db_out,
                                ftn_stream_t stream, ftn_tensor_t* da, ftn_tensor_t* db);
@@ -354,7 +358,7 @@ int ftn_contract_network(ftn_net_t net, int nsteps, const int32_t* ssa_path, int
    backwards through the adjoints of contraction (Eq. standardcontract is
    bilinear), fusion (a signed permutation) and compression (the truncated-SVD
    derivative of ftn_compress_bond_backward, kept counts fixed; bond sectors up
-   to 128), each rescaling by its own power of two, and the sign of the dummy
+   to 1024), each rescaling by its own power of two, and the sign of the dummy
    legs of odd tensors as a constant factor. value = mantissa * 2^exp2;
    grads[t] (ntensors new handles, structure of tensor t) holds
    d(value)/d(tensor t) * 2^-exp2. checkpoint = 0 keeps every intermediate for

@@ -504,7 +504,7 @@ class Network:
         return m.value, e.value, stats
 
 
-def _network_grad(self, path, chi=0, checkpoint=0):
+def _network_grad(self, path, chi=0, checkpoint=0, gemm=GEMM_F64):
     """(mantissa, exp2, grads) of a closed network: value = m * 2**e and
     grads[t] = d(value)/d(tensor t) * 2**-e, computed by the library's
     backward pass (checkpoint: path steps per recomputation segment, 0 keeps
@@ -516,7 +516,7 @@ def _network_grad(self, path, chi=0, checkpoint=0):
     e = ctypes.c_int64()
     n = len(self.tensors)
     gh = (ctypes.c_void_p * n)()
-    _check(_lib.ftn_contract_network_grad(self.h, len(path), _arr(flat, ctypes.c_int32), int(chi or 0), GEMM_F64,
+    _check(_lib.ftn_contract_network_grad(self.h, len(path), _arr(flat, ctypes.c_int32), int(chi or 0), int(gemm),
                                           int(checkpoint), _stream(), ctypes.byref(m), ctypes.byref(e), gh))
     return m.value, e.value, [Tensor(ctypes.c_void_p(gh[t])) for t in range(n)]
 

@@ -483,3 +483,30 @@ def test_differentiation_workload_hop_gradient_at_chi32(P):
     assert verr <= 1e-10
     assert gerr <= 1e-10
     assert perr <= 1e-10
+
+
+def test_network_gradient_and_axpy_reject_unsupported_arguments(P):
+    # FP32 tensors or GEMM forms, an open network and a negative checkpoint
+    # are refused with an error code; axpy needs one structure
+    rng = np.random.default_rng(36)
+    sym = S.Z2
+    l = lambda e, o, d: make_leg(sym, [(0,), (1,)], [e, o], d)
+    A = rand_tensor(rng, sym, [l(2, 2, 0), l(3, 1, 1)], total=(0,))
+    B = rand_tensor(rng, sym, [l(3, 1, 0), l(2, 2, 1)], total=(0,))
+    closed = P.Network([to_gpu(A), to_gpu(B)], [(0, 0, 1, 1), (0, 1, 1, 0)], conv=P.LOCAL)
+    with pytest.raises(P.FtnError) as e:
+        closed.contract_grad([(0, 1)], chi=0, gemm=P.GEMM_F32)
+    assert e.value.code == -6  # FTN_ENOTSUP
+    with pytest.raises(P.FtnError) as e:
+        closed.contract_grad([(0, 1)], chi=0, checkpoint=-1)
+    assert e.value.code == -1  # FTN_EINVAL
+    opened = P.Network([to_gpu(A), to_gpu(B)], [(0, 1, 1, 0)], conv=P.LOCAL)
+    with pytest.raises(P.FtnError) as e:
+        opened.contract_grad([(0, 1)], chi=0)
+    assert e.value.code == -6
+    with pytest.raises(P.FtnError) as e:
+        P.ftn.axpy(1.0, to_gpu(A), to_gpu(B))
+    assert e.value.code == -1
+    # the exact gradient of the closed pair is the other tensor, arranged
+    m, ex, g = closed.contract_grad([(0, 1)], chi=0)
+    assert len(g) == 2 and m != 0.0
