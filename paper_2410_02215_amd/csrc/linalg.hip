@@ -1411,6 +1411,7 @@ struct Sect {
   bool sideA = true;     // eigenvectors live on the A side (U) or the B side (V)
   bool acc = false;      // d <= 128: accurate factors, X formed explicitly
   bool svd = false;      // spectrum redone by the one-sided Jacobi SVD of X (V available)
+  bool thin = false;     // N <= d < M: spectrum from Y = A~ B~ (M x N), no factor of A~
   int kept = 0;
   Q charge;
   int crank = 0;
@@ -1648,14 +1649,17 @@ struct AccSrc {
   int64_t goff;  // Gram matrix and output R (d x d) offset
   int d;
   int64_t qoff = 0;  // optional output Q (m x d) offset
+  int64_t moff = 0;  // optional output R^-1 (d x d, dropped columns zero) offset
 };
 
 // R (d x d, zero rows for dropped directions) of every listed factor into
 // Rout at goff, from the Gram matrices Gm at goff and the sources; with Qout,
 // also Q (m x d, orthonormal kept columns, zero dropped ones) at qoff, so
-// that the source equals Q R
+// that the source equals Q R; with Minv as well, the inverse used for Q
+// (source x Minv = Q, the product of the three passes' inverses with
+// dropped columns zero) at moff
 static void acc_factor(const std::vector<AccSrc>& J, const double* At, const double* Bt, const double* Gm,
-                       double* Rout, hipStream_t s, double* Qout = nullptr) {
+                       double* Rout, hipStream_t s, double* Qout = nullptr, double* Minv = nullptr) {
   const int nj = (int)J.size();
   if (!nj) return;
   std::vector<int64_t> wo(nj), qo(nj);
@@ -1734,6 +1738,17 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
       gq3.push_back(plain_group(J[j].m, J[j].d, J[j].d, qs + qo[j], J[j].d, 0, 6 * ws + wo[j], J[j].d, 0, J[j].qoff,
                                 J[j].d));
     run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gq3, Q.p, W.p, Qout, nullptr, s);
+    if (Minv) {
+      // M1 M2 into the free T slot, then (M1 M2) M3
+      std::vector<GemmGroup> g12, g123;
+      for (int j = 0; j < nj; ++j) {
+        const int64_t d = J[j].d;
+        g12.push_back(plain_group(d, d, d, 3 * ws + wo[j], d, 0, 4 * ws + wo[j], d, 0, 5 * ws + wo[j], d));
+        g123.push_back(plain_group(d, d, d, 5 * ws + wo[j], d, 0, 6 * ws + wo[j], d, 0, J[j].moff, d));
+      }
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g12, W.p, W.p, W.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, g123, W.p, W.p, Minv, nullptr, s);
+    }
   }
 }
 
@@ -2015,6 +2030,12 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     std::sort(order.begin(), order.end(), [&](int x, int y) { return q_lt(S[x].charge, S[y].charge); });
     for (int r = 0; r < ng; ++r) S[order[r]].crank = r;
   }
+  // Sectors with d <= 128 whose B side is thin (N <= d) while A~ is tall
+  // (M > d): the product C = A~ B~ has rank <= N, and its singular values and
+  // right singular vectors are those of R_Y from a QR of Y = A~ B~ (M x N,
+  // shifted Cholesky QR three times), so the tall A~ is never factored (its
+  // Gram matrix and Cholesky-QR passes cost M d^2 each, Y's M N^2).
+  for (auto& x : S) x.thin = x.d <= JMAX && x.N >= 1 && x.N <= x.d && x.M > x.d;
   // Gram matrices with split-K
   std::vector<int64_t> goffA(ng), goffB(ng);
   int64_t gsz = 0;
@@ -2034,6 +2055,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     for (int k = 0; k < nsplit; ++k)
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
+        if (x.thin) continue;  // neither Gram matrix is used
         int64_t ca = cdiv(x.M, nsplit), k0 = std::min<int64_t>(k * ca, x.M), k1 = std::min<int64_t>(k0 + ca, x.M);
         // G_A = A~^T A~ : op(A) = A~^T (transA, lda = d), op(B) = A~ (ldb = d)
         gA.push_back(sym_group(plain_group(x.d, x.d, k1 - k0, x.a_off + k0 * x.d, x.d, 1, x.a_off + k0 * x.d, x.d,
@@ -2043,8 +2065,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         gB.push_back(sym_group(plain_group(x.d, x.d, j1 - j0, x.b_off + j0, x.N, 0, x.b_off + j0, x.N, 1,
                                            (int64_t)k * gsz + goffB[g], x.d)));
       }
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gA, At.p, At.p, part.p, nullptr, s);
-    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gB, Bt.p, Bt.p, part.p, nullptr, s);
+    if (!gA.empty()) {
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gA, At.p, At.p, part.p, nullptr, s);
+      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gB, Bt.p, Bt.p, part.p, nullptr, s);
+    }
     LAUNCH(k_sum_partials, dim3((unsigned)cdiv(gsz, 256)), dim3(256), 0, s, part.p, gsz, nsplit, Gm.p);
     HIPC(hipGetLastError());
   }
@@ -2067,6 +2091,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       for (int side = 0; side < 2; ++side) {
         const int64_t off = side ? goffB[g] : goffA[g];
         const int64_t m = side ? x.N : x.M;
+        if (x.thin && side == 0) {  // R_Y stands in for R_A R_B^T (below)
+          ranks[2 * g] = (int)x.N;
+          continue;
+        }
         if (x.d > JMAX) {
           HIPC(hipMemcpyAsync(Fm.p + off, Gm.p + off, x.d * x.d * 8, hipMemcpyDeviceToDevice, s));
           coffs.push_back(off);
@@ -2116,6 +2144,75 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     }
     HIPC(hipStreamSynchronize(s));
     for (int i = 0; i < np; ++i) ranks[pidx[i]] = prk[i];
+  }
+  // thin sectors: Y = A~ B~ (M x N) and R_Y (N x N) from its QR; a left
+  // inverse E of B~ (d x N) for the B-side projector P_B = S^1/2 V_k^T E (so
+  // that P_B B~ = S^1/2 V_k^T): E0 = R_t^-1 Q_t^T from the QR of B~, then one
+  // Newton step E = 2 E0 - (E0 B~) E0, which squares the residual I - E B~
+  // (E0 alone leaves it at about u cond(B~)^2)
+  std::vector<int64_t> tyo(ng, 0), tno(ng, 0), tqo(ng, 0);
+  int64_t tys = 0, tns = 0, tqs = 0;
+  for (int g = 0; g < ng; ++g) {
+    const Sect& x = S[g];
+    if (!x.thin) continue;
+    tyo[g] = tys;
+    tys += x.M * x.N;
+    tno[g] = tns;
+    tns += x.N * x.N;
+    tqo[g] = tqs;
+    tqs += x.d * x.N;
+  }
+  DBuf<double> RY(std::max<int64_t>(tns, 1), s), Rti(std::max<int64_t>(tns, 1), s), Qt(std::max<int64_t>(tqs, 1), s),
+      El(std::max<int64_t>(tqs, 1), s);
+  if (tns) {
+    DBuf<double> Yb(tys, s), GY(tns, s), Gt(tns, s), Rt(tns, s);
+    std::vector<GemmGroup> gy, ggy, ggt;
+    std::vector<AccSrc> jy, jt;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.thin) continue;
+      gy.push_back(plain_group(x.M, x.N, x.d, x.a_off, x.d, 0, x.b_off, x.N, 0, tyo[g], x.N));
+      ggy.push_back(sym_group(plain_group(x.N, x.N, x.M, tyo[g], x.N, 1, tyo[g], x.N, 0, tno[g], x.N)));
+      ggt.push_back(sym_group(plain_group(x.N, x.N, x.d, x.b_off, x.N, 1, x.b_off, x.N, 0, tno[g], x.N)));
+      AccSrc u;
+      u.side = 0;
+      u.trans = 0;
+      u.off = tyo[g];
+      u.ld = x.N;
+      u.m = x.M;
+      u.goff = tno[g];
+      u.d = (int)x.N;
+      jy.push_back(u);
+      AccSrc t;
+      t.side = 1;
+      t.trans = 0;
+      t.off = x.b_off;
+      t.ld = x.N;
+      t.m = x.d;
+      t.goff = tno[g];
+      t.d = (int)x.N;
+      t.qoff = tqo[g];
+      t.moff = tno[g];
+      jt.push_back(t);
+    }
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gy, At.p, Bt.p, Yb.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggy, Yb.p, Yb.p, GY.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggt, Bt.p, Bt.p, Gt.p, nullptr, s);
+    acc_factor(jy, Yb.p, Bt.p, GY.p, RY.p, s);
+    acc_factor(jt, Yb.p, Bt.p, Gt.p, Rt.p, s, Qt.p, Rti.p);
+    std::vector<GemmGroup> ge0, gz, ge1;
+    for (int g = 0; g < ng; ++g) {
+      const Sect& x = S[g];
+      if (!x.thin) continue;
+      ge0.push_back(plain_group(x.N, x.d, x.N, tno[g], x.N, 0, tqo[g], x.N, 1, tqo[g], x.d));  // E0 = R_t^-1 Q_t^T
+      gz.push_back(plain_group(x.N, x.N, x.d, tqo[g], x.d, 0, x.b_off, x.N, 0, tno[g], x.N));    // Z = E0 B~
+      ge1.push_back(plain_group(x.N, x.d, x.N, tno[g], x.N, 0, tqo[g], x.d, 0, tqo[g], x.d));   // E = 2 E0 - Z E0
+    }
+    DBuf<double> E0(tqs, s), Zt(tns, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ge0, Rti.p, Qt.p, E0.p, nullptr, s);
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gz, E0.p, Bt.p, Zt.p, nullptr, s);
+    HIPC(hipMemcpyAsync(El.p, E0.p, tqs * 8, hipMemcpyDeviceToDevice, s));
+    run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ge1, Zt.p, E0.p, El.p, nullptr, s, -1.0, 2.0);
   }
   // per sector: the side with the smaller rank (A when rA <= rB, and always
   // for iterated sectors) gives R = R_side, G_o = the other Gram matrix;
@@ -2169,9 +2266,13 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       }
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
       if (x.acc) {
-        // accurate factors: X = R R_o^T (r x r_o), H = X X^T
+        // accurate factors: X = R R_o^T (r x r_o), H = X X^T; a thin sector
+        // takes X = R_Y (N x N: the same singular values and right vectors)
         const int64_t r = x.ns, r_o = x.sideA ? x.rB : x.rA;
-        gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
+        if (x.thin)
+          HIPC(hipMemcpyAsync(Xm.p + xoff[g], RY.p + tno[g], x.N * x.N * 8, hipMemcpyDeviceToDevice, s));
+        else
+          gxs.push_back(plain_group(r, r_o, x.d, ro, x.d, 0, go, x.d, 1, xoff[g], r_o));
         gxh.push_back(sym_group(plain_group(r, r, r_o, xoff[g], r_o, 0, xoff[g], r_o, 1, hoff[g], r)));
         continue;
       }
@@ -2180,10 +2281,8 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       gh.push_back(plain_group(x.ns, x.ns, x.d, ro, x.d, 0, u1off[g], x.ns, 0, hoff[g], x.ns));
     }
     if (!gx.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gx, Rc.p, Rc.p, Xm.p, nullptr, s);
-    if (!gxs.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxh, Xm.p, Xm.p, Hm.p, nullptr, s);
-    }
+    if (!gxs.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxs, Rc.p, Rc.p, Xm.p, nullptr, s);
+    if (!gxh.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gxh, Xm.p, Xm.p, Hm.p, nullptr, s);
     if (!gu.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gu, Gm.p, Rc.p, U1.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gh, Rc.p, U1.p, Hm.p, nullptr, s);
@@ -2289,7 +2388,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       double smax = 0;
       for (double v : vals) smax = std::max(smax, v);
       std::string d;
-      for (int g = 0; g < ng; ++g) d += std::to_string(S[g].d) + ":" + std::to_string(kept[g]) + " ";
+      for (int g = 0; g < ng; ++g)
+        d += std::to_string(S[g].d) + ":" + std::to_string(kept[g]) + "(" + std::to_string(S[g].M) + "x" +
+             std::to_string(S[g].N) + " r" + std::to_string(S[g].rA) + "/" + std::to_string(S[g].rB) + ") ";
       std::fprintf(stderr, "[ftn] compress: sectors %s chi-th %.17g next %.17g max %.17g\n", d.c_str(), a1, a2, smax);
     }
     for (int g = 0; g < ng; ++g) S[g].kept = kept[g];
@@ -2345,7 +2446,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       if (!x.kept) continue;
       const int64_t r = x.sideA ? x.rA : x.rB;
       const int64_t ro = x.sideA ? goffA[g] : goffB[g], go = x.sideA ? goffB[g] : goffA[g];
-      gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
+      if (!x.thin) gf.push_back(plain_group(x.d, x.kept, r, ro, x.d, 1, eoff[g], x.p, 0, fo[g], x.kept));
       if (x.acc) {
         // W_k = V_k S_k: from the accumulated rotations of the one-sided SVD,
         // else X^T E_k (accurate while the kept values stay above 1e-4 s_max)
@@ -2359,8 +2460,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
         ggf.push_back(plain_group(x.d, x.kept, x.d, go, x.d, 0, fo[g], x.kept, 0, fo[g], x.kept));
       }
     }
-    if (!gf.empty()) {
-      run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gf, Rc.p, Em.p, Fk.p, nullptr, s);
+    bool anykept = false;
+    for (int g = 0; g < ng; ++g) anykept = anykept || S[g].kept > 0;
+    if (anykept) {
+      if (!gf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gf, Rc.p, Em.p, Fk.p, nullptr, s);
       if (!ggf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, ggf, Gm.p, Fk.p, GF.p, nullptr, s);
       if (!scols.empty()) {
         int64_t mx = 1;
@@ -2371,6 +2474,17 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       }
       if (!gw.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gw, Xm.p, Em.p, Wk.p, nullptr, s);
       if (!gwf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);
+      {
+        // thin sectors: F = E^T W_k (W_k = V_k S_k), so that
+        // P_B = S^-1/2 F^T = S^1/2 V_k^T E
+        std::vector<GemmGroup> gt1;
+        for (int g = 0; g < ng; ++g) {
+          const Sect& x = S[g];
+          if (!x.kept || !x.thin) continue;
+          gt1.push_back(plain_group(x.d, x.kept, x.N, tqo[g], x.d, 1, wo[g], x.kept, 0, fo[g], x.kept));
+        }
+        if (!gt1.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt1, El.p, Wk.p, Fk.p, nullptr, s);
+      }
       for (int g = 0; g < ng; ++g) {
         const Sect& x = S[g];
         if (!x.kept) continue;
