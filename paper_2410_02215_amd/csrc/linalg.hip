@@ -2034,7 +2034,10 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   // (M > d): the product C = A~ B~ has rank <= N, and its singular values and
   // right singular vectors are those of R_Y from a QR of Y = A~ B~ (M x N,
   // shifted Cholesky QR three times), so the tall A~ is never factored (its
-  // Gram matrix and Cholesky-QR passes cost M d^2 each, Y's M N^2).
+  // Gram matrix and Cholesky-QR passes cost M d^2 each, Y's M N^2). (For
+  // d > 128 the same route measured slower on the 40-site workload: those
+  // sectors' A sides are not tall enough to pay for its extra small
+  // factorisations, and their spectra send them to the one-sided SVD.)
   for (auto& x : S) x.thin = x.d <= JMAX && x.N >= 1 && x.N <= x.d && x.M > x.d;
   // Gram matrices with split-K
   std::vector<int64_t> goffA(ng), goffB(ng);
@@ -2095,7 +2098,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
           ranks[2 * g] = (int)x.N;
           continue;
         }
-        if (x.d > JMAX) {
+        if (x.d > JMAX && !x.thin) {
           HIPC(hipMemcpyAsync(Fm.p + off, Gm.p + off, x.d * x.d * 8, hipMemcpyDeviceToDevice, s));
           coffs.push_back(off);
           cdims.push_back(x.d);
@@ -2228,7 +2231,7 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     x.iterate = x.ns > JMAX;
     x.p = x.iterate ? JMAX : x.ns;
     x.sideA = x.iterate || x.rA <= x.rB;
-    x.acc = x.d <= JMAX;
+    x.acc = x.d <= JMAX || x.thin;
     xoff[g] = xs;
     xs += (x.iterate || x.acc) ? (int64_t)x.rA * x.rB : 0;
     hoff[g] = hs;

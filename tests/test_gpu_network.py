@@ -289,6 +289,40 @@ def test_compress_mixed_sector_sizes(P, dims):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("case", [
+    ((90, 70), (300, 260), (8, 5), 20),      # d <= 128, thin B side, nothing truncated
+    ((120, 100), (900, 700), (60, 40), 30),  # d <= 128, thin B side, truncated
+    ((300, 200), (700, 500), (100, 128), 60),  # d > 128 (the Gram route) beside the same shapes
+    ((80, 60), (400, 300), (16, 12), 10),    # thin, with B~ of rank below N
+])
+def test_compress_thin_b_side_matches_oracle(P, case):
+    # sectors whose B side is thin (N <= d, N <= 128) and A~ tall (M > d):
+    # spectrum from the QR of Y = A~ B~, B projector through a left inverse
+    # of B~; kept dims bit-exact and the compressed product against the oracle
+    (d0, d1), (m0, m1), (n0, n1), chi = case
+    rng = np.random.default_rng(811 + d0)
+    sym = S.Z2
+    from oracle.tensor import make_leg, FTensor
+    bond = make_leg(sym, [(0,), (1,)], [d0, d1], 1)
+    ra = make_leg(sym, [(0,), (1,)], [m0, m1], 0)
+    rb = make_leg(sym, [(0,), (1,)], [n0, n1], 1)
+    A = FTensor.zeros(sym, [ra, bond], (0,))
+    B = FTensor.zeros(sym, [partner(bond), rb], (0,))
+    for q, (m, d, n) in enumerate(((m0, d0, n0), (m1, d1, n1))):
+        A.blocks[(q, q)] = torch.from_numpy(rng.standard_normal((m, d)))
+        Bq = rng.standard_normal((d, n)) * np.logspace(0, -2, n)[None, :]
+        if chi == 10:  # two dependent columns of B~
+            Bq[:, -1] = Bq[:, 0] - 2.0 * Bq[:, 1]
+        B.blocks[(q, q)] = torch.from_numpy(Bq)
+    A2, B2, info = o_compress(A, B, 1, 0, chi, cutoff=1e-12)
+    ref = ftensordot(A2, B2, [1], [0]).to_dense()
+    GA, GB, ginfo = P.compress_bond(to_gpu(A), to_gpu(B), 1, 0, chi, 1e-12)
+    assert GA.legs()[1][1] == list(A2.legs[1].dims)
+    got = P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy()
+    assert np.all(np.isfinite(got))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
 def test_concurrent_contractions_on_two_streams(P):
     # two independent approximate contractions issued from two host threads on
     # two streams give exactly the results of running them one after another
