@@ -35,10 +35,11 @@ for _k in ("64x64", "128x128", "256x16", "256x32", "16x256", "32x256"):
     PEAK["k_gemm_f64_" + _k] = (78.6, "TFLOP/s", "mfma")
 for _k in ("k_orth_factor", "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"):
     PEAK[_k] = (78.6, "TFLOP/s", "alu")
+PEAK["k_skinny_f64"] = (8000.0, "GB/s", "hbm")  # tall-skinny A^T B reads A and B once
 # single kernels (the classes gemm_f64 and factor are families of kernels)
 KERNELS = ["gemm_f32", "gemm_bf16x3", "permute", "k_splitk_reduce_f64", "k_gemm_f64_64x64", "k_gemm_f64_128x128",
            "k_gemm_f64_256x16", "k_gemm_f64_256x32", "k_gemm_f64_16x256", "k_gemm_f64_32x256", "k_orth_factor",
-           "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"]
+           "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols", "k_skinny_f64"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 

@@ -704,9 +704,264 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tall-skinny products C = alpha op(A)^T B (+ beta C), A (K x M) and B (K x N)
+// row-major with M, N <= 32 and a long K: the Gram matrices of tall thin
+// factors. They are bound by reading A and B once; MFMA tiles of 64 x 64
+// would leave nearly all of their work and loads idle. C is cut into 8 x 8
+// parts; each thread owns one part (64 accumulators in registers) and a
+// stride of rows of its workgroup's chunk of K, reading its eight entries of
+// A and of B per row straight from memory. The threads of one part are
+// summed by a fixed butterfly across the wavefront and then across the
+// workgroup's waves in LDS; the chunks' partial C go to a workspace that a
+// second kernel sums in a fixed order into C, so results are deterministic.
+constexpr int SK_T = 256, SK_MAX = 32, SK_P = 8;
+
+struct SkinnyGroup {
+  int64_t M, N, K, a_off, lda, b_off, ldb, c_off, ldc, w_off, kc;
+  int chunks, pp;  // chunks of K; parts of C rounded up to a power of two
+  int same, pad;   // B is A (same matrix, offsets and strides): diagonal parts load one row
+};
+
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+
+// eight entries of a row; VEC: as four aligned pairs (the host checked the
+// alignment of every row start), else one by one with entries past `lim`
+// read as zero
+template <typename T, bool VEC>
+__device__ __forceinline__ void skinny_row(T (&x)[SK_P], const T* p, int lim) {
+  if constexpr (VEC) {
+    using P2 = typename Pair2<T>::type;
+#pragma unroll
+    for (int a = 0; a < SK_P / 2; ++a) {
+      const P2 v = reinterpret_cast<const P2*>(p)[a];
+      x[2 * a] = v.x;
+      x[2 * a + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < SK_P; ++a) x[a] = a < lim ? p[a] : T(0);
+  }
+}
+
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(SK_T) k_skinny_atb(const SkinnyGroup* gs, const T* __restrict__ A,
+                                                     const T* __restrict__ B, T* __restrict__ W) {
+  const SkinnyGroup G = gs[blockIdx.y];
+  const int ch = blockIdx.x;
+  if (ch >= G.chunks) return;
+  __shared__ T red[SK_T / 64][(SK_MAX / SK_P) * (SK_MAX / SK_P)][SK_P * SK_P];
+  const int m = (int)G.M, n = (int)G.N, t = threadIdx.x, pp = G.pp;
+  const int pn = (n + SK_P - 1) / SK_P, np = ((m + SK_P - 1) / SK_P) * pn;
+  const int part = t % pp, lane_rows = SK_T / pp, rl = t / pp;
+  const int i0 = (part / pn) * SK_P, j0 = (part % pn) * SK_P;
+  const bool act = part < np;
+  T acc[SK_P][SK_P];
+#pragma unroll
+  for (int a = 0; a < SK_P; ++a)
+#pragma unroll
+    for (int b = 0; b < SK_P; ++b) acc[a][b] = T(0);
+  const int64_t k0 = (int64_t)ch * G.kc, k1 = k0 + G.kc < G.K ? k0 + G.kc : G.K;
+  if (act) {
+    const T* pa = A + G.a_off + i0;
+    const T* pb = B + G.b_off + j0;
+    const bool diag = G.same && i0 == j0;
+#pragma unroll 2
+    for (int64_t r = k0 + rl; r < k1; r += lane_rows) {
+      T xa[SK_P], xb[SK_P];
+      skinny_row<T, VEC>(xa, pa + r * G.lda, m - i0);
+      if (diag) {
+#pragma unroll
+        for (int b = 0; b < SK_P; ++b) xb[b] = xa[b];
+      } else {
+        skinny_row<T, VEC>(xb, pb + r * G.ldb, n - j0);
+      }
+#pragma unroll
+      for (int a = 0; a < SK_P; ++a)
+#pragma unroll
+        for (int b = 0; b < SK_P; ++b) acc[a][b] += xa[a] * xb[b];
+    }
+  }
+  // lanes of one part sit pp apart within a wavefront (pp divides 64)
+  for (int off = pp; off < 64; off <<= 1)
+#pragma unroll
+    for (int a = 0; a < SK_P; ++a)
+#pragma unroll
+      for (int b = 0; b < SK_P; ++b) acc[a][b] += __shfl_xor(acc[a][b], off, 64);
+  const int wv = t / 64, ln = t % 64;
+  if (ln < pp && act) {
+#pragma unroll
+    for (int a = 0; a < SK_P; ++a)
+#pragma unroll
+      for (int b = 0; b < SK_P; ++b) red[wv][part][a * SK_P + b] = acc[a][b];
+  }
+  __syncthreads();
+  const int mn = m * n;
+  T* w = W + G.w_off + (int64_t)ch * mn;
+  for (int e = t; e < mn; e += SK_T) {
+    const int i = e / n, j = e - i * n;
+    const int pt = (i / SK_P) * pn + j / SK_P, sl = (i % SK_P) * SK_P + j % SK_P;
+    T s = red[0][pt][sl];
+    for (int u = 1; u < SK_T / 64; ++u) s += red[u][pt][sl];
+    w[e] = s;
+  }
+}
+
+// one wavefront per entry of C: lane l sums the chunks l, l + 64, ... (four
+// loads in flight), then a fixed butterfly across the wavefront
+template <typename T>
+__global__ void __launch_bounds__(256) k_skinny_reduce(const SkinnyGroup* gs, const T* __restrict__ W,
+                                                       T* __restrict__ C, double alpha, double beta) {
+  const SkinnyGroup G = gs[blockIdx.y];
+  const int mn = (int)(G.M * G.N), ln = threadIdx.x % 64;
+  const int e = blockIdx.x * 4 + threadIdx.x / 64;
+  if (e >= mn) return;  // whole wavefronts leave together
+  const T* w = W + G.w_off + e;
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+  int c = ln;
+  for (; c + 192 < G.chunks; c += 256) {
+    s0 += w[(int64_t)c * mn];
+    s1 += w[(int64_t)(c + 64) * mn];
+    s2 += w[(int64_t)(c + 128) * mn];
+    s3 += w[(int64_t)(c + 192) * mn];
+  }
+  for (; c < G.chunks; c += 64) s0 += w[(int64_t)c * mn];
+  T s = (s0 + s1) + (s2 + s3);
+  for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+  if (ln == 0) {
+    const int i = e / (int)G.N, j = e - i * (int)G.N;
+    T* p = C + G.c_off + i * G.ldc + j;
+    *p = beta != 0.0 ? (T)alpha * s + (T)beta * *p : (T)alpha * s;
+  }
+}
+
+// groups all of the tall-skinny A^T B form (plain outputs), at least one of
+// them with a long K
+static bool skinny_form(const std::vector<GemmGroup>& gs) {
+  bool any = false;
+  for (auto& g : gs) {
+    if (g.M <= 0 || g.N <= 0) continue;
+    if (!g.transA || g.transB || g.scatter || g.M > SK_MAX || g.N > SK_MAX) return false;
+    if (g.K >= 1024) any = true;
+  }
+  return any;
+}
+
+template <typename T>
+static void run_skinny(const std::vector<GemmGroup>& gs, const T* A, const T* B, T* C, hipStream_t s,
+                       double alpha, double beta, int cls, double flops) {
+  std::vector<SkinnyGroup> sg;
+  int64_t ws = 0, tot_k = 0;
+  int maxch = 1;
+  bool vec = ((uintptr_t)A % (2 * sizeof(T))) == 0 && ((uintptr_t)B % (2 * sizeof(T))) == 0;
+  for (auto& g : gs)
+    if (g.M > 0 && g.N > 0) tot_k += g.K;
+  for (auto& g : gs) {
+    if (g.M <= 0 || g.N <= 0) continue;
+    SkinnyGroup x;
+    x.M = g.M;
+    x.N = g.N;
+    x.K = g.K;
+    x.a_off = g.a_off;
+    x.lda = g.lda;
+    x.b_off = g.b_off;
+    x.ldb = g.ldb;
+    x.c_off = g.c_off;
+    x.ldc = g.ldc;
+    // about 2048 workgroups over all groups, chunks of at least 1024 rows
+    const int64_t want = std::max<int64_t>(1, (int64_t)(2048.0 * (double)g.K / (double)std::max<int64_t>(tot_k, 1)));
+    x.chunks = (int)std::min<int64_t>(want, std::max<int64_t>(1, g.K / 1024));
+    x.kc = std::max<int64_t>(1, cdiv(g.K, x.chunks));
+    x.chunks = g.K > 0 ? (int)cdiv(g.K, x.kc) : 1;
+    x.w_off = ws;
+    ws += (int64_t)x.chunks * g.M * g.N;
+    const int np = (int)(cdiv(g.M, SK_P) * cdiv(g.N, SK_P));
+    x.pp = 1;
+    while (x.pp < np) x.pp <<= 1;
+    x.same = (const void*)A == (const void*)B && g.a_off == g.b_off && g.lda == g.ldb ? 1 : 0;
+    x.pad = 0;
+    // pair loads: whole parts of 8 and every row start on a pair boundary
+    vec = vec && g.M % SK_P == 0 && g.N % SK_P == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 && g.a_off % 2 == 0 &&
+          g.b_off % 2 == 0;
+    maxch = std::max(maxch, x.chunks);
+    sg.push_back(x);
+  }
+  if (sg.empty()) return;
+  DBuf<SkinnyGroup> d = to_device(sg, s);
+  DBuf<T> W(ws, s);
+  // FTN_TRACE_GEMM=2: one timed line per launch (synchronising the stream)
+  static const char* trace_env = std::getenv("FTN_TRACE_GEMM");
+  static const bool trace_time = trace_env && trace_env[0] == '2';
+  hipEvent_t te0 = nullptr, te1 = nullptr;
+  if (trace_time) {
+    HIPC(hipEventCreate(&te0));
+    HIPC(hipEventCreate(&te1));
+    HIPC(hipEventRecord(te0, s));
+  }
+  void* tok = prof_begin(s);
+  if (vec)
+    ELAUNCH((k_skinny_atb<T, true>), dim3((unsigned)maxch, (unsigned)sg.size()), dim3(SK_T), 0, s, prof_ev(tok, 0),
+            nullptr, d.p, A, B, W.p);
+  else
+    ELAUNCH((k_skinny_atb<T, false>), dim3((unsigned)maxch, (unsigned)sg.size()), dim3(SK_T), 0, s, prof_ev(tok, 0),
+            nullptr, d.p, A, B, W.p);
+  int64_t max_mn = 1;
+  for (auto& g : sg) max_mn = std::max(max_mn, g.M * g.N);
+  ELAUNCH((k_skinny_reduce<T>), dim3((unsigned)cdiv(max_mn, 4), (unsigned)sg.size()), dim3(256), 0, s, nullptr,
+          prof_ev(tok, 1), d.p, W.p, C, alpha, beta);
+  // algorithmic bytes: A and B read once (once in all when they are the same
+  // matrix, as for a Gram matrix), C written
+  double ab = 0;
+  for (auto& g : sg) {
+    ab += (double)(g.K * (g.same && g.M == g.N ? g.M : g.M + g.N) + g.M * g.N);
+  }
+  prof_end(tok, s, cls, cls == FTN_PROF_K_SKINNY_F64 ? ab * sizeof(T) : flops, ab * sizeof(T));
+  if (trace_time) {
+    HIPC(hipEventRecord(te1, s));
+    HIPC(hipEventSynchronize(te1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, te0, te1));
+    int64_t mm = 0, mn = 0, mk = 0;
+    for (auto& g : sg) {
+      mm = std::max(mm, g.M);
+      mn = std::max(mn, g.N);
+      mk = std::max(mk, g.K);
+    }
+    std::fprintf(stderr, "[skinny] us %.1f GB/s %.1f groups %zu blocks %d bytes %.4g maxM %lld maxN %lld maxK %lld\n",
+                 1000.0 * ms, ms > 0 ? ab * sizeof(T) / (ms * 1e-3) / 1e9 : 0.0, sg.size(), maxch, ab * sizeof(T),
+                 (long long)mm, (long long)mn, (long long)mk);
+    HIPC(hipEventDestroy(te0));
+    HIPC(hipEventDestroy(te1));
+  }
+}
+
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,
                       const void* B, void* C, const GemmScatter* sc, hipStream_t s, double alpha,
                       double beta) {
+  if (!sc && gemm != FTN_GEMM_BF16X3 && skinny_form(groups)) {
+    double fl = 0;
+    for (auto& g : groups)
+      if (g.M > 0 && g.N > 0) fl += 2.0 * (double)g.M * g.N * g.K;
+    if (gemm == FTN_GEMM_F64) {
+      if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
+      run_skinny<double>(groups, (const double*)A, (const double*)B, (double*)C, s, alpha, beta,
+                         FTN_PROF_K_SKINNY_F64, fl);
+    } else {
+      if (dtype != FTN_F32) fail(FTN_ENOTSUP, "FP32 GEMM needs FP32 tensors");
+      run_skinny<float>(groups, (const float*)A, (const float*)B, (float*)C, s, alpha, beta, FTN_PROF_GEMM_F32,
+                        fl);
+    }
+    return;
+  }
   GemmPlan p;
   gemm_plan(p, groups, gemm, s);
   run_gemm(p, dtype, A, B, C, sc, s, alpha, beta);

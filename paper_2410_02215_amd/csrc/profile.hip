@@ -65,7 +65,9 @@ void settle(std::vector<Rec>& recs, bool block) {
     g_work[r.cls] += r.work;
     g_bytes[r.cls] += r.bytes;
     // single-kernel classes also count in their family class
-    const int par = r.cls >= FTN_PROF_K_GEMM_F64_64x64 && r.cls <= FTN_PROF_K_SPLITK_F64 ? FTN_PROF_GEMM_F64
+    const int par = (r.cls >= FTN_PROF_K_GEMM_F64_64x64 && r.cls <= FTN_PROF_K_SPLITK_F64) ||
+                            r.cls == FTN_PROF_K_SKINNY_F64
+                        ? FTN_PROF_GEMM_F64
                     : r.cls >= FTN_PROF_K_ORTH && r.cls <= FTN_PROF_K_SVD_COLS  ? FTN_PROF_FACTOR
                                                                                 : -1;
     if (par >= 0) {

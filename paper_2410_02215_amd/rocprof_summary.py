@@ -52,6 +52,8 @@ def kernel_key(name):
         return "k_gemm_f64_%sx%s" % (m.group(1), m.group(2))
     if re.search(r"k_splitk_reduce<double", name):
         return "k_splitk_reduce_f64"
+    if re.search(r"k_skinny_(atb|reduce)<double", name):
+        return "k_skinny_f64"
     if re.search(r"k_block_perm<", name):
         return "permute"
     for k in ("k_jacobi_sweep_la", "k_jacobi_sweep", "k_jacobi_vectors", "k_orth_factor", "k_svd_cols"):

@@ -294,6 +294,10 @@ def test_compress_mixed_sector_sizes(P, dims):
     ((120, 100), (900, 700), (60, 40), 30),  # d <= 128, thin B side, truncated
     ((300, 200), (700, 500), (100, 128), 60),  # d > 128 (the Gram route) beside the same shapes
     ((80, 60), (400, 300), (16, 12), 10),    # thin, with B~ of rank below N
+    # thin with long A~ sides: the Gram of Y = A~ B~ (N <= 32 columns, over
+    # 1000 rows, ragged) takes the tall-skinny A^T B kernel
+    ((100, 80), (3001, 1100), (24, 9), 25),
+    ((128, 64), (5000, 2049), (32, 1), 20),
 ])
 def test_compress_thin_b_side_matches_oracle(P, case):
     # sectors whose B side is thin (N <= d, N <= 128) and A~ tall (M > d):
