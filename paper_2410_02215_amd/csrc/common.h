@@ -270,10 +270,11 @@ struct PermDesc {
   int32_t mode;        // 0 rows contiguous on both sides, 1 LDS transpose, 2 per element, 3 nothing
   int32_t ta, tr;      // tile: extent along leg 0, rows per tile (powers of two)
   int32_t neg;         // sign bit of the block
+  int32_t sub;         // sub-tiles per workgroup (1 in mode 1, else up to PM_SUB)
   int64_t nx, nr;      // tiles along leg 0 and along the rows
   int64_t rows;        // rows: mode 0 all outer positions, mode 1 the extent of leg y
   int64_t nel;         // entries of the block
-  int64_t nsub;        // sub-tiles of the block (a workgroup takes up to PM_SUB)
+  int64_t nsub;        // sub-tiles of the block
 };
 // a ready-to-launch permute: tasks, descriptors and tile map on the device
 struct PermPlan {

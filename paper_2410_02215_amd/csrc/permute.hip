@@ -66,6 +66,7 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
   D.mode = 3;
   D.ta = D.tr = 1;
   D.neg = 0;
+  D.sub = PM_SUB;
   D.nx = D.nr = D.rows = D.nel = D.nsub = 0;
   for (int j = 0; j < MAXD; ++j) {
     D.sb[j] = D.ts[j] = 0;
@@ -150,6 +151,9 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
       D.nx = (dx + D.ta - 1) / D.ta;
       D.nr = (dy + D.tr - 1) / D.tr;
       ntile = (D.nel / (dx * dy)) * D.nx * D.nr;
+      // whole-size tiles: one per workgroup (no serial round trips); smaller
+      // ones are grouped so that a workgroup still moves a full tile's worth
+      D.sub = D.ta * D.tr >= PM_TILE ? 1 : PM_SUB;
     } else {
       D.mode = 2;
       ntile = (D.nel + PM_TILE - 1) / PM_TILE;
@@ -157,7 +161,7 @@ __global__ void k_perm_desc(SignOp op, const PermTask* __restrict__ tasks, int64
   }
   D.nsub = ntile;
   desc[t] = D;
-  tiles[t] = (ntile + PM_SUB - 1) / PM_SUB;
+  tiles[t] = (ntile + D.sub - 1) / D.sub;
 }
 
 // task of every tile (once per plan)
@@ -194,24 +198,18 @@ __global__ void __launch_bounds__(PM_THREADS)
                  T alpha) {
   // transpose staging (tr x (ta + 1) entries, tr <= PM_TILE / 2) or row bases
   __shared__ double smem[PM_TILE + PM_TILE / 2];
-  __shared__ PermDesc D;
-  __shared__ int64_t s_task, s_bb, s_sb;
   T* tile = (T*)smem;
   int64_t* rbase = (int64_t*)smem;
   const int64_t tl = blockIdx.x;
-  if (threadIdx.x == 0) s_task = tile_task[tl];
-  __syncthreads();
-  {
-    const int* srcw = (const int*)(desc + s_task);
-    int* dstw = (int*)&D;
-    for (int w = threadIdx.x; w < (int)(sizeof(PermDesc) / sizeof(int)); w += PM_THREADS) dstw[w] = srcw[w];
-  }
-  __syncthreads();
-  const int64_t first = (tl - tile_start[s_task]) * PM_SUB;
+  // the task and its descriptor are the same for the whole workgroup: read
+  // through the scalar cache, with no staging or barrier before the loads
+  const int task = __builtin_amdgcn_readfirstlane(tile_task[tl]);
+  const PermDesc& D = desc[task];
+  const int64_t first = (tl - tile_start[task]) * D.sub;
   const T v = D.neg ? -alpha : alpha;
   const int ta = D.ta, tr = D.tr;
   const int lta = __ffs(ta) - 1, ltr = __ffs(tr) - 1;  // ta, tr are powers of two
-  for (int k = 0; k < PM_SUB; ++k) {
+  for (int k = 0; k < D.sub; ++k) {
     const int64_t lt = first + k;
     if (lt >= D.nsub) break;
     if (D.mode == 0) {
@@ -283,28 +281,93 @@ __global__ void __launch_bounds__(PM_THREADS)
       const int64_t bt = lt / per, rem = lt % per;
       const int64_t ix = rem % D.nx, ir = rem / D.nx;
       const int64_t x0 = ix * ta, y0 = ir * tr, dx = D.dim[0], dy = D.dim[y];
-      if (threadIdx.x == 0) {  // batch position over the legs other than 0 and y
-        int64_t q = bt, bb = 0, sbb = 0;
-        for (int j = 1; j < D.m; ++j) {
+      // batch position over the legs other than 0 and y (every thread, no
+      // barrier before the loads)
+      int64_t bbase = D.boff, sbase = D.moff;
+      {
+        int64_t q = bt;
+        for (int j = 1; j < D.m && q; ++j) {
           if (j == y) continue;
           const int64_t dj = D.dim[j];
           const int64_t ij = q % dj;
           q /= dj;
-          bb += ij * D.sb[j];
-          sbb += ij * D.ts[j];
+          bbase += ij * D.sb[j];
+          sbase += ij * D.ts[j];
         }
-        s_bb = bb;
-        s_sb = sbb;
       }
-      __syncthreads();
-      const int64_t bbase = D.boff + s_bb, sbase = D.moff + s_sb;
       const int64_t sby = D.sb[y], tsx = D.ts[0];
       const int ld = ta + 1, n = ta * tr;
+      typedef typename Pair<T>::type T2;
+      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
+      // whole tile, every pair aligned on both sides: unchecked 2-wide
+      // accesses with 32-bit in-tile offsets
+      if (x0 + ta <= dx && y0 + tr <= dy && ((bbase | sby | sbase | tsx) & 1) == 0 &&
+          ((((uintptr_t)src) | ((uintptr_t)dst)) & (sizeof(T2) - 1)) == 0) {
+        const T* bp = (DIR == 0 ? src : dst) + bbase + y0 * sby + x0;  // block side
+        const T* sp = (DIR == 0 ? dst : src) + sbase + y0 + x0 * tsx;  // strided side
+        T2 buf[PPT];
+        if (DIR == 0) {
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            if (e < n) buf[u] = *(const T2*)(bp + (int64_t)(e >> lta) * sby + (e & (ta - 1)));
+          }
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            const int r = e >> lta, i = e & (ta - 1);
+            if (e < n) {
+              tile[r * ld + i] = v * buf[u].x;
+              tile[r * ld + i + 1] = v * buf[u].y;
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            const int r = e & (tr - 1), i = e >> ltr;
+            if (e < n) {
+              T2 w;
+              w.x = tile[r * ld + i];
+              w.y = tile[(r + 1) * ld + i];
+              *(T2*)(const_cast<T*>(sp) + r + (int64_t)i * tsx) = w;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            if (e < n) buf[u] = *(const T2*)(sp + (e & (tr - 1)) + (int64_t)(e >> ltr) * tsx);
+          }
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            const int r = e & (tr - 1), i = e >> ltr;
+            if (e < n) {
+              tile[r * ld + i] = v * buf[u].x;
+              tile[(r + 1) * ld + i] = v * buf[u].y;
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            const int e = 2 * (threadIdx.x + u * PM_THREADS);
+            const int r = e >> lta, i = e & (ta - 1);
+            if (e < n) {
+              T2 w;
+              w.x = tile[r * ld + i];
+              w.y = tile[r * ld + i + 1];
+              *(T2*)(const_cast<T*>(bp) + (int64_t)r * sby + i) = w;
+            }
+          }
+        }
+        __syncthreads();  // the staging buffer is reused by the next sub-tile
+        continue;
+      }
       // the block side is walked with leg 0 fastest, the strided side with leg y;
       // each thread moves two neighbours along the contiguous direction of the
       // side it touches (ta and tr are powers of two >= 2), with one 2-wide
       // access when the pair is aligned
-      typedef typename Pair<T>::type T2;
       auto ld2 = [](const T* p, bool two, T& a0, T& a1) {
         if (two && (((uintptr_t)p) & (sizeof(T2) - 1)) == 0) {
           const T2 t = *(const T2*)p;
@@ -328,7 +391,6 @@ __global__ void __launch_bounds__(PM_THREADS)
       };
       // the loads of a thread are issued together (PPT pairs at most) before
       // the staging writes, so that several are in flight
-      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
       if (DIR == 0) {
         T la0[PPT], la1[PPT];
 #pragma unroll
