@@ -36,10 +36,11 @@ for _k in ("64x64", "128x128", "256x16", "256x32", "16x256", "32x256"):
 for _k in ("k_orth_factor", "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"):
     PEAK[_k] = (78.6, "TFLOP/s", "alu")
 PEAK["k_skinny_f64"] = (8000.0, "GB/s", "hbm")  # tall-skinny A^T B reads A and B once
+PEAK["k_gemm_f64_tall"] = (8000.0, "GB/s", "hbm")  # tall A (N <= 16, K <= 256) streamed once
 # single kernels (the classes gemm_f64 and factor are families of kernels)
 KERNELS = ["gemm_f32", "gemm_bf16x3", "permute", "k_splitk_reduce_f64", "k_gemm_f64_64x64", "k_gemm_f64_128x128",
            "k_gemm_f64_256x16", "k_gemm_f64_256x32", "k_gemm_f64_16x256", "k_gemm_f64_32x256", "k_orth_factor",
-           "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols", "k_skinny_f64"]
+           "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols", "k_skinny_f64", "k_gemm_f64_tall"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -471,6 +472,8 @@ def roofline(prof, workload):
     dom = max((c for c in prof if c in KERNELS), key=lambda c: prof[c][0])
     ms, cnt, work = prof[dom][:3]
     peak, unit, bound = PEAK[dom]
+    if unit == "GB/s":  # memory-bound classes are priced on their algorithmic bytes
+        work = prof[dom][3]
     scale = 1e12 if unit == "TFLOP/s" else 1e9
     achieved = work / (ms * 1e-3) / scale if ms > 0 else 0.0
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
@@ -573,7 +576,8 @@ def main():
                                     "the compressions, per second of the timed steps"},
         "autotune": dict(tune_stats, enabled=not args.no_autotune),
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
-        "kernel_rate": {c: "%.4g %s" % (prof[c][2] / (prof[c][0] * 1e-3) / (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
+        "kernel_rate": {c: "%.4g %s" % (prof[c][2 if PEAK[c][1] == "TFLOP/s" else 3] / (prof[c][0] * 1e-3) /
+                                        (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
                                         PEAK[c][1])
                         for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},

@@ -449,8 +449,9 @@ enum {
   FTN_PROF_K_JACOBI_VEC = 16,      /* eigenvector accumulation (work counted with the sweeps) */
   FTN_PROF_K_SVD_COLS = 17,        /* one-sided Jacobi SVD */
   FTN_PROF_K_SKINNY_F64 = 18,      /* tall-skinny A^T B (outputs of at most 32 x 32), FP64, with
-                                      its partial-sum reduction; work = algorithmic bytes */
-  FTN_PROF_NCLASS = 19
+                                      its partial-sum reduction */
+  FTN_PROF_K_GEMM_F64_TALL = 19,   /* tall A B with N <= 16 and K <= 256 (A streamed once), FP64 */
+  FTN_PROF_NCLASS = 20
 };
 
 /* on != 0: bracket every instrumented launch with HIP events on its stream

@@ -467,9 +467,132 @@ double gemm_flops(const std::vector<GemmGroup>& groups) {
 constexpr int TBM = 64, TBN = 64;  // split-BF16 tile
 
 // tile configurations of the FP64 / FP32 kernel
-enum { CFG_64 = 0, CFG_128 = 1, CFG_256x16 = 2, CFG_256x32 = 3, CFG_16x256 = 4, CFG_32x256 = 5 };
-static const int CFG_BM[] = {64, 128, 256, 256, 16, 32};
-static const int CFG_BN[] = {64, 128, 16, 32, 256, 256};
+// ---------------------------------------------------------------------------
+// Tall FP64 products C = alpha A B (+ beta C, or a block scatter) with A
+// (M x K) and B (K x N) row-major, N <= 16, K <= 256 and M large: a tall
+// factor times a small matrix, bound by streaming A once. The MFMA tiles
+// above stage A through LDS, whose 64 KB per workgroup leave too few
+// resident workgroups to keep HBM busy here. Instead B (at most 256 x 16)
+// is the only LDS operand; each wave takes four 16-row tiles and feeds A to
+// v_mfma_f64_16x16x4f64 straight from its registers: lane (r, g) = (lane %
+// 16, lane / 16) loads the four consecutive entries k0 + 4g .. k0 + 4g + 3 of
+// row r (two 16-byte loads, a 128-byte line per row across the four lane
+// groups), and the four MFMAs of a 16-wide K step take them as their K slot
+// g (the B operand is read from LDS in the same order). The loads of the
+// next K step are issued before the MFMAs of the current one.
+constexpr int TL_T = 256, TL_RT = 4, TL_BM = 16 * TL_RT * (TL_T / 64), TL_KMAX = 256, TL_N = 16;
+
+template <bool VEC>
+__global__ void __launch_bounds__(TL_T) k_gemm_tall(GemmLaunch L, const double* __restrict__ A,
+                                                    const double* __restrict__ B, double* __restrict__ C) {
+  __shared__ double Bs[TL_KMAX][TL_N];
+  __shared__ EpiTab<TL_BM, TL_N> epi;
+  __shared__ int s_g;
+  const int64_t tile = xcd_tile(blockIdx.x, L.ntiles);
+  if (threadIdx.x == 0) s_g = find_group(L.groups, L.ngroups, tile);
+  __syncthreads();
+  const GemmGroup G = L.groups[s_g];
+  const int64_t mb = (tile - G.tile0) * TL_BM;
+  const int K = (int)G.K, N = (int)G.N, kp = (K + 15) & ~15;
+  for (int e = threadIdx.x; e < kp * TL_N; e += TL_T) {
+    const int k = e / TL_N, n = e % TL_N;
+    Bs[k][n] = k < K && n < N ? B[G.b_off + (int64_t)k * G.ldb + n] : 0.0;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  const int64_t m0 = mb + 64 * w;
+  const double* ap[TL_RT];
+  bool rok[TL_RT];
+#pragma unroll
+  for (int t = 0; t < TL_RT; ++t) {
+    const int64_t m = m0 + 16 * t + r;
+    rok[t] = m < G.M;
+    ap[t] = A + G.a_off + (rok[t] ? m : 0) * G.lda + 4 * g;
+  }
+  // entries k0 + 4g .. k0 + 4g + 3 of each of the lane's rows (zero past M or K)
+  auto load = [&](double2 (&buf)[TL_RT][2], int k0) {
+    const int k = k0 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < TL_RT; ++t) {
+      const double* q = ap[t] + k0;
+      if constexpr (VEC) {  // K % 4 == 0 and every row start on a pair boundary
+        if (rok[t] && k < K) {
+          buf[t][0] = *(const double2*)q;
+          buf[t][1] = *(const double2*)(q + 2);
+        } else {
+          buf[t][0] = buf[t][1] = double2{0.0, 0.0};
+        }
+      } else {
+        buf[t][0].x = rok[t] && k < K ? q[0] : 0.0;
+        buf[t][0].y = rok[t] && k + 1 < K ? q[1] : 0.0;
+        buf[t][1].x = rok[t] && k + 2 < K ? q[2] : 0.0;
+        buf[t][1].y = rok[t] && k + 3 < K ? q[3] : 0.0;
+      }
+    }
+  };
+  d4 acc[TL_RT];
+#pragma unroll
+  for (int t = 0; t < TL_RT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  double2 cur[TL_RT][2], nxt[TL_RT][2];
+  load(cur, 0);
+  __syncthreads();  // B in LDS
+  const int nks = kp / 16;
+  for (int ks = 0; ks < nks; ++ks) {
+    if (ks + 1 < nks) load(nxt, 16 * (ks + 1));
+    const int kb = 16 * ks + 4 * g;
+    const double b0 = Bs[kb][r], b1 = Bs[kb + 1][r], b2 = Bs[kb + 2][r], b3 = Bs[kb + 3][r];
+#pragma unroll
+    for (int t = 0; t < TL_RT; ++t) {
+      acc[t] = MfmaOp<double>::run(cur[t][0].x, b0, acc[t]);
+      acc[t] = MfmaOp<double>::run(cur[t][0].y, b1, acc[t]);
+      acc[t] = MfmaOp<double>::run(cur[t][1].x, b2, acc[t]);
+      acc[t] = MfmaOp<double>::run(cur[t][1].y, b3, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < TL_RT; ++t) {
+      cur[t][0] = nxt[t][0];
+      cur[t][1] = nxt[t][1];
+    }
+  }
+  if (G.scatter == 1) {
+    build_epi<TL_BM, TL_N>(epi, G, L.sc, mb, 0);
+    __syncthreads();
+  }
+  const double alpha = L.alpha, beta = L.beta;
+  if (r >= N) return;
+#pragma unroll
+  for (int t = 0; t < TL_RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = 64 * w + 16 * t + MfmaOp<double>::row(lane, i);
+      const int64_t m = mb + rr;
+      if (m >= G.M) continue;
+      const double v = alpha * acc[t][i];
+      if (G.scatter == 1) {
+        const int64_t bo = L.sc.boff[G.boff_base + (int64_t)epi.rfi[rr] * G.ncc + epi.cgj[r]];
+        if (bo >= 0) C[bo + epi.rlr[rr] * epi.cnd[r] + epi.clc[r]] = v;
+      } else {
+        double* p = C + G.c_off + m * G.ldc + r;
+        *p = beta != 0.0 ? v + beta * *p : v;
+      }
+    }
+}
+
+// the tall kernel takes FP64 groups of plain or block-scatter output with
+// A and B untransposed, N <= 16, K <= 256 and at least one tall A
+static bool tall_form(const std::vector<GemmGroup>& gs, int kind) {
+  if (kind != FTN_GEMM_F64) return false;
+  bool tall = false;
+  for (auto& g : gs) {
+    if (g.M <= 0 || g.N <= 0) continue;
+    if (g.transA || g.transB || g.sym || g.scatter == 2 || g.N > TL_N || g.K > TL_KMAX || g.K < 1) return false;
+    if (g.M >= 4096) tall = true;
+  }
+  return tall;
+}
+
+enum { CFG_64 = 0, CFG_128 = 1, CFG_256x16 = 2, CFG_256x32 = 3, CFG_16x256 = 4, CFG_32x256 = 5, CFG_TALL = 6 };
+static const int CFG_BM[] = {64, 128, 256, 256, 16, 32, TL_BM};
+static const int CFG_BN[] = {64, 128, 16, 32, 256, 256, TL_N};
 constexpr int NCU = 256;  // compute units to fill
 
 static int choose_cfg(const std::vector<GemmGroup>& gs) {
@@ -495,7 +618,10 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
   for (auto& g : groups)
     if (g.M > 0 && g.N > 0) gs.push_back(g);
   int cfg = -1, split = -1;
-  if (kind != FTN_GEMM_BF16X3 && !gs.empty()) tune_choice(gs, kind, s, &cfg, &split);
+  if (tall_form(gs, kind))
+    cfg = CFG_TALL;  // not a tuning choice: the tall kernel is the streaming bound
+  else if (kind != FTN_GEMM_BF16X3 && !gs.empty())
+    tune_choice(gs, kind, s, &cfg, &split);
   gemm_plan_with(p, gs, kind, s, persistent, cfg, split);
 }
 
@@ -530,6 +656,10 @@ void gemm_plan_with(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind,
   int64_t split = 1;
   if (kind != FTN_GEMM_BF16X3 && tiles > 0 && tiles < 4 * NCU) split = std::max<int64_t>(1, cdiv(8 * NCU, tiles));
   if (kind != FTN_GEMM_BF16X3 && split_override >= 1) split = split_override;
+  if (p.cfg == CFG_TALL) {
+    if (!tall_form(gs, kind)) fail(FTN_EINVAL, "tall GEMM configuration for groups it does not take");
+    split = 1;  // K <= 256: one pass
+  }
   p.split = split;
   int64_t t = 0;
   for (auto g : gs) {
@@ -648,7 +778,21 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
   DBuf<char> ws_own(ws_ext ? 0 : p.ws_elems * es, s);
   char* wsp = ws_ext ? (char*)ws_ext : ws_own.p;
   void* tok = prof_begin(s);
-  if (p.kind == FTN_GEMM_F64) {
+  if (p.kind == FTN_GEMM_F64 && p.cfg == CFG_TALL) {
+    if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
+    // pair loads of A: K a multiple of 4 and every row start 16-byte aligned
+    bool vec = ((uintptr_t)A & 15) == 0;
+    for (auto& g : p.host) vec = vec && g.K % 4 == 0 && g.lda % 2 == 0 && g.a_off % 2 == 0;
+    if (vec)
+      ELAUNCH((k_gemm_tall<true>), grid, dim3(TL_T), 0, s, prof_ev(tok, 0), prof_ev(tok, 1), L, (const double*)A,
+              (const double*)B, (double*)C);
+    else
+      ELAUNCH((k_gemm_tall<false>), grid, dim3(TL_T), 0, s, prof_ev(tok, 0), prof_ev(tok, 1), L, (const double*)A,
+              (const double*)B, (double*)C);
+    HIPC(hipGetLastError());
+    prof_end(tok, s, FTN_PROF_K_GEMM_F64_TALL, p.flops, p.abytes * (double)es);
+    tok = nullptr;
+  } else if (p.kind == FTN_GEMM_F64) {
     if (dtype != FTN_F64) fail(FTN_ENOTSUP, "FP64 GEMM needs FP64 tensors");
     launch_cfg<double>(p.cfg, grid, s, L, (const double*)A, (const double*)B, (double*)C, (double*)wsp,
                        prof_ev(tok, 0), prof_ev(tok, 1));
@@ -924,7 +1068,7 @@ static void run_skinny(const std::vector<GemmGroup>& gs, const T* A, const T* B,
   for (auto& g : sg) {
     ab += (double)(g.K * (g.same && g.M == g.N ? g.M : g.M + g.N) + g.M * g.N);
   }
-  prof_end(tok, s, cls, cls == FTN_PROF_K_SKINNY_F64 ? ab * sizeof(T) : flops, ab * sizeof(T));
+  prof_end(tok, s, cls, flops, ab * sizeof(T));
   if (trace_time) {
     HIPC(hipEventRecord(te1, s));
     HIPC(hipEventSynchronize(te1));

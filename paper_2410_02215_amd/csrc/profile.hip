@@ -66,7 +66,7 @@ void settle(std::vector<Rec>& recs, bool block) {
     g_bytes[r.cls] += r.bytes;
     // single-kernel classes also count in their family class
     const int par = (r.cls >= FTN_PROF_K_GEMM_F64_64x64 && r.cls <= FTN_PROF_K_SPLITK_F64) ||
-                            r.cls == FTN_PROF_K_SKINNY_F64
+                            r.cls == FTN_PROF_K_SKINNY_F64 || r.cls == FTN_PROF_K_GEMM_F64_TALL
                         ? FTN_PROF_GEMM_F64
                     : r.cls >= FTN_PROF_K_ORTH && r.cls <= FTN_PROF_K_SVD_COLS  ? FTN_PROF_FACTOR
                                                                                 : -1;

@@ -81,7 +81,7 @@ PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_bf16x3", "permute", "factor", "oth
                 # single kernels inside gemm_f64 and factor (also counted there)
                 "k_gemm_f64_64x64", "k_gemm_f64_128x128", "k_gemm_f64_256x16", "k_gemm_f64_256x32",
                 "k_gemm_f64_16x256", "k_gemm_f64_32x256", "k_splitk_reduce_f64", "k_orth_factor",
-                "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols", "k_skinny_f64"]
+                "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols", "k_skinny_f64", "k_gemm_f64_tall"]
 # the classes that are single kernels (the permute class is one kernel template)
 PROF_KERNELS = ["gemm_f32", "gemm_bf16x3", "permute"] + PROF_CLASSES[6:]
 

@@ -34,6 +34,8 @@ import sys
 CLASSES = [
     ("gemm_f64", re.compile(r"k_gemm<double"), True),
     ("gemm_f64", re.compile(r"k_splitk_reduce<double"), False),
+    ("gemm_f64", re.compile(r"k_skinny_atb<double|k_gemm_tall<"), True),
+    ("gemm_f64", re.compile(r"k_skinny_reduce<double"), False),
     ("gemm_f32", re.compile(r"k_gemm<float"), True),
     ("gemm_f32", re.compile(r"k_splitk_reduce<float"), False),
     ("gemm_bf16x3", re.compile(r"k_gemm_bf16x3"), True),
@@ -54,6 +56,8 @@ def kernel_key(name):
         return "k_splitk_reduce_f64"
     if re.search(r"k_skinny_(atb|reduce)<double", name):
         return "k_skinny_f64"
+    if re.search(r"k_gemm_tall<", name):
+        return "k_gemm_f64_tall"
     if re.search(r"k_block_perm<", name):
         return "permute"
     for k in ("k_jacobi_sweep_la", "k_jacobi_sweep", "k_jacobi_vectors", "k_orth_factor", "k_svd_cols"):

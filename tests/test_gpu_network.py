@@ -298,6 +298,8 @@ def test_compress_mixed_sector_sizes(P, dims):
     # 1000 rows, ragged) takes the tall-skinny A^T B kernel
     ((100, 80), (3001, 1100), (24, 9), 25),
     ((128, 64), (5000, 2049), (32, 1), 20),
+    # Y = A~ B~ with over 4096 rows and N <= 16 takes the streaming tall kernel
+    ((64, 48), (5000, 4100), (16, 7), 20),
 ])
 def test_compress_thin_b_side_matches_oracle(P, case):
     # sectors whose B side is thin (N <= d, N <= 128) and A~ tall (M > d):

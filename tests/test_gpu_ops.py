@@ -149,6 +149,36 @@ def test_ftensordot_tiles_and_ragged_tails(P):
     np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * np.abs(r).max())
 
 
+@pytest.mark.parametrize("case", [
+    # (A legs, B legs, contracted legs of A): tall fused A (M >= 4096), N <= 16
+    # and K <= 256 take the streaming tall kernel; odd K reads A entry by
+    # entry, K % 4 == 0 in pairs; ragged M; N of 1; several row combos
+    (((5000, 4200, 0), (40, 37, 1)), ((40, 37, 0), (9, 16, 1)), [1]),
+    (((4500, 6000, 0), (64, 128, 1)), ((64, 128, 0), (1, 12, 1)), [1]),
+    (((70, 65, 0), (80, 75, 0), (128, 128, 1)), ((128, 128, 0), (5, 3, 1)), [2]),
+    (((300, 257, 0), (16, 16, 0), (256, 252, 1)), ((256, 252, 0), (16, 15, 1)), [2]),
+])
+def test_ftensordot_tall_thin_products(P, case):
+    la, lb, ax = case
+    rng = np.random.default_rng(sum(d for l in la for d in l[:2]))
+    sym = S.Z2
+    A = rand_tensor(rng, sym, [make_leg(sym, [(0,), (1,)], [e, o], d) for e, o, d in la], total=(0,))
+    B = rand_tensor(rng, sym, [make_leg(sym, [(0,), (1,)], [e, o], d) for e, o, d in lb], total=(0,))
+    from paper_2410_02215_amd import ftn
+    ref = ftensordot(A, B, ax, [0], conv="local")
+    ga, gb = to_gpu(A), to_gpu(B)
+    torch.cuda.synchronize()
+    ftn.profile_collect()
+    ftn.profile_enable(True)
+    G = P.ftensordot(ga, gb, ax, [0])
+    torch.cuda.synchronize()
+    ftn.profile_enable(False)
+    assert ftn.profile_collect()["k_gemm_f64_tall"][1] == 1
+    assert_same_structure(ref, G)
+    r = flat_blocks(ref)
+    np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * np.abs(r).max())
+
+
 @pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
 def test_ftensordot_fp32_forms(P, gemm):
     # FP32 tensors hold the FP64 inputs rounded to nearest; the oracle runs on
@@ -288,7 +318,7 @@ def test_profiler_kernel_classes_add_up_to_their_families(P):
     torch.cuda.synchronize()
     ftn.profile_enable(False)
     pr = ftn.profile_collect()
-    gk = [k for k in ftn.PROF_CLASSES if k.startswith("k_gemm_f64_")]
+    gk = [k for k in ftn.PROF_CLASSES if k.startswith("k_gemm_f64_")] + ["k_skinny_f64"]
     fk = ["k_orth_factor", "k_jacobi_sweep", "k_jacobi_sweep_la", "k_jacobi_vectors", "k_svd_cols"]
     assert pr["gemm_f64"][1] > 0 and pr["factor"][1] > 0
     ms = sum(pr[k][0] for k in gk) + pr["k_splitk_reduce_f64"][0]
