@@ -315,6 +315,7 @@ def main_amplitudes(args):
         "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": cfg["chi"],
                    "amplitudes_per_step": B, "workers": args.workers},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
+        "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
         # launches of the library's worker threads are not instrumented: with
         # more than one worker the line carries wall-clock rates only
         "roofline": roofline(prof, cfg["name"]) if any(prof[c][0] > 0 for c in prof) else None,
@@ -436,6 +437,7 @@ def main_gradient(args):
         "peak_memory_gb": {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
                            "torch": torch.cuda.max_memory_allocated() / 1e9},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
+        "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
         "result": {"energy": E, "grad_norm": gnorm},
         "roofline": roofline(prof, cfg["name"]),
     }
@@ -576,6 +578,7 @@ def main():
                                     "the compressions, per second of the timed steps"},
         "autotune": dict(tune_stats, enabled=not args.no_autotune),
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
+        "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_rate": {c: "%.4g %s" % (prof[c][2 if PEAK[c][1] == "TFLOP/s" else 3] / (prof[c][0] * 1e-3) /
                                         (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
                                         PEAK[c][1])

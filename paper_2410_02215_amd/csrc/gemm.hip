@@ -770,8 +770,9 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
       mn = std::max(mn, g.N);
       mk = std::max(mk, g.K);
     }
-    std::fprintf(stderr, "[gemm] tiles %lld groups %zu flops %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sc %d cfg %d split %zu\n",
-                 (long long)p.ntiles, p.host.size(), p.flops, (long long)mm, (long long)mn, (long long)mk,
+    std::fprintf(stderr, "[gemm] tiles %lld groups %zu flops %.4g bytes %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sc %d cfg %d split %zu\n",
+                 (long long)p.ntiles, p.host.size(), p.flops, p.abytes * (dtype == FTN_F64 ? 8.0 : 4.0), (long long)mm,
+                 (long long)mn, (long long)mk,
                  p.host[0].transA, p.host[0].transB, p.host[0].scatter, p.cfg, p.red_host.size());
   }
   const size_t es = dtype == FTN_F64 ? 8 : 4;
@@ -839,9 +840,9 @@ void run_gemm(const GemmPlan& p, int dtype, const void* A, const void* B, void* 
       mn = std::max(mn, g.N);
       mk = std::max(mk, g.K);
     }
-    std::fprintf(stderr, "[gemm] us %.1f tflops %.2f tiles %lld groups %zu flops %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sym %d sc %d cfg %d split %lld\n",
+    std::fprintf(stderr, "[gemm] us %.1f tflops %.2f tiles %lld groups %zu flops %.4g bytes %.4g maxM %lld maxN %lld maxK %lld ta %d tb %d sym %d sc %d cfg %d split %lld\n",
                  1000.0 * ms, ms > 0 ? p.flops / (ms * 1e-3) / 1e12 : 0.0, (long long)p.ntiles, p.host.size(), p.flops,
-                 (long long)mm, (long long)mn, (long long)mk, p.host[0].transA, p.host[0].transB, p.host[0].sym,
+                 p.abytes * (double)es, (long long)mm, (long long)mn, (long long)mk, p.host[0].transA, p.host[0].transB, p.host[0].sym,
                  p.host[0].scatter, p.cfg, (long long)p.split);
     (void)hipEventDestroy(te0);
     (void)hipEventDestroy(te1);

@@ -539,9 +539,10 @@ __global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const EigJob* 
 // broadcast by cross-lane reads; pivots by a reciprocal square root with
 // two Newton steps), the panel row R12 = R11^-T A12 is solved one column per
 // thread with the stored reciprocals of the pivots, and the trailing update
-// A22 -= R12^T R12 runs on FP64 MFMA tiles. R is padded with the
-// identity to order 128 and inverted in place: 16 x 16 diagonal blocks by
-// back substitution, then three doubling levels
+// A22 -= R12^T R12 runs on FP64 MFMA tiles. The work is done at the order
+// p padded with the identity to the next power of two (16 .. 128). R is
+// inverted in place: 16 x 16 diagonal blocks by back substitution, then up
+// to three doubling levels
 // [U11 U12; 0 U22]^-1 = [U11^-1, -U11^-1 U12 U22^-1; 0, U22^-1] on MFMA
 // tiles (U11^-1 U12 is staged in the free lower triangle).
 struct OrthJob {
@@ -560,8 +561,12 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   __shared__ double rinv[JMAX];  // 1 / R_jj, 0 for a dropped column
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int e = tid; e < JMAX * JMAX; e += LT) {
-    const int i = e >> 7, c = e & 127;
+  // working order: p padded with the identity to a power of two >= 16
+  int pn = 16;
+  while (pn < p) pn *= 2;
+  const int lpn = __ffs(pn) - 1;
+  for (int e = tid; e < pn * pn; e += LT) {
+    const int i = e >> lpn, c = e & (pn - 1);
     A[i][c] = (i < p && c < p) ? J.G[(int64_t)i * J.ldg + c] : (i == c ? 1.0 : 0.0);
   }
   __syncthreads();
@@ -569,7 +574,7 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   for (int i = lane; i < p; i += 64) mx = fmax(mx, A[i][i]);
   mx = wave_max(mx);
   const double thr = J.thr ? *J.thr : tol * mx;
-  for (int j0 = 0; j0 < JMAX; j0 += 16) {
+  for (int j0 = 0; j0 < pn; j0 += 16) {
     if (w == 0) {  // 16 x 16 diagonal block in registers of wave 0
       // lane: column b = lane & 15, rows a0 + t (t < 4), a0 = 4 (lane >> 4)
       const int b = lane & 15, a0 = 4 * (lane >> 4);
@@ -608,7 +613,7 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
         if (a0 + t <= b) A[j0 + a0 + t][j0 + b] = x[t];
     }
     __syncthreads();
-    const int rest = JMAX - j0 - 16;
+    const int rest = pn - j0 - 16;
     if (tid < rest) {  // R12 = R11^-T A12, column c (right-looking: independent updates per step)
       const int c = j0 + 16 + tid;
       double x[16];
@@ -656,7 +661,7 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
   // every wave has read R before the inversion below overwrites it in place
   __syncthreads();
   // 16 x 16 diagonal blocks: lane c of wave w solves column c of block w
-  if (w < JMAX / 16 && lane < 16) {
+  if (w < pn / 16 && lane < 16) {
     const int o = 16 * w, c = lane;
     double x[16];
 #pragma unroll
@@ -671,8 +676,8 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double 
       if (i <= c) A[o + i][o + c] = x[i];
   }
   __syncthreads();
-  for (int h = 16; h < JMAX; h *= 2) {
-    const int m = 2 * h, nt = h / 16, tiles = (JMAX / m) * nt * nt;
+  for (int h = 16; h < pn; h *= 2) {
+    const int m = 2 * h, nt = h / 16, tiles = (pn / m) * nt * nt;
     const int pr = w / (nt * nt), t = w % (nt * nt);
     const int b = pr * m, i0 = 16 * (t / nt), j0 = 16 * (t % nt);
     if (w < tiles) {  // T = U11^-1 U12 into the lower-left block

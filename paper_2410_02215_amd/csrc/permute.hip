@@ -514,8 +514,10 @@ void run_perm(int dir, const Structure& S, int dtype, const PermPlan& p, const v
       em[d.mode & 3] += d.nel;
       if (d.mode == 0) dxs += d.nel * d.dim[0];
     }
-    std::fprintf(stderr, "[perm] dir %d nel %lld nblocks %lld nA %d nG %d perm [%s] biggest [%s] modes %lld %lld %lld "
-                 "row0 %.1f\n", dir, (long long)p.nelem, (long long)S.nblocks, p.op.nA, p.op.nG, pm.c_str(), sh.c_str(),
+    std::fprintf(stderr, "[perm] dir %d nel %lld bytes %lld nblocks %lld nA %d nG %d perm [%s] biggest [%s] modes %lld "
+                 "%lld %lld row0 %.1f\n", dir, (long long)p.nelem,
+                 (long long)(2 * p.nelem * (dtype == FTN_F64 ? 8 : 4)), (long long)S.nblocks, p.op.nA, p.op.nG,
+                 pm.c_str(), sh.c_str(),
                  (long long)em[0], (long long)em[1], (long long)em[2], em[0] ? (double)dxs / em[0] : 0.0);
   }
   if (trace_time) {
