@@ -2042,8 +2042,14 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
   // Gram matrix and Cholesky-QR passes cost M d^2 each, Y's M N^2). (For
   // d > 128 the same route measured slower on the 40-site workload: those
   // sectors' A sides are not tall enough to pay for its extra small
-  // factorisations, and their spectra send them to the one-sided SVD.)
-  for (auto& x : S) x.thin = x.d <= JMAX && x.N >= 1 && x.N <= x.d && x.M > x.d;
+  // factorisations, and their spectra send them to the one-sided SVD.) The
+  // route adds about ten launches per compression, so it is taken only when
+  // A~ holds at least 2^22 entries: below that, its passes over A~ cost less
+  // than the launches (small networks, e.g. sampled amplitudes, stay on the
+  // Gram route).
+  constexpr int64_t THIN_MIN_ENTRIES = int64_t(1) << 22;
+  for (auto& x : S)
+    x.thin = x.d <= JMAX && x.N >= 1 && x.N <= x.d && x.M > x.d && x.M * x.d >= THIN_MIN_ENTRIES;
   // Gram matrices with split-K
   std::vector<int64_t> goffA(ng), goffB(ng);
   int64_t gsz = 0;

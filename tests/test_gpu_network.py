@@ -290,16 +290,20 @@ def test_compress_mixed_sector_sizes(P, dims):
 
 
 @pytest.mark.parametrize("case", [
-    ((90, 70), (300, 260), (8, 5), 20),      # d <= 128, thin B side, nothing truncated
-    ((120, 100), (900, 700), (60, 40), 30),  # d <= 128, thin B side, truncated
-    ((300, 200), (700, 500), (100, 128), 60),  # d > 128 (the Gram route) beside the same shapes
-    ((80, 60), (400, 300), (16, 12), 10),    # thin, with B~ of rank below N
-    # thin with long A~ sides: the Gram of Y = A~ B~ (N <= 32 columns, over
-    # 1000 rows, ragged) takes the tall-skinny A^T B kernel
-    ((100, 80), (3001, 1100), (24, 9), 25),
-    ((128, 64), (5000, 2049), (32, 1), 20),
-    # Y = A~ B~ with over 4096 rows and N <= 16 takes the streaming tall kernel
-    ((64, 48), (5000, 4100), (16, 7), 20),
+    # the thin route needs A~ sectors of at least 2^22 entries (M d); the
+    # small shapes beside them take the Gram route with the same structure
+    ((90, 70), (50000, 60000), (8, 5), 20),     # d <= 128, thin B side, nothing truncated
+    ((90, 70), (300, 260), (8, 5), 20),         # the same shape, small: Gram route
+    ((120, 100), (36000, 42000), (60, 40), 30),  # d <= 128, thin B side, truncated
+    ((120, 100), (900, 700), (60, 40), 30),     # small: Gram route
+    ((300, 200), (700, 500), (100, 128), 60),   # d > 128 (the Gram route) beside the same shapes
+    ((80, 60), (53000, 70000), (16, 12), 10),   # thin, with B~ of rank below N
+    # the Gram of Y = A~ B~ (N <= 32 columns, ragged long sides) takes the
+    # tall-skinny A^T B kernel; N = 1
+    ((100, 80), (42001, 53000), (24, 9), 25),
+    ((128, 64), (33000, 65601), (32, 1), 20),
+    # Y = A~ B~ with N <= 16 takes the streaming tall kernel
+    ((64, 48), (66000, 88000), (16, 7), 20),
 ])
 def test_compress_thin_b_side_matches_oracle(P, case):
     # sectors whose B side is thin (N <= d, N <= 128) and A~ tall (M > d):
