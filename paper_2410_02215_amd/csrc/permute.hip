@@ -226,25 +226,61 @@ __global__ void __launch_bounds__(PM_THREADS)
         rbase[r] = a;
       }
       __syncthreads();
+      typedef typename Pair<T>::type T2;
+      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
+      // whole tile with every pair aligned on both sides and rows of at most
+      // 2 * PM_THREADS entries: pair u of a thread sits u * (2 PM_THREADS / ta)
+      // rows below its first, at the same column; unchecked 2-wide accesses
+      // with no branch around them, so that all loads leave before the first
+      // wait
+      {
+        constexpr int STEP = 2 * PM_THREADS;
+        bool even = ((D.boff | dx | D.moff) & 1) == 0 &&
+                    ((((uintptr_t)src) | ((uintptr_t)dst)) & (sizeof(T2) - 1)) == 0;
+        for (int j = 1; j < D.m; ++j) even = even && (D.ts[j] & 1) == 0;
+        if (even && ta <= STEP && r0 + tr <= D.rows && x0 + ta <= dx) {
+          const int e0 = 2 * threadIdx.x, ra = STEP >> lta, rb0 = e0 >> lta, ib0 = e0 & (ta - 1);
+          T* bq = (DIR == 0 ? const_cast<T*>(src) : dst) + D.boff + (r0 + rb0) * dx + x0 + ib0;
+          T* sq = (DIR == 0 ? dst : const_cast<T*>(src)) + D.moff + x0 + ib0;
+          const int64_t bstep = (int64_t)ra * dx;
+          T2 buf[PPT];
+#pragma unroll
+          for (int u = 0; u < PPT; ++u)
+            buf[u] = DIR == 0 ? *(const T2*)(bq + u * bstep) : *(const T2*)(sq + rbase[rb0 + u * ra]);
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) {
+            T2 w;
+            w.x = v * buf[u].x;
+            w.y = v * buf[u].y;
+            *(T2*)(DIR == 0 ? sq + rbase[rb0 + u * ra] : bq + u * bstep) = w;
+          }
+          __syncthreads();  // rbase is rewritten by the next sub-tile
+          continue;
+        }
+      }
       // two neighbouring entries of a row per thread (ta is an even power of
       // two, so a pair never straddles rows): one 2-wide load and store when
       // both addresses are aligned to the pair, else two single entries. The
       // PPT pairs of a thread are all loaded before any is stored, so that
       // each thread keeps several loads in flight.
-      typedef typename Pair<T>::type T2;
-      constexpr int PPT = PM_TILE / (2 * PM_THREADS);
       T2 buf[PPT];
-      int64_t bis[PPT], sis[PPT];
       unsigned okm = 0, twom = 0, vecm = 0;
-#pragma unroll
-      for (int u = 0; u < PPT; ++u) {
+      // block-side and strided-side index of pair u of this thread (the
+      // stores recompute them rather than keep them in registers)
+      auto idx = [&](int u, int64_t& bi, int64_t& si) {
         const int e = 2 * threadIdx.x + u * 2 * PM_THREADS;
         const int r = e >> lta, i = e & (ta - 1);
         const int64_t row = r0 + r, x = x0 + i;
         const bool ok = row < D.rows && x < dx;
-        const int64_t bi = D.boff + row * dx + x, si = D.moff + (ok ? rbase[r] : 0) + x;
-        bis[u] = bi;
-        sis[u] = si;
+        bi = D.boff + row * dx + x;
+        si = D.moff + (ok ? rbase[r] : 0) + x;
+        return ok;
+      };
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        int64_t bi, si;
+        const bool ok = idx(u, bi, si);
+        const int64_t x = x0 + ((2 * threadIdx.x + u * 2 * PM_THREADS) & (ta - 1));
         const T* sp = DIR == 0 ? src + bi : src + si;
         T* dp = DIR == 0 ? dst + si : dst + bi;
         const bool two = x + 1 < dx;
@@ -264,7 +300,9 @@ __global__ void __launch_bounds__(PM_THREADS)
 #pragma unroll
       for (int u = 0; u < PPT; ++u) {
         if (!((okm >> u) & 1u)) continue;
-        T* dp = DIR == 0 ? dst + sis[u] : dst + bis[u];
+        int64_t bi, si;
+        idx(u, bi, si);
+        T* dp = DIR == 0 ? dst + si : dst + bi;
         T2 b;
         b.x = v * buf[u].x;
         b.y = v * buf[u].y;
@@ -299,66 +337,58 @@ __global__ void __launch_bounds__(PM_THREADS)
       const int ld = ta + 1, n = ta * tr;
       typedef typename Pair<T>::type T2;
       constexpr int PPT = PM_TILE / (2 * PM_THREADS);
-      // whole tile, every pair aligned on both sides: unchecked 2-wide
-      // accesses with 32-bit in-tile offsets
-      if (x0 + ta <= dx && y0 + tr <= dy && ((bbase | sby | sbase | tsx) & 1) == 0 &&
-          ((((uintptr_t)src) | ((uintptr_t)dst)) & (sizeof(T2) - 1)) == 0) {
-        const T* bp = (DIR == 0 ? src : dst) + bbase + y0 * sby + x0;  // block side
-        const T* sp = (DIR == 0 ? dst : src) + sbase + y0 + x0 * tsx;  // strided side
+      // whole tile of PM_TILE entries, every pair aligned on both sides, ta
+      // and tr at most 2 * PM_THREADS: unchecked 2-wide accesses with no
+      // branch around them, so that a thread's loads all leave before the
+      // first wait. Pair u of a thread is entry e = e0 + 2 PM_THREADS u of the
+      // tile, so along the block-side walk (leg 0 fastest) it advances by
+      // whole rows and along the strided-side walk (leg y fastest) by whole
+      // columns: one pointer per walk, stepped by a uniform stride.
+      constexpr int STEP = 2 * PM_THREADS;
+      if (n == PM_TILE && ta <= STEP && tr <= STEP && x0 + ta <= dx && y0 + tr <= dy &&
+          ((bbase | sby | sbase | tsx) & 1) == 0 && ((((uintptr_t)src) | ((uintptr_t)dst)) & (sizeof(T2) - 1)) == 0) {
+        const int e0 = 2 * threadIdx.x;
+        const int ra = STEP >> lta, rb0 = e0 >> lta, ib0 = e0 & (ta - 1);  // block-side walk
+        const int ia = STEP >> ltr, rs0 = e0 & (tr - 1), is0 = e0 >> ltr;  // strided-side walk
+        T* bq = (DIR == 0 ? const_cast<T*>(src) : dst) + bbase + (y0 + rb0) * sby + x0 + ib0;
+        T* sq = (DIR == 0 ? dst : const_cast<T*>(src)) + sbase + y0 + rs0 + (x0 + is0) * tsx;
+        const int64_t bstep = (int64_t)ra * sby, sstep = (int64_t)ia * tsx;
         T2 buf[PPT];
         if (DIR == 0) {
 #pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            if (e < n) buf[u] = *(const T2*)(bp + (int64_t)(e >> lta) * sby + (e & (ta - 1)));
-          }
+          for (int u = 0; u < PPT; ++u) buf[u] = *(const T2*)(bq + u * bstep);
 #pragma unroll
           for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            const int r = e >> lta, i = e & (ta - 1);
-            if (e < n) {
-              tile[r * ld + i] = v * buf[u].x;
-              tile[r * ld + i + 1] = v * buf[u].y;
-            }
+            T* t = tile + (rb0 + u * ra) * ld + ib0;
+            t[0] = v * buf[u].x;
+            t[1] = v * buf[u].y;
           }
           __syncthreads();
 #pragma unroll
           for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            const int r = e & (tr - 1), i = e >> ltr;
-            if (e < n) {
-              T2 w;
-              w.x = tile[r * ld + i];
-              w.y = tile[(r + 1) * ld + i];
-              *(T2*)(const_cast<T*>(sp) + r + (int64_t)i * tsx) = w;
-            }
+            const T* t = tile + rs0 * ld + is0 + u * ia;
+            T2 w;
+            w.x = t[0];
+            w.y = t[ld];
+            *(T2*)(sq + u * sstep) = w;
           }
         } else {
 #pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            if (e < n) buf[u] = *(const T2*)(sp + (e & (tr - 1)) + (int64_t)(e >> ltr) * tsx);
-          }
+          for (int u = 0; u < PPT; ++u) buf[u] = *(const T2*)(sq + u * sstep);
 #pragma unroll
           for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            const int r = e & (tr - 1), i = e >> ltr;
-            if (e < n) {
-              tile[r * ld + i] = v * buf[u].x;
-              tile[(r + 1) * ld + i] = v * buf[u].y;
-            }
+            T* t = tile + rs0 * ld + is0 + u * ia;
+            t[0] = v * buf[u].x;
+            t[ld] = v * buf[u].y;
           }
           __syncthreads();
 #pragma unroll
           for (int u = 0; u < PPT; ++u) {
-            const int e = 2 * (threadIdx.x + u * PM_THREADS);
-            const int r = e >> lta, i = e & (ta - 1);
-            if (e < n) {
-              T2 w;
-              w.x = tile[r * ld + i];
-              w.y = tile[r * ld + i + 1];
-              *(T2*)(const_cast<T*>(bp) + (int64_t)r * sby + i) = w;
-            }
+            const T* t = tile + (rb0 + u * ra) * ld + ib0;
+            T2 w;
+            w.x = t[0];
+            w.y = t[1];
+            *(T2*)(bq + u * bstep) = w;
           }
         }
         __syncthreads();  // the staging buffer is reused by the next sub-tile
