@@ -8,9 +8,12 @@ a seeded greedy path, FP64 throughout. One step = the norm <psi|psi> plus
 the hopping term <psi|h|psi> on the first edge: two network contractions
 (metric unit: contractions per second).
 
-Prints one JSON line with the throughput, a roofline entry for the dominant
-kernel class (timed with HIP events on the library's stream inside the
-timed region), and the CPU oracle timed on a bounded sample on rank 0.
+Prints one JSON line with the throughput of the timed steps, a roofline
+entry for the dominant kernel (timed with two HIP events on each of its
+dispatches, on the stream it runs on, over an instrumented repeat of the
+timed steps: the events cost host time per launch, about 12% of the step,
+so they stay out of the steps that give the throughput), and the CPU oracle
+timed on a bounded sample on rank 0.
 """
 
 import argparse
@@ -412,14 +415,24 @@ def main_gradient(args):
     torch.cuda.synchronize()
     P.ftn.memory_stats(torch.cuda.current_device(), reset_peak=True)
     torch.cuda.reset_peak_memory_stats()
-    P.ftn.profile_collect()
-    P.ftn.profile_enable(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         E, gs = step()
         print("[bench] gradient %d done" % k, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    peak = {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
+            "torch": torch.cuda.max_memory_allocated() / 1e9}
+    # an instrumented repeat (two HIP events on every dispatch) for the
+    # per-kernel durations and the roofline, timed apart from `value`
+    P.ftn.profile_collect()
+    P.ftn.profile_enable(True)
+    tp0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        print("[bench] profiled gradient %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
     P.ftn.profile_enable(False)
     prof = P.ftn.profile_collect()
     el = t1 - t0
@@ -434,8 +447,8 @@ def main_gradient(args):
                    "checkpoint_steps": ck or 0,
                    "backward": "torch.autograd over the library's adjoints" if args.autograd
                    else "library network backward (ftn_contract_network_grad)"},
-        "peak_memory_gb": {"library": P.ftn.memory_stats(torch.cuda.current_device())["peak"] / 1e9,
-                           "torch": torch.cuda.max_memory_allocated() / 1e9},
+        "peak_memory_gb": peak,
+        "profiled_ms_per_step": 1000.0 * (tp1 - tp0) / args.steps,
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
         "result": {"energy": E, "grad_norm": gnorm},
@@ -539,8 +552,7 @@ def main():
         if args.save_tuning:
             P.ftn.autotune_save(args.save_tuning)
     tune_stats = P.ftn.autotune_stats()
-    P.ftn.profile_collect()
-    P.ftn.profile_enable(True)
+    # timed steps, uninstrumented: `value`
     w0 = time.monotonic_ns()
     t0 = time.perf_counter()
     flops = 0.0
@@ -555,8 +567,21 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     w1 = time.monotonic_ns()
+    # the same steps again with the library's kernel timer on (two HIP events
+    # on every dispatch): per-kernel durations and the roofline. The events
+    # cost host time per launch, so these steps are timed apart from `value`.
+    P.ftn.profile_collect()
+    P.ftn.profile_enable(True)
+    p0 = time.monotonic_ns()
+    tp0 = time.perf_counter()
+    for k in range(args.steps):
+        gpu_step(g, chi, not args.serial)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    p1 = time.monotonic_ns()
     P.ftn.profile_enable(False)
     prof = P.ftn.profile_collect()
+    print("[bench] profiled steps done", file=sys.stderr, flush=True)
     el = t1 - t0
     ms_step = 1000.0 * el / args.steps
     value = 2.0 * args.steps / el
@@ -585,9 +610,12 @@ def main():
                         for c in prof if c in PEAK and prof[c][0] > 0},
         "result": {"log2_norm": math.log2(abs(norm)) if norm else None, "hop_expectation": hop},
         "rel_err_vs_oracle": golden_errors(norm, hop),
-        # CLOCK_MONOTONIC bounds of the timed steps: a rocprofv3 kernel trace of
-        # the same run can be cut to them (rocprof_summary stats <dir> <this line>)
+        # CLOCK_MONOTONIC bounds of the timed steps and of their instrumented
+        # repeat (kernel_* and roofline): a rocprofv3 kernel trace of the same
+        # run can be cut to the latter (rocprof_summary stats <dir> <this line>)
         "timed_window_ns": [w0, w1],
+        "profiled_window_ns": [p0, p1],
+        "profiled_ms_per_step": 1000.0 * (tp1 - tp0) / args.steps,
         "roofline": roof,
     }
     if not args.no_forms:

@@ -6,9 +6,10 @@ Usage (CSV output of rocprofv3, ``--output-format csv``):
         per-kernel table from the ``*_kernel_stats.csv`` of a
         ``--kernel-trace --stats`` run, plus the library's profiler classes;
         with the JSON line that bench.py printed in that run, also the same
-        tables over its timed steps only (dispatches of ``*_kernel_trace.csv``
-        inside its ``timed_window_ns``, CLOCK_MONOTONIC nanoseconds as the
-        trace's timestamps), which is what the line's roofline averages over
+        tables over its instrumented steps only (dispatches of
+        ``*_kernel_trace.csv`` inside its ``profiled_window_ns``, else its
+        ``timed_window_ns``; CLOCK_MONOTONIC nanoseconds as the trace's
+        timestamps), which is what the line's roofline averages over
     python3 -m paper_2410_02215_amd.rocprof_summary pmc <dir>
         per-class sums and per-launch means of every counter in the
         ``*_counter_collection.csv`` files of a ``--pmc`` run
@@ -103,7 +104,8 @@ def stats(d, bench_out=None, top=30):
     if bench_out:
         import json
         line = [l for l in open(bench_out).read().splitlines() if l.startswith("{")][-1]
-        w0, w1 = json.loads(line)["timed_window_ns"]
+        bl = json.loads(line)
+        w0, w1 = bl.get("profiled_window_ns", bl["timed_window_ns"])
         rows = []
         for f in _find(d, "kernel_trace.csv"):
             with open(f) as fh:
