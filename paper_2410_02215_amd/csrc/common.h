@@ -359,6 +359,9 @@ void gemm_plan(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipS
 void gemm_plan_with(GemmPlan& p, const std::vector<GemmGroup>& groups, int kind, hipStream_t s,
                     bool persistent, int cfg, int split);
 int gemm_ncfg();
+// a plan for these groups from the process-wide cache of grouped-product
+// plans (built, uploaded and completed on s on a miss)
+std::shared_ptr<const GemmPlan> gemm_plan_cached(const std::vector<GemmGroup>& groups, int kind, hipStream_t s);
 // tile autotuner: the (cfg, split) for these groups from the tuning cache, or
 // tuned now (tuning mode), or -1 / -1 (the built-in heuristic)
 void tune_choice(const std::vector<GemmGroup>& gs, int kind, hipStream_t s, int* cfg, int* split);

@@ -11,6 +11,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -1089,6 +1093,63 @@ static void run_skinny(const std::vector<GemmGroup>& gs, const T* A, const T* B,
   }
 }
 
+// Plans of the grouped products issued by the factorisations are cached by
+// the groups' shapes and offsets (which are relative to the operand base
+// pointers, so a repeated step meets the same keys): a hit costs no host
+// planning and no upload of the group tables. Cached plans keep their tables
+// in device memory of their own; a plan is complete on the device before it
+// is cached, since another stream may use it next.
+namespace {
+std::mutex g_gp_mu;
+auto& g_gp = *new std::unordered_map<std::string, std::shared_ptr<const GemmPlan>>();
+constexpr size_t GP_CACHE_MAX = 8192;
+
+std::string groups_key(const std::vector<GemmGroup>& gs, int kind) {
+  std::string k;
+  k.reserve(8 + gs.size() * 18 * 8);
+  auto put = [&](int64_t v) { k.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
+  put(kind);
+  for (const GemmGroup& g : gs) {
+    put(g.M);
+    put(g.N);
+    put(g.K);
+    put(g.a_off);
+    put(g.b_off);
+    put(g.lda);
+    put(g.ldb);
+    put(g.transA);
+    put(g.transB);
+    put(g.c_off);
+    put(g.ldc);
+    put(g.scatter);
+    put(g.sym);
+    if (g.scatter == 1) {
+      put(g.nrc);
+      put(g.ncc);
+      put(g.rc_base);
+      put(g.cc_base);
+      put(g.boff_base);
+    }
+  }
+  return k;
+}
+}  // namespace
+
+std::shared_ptr<const GemmPlan> gemm_plan_cached(const std::vector<GemmGroup>& groups, int kind, hipStream_t s) {
+  const std::string key = groups_key(groups, kind);
+  {
+    std::lock_guard<std::mutex> g(g_gp_mu);
+    auto it = g_gp.find(key);
+    if (it != g_gp.end()) return it->second;
+  }
+  auto P = std::make_shared<GemmPlan>();
+  gemm_plan(*P, groups, kind, s, true);
+  HIPC(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> g(g_gp_mu);
+  if (g_gp.size() >= GP_CACHE_MAX) g_gp.clear();
+  return g_gp.try_emplace(key, std::move(P)).first->second;
+}
+
 void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups, const void* A,
                       const void* B, void* C, const GemmScatter* sc, hipStream_t s, double alpha,
                       double beta) {
@@ -1107,9 +1168,8 @@ void run_grouped_gemm(int gemm, int dtype, const std::vector<GemmGroup>& groups,
     }
     return;
   }
-  GemmPlan p;
-  gemm_plan(p, groups, gemm, s);
-  run_gemm(p, dtype, A, B, C, sc, s, alpha, beta);
+  const std::shared_ptr<const GemmPlan> p = gemm_plan_cached(groups, gemm, s);
+  run_gemm(*p, dtype, A, B, C, sc, s, alpha, beta);
 }
 
 }  // namespace ftn
