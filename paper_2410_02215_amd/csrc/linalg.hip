@@ -1823,14 +1823,11 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
     gaz.push_back(plain_group(rB, p, p, zo[t], p, 0, go, p, 0, zo[t], p));         // Z M
     ge.push_back(plain_group(rA, p, p, qo[t], p, 0, go, p, 0, eoff[g], p));        // E = Q Zs
   }
-  GemmPlan Pxt, Px, Pgq, Pgz, Paq, Paz, Pe;
-  gemm_plan(Pxt, gxt, FTN_GEMM_F64, s);
-  gemm_plan(Px, gx, FTN_GEMM_F64, s);
-  gemm_plan(Pgq, ggq, FTN_GEMM_F64, s);
-  gemm_plan(Pgz, ggz, FTN_GEMM_F64, s);
-  gemm_plan(Paq, gaq, FTN_GEMM_F64, s);
-  gemm_plan(Paz, gaz, FTN_GEMM_F64, s);
-  gemm_plan(Pe, ge, FTN_GEMM_F64, s);
+  const auto cpx = gemm_plan_cached(gxt, FTN_GEMM_F64, s), cx = gemm_plan_cached(gx, FTN_GEMM_F64, s),
+             cgq = gemm_plan_cached(ggq, FTN_GEMM_F64, s), cgz = gemm_plan_cached(ggz, FTN_GEMM_F64, s),
+             caq = gemm_plan_cached(gaq, FTN_GEMM_F64, s), caz = gemm_plan_cached(gaz, FTN_GEMM_F64, s),
+             ce = gemm_plan_cached(ge, FTN_GEMM_F64, s);
+  const GemmPlan &Pxt = *cpx, &Px = *cx, &Pgq = *cgq, &Pgz = *cgz, &Paq = *caq, &Paz = *caz, &Pe = *ce;
   std::vector<OrthJob> oj;
   std::vector<EigJob> ej;
   for (int t = 0; t < ni; ++t) {
