@@ -135,6 +135,34 @@ DBuf<T> to_device(const std::vector<T>& v, hipStream_t s) {
   return b;
 }
 
+// Job table of a kernel that runs one workgroup (or one grid row) per job.
+// Up to JT_INLINE jobs travel by value in the kernel arguments, so that the
+// common case of a few sectors needs no upload; longer tables are uploaded.
+constexpr int JT_INLINE = 8;
+template <typename J>
+struct JobTable {
+  const J* p;  // uploaded table, or null: the jobs are in v
+  J v[JT_INLINE];
+  __device__ __forceinline__ J operator[](int64_t i) const { return p ? p[i] : v[i]; }
+};
+template <typename J>
+struct Jobs {  // host side: the table and, for long ones, its device copy
+  JobTable<J> t;
+  DBuf<J> buf;
+  Jobs(const J* jobs, size_t n, hipStream_t s) {
+    static_assert(sizeof(JobTable<J>) <= 2048, "job table too large for the kernel arguments");
+    std::memset(&t, 0, sizeof(t));
+    if (n <= (size_t)JT_INLINE) {
+      for (size_t i = 0; i < n; ++i) t.v[i] = jobs[i];
+    } else {
+      buf = DBuf<J>(n, s);
+      buf.upload(jobs, n);
+      t.p = buf.p;
+    }
+  }
+  Jobs(const std::vector<J>& jobs, hipStream_t s) : Jobs(jobs.data(), jobs.size(), s) {}
+};
+
 // buffers of cached plans live for the whole process: allocated with
 // hipMalloc (no stream), filled on the stream that builds the plan
 template <typename T>

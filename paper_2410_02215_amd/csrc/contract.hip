@@ -653,9 +653,4 @@ void op_ftensordot_backward(const Tensor& a, const Tensor& b, const Tensor& dc, 
   run_perm(1, b.S(), b.dtype, P->pb, dBt.p, db->data, s);
 }
 
-void clear_plan_cache() {
-  std::lock_guard<std::mutex> g(g_plan_mu);
-  g_plans.clear();
-}
-
 }  // namespace ftn

@@ -135,7 +135,7 @@ __host__ __device__ inline double jacobi_stop(int n) {
   return fmax(1e-30, f * f);
 }
 
-__global__ void __launch_bounds__(LT) k_jacobi_sweep(const EigJob* jobs) {
+__global__ void __launch_bounds__(LT) k_jacobi_sweep(const JobTable<EigJob> jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int n = J.n;
   if (n <= 0) return;
@@ -287,7 +287,7 @@ __device__ inline int rr_slot(int n2, int r, int x) {
 // buffer; waves 1..15 update the remaining blocks meanwhile. Every entry gets
 // the same operations in the same order as in k_jacobi_sweep, so the results
 // are bitwise the same.
-__global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
+__global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const JobTable<EigJob> jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int n = J.n;
   if (n <= 0) return;
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(LT) k_jacobi_sweep_la(const EigJob* jobs) {
 // grid (jobs, ceil(n / JV_WAVES)), JV_WAVES waves: wave w owns row
 // blockIdx.y * JV_WAVES + w of V and lane k applies rotation k of every
 // round; the log is read PF rounds ahead, double-buffered in registers.
-__global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const EigJob* jobs) {
+__global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const JobTable<EigJob> jobs) {
   constexpr int PF = 8;
   const EigJob J = jobs[blockIdx.x];
   const int n = J.n;
@@ -553,7 +553,7 @@ struct OrthJob {
   int p, ldg, ldr, ldm;
 };
 
-__global__ void __launch_bounds__(LT) k_orth_factor(const OrthJob* jobs, double tol) {
+__global__ void __launch_bounds__(LT) k_orth_factor(const JobTable<OrthJob> jobs, double tol) {
   const OrthJob J = jobs[blockIdx.x];
   const int p = J.p;
   __shared__ double A[JMAX][JMAX + 1];
@@ -803,7 +803,7 @@ struct ScaleColsJob {
   double* W;
   int64_t rows, cols, ldv;
 };
-__global__ void k_scale_cols(const ScaleColsJob* jobs) {
+__global__ void k_scale_cols(const JobTable<ScaleColsJob> jobs) {
   const ScaleColsJob J = jobs[blockIdx.y];
   const int64_t n = J.rows * J.cols;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -915,19 +915,21 @@ static void jacobi_eig(std::vector<EigJob>& ej, hipStream_t s, std::vector<int>*
   std::stable_partition(ord.begin(), ord.end(), [](const EigJob& e) { return e.n < 63; });
   int nsmall = 0;
   while (nsmall < nj && ord[nsmall].n < 63) ++nsmall;
-  DBuf<EigJob> dj = to_device(ord, s);
+  const Jobs<EigJob> dj(ord, s);
   if (nsmall > 0) {
     const std::vector<EigJob> part(ord.begin(), ord.begin() + nsmall);
-    FACTOR_LAUNCH(FTN_PROF_K_JACOBI, eig_flops(part), k_jacobi_sweep, dim3((unsigned)nsmall), dim3(LT), 0, s, dj.p);
+    const Jobs<EigJob> dp(part, s);
+    FACTOR_LAUNCH(FTN_PROF_K_JACOBI, eig_flops(part), k_jacobi_sweep, dim3((unsigned)nsmall), dim3(LT), 0, s, dp.t);
   }
   if (nsmall < nj) {
     const std::vector<EigJob> part(ord.begin() + nsmall, ord.end());
+    const Jobs<EigJob> dp(part, s);
     FACTOR_LAUNCH(FTN_PROF_K_JACOBI_LA, eig_flops(part), k_jacobi_sweep_la, dim3((unsigned)(nj - nsmall)), dim3(LT), 0,
-                  s, dj.p + nsmall);
+                  s, dp.t);
   }
   if (nmax > 0)
     FACTOR_LAUNCH(FTN_PROF_K_JACOBI_VEC, 0.0, k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(nmax, JV_WAVES)),
-                  dim3(64 * JV_WAVES), 0, s, dj.p);
+                  dim3(64 * JV_WAVES), 0, s, dj.t);
   if (rounds) {
     rounds->assign(nj, 0);
     for (int t = 0; t < nj; ++t)
@@ -1234,7 +1236,7 @@ struct SvdJob {
   int r, c, ldx, ldu;
 };
 
-__global__ void __launch_bounds__(LT) k_svd_cols(const SvdJob* jobs, double tol) {
+__global__ void __launch_bounds__(LT) k_svd_cols(const JobTable<SvdJob> jobs, double tol) {
   const SvdJob J = jobs[blockIdx.x];
   const int r = J.r, c = J.c;
   if (r <= 0 || c <= 0) return;
@@ -1398,11 +1400,11 @@ static void svd_cols(std::vector<SvdJob>& sj, const std::vector<double*>& V, hip
     e.rk = j.rk;
     e.n = j.c;
   }
-  DBuf<SvdJob> d = to_device(sj, s);
-  DBuf<EigJob> de = to_device(ej, s);
-  FACTOR_LAUNCH(FTN_PROF_K_SVD_COLS, f, k_svd_cols, dim3((unsigned)nj), dim3(LT), 0, s, d.p, 1e-15);
+  const Jobs<SvdJob> d(sj, s);
+  const Jobs<EigJob> de(ej, s);
+  FACTOR_LAUNCH(FTN_PROF_K_SVD_COLS, f, k_svd_cols, dim3((unsigned)nj), dim3(LT), 0, s, d.t, 1e-15);
   FACTOR_LAUNCH(FTN_PROF_K_JACOBI_VEC, 0.0, k_jacobi_vectors, dim3((unsigned)nj, (unsigned)cdiv(cmax, JV_WAVES)),
-                dim3(64 * JV_WAVES), 0, s, de.p);
+                dim3(64 * JV_WAVES), 0, s, de.t);
 }
 
 // per bond sector q
@@ -1429,7 +1431,7 @@ struct DiagJob {
   int d;
   int pad;
 };
-__global__ void __launch_bounds__(256) k_diag_thr(const DiagJob* jobs, double tol) {
+__global__ void __launch_bounds__(256) k_diag_thr(const JobTable<DiagJob> jobs, double tol) {
   const DiagJob J = jobs[blockIdx.x];
   __shared__ double red[4];
   double m = 0.0;
@@ -1514,8 +1516,8 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
   {
     std::vector<DiagJob> dj(nm);
     for (int m = 0; m < nm; ++m) dj[m] = DiagJob{Gm + off[m], thr.p + m, (int)dim[m], 0};
-    DBuf<DiagJob> d = to_device(dj, s);
-    LAUNCH(k_diag_thr, dim3(nm), dim3(256), 0, s, d.p, tol);
+    const Jobs<DiagJob> d(dj, s);
+    LAUNCH(k_diag_thr, dim3(nm), dim3(256), 0, s, d.t, tol);
   }
   int64_t dmax = 0, r12n = 0;
   std::vector<int64_t> r12off(nm);
@@ -1555,8 +1557,8 @@ static void chol_drop(double* Gm, const std::vector<int64_t>& off, const std::ve
                                            off[m] + (j0 + nb) * d + j0 + nb, d)));
       }
     }
-    DBuf<OrthJob> doj = to_device(oj, s);
-    FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.p, tol);
+    const Jobs<OrthJob> doj(oj, s);
+    FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, doj.t, tol);
     if (!gt.empty()) {
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gt, Mout ? Mout : Minv.p, Gm, R12.p, nullptr, s);
       run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gs, R12.p, R12.p, Gm, nullptr, s, -1.0, 1.0);
@@ -1612,7 +1614,7 @@ struct ShiftJob {
   int64_t m;        // rows of the factor
 };
 
-__global__ void __launch_bounds__(256) k_shift_diag(const ShiftJob* jobs) {
+__global__ void __launch_bounds__(256) k_shift_diag(const JobTable<ShiftJob> jobs) {
   const ShiftJob J = jobs[blockIdx.x];
   const int d = J.d;
   __shared__ double red[4];
@@ -1636,7 +1638,7 @@ struct RowsJob {
   int d, trans;
 };
 
-__global__ void k_copy_rows(const RowsJob* jobs) {
+__global__ void k_copy_rows(const JobTable<RowsJob> jobs) {
   const RowsJob J = jobs[blockIdx.y];
   const int64_t n = J.m * J.d;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -1682,8 +1684,8 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
   {
     std::vector<ShiftJob> sj(nj);
     for (int j = 0; j < nj; ++j) sj[j] = ShiftJob{Gm + J[j].goff, R1 + wo[j], J[j].d, 0, J[j].m};
-    DBuf<ShiftJob> d = to_device(sj, s);
-    LAUNCH(k_shift_diag, dim3(nj), dim3(256), 0, s, d.p);
+    const Jobs<ShiftJob> d(sj, s);
+    LAUNCH(k_shift_diag, dim3(nj), dim3(256), 0, s, d.t);
   }
   auto factor = [&](double* R, double* M, double tol) {
     std::vector<OrthJob> oj;
@@ -1703,8 +1705,8 @@ static void acc_factor(const std::vector<AccSrc>& J, const double* At, const dou
       oj.push_back(o);
     }
     if (!oj.empty()) {
-      DBuf<OrthJob> d = to_device(oj, s);
-      FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, d.p, tol);
+      const Jobs<OrthJob> d(oj, s);
+      FACTOR_LAUNCH(FTN_PROF_K_ORTH, orth_flops(oj), k_orth_factor, dim3((unsigned)oj.size()), dim3(LT), 0, s, d.t, tol);
     }
     if (!boff.empty()) chol_drop(R, boff, bdim, tol, s, M);
   };
@@ -1847,13 +1849,13 @@ static void x_spectrum(std::vector<Sect>& S, int64_t chi, const double* Hm, cons
     e.n = (int)p;
     ej.push_back(e);
   }
-  DBuf<OrthJob> doj = to_device(oj, s);
+  const Jobs<OrthJob> doj(oj, s);
   const double of_it = orth_flops(oj);
   double *q = Q0.p, *qt = Q1.p, *z = Z0.p, *zt = Z1.p, *zu = Z2.p;
   // y <- orthonormal basis of span(y), dependent columns zeroed
   auto orth = [&](const GemmPlan& gram, const GemmPlan& app, double*& y, double*& yt) {
     run_gemm(gram, FTN_F64, y, y, Gy.p, nullptr, s);
-    FACTOR_LAUNCH(FTN_PROF_K_ORTH, of_it, k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.p, tol);
+    FACTOR_LAUNCH(FTN_PROF_K_ORTH, of_it, k_orth_factor, dim3((unsigned)ni), dim3(LT), 0, s, doj.t, tol);
     run_gemm(app, FTN_F64, y, Mm.p, yt, nullptr, s);
     std::swap(y, yt);
   };
@@ -2141,9 +2143,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
     if (!coffs.empty()) chol_drop(Fm.p, coffs, cdims, 1e-13, s);
     acc_factor(acc, At.p, Bt.p, Gm.p, Fm.p, s);
     if (!rows.empty()) {
-      DBuf<RowsJob> dr = to_device(rows, s);
+      const Jobs<RowsJob> dr(rows, s);
       LAUNCH(k_copy_rows, dim3((unsigned)std::min<int64_t>(cdiv(maxrows, 256), 1024), (unsigned)rows.size()),
-             dim3(256), 0, s, dr.p);
+             dim3(256), 0, s, dr.t);
     }
     const int np = (int)poffs.size();
     std::vector<int> prk(std::max(np, 1));
@@ -2375,22 +2377,32 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       for (int i = 0; i < n; ++i)
         if (!S[grp[i]].acc && vals[i] < 1e-6 * smax[grp[i]]) vals[i] = 0.0;
     }
-    DBuf<double> dv = to_device(vals, s);
-    DBuf<int> dg = to_device(grp, s), di = to_device(idx, s), dc = to_device(crank, s);
-    DBuf<int> dk(std::max(ng, 1), s);
-    DBuf<double> dst(4, s);
-    std::vector<double> st(4, 0.0);
-    HIPC(hipMemsetAsync(dst.p, 0, 32, s));
     if (ng > 1024) fail(FTN_ENOTSUP, "more than 1024 bond sectors");
     if (cutoff < 0 || !std::isfinite(cutoff)) fail(FTN_EINVAL, "cutoff must be finite and >= 0");
     const double eff_cut = cutoff;
-    if (n)
-      LAUNCH(k_select, dim3(1), dim3(LT), 0, s, dv.p, dg.p, di.p, dc.p, n, ng, chi, eff_cut, dk.p, dst.p);
+    // inputs of the selection in one upload (values | group | index | charge
+    // rank), its outputs in one read-back (4 statistics | kept per group)
+    const int64_t ni8 = cdiv(n, 2), nc8 = cdiv(ng, 2);
+    std::vector<double> pin(std::max<int64_t>(n + 2 * ni8 + nc8, 1), 0.0);
+    std::copy(vals.begin(), vals.end(), pin.begin());
+    std::memcpy(pin.data() + n, grp.data(), n * sizeof(int));
+    std::memcpy(pin.data() + n + ni8, idx.data(), n * sizeof(int));
+    std::memcpy(pin.data() + n + 2 * ni8, crank.data(), ng * sizeof(int));
+    DBuf<double> dpin = to_device(pin, s);
+    const double* dv = dpin.p;
+    const int *dg = (const int*)(dpin.p + n), *di = (const int*)(dpin.p + n + ni8),
+              *dc = (const int*)(dpin.p + n + 2 * ni8);
+    DBuf<double> dout(4 + std::max<int64_t>(nc8, 1), s);
+    int* dk = (int*)(dout.p + 4);
+    HIPC(hipMemsetAsync(dout.p, 0, 32, s));
+    if (n) LAUNCH(k_select, dim3(1), dim3(LT), 0, s, dv, dg, di, dc, n, ng, chi, eff_cut, dk, dout.p);
     HIPC(hipGetLastError());
-    std::vector<int> kept(std::max(ng, 1), 0);
-    if (n) HIPC(hipMemcpyAsync(kept.data(), dk.p, ng * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(st.data(), dst.p, 32, hipMemcpyDeviceToHost, s));
+    std::vector<double> hout(4 + std::max<int64_t>(nc8, 1), 0.0);
+    HIPC(hipMemcpyAsync(hout.data(), dout.p, (4 + (n ? nc8 : 0)) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    std::vector<double> st(hout.begin(), hout.begin() + 4);
+    std::vector<int> kept(std::max(ng, 1), 0);
+    if (n) std::memcpy(kept.data(), hout.data() + 4, ng * sizeof(int));
     res.discarded = st[0];
     double a1 = st[1], a2 = st[2];
     res.near_tie = (a2 > 0 && std::fabs(a1 - a2) <= 1e3 * 2.220446049250313e-16 * std::fabs(a1));
@@ -2479,9 +2491,9 @@ CompressResult op_compress_bond(const Tensor& a, const Tensor& b, int la, int lb
       if (!scols.empty()) {
         int64_t mx = 1;
         for (auto& j : scols) mx = std::max<int64_t>(mx, j.rows * j.cols);
-        DBuf<ScaleColsJob> dj = to_device(scols, s);
+        const Jobs<ScaleColsJob> dj(scols, s);
         LAUNCH(k_scale_cols, dim3((unsigned)std::min<int64_t>(cdiv(mx, 256), 1024), (unsigned)scols.size()), dim3(256),
-               0, s, dj.p);
+               0, s, dj.t);
       }
       if (!gw.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gw, Xm.p, Em.p, Wk.p, nullptr, s);
       if (!gwf.empty()) run_grouped_gemm(FTN_GEMM_F64, FTN_F64, gwf, Rc.p, Wk.p, GF.p, nullptr, s);

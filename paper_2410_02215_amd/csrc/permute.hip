@@ -42,7 +42,7 @@ __device__ inline int sign_bit(const SignOp& op, uint32_t P, int extra) {
 
 constexpr int PM_THREADS = 256;
 constexpr int PM_TILE = 2048;  // entries of one sub-tile
-constexpr int PM_SUB = 4;      // consecutive sub-tiles of one block per workgroup
+constexpr int PM_SUB = 4;      // consecutive sub-tiles of one block per workgroup (at most)
 
 __host__ __device__ inline int pow2ceil(int64_t v) {
   int p = 1;
