@@ -191,6 +191,64 @@ struct Pair<float> {
   typedef float2 type;
 };
 
+// One LDS-staged transpose tile of NU * 2 * PM_THREADS entries with every
+// access in bounds and pair-aligned: pair u of a thread is entry
+// e = 2 threadIdx.x + 2 PM_THREADS u of the tile, so along the block-side
+// walk (leg 0 fastest) it advances by whole rows and along the strided-side
+// walk (leg y fastest) by whole columns. One pointer per walk, stepped by a
+// uniform stride; all loads of a thread leave before the first wait.
+struct TileWalk {
+  void *bq, *sq;           // first pair of this thread on the block / strided side
+  int64_t bstep, sstep;    // advance per pair (elements)
+  int tb0, tbstep;         // staging index of the block-side walk and its step
+  int ts0, tsstep, ld;     // staging index of the strided-side walk, its step, row length
+};
+
+template <typename T, int DIR, int NU>
+__device__ __forceinline__ void perm_tile_t(T* tile, const TileWalk& w, T v) {
+  typedef typename Pair<T>::type T2;
+  T* bq = (T*)w.bq;
+  T* sq = (T*)w.sq;
+  T2 buf[NU];
+  if (DIR == 0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) buf[u] = *(const T2*)(bq + u * w.bstep);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      T* t = tile + w.tb0 + u * w.tbstep;
+      t[0] = v * buf[u].x;
+      t[1] = v * buf[u].y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const T* t = tile + w.ts0 + u * w.tsstep;
+      T2 o;
+      o.x = t[0];
+      o.y = t[w.ld];
+      *(T2*)(sq + u * w.sstep) = o;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) buf[u] = *(const T2*)(sq + u * w.sstep);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      T* t = tile + w.ts0 + u * w.tsstep;
+      t[0] = v * buf[u].x;
+      t[w.ld] = v * buf[u].y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const T* t = tile + w.tb0 + u * w.tbstep;
+      T2 o;
+      o.x = t[0];
+      o.y = t[1];
+      *(T2*)(bq + u * w.bstep) = o;
+    }
+  }
+}
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(PM_THREADS)
     k_block_perm(const PermDesc* __restrict__ desc, const int64_t* __restrict__ tile_start,
@@ -337,15 +395,12 @@ __global__ void __launch_bounds__(PM_THREADS)
       const int ld = ta + 1, n = ta * tr;
       typedef typename Pair<T>::type T2;
       constexpr int PPT = PM_TILE / (2 * PM_THREADS);
-      // whole tile of PM_TILE entries, every pair aligned on both sides, ta
-      // and tr at most 2 * PM_THREADS: unchecked 2-wide accesses with no
-      // branch around them, so that a thread's loads all leave before the
-      // first wait. Pair u of a thread is entry e = e0 + 2 PM_THREADS u of the
-      // tile, so along the block-side walk (leg 0 fastest) it advances by
-      // whole rows and along the strided-side walk (leg y fastest) by whole
-      // columns: one pointer per walk, stepped by a uniform stride.
+      // whole tile of at least 2 * PM_THREADS entries (n = NU 2 PM_THREADS,
+      // NU = 1, 2 or 4), every pair aligned on both sides, ta and tr at most
+      // 2 * PM_THREADS: unchecked 2-wide accesses with no branch around them
+      // (perm_tile_t)
       constexpr int STEP = 2 * PM_THREADS;
-      if (n == PM_TILE && ta <= STEP && tr <= STEP && x0 + ta <= dx && y0 + tr <= dy &&
+      if (n >= STEP && ta <= STEP && tr <= STEP && x0 + ta <= dx && y0 + tr <= dy &&
           ((bbase | sby | sbase | tsx) & 1) == 0 && ((((uintptr_t)src) | ((uintptr_t)dst)) & (sizeof(T2) - 1)) == 0) {
         const int e0 = 2 * threadIdx.x;
         const int ra = STEP >> lta, rb0 = e0 >> lta, ib0 = e0 & (ta - 1);  // block-side walk
@@ -353,44 +408,13 @@ __global__ void __launch_bounds__(PM_THREADS)
         T* bq = (DIR == 0 ? const_cast<T*>(src) : dst) + bbase + (y0 + rb0) * sby + x0 + ib0;
         T* sq = (DIR == 0 ? dst : const_cast<T*>(src)) + sbase + y0 + rs0 + (x0 + is0) * tsx;
         const int64_t bstep = (int64_t)ra * sby, sstep = (int64_t)ia * tsx;
-        T2 buf[PPT];
-        if (DIR == 0) {
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) buf[u] = *(const T2*)(bq + u * bstep);
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            T* t = tile + (rb0 + u * ra) * ld + ib0;
-            t[0] = v * buf[u].x;
-            t[1] = v * buf[u].y;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            const T* t = tile + rs0 * ld + is0 + u * ia;
-            T2 w;
-            w.x = t[0];
-            w.y = t[ld];
-            *(T2*)(sq + u * sstep) = w;
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) buf[u] = *(const T2*)(sq + u * sstep);
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            T* t = tile + rs0 * ld + is0 + u * ia;
-            t[0] = v * buf[u].x;
-            t[ld] = v * buf[u].y;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < PPT; ++u) {
-            const T* t = tile + (rb0 + u * ra) * ld + ib0;
-            T2 w;
-            w.x = t[0];
-            w.y = t[1];
-            *(T2*)(bq + u * bstep) = w;
-          }
-        }
+        const TileWalk w{bq, sq, bstep, sstep, (rb0 * ld + ib0), ra * ld, (rs0 * ld + is0), ia, ld};
+        if (n == PM_TILE)
+          perm_tile_t<T, DIR, PM_TILE / STEP>(tile, w, v);
+        else if (n == 2 * STEP)
+          perm_tile_t<T, DIR, 2>(tile, w, v);
+        else
+          perm_tile_t<T, DIR, 1>(tile, w, v);
         __syncthreads();  // the staging buffer is reused by the next sub-tile
         continue;
       }
