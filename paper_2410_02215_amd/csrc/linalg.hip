@@ -524,6 +524,14 @@ __global__ void __launch_bounds__(64 * JV_WAVES) k_jacobi_vectors(const JobTable
   for (int c = lane; c < n; c += 64) J.V[(int64_t)row * n + J.rk[c]] = V[c];
 }
 
+// value of v in lane l (l the same for the whole wavefront), read through
+// the scalar unit rather than a cross-lane permute
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // ---------------------------------------------------------------------------
 // Rank-revealing orthonormalisation factor (one workgroup per matrix): for
 // the Gram matrix G = Y^T Y (p x p, p <= 128), Cholesky G = R^T R in which a
@@ -584,7 +592,7 @@ __global__ void __launch_bounds__(LT) k_orth_factor(const JobTable<OrthJob> jobs
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const int j = j0 + jj, tj = jj & 3, lb = 16 * (jj >> 2);
-        const double d = __shfl(x[tj], lb + jj);
+        const double d = readlane_d(x[tj], lb + jj);  // the pivot: one lane, known at compile time
         const bool drop = (j < p) && !(d > thr);
         // 1 / sqrt(d): hardware estimate and two Newton steps
         double y = __builtin_amdgcn_rsq(d);
