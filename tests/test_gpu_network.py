@@ -289,6 +289,33 @@ def test_compress_mixed_sector_sizes(P, dims):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
 
 
+def test_compress_many_sectors_repeat_is_bit_exact(P):
+    # a U(1) bond of 12 sectors: the factorisation kernels take their job
+    # tables from an upload (more than eight sectors, the most the kernel
+    # arguments carry); a second identical call takes every grouped-product
+    # plan from the plan cache and reproduces the first bit for bit
+    from oracle.tensor import make_leg
+    rng = np.random.default_rng(907)
+    sym = S.U1
+    qs = [(q,) for q in range(-5, 7)]
+    bond = make_leg(sym, qs, [int(x) for x in rng.integers(3, 14, len(qs))], 1)
+    ra = make_leg(sym, qs, [int(x) for x in rng.integers(10, 40, len(qs))], 0)
+    rb = make_leg(sym, qs, [int(x) for x in rng.integers(10, 40, len(qs))], 1)
+    A = rand_tensor(rng, sym, [ra, bond], total=(0,))
+    B = rand_tensor(rng, sym, [partner(bond), rb], total=(0,))
+    chi = 40
+    A2, B2, info = o_compress(A, B, 1, 0, chi, cutoff=1e-12)
+    ref = ftensordot(A2, B2, [1], [0]).to_dense()
+    ga, gb = to_gpu(A), to_gpu(B)
+    outs = []
+    for _ in range(2):
+        GA, GB, _ = P.compress_bond(ga, gb, 1, 0, chi, 1e-12)
+        assert GA.legs()[1][1] == list(A2.legs[1].dims)
+        outs.append(P.ftensordot(GA, GB, [1], [0]).to_dense().cpu().numpy())
+    np.testing.assert_allclose(outs[0], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("case", [
     # the thin route needs A~ sectors of at least 2^22 entries (M d); the
     # small shapes beside them take the Gram route with the same structure
