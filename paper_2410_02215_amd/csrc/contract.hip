@@ -121,6 +121,10 @@ struct DotPlan {
   GemmPlan gp;
   DBuf<int64_t> rc_start, cc_start, cc_dim, boff;
   GemmScatter sc;
+  // forward product reading A's blocks where they lie (set when A needs no
+  // fused copy); gp above keeps the fused-operand form for the adjoint
+  bool direct_a = false;
+  GemmPlan gpd;
   int64_t asz = 0, bsz = 0;
   double flops = 0;
   std::vector<Q> gq;  // contracted charge Q of each GEMM group
@@ -228,6 +232,61 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       }
     }
   }
+  // A in place. When A's legs already stand in the fused order (free legs,
+  // then the contracted ones, each in its original order) no pair of legs is
+  // exchanged, so every sign of A's signed permute is +1 (Eq. standardcontract
+  // gives A no other sign), and when a group holds a single contracted sector
+  // combination the block (r, kk) of A is, as stored, the R.d[r] x Kg row-major
+  // row slab of that group's fused matrix. The product then reads the blocks
+  // in place, as one GEMM group per row combination, and A's copy is skipped.
+  // Row combinations much shorter than a tile would pad the product, so the
+  // fused copy stays when splitting the rows adds more than 1/8 of padding.
+  const int nf = (int)fa.size();
+  bool direct = k > 0;
+  for (int i = 0; direct && i < nf; ++i) direct = fa[i] == i;
+  for (int t = 0; direct && t < k; ++t) direct = axa[t] == nf + t;
+  std::vector<int64_t> kofg(G, -1), ablk(R.q.size(), -1);
+  if (direct) {
+    std::vector<int> nkg(G, 0);
+    for (size_t kk = 0; kk < K.q.size(); ++kk)
+      for (int g = 0; g < G; ++g)
+        if (q_eq(K.q[kk], gQ[g])) {
+          ++nkg[g];
+          kofg[g] = (int64_t)kk;
+          break;
+        }
+    for (int g = 0; direct && g < G; ++g) direct = N[g] == 0 || M[g] == 0 || nkg[g] <= 1;
+  }
+  if (direct) {
+    const Structure& AS = A.S();
+    for (int64_t b = 0; b < AS.nblocks; ++b) {
+      const int32_t* key = &AS.keys[b * na];
+      int64_t r = 0, kk = 0;
+      bool ok = true;
+      for (int i = 0; i < nf; ++i) r = r * A.legs()[i].nsect() + key[i];
+      for (int t = 0; t < k; ++t) {
+        const int32_t c = kmapA[t][key[nf + t]];
+        ok = ok && c >= 0;
+        kk = kk * (int64_t)kq[t].size() + (c < 0 ? 0 : c);
+      }
+      if (ok && kk == kofg[rgroup[r]]) ablk[r] = b;
+    }
+    // (a group without contracted combinations, K = 0, stays whole: its
+    // product writes zeros and reads no A)
+    int64_t rows_f = 0, rows_d = 0;
+    for (int g = 0; g < G; ++g)
+      if (N[g] > 0 && M[g] > 0) {
+        rows_f += cdiv(M[g], 128) * 128;
+        if (Kg[g] == 0) rows_d += cdiv(M[g], 128) * 128;
+      }
+    for (size_t r = 0; direct && r < R.q.size(); ++r) {
+      const int g = rgroup[r];
+      if (N[g] == 0 || M[g] == 0 || Kg[g] == 0) continue;
+      direct = ablk[r] >= 0;
+      rows_d += cdiv(R.d[r], 128) * 128;
+    }
+    direct = direct && 8 * rows_d <= 9 * rows_f;
+  }
   // buffers: A~ groups, B~ groups; groups without columns are dropped
   auto P = std::make_shared<DotPlan>();
   std::vector<int64_t> abase(G, -1), bbase(G, -1);
@@ -326,7 +385,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   // scatter tables + GEMM groups
   std::vector<int64_t> rcs, ccs, ccd, gboff(G, 0);
   std::vector<int32_t> gncc(G, 0);
-  std::vector<GemmGroup> groups;
+  std::vector<GemmGroup> groups, dgroups;
   int64_t boff_n = 0;
   for (int g = 0; g < G; ++g) {
     // a group without rows or columns writes nothing (and the GEMM plan
@@ -357,9 +416,28 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
     P->gq.push_back(gQ[g]);
     gboff[g] = boff_n;
     gncc[g] = ncc[g];
+    if (direct && Kg[g] == 0) {
+      GemmGroup d = gg;
+      d.a_off = 0;
+      d.lda = 1;
+      dgroups.push_back(d);
+    } else if (direct)
+      for (size_t r = 0; r < R.q.size(); ++r)
+        if (rgroup[r] == g) {
+          GemmGroup d = gg;
+          d.M = R.d[r];
+          d.a_off = A.S().offsets[ablk[r]];
+          d.lda = Kg[g];
+          d.nrc = 1;  // rc_base: the zero entry appended below
+          d.boff_base = boff_n + (int64_t)rlocal[r] * ncc[g];
+          dgroups.push_back(d);
+        }
     boff_n += (int64_t)nrc[g] * ncc[g];
     groups.push_back(gg);
   }
+  for (auto& d : dgroups)
+    if (d.nrc == 1 && d.K > 0) d.rc_base = (int64_t)rcs.size();
+  rcs.push_back(0);
   P->rc_start = persist_upload(rcs, s);
   P->cc_start = persist_upload(ccs, s);
   P->cc_dim = persist_upload(ccd, s);
@@ -403,6 +481,8 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   P->sc.cc_dim = P->cc_dim.p;
   P->sc.boff = P->boff.p;
   gemm_plan(P->gp, groups, gemm, s, true);
+  P->direct_a = direct && !dgroups.empty();
+  if (P->direct_a) gemm_plan(P->gpd, dgroups, gemm, s, true);
   P->flops = gemm_flops(groups);
   // cached plans may be used on other streams: finish building them here
   HIPC(hipStreamSynchronize(s));
@@ -467,12 +547,15 @@ std::unique_ptr<Tensor> op_ftensordot(const Tensor& a, const Tensor& b, const st
   if (flops) *flops = P->flops;
   if (out->size() == 0) return out;
   const size_t es = a.esize();
-  void* At = P->asz ? dmalloc(P->asz * es, s) : nullptr;
+  void* At = (P->asz && !P->direct_a) ? dmalloc(P->asz * es, s) : nullptr;
   void* Bt = P->bsz ? dmalloc(P->bsz * es, s) : nullptr;
   try {
-    run_perm(0, a.S(), a.dtype, P->pa, a.data, At, s);
+    if (!P->direct_a) run_perm(0, a.S(), a.dtype, P->pa, a.data, At, s);
     run_perm(0, b.S(), b.dtype, P->pb, b.data, Bt, s);
-    run_gemm(P->gp, a.dtype, At, Bt, out->data, &P->sc, s);
+    if (P->direct_a)
+      run_gemm(P->gpd, a.dtype, a.data, Bt, out->data, &P->sc, s);
+    else
+      run_gemm(P->gp, a.dtype, At, Bt, out->data, &P->sc, s);
   } catch (...) {
     dfree(At, s);
     dfree(Bt, s);
@@ -504,16 +587,17 @@ void op_ftensordot_into(const Tensor& a, const Tensor& b, const std::vector<int>
   if (!out) fail(FTN_EINVAL, "null output buffer");
   const size_t es = a.esize();
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t ba = up(P->asz * es), bb = up(P->bsz * es), bw = up(P->gp.ws_elems * es);
+  const GemmPlan& gp = P->direct_a ? P->gpd : P->gp;
+  const size_t ba = P->direct_a ? 0 : up(P->asz * es), bb = up(P->bsz * es), bw = up(gp.ws_elems * es);
   if (ba + bb + bw > scratch_bytes)
     fail(FTN_EINVAL, "contraction needs " + std::to_string(ba + bb + bw) + " bytes of temporaries, the scratch buffer holds " +
                          std::to_string(scratch_bytes));
   char* At = scratch;
   char* Bt = scratch + ba;
   char* W = scratch + ba + bb;
-  run_perm(0, a.S(), a.dtype, P->pa, a.data, At, s);
+  if (!P->direct_a) run_perm(0, a.S(), a.dtype, P->pa, a.data, At, s);
   run_perm(0, b.S(), b.dtype, P->pb, b.data, Bt, s);
-  run_gemm(P->gp, a.dtype, At, Bt, out, &P->sc, s, 1.0, 0.0, W);
+  run_gemm(gp, a.dtype, P->direct_a ? a.data : At, Bt, out, &P->sc, s, 1.0, 0.0, W);
 }
 
 // ---------------------------------------------------------------------------

@@ -179,6 +179,57 @@ def test_ftensordot_tall_thin_products(P, case):
     np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * np.abs(r).max())
 
 
+def _u1_leg(dims, dual, qs=(-1, 0, 1)):
+    return make_leg(S.U1, [(q,) for q in qs[:len(dims)]], dims, dual)
+
+
+@pytest.mark.parametrize("case", [
+    # (sym, A legs, B legs, contracted legs of A and of B, A read in place)
+    # A's legs in fused order, one contracted sector combination per charge
+    # group and long row combinations: the product reads A's blocks in place
+    ("z2", [(40, 24, 0), (33, 31, 0), (64, 64, 1)], [(64, 64, 0), (20, 12, 1)], [2], [0], True),
+    ("z2g", [(40, 24, 0), (33, 31, 0), (64, 64, 1)], [(64, 64, 0), (20, 12, 1)], [2], [0], True),
+    # two contracted legs, the second with a single sector
+    ("u1", [((30, 50, 40), 0), ((60, 70), 0), ((64, 48), 1), ((3,), 1)],
+     [((64, 48), 0), ((3,), 0), ((5, 6, 7), 1)], [2, 3], [0, 1], True),
+    # contracted legs not trailing, or two contracted combinations per group,
+    # or row combinations far shorter than a tile: A is copied as before
+    ("z2", [(64, 64, 1), (40, 24, 0), (33, 31, 0)], [(64, 64, 0), (20, 12, 1)], [0], [0], False),
+    ("z2", [(40, 24, 0), (64, 64, 1), (6, 5, 1)], [(64, 64, 0), (6, 5, 0), (20, 12, 1)], [1, 2], [0, 1], False),
+    ("z2", [(3, 2, 0), (2, 3, 0), (64, 64, 1)], [(64, 64, 0), (20, 12, 1)], [2], [0], False),
+])
+def test_ftensordot_reads_a_in_place(P, case):
+    name, la, lb, ax_a, ax_b, in_place = case
+    rng = np.random.default_rng(len(name) + 7 * len(la) + sum(ax_a))
+    if name.startswith("z2"):
+        sym = S.Z2
+        mk = lambda e, o, du: make_leg(sym, [(0,), (1,)], [e, o], du)
+        legs_a, legs_b = [mk(*l) for l in la], [mk(*l) for l in lb]
+    else:
+        sym = S.U1
+        legs_a = [_u1_leg(d, du, (0, 1) if len(d) == 2 else (-1, 0, 1) if len(d) == 3 else (0,)) for d, du in la]
+        legs_b = [_u1_leg(d, du, (0, 1) if len(d) == 2 else (-1, 0, 1) if len(d) == 3 else (0,)) for d, du in lb]
+    A = rand_tensor(rng, sym, legs_a, total=S.zero(sym))
+    B = rand_tensor(rng, sym, legs_b, total=S.zero(sym))
+    conv = "global" if name.endswith("g") else "local"
+    from paper_2410_02215_amd import ftn
+    ref = ftensordot(A, B, ax_a, ax_b, conv=conv)
+    ga, gb = to_gpu(A), to_gpu(B)
+    pc = P.LOCAL if conv == "local" else P.GLOBAL
+    P.ftensordot(ga, gb, ax_a, ax_b, conv=pc)  # builds and caches the plan
+    torch.cuda.synchronize()
+    ftn.profile_collect()
+    ftn.profile_enable(True)
+    G = P.ftensordot(ga, gb, ax_a, ax_b, conv=pc)
+    torch.cuda.synchronize()
+    ftn.profile_enable(False)
+    # one signed permute (B's) when A is read in place, else two
+    assert ftn.profile_collect()["permute"][1] == (1 if in_place else 2)
+    assert_same_structure(ref, G)
+    r = flat_blocks(ref)
+    np.testing.assert_allclose(_data(G), r, rtol=0, atol=1e-12 * np.abs(r).max())
+
+
 @pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
 def test_ftensordot_fp32_forms(P, gemm):
     # FP32 tensors hold the FP64 inputs rounded to nearest; the oracle runs on

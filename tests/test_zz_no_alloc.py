@@ -3,7 +3,8 @@
 library's fixed per-GPU scratch array, so the outputs agree bit for bit; two
 calls in a row, the second on a smaller contraction; the library's caching
 allocator does not move during the calls; errors for an uncached plan, a
-wrong output size and temporaries beyond the scratch array.
+wrong output size and temporaries beyond the scratch array; a product whose
+A is read in place needing only B's copy in the array.
 """
 
 import numpy as np
@@ -68,11 +69,25 @@ def test_noalloc_errors(P):
     with pytest.raises(P.FtnError) as e:                          # wrong output size
         P.ftensordot_noalloc(Ga, Gb, [1], [0], out[:ref.size - 1], conv=P.GLOBAL)
     assert e.value.code == -1
-    # temporaries of 2 x 4096 x 1200 FP64 per operand exceed the 64 MiB array
-    big_a = P.Tensor.create(0, [([(0, 0), (1, 0)], [4096, 4096], 0), ([(0, 0), (1, 0)], [1200, 1200], 1)], (0, 0))
+    # A's fused copy, 2 x 4096 x 1200 FP64 (A's contracted leg comes first, so
+    # its blocks cannot be read in place), exceeds the 64 MiB array
+    big_a = P.Tensor.create(0, [([(0, 0), (1, 0)], [1200, 1200], 1), ([(0, 0), (1, 0)], [4096, 4096], 0)], (0, 0))
     big_b = P.Tensor.create(0, [([(0, 0), (1, 0)], [1200, 1200], 0), ([(0, 0), (1, 0)], [8, 8], 1)], (0, 0))
-    c = P.ftensordot(big_a, big_b, [1], [0])
+    c = P.ftensordot(big_a, big_b, [0], [0])
     o2 = torch.zeros(c.size, device="cuda", dtype=torch.float64)
     with pytest.raises(P.FtnError) as e:
-        P.ftensordot_noalloc(big_a, big_b, [1], [0], o2)
+        P.ftensordot_noalloc(big_a, big_b, [0], [0], o2)
     assert e.value.code == -1
+    # with A's contracted leg last A's blocks are read in place: only B's fused
+    # copy takes scratch space, so the same product at that size fits
+    big_a2 = P.Tensor.create(0, [([(0, 0), (1, 0)], [4096, 4096], 0), ([(0, 0), (1, 0)], [1200, 1200], 1)], (0, 0))
+    g = torch.Generator(device="cuda").manual_seed(702)
+    big_a2.data_view().normal_(generator=g)
+    big_b.data_view().normal_(generator=g)
+    torch.cuda.synchronize()
+    c2 = P.ftensordot(big_a2, big_b, [1], [0])
+    want = c2.data()
+    o3 = torch.full((c2.size,), float("nan"), device="cuda", dtype=torch.float64)
+    P.ftensordot_noalloc(big_a2, big_b, [1], [0], o3)
+    torch.cuda.synchronize()
+    assert torch.equal(o3, want) and want.abs().max().item() > 0
