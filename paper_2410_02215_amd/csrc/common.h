@@ -346,6 +346,9 @@ struct GemmGroup {
   // mirrored, so C is still written in full
   int32_t sym;
   int32_t nrc, ncc;         // number of row / col combos
+  // neg: the group's product enters its output negated (the sign of an
+  // operand block that is read in place instead of through a signed permute)
+  int32_t neg, pad;
   int64_t rc_base, cc_base; // offsets into the combo start arrays
   int64_t boff_base;        // offset into block offset table (nrc * ncc)
   int64_t tile0;            // first tile index of this group

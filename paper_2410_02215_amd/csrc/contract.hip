@@ -133,6 +133,18 @@ struct DotPlan {
 static std::mutex g_plan_mu;
 static auto& g_plans = *new std::unordered_map<std::string, std::shared_ptr<DotPlan>>();
 
+// the sign bit a signed permute with descriptor op gives a block of parity
+// mask P (the device's sign_bit, for plans built on the host)
+static int host_sign_bit(const SignOp& op, uint32_t P) {
+  int e = op.phase;
+  for (int p = 0; p < op.ndim; ++p)
+    if ((P >> op.perm[p]) & 1u) e ^= __builtin_popcount(P & op.kmask[p]) & 1;
+  const int n = __builtin_popcount(P & op.rev_mask);
+  e ^= ((n * (n - 1)) >> 1) & 1;
+  e ^= __builtin_popcount(P & op.flip_mask) & 1;
+  return e & 1;
+}
+
 static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, const std::vector<int>& axa,
                                            const std::vector<int>& axb, int conv, int gemm, hipStream_t s) {
   const int sym = A.sym();
@@ -232,20 +244,28 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       }
     }
   }
-  // A in place. When A's legs already stand in the fused order (free legs,
-  // then the contracted ones, each in its original order) no pair of legs is
-  // exchanged, so every sign of A's signed permute is +1 (Eq. standardcontract
-  // gives A no other sign), and when a group holds a single contracted sector
-  // combination the block (r, kk) of A is, as stored, the R.d[r] x Kg row-major
-  // row slab of that group's fused matrix. The product then reads the blocks
-  // in place, as one GEMM group per row combination, and A's copy is skipped.
-  // Row combinations much shorter than a tile would pad the product, so the
-  // fused copy stays when splitting the rows adds more than 1/8 of padding.
+  // A in place. Let A's contracted legs be one run c0 .. c0+k-1 in their
+  // original order, and let every charge group hold a single contracted sector
+  // combination. A block of row combination r, with P entries over the free legs
+  // before the run, Kd over the run and S over the free legs after it, is stored
+  // as [P][Kd][S]. Its rows of the group's fused matrix (row p S + s, column k)
+  // are then, for each p, the transpose of the Kd x S row-major matrix at
+  // p Kd S; without free legs after the run (S = 1) the block is itself the
+  // P x Kd row-major slab. Moving the run behind the S legs is the only
+  // exchange of legs in A's permute, so its sign (Eq. standardcontract gives A
+  // no other) is one per block: (-1)^(parity of the run x parity of the S legs).
+  // The product then reads A in place, as one GEMM group per row combination
+  // (per p when S > 1, transposed, its sign carried by the group), and A's
+  // permute and temporary are skipped. Groups shorter than a tile pad the
+  // product, so the fused copy stays when the split adds more than 1/8 of
+  // padded rows (or more than 2^16 groups).
   const int nf = (int)fa.size();
+  const int c0 = k > 0 ? axa[0] : 0;
   bool direct = k > 0;
-  for (int i = 0; direct && i < nf; ++i) direct = fa[i] == i;
-  for (int t = 0; direct && t < k; ++t) direct = axa[t] == nf + t;
-  std::vector<int64_t> kofg(G, -1), ablk(R.q.size(), -1);
+  for (int t = 0; direct && t < k; ++t) direct = axa[t] == c0 + t;
+  const bool trail = c0 + k < na;  // free legs after the run: transposed groups
+  std::vector<int64_t> kofg(G, -1), ablk(R.q.size(), -1), apre(R.q.size(), 1), asuf(R.q.size(), 1);
+  std::vector<int32_t> aneg(R.q.size(), 0);
   if (direct) {
     std::vector<int> nkg(G, 0);
     for (size_t kk = 0; kk < K.q.size(); ++kk)
@@ -259,21 +279,28 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   }
   if (direct) {
     const Structure& AS = A.S();
+    std::vector<int> order(fa);
+    order.insert(order.end(), axa.begin(), axa.end());
+    const SignOp aop = make_signop(na, order.data(), nf, k);
     for (int64_t b = 0; b < AS.nblocks; ++b) {
       const int32_t* key = &AS.keys[b * na];
       int64_t r = 0, kk = 0;
       bool ok = true;
-      for (int i = 0; i < nf; ++i) r = r * A.legs()[i].nsect() + key[i];
+      for (int i = 0; i < nf; ++i) r = r * A.legs()[fa[i]].nsect() + key[fa[i]];
       for (int t = 0; t < k; ++t) {
-        const int32_t c = kmapA[t][key[nf + t]];
+        const int32_t c = kmapA[t][key[c0 + t]];
         ok = ok && c >= 0;
         kk = kk * (int64_t)kq[t].size() + (c < 0 ? 0 : c);
       }
-      if (ok && kk == kofg[rgroup[r]]) ablk[r] = b;
+      if (!ok || kk != kofg[rgroup[r]]) continue;
+      ablk[r] = b;
+      for (int i = 0; i < c0; ++i) apre[r] *= AS.shapes[b * na + i];
+      for (int i = c0 + k; i < na; ++i) asuf[r] *= AS.shapes[b * na + i];
+      aneg[r] = host_sign_bit(aop, AS.parmask[b]);
     }
     // (a group without contracted combinations, K = 0, stays whole: its
     // product writes zeros and reads no A)
-    int64_t rows_f = 0, rows_d = 0;
+    int64_t rows_f = 0, rows_d = 0, nsub = 0;
     for (int g = 0; g < G; ++g)
       if (N[g] > 0 && M[g] > 0) {
         rows_f += cdiv(M[g], 128) * 128;
@@ -283,9 +310,15 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       const int g = rgroup[r];
       if (N[g] == 0 || M[g] == 0 || Kg[g] == 0) continue;
       direct = ablk[r] >= 0;
-      rows_d += cdiv(R.d[r], 128) * 128;
+      if (trail) {
+        rows_d += apre[r] * (cdiv(asuf[r], 128) * 128);
+        nsub += apre[r];
+      } else {
+        rows_d += cdiv(R.d[r], 128) * 128;
+        nsub += 1;
+      }
     }
-    direct = direct && 8 * rows_d <= 9 * rows_f;
+    direct = direct && 8 * rows_d <= 9 * rows_f && nsub <= (1 << 16);
   }
   // buffers: A~ groups, B~ groups; groups without columns are dropped
   auto P = std::make_shared<DotPlan>();
@@ -386,6 +419,7 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
   std::vector<int64_t> rcs, ccs, ccd, gboff(G, 0);
   std::vector<int32_t> gncc(G, 0);
   std::vector<GemmGroup> groups, dgroups;
+  std::vector<int64_t> drow;  // per in-place group: its row table entry
   int64_t boff_n = 0;
   for (int g = 0; g < G; ++g) {
     // a group without rows or columns writes nothing (and the GEMM plan
@@ -421,23 +455,32 @@ static std::shared_ptr<DotPlan> build_plan(const Tensor& A, const Tensor& B, con
       d.a_off = 0;
       d.lda = 1;
       dgroups.push_back(d);
+      drow.push_back(INT64_MIN);  // keeps the group's own row table
     } else if (direct)
-      for (size_t r = 0; r < R.q.size(); ++r)
-        if (rgroup[r] == g) {
+      for (size_t r = 0; r < R.q.size(); ++r) {
+        if (rgroup[r] != g) continue;
+        const int64_t ps = trail ? apre[r] : 1;
+        for (int64_t q = 0; q < ps; ++q) {
           GemmGroup d = gg;
-          d.M = R.d[r];
-          d.a_off = A.S().offsets[ablk[r]];
-          d.lda = Kg[g];
-          d.nrc = 1;  // rc_base: the zero entry appended below
+          d.M = trail ? asuf[r] : R.d[r];
+          d.a_off = A.S().offsets[ablk[r]] + q * Kg[g] * asuf[r];
+          d.transA = trail ? 1 : 0;
+          d.lda = trail ? asuf[r] : Kg[g];
+          d.neg = aneg[r];
+          d.nrc = 1;  // one row table entry: row m of the group is row m + q S of block r
           d.boff_base = boff_n + (int64_t)rlocal[r] * ncc[g];
           dgroups.push_back(d);
+          drow.push_back(-q * asuf[r]);
         }
+      }
     boff_n += (int64_t)nrc[g] * ncc[g];
     groups.push_back(gg);
   }
-  for (auto& d : dgroups)
-    if (d.nrc == 1 && d.K > 0) d.rc_base = (int64_t)rcs.size();
-  rcs.push_back(0);
+  for (size_t i = 0; i < dgroups.size(); ++i)
+    if (drow[i] != INT64_MIN) {
+      dgroups[i].rc_base = (int64_t)rcs.size();
+      rcs.push_back(drow[i]);
+    }
   P->rc_start = persist_upload(rcs, s);
   P->cc_start = persist_upload(ccs, s);
   P->cc_dim = persist_upload(ccd, s);

@@ -118,7 +118,8 @@ __device__ inline void build_epi(EpiTab<BM, BN>& e, const GemmGroup& G, const Ge
 // column) so that the 16 lanes reading an MFMA operand column touch
 // consecutive addresses and the global-to-LDS stores do not collide.
 // Output modes per group: plain (alpha / beta), block scatter, or raw
-// partial sums of a K slice into the split-K workspace.
+// partial sums of a K slice into the split-K workspace; a group marked `neg`
+// writes its product negated in each of them.
 constexpr int GBK = 16;
 
 template <typename T>
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_gemm(GemmLaunch L, const T* 
     build_epi<BM, BN>(epi, G, L.sc, m0, n0);
     __syncthreads();
   }
-  const T alpha = (T)L.alpha, beta = (T)L.beta;
+  const T alpha = (T)(G.neg ? -L.alpha : L.alpha), beta = (T)L.beta;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -303,7 +304,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN) k_gemm(GemmLaunch L, const T* 
           const int64_t bo = L.sc.boff[G.boff_base + (int64_t)epi.rfi[rr] * G.ncc + epi.cgj[cc]];
           if (bo >= 0) C[bo + epi.rlr[rr] * epi.cnd[cc] + epi.clc[cc]] = alpha * acc[i][j][r];
         } else if (G.scatter == 2) {
-          Wk[G.c_off + m * G.ldc + n] = acc[i][j][r];
+          Wk[G.c_off + m * G.ldc + n] = G.neg ? -acc[i][j][r] : acc[i][j][r];
         } else {
           const T v = alpha * acc[i][j][r];
           T* p = C + G.c_off + m * G.ldc + n;
@@ -437,7 +438,7 @@ __global__ void __launch_bounds__(GT) k_gemm_bf16x3(GemmLaunch L, const float* _
     build_epi<BM, BN>(epi, G, L.sc, m0, n0);
     __syncthreads();
   }
-  const float alpha = (float)L.alpha, beta = (float)L.beta;
+  const float alpha = (float)(G.neg ? -L.alpha : L.alpha), beta = (float)L.beta;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -561,7 +562,7 @@ __global__ void __launch_bounds__(TL_T) k_gemm_tall(GemmLaunch L, const double* 
     build_epi<TL_BM, TL_N>(epi, G, L.sc, mb, 0);
     __syncthreads();
   }
-  const double alpha = L.alpha, beta = L.beta;
+  const double alpha = G.neg ? -L.alpha : L.alpha, beta = L.beta;
   if (r >= N) return;
 #pragma unroll
   for (int t = 0; t < TL_RT; ++t)
@@ -999,7 +1000,7 @@ static bool skinny_form(const std::vector<GemmGroup>& gs) {
   bool any = false;
   for (auto& g : gs) {
     if (g.M <= 0 || g.N <= 0) continue;
-    if (!g.transA || g.transB || g.scatter || g.M > SK_MAX || g.N > SK_MAX) return false;
+    if (!g.transA || g.transB || g.scatter || g.neg || g.M > SK_MAX || g.N > SK_MAX) return false;
     if (g.K >= 1024) any = true;
   }
   return any;
@@ -1123,6 +1124,7 @@ std::string groups_key(const std::vector<GemmGroup>& gs, int kind) {
     put(g.ldc);
     put(g.scatter);
     put(g.sym);
+    put(g.neg);
     if (g.scatter == 1) {
       put(g.nrc);
       put(g.ncc);

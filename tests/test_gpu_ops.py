@@ -192,15 +192,25 @@ def _u1_leg(dims, dual, qs=(-1, 0, 1)):
     # two contracted legs, the second with a single sector
     ("u1", [((30, 50, 40), 0), ((60, 70), 0), ((64, 48), 1), ((3,), 1)],
      [((64, 48), 0), ((3,), 0), ((5, 6, 7), 1)], [2, 3], [0, 1], True),
-    # contracted legs not trailing, or two contracted combinations per group,
-    # or row combinations far shorter than a tile: A is copied as before
-    ("z2", [(64, 64, 1), (40, 24, 0), (33, 31, 0)], [(64, 64, 0), (20, 12, 1)], [0], [0], False),
+    # the contracted run first or in the middle: each block read as transposed
+    # matrices (one per entry of the legs before the run), with the sign of
+    # moving the run behind the legs after it
+    ("z2", [(64, 64, 1), (40, 24, 0), (33, 31, 0)], [(64, 64, 0), (20, 12, 1)], [0], [0], True),
+    ("z2", [(6, 5, 0), (64, 64, 1), (40, 24, 0), (16, 12, 0)], [(64, 64, 0), (20, 12, 1)], [1], [0], True),
+    ("z2g", [(6, 5, 0), (64, 64, 1), (40, 24, 0), (16, 12, 0)], [(64, 64, 0), (20, 12, 1)], [1], [0], True),
+    ("u1", [((3, 4, 2), 0), ((64, 48), 1), ((3,), 1), ((16, 16), 0), ((24, 32, 16), 0)],
+     [((64, 48), 0), ((3,), 0), ((5, 6, 7), 1)], [1, 2], [0, 1], True),
+    # two contracted combinations per group, contracted legs not one run, or
+    # row groups far shorter than a tile: A is copied
     ("z2", [(40, 24, 0), (64, 64, 1), (6, 5, 1)], [(64, 64, 0), (6, 5, 0), (20, 12, 1)], [1, 2], [0, 1], False),
+    ("z2", [(40, 24, 0), (64, 64, 1), (33, 31, 0), (6, 5, 1)], [(6, 5, 0), (64, 64, 0), (20, 12, 1)], [1, 3], [1, 0],
+     False),
     ("z2", [(3, 2, 0), (2, 3, 0), (64, 64, 1)], [(64, 64, 0), (20, 12, 1)], [2], [0], False),
+    ("z2", [(64, 64, 0), (32, 32, 1), (4, 4, 0)], [(32, 32, 0), (20, 12, 1)], [1], [0], False),
 ])
 def test_ftensordot_reads_a_in_place(P, case):
     name, la, lb, ax_a, ax_b, in_place = case
-    rng = np.random.default_rng(len(name) + 7 * len(la) + sum(ax_a))
+    rng = np.random.default_rng(len(name) + 7 * len(la) + 3 * sum(ax_a) + len(lb))
     if name.startswith("z2"):
         sym = S.Z2
         mk = lambda e, o, du: make_leg(sym, [(0,), (1,)], [e, o], du)

@@ -3,8 +3,9 @@
 library's fixed per-GPU scratch array, so the outputs agree bit for bit; two
 calls in a row, the second on a smaller contraction; the library's caching
 allocator does not move during the calls; errors for an uncached plan, a
-wrong output size and temporaries beyond the scratch array; a product whose
-A is read in place needing only B's copy in the array.
+wrong output size and temporaries beyond the scratch array; products whose
+A is read in place (row slabs, transposed blocks) needing only B's copy in
+the array.
 """
 
 import numpy as np
@@ -69,15 +70,17 @@ def test_noalloc_errors(P):
     with pytest.raises(P.FtnError) as e:                          # wrong output size
         P.ftensordot_noalloc(Ga, Gb, [1], [0], out[:ref.size - 1], conv=P.GLOBAL)
     assert e.value.code == -1
-    # A's fused copy, 2 x 4096 x 1200 FP64 (A's contracted leg comes first, so
-    # its blocks cannot be read in place), exceeds the 64 MiB array
-    big_a = P.Tensor.create(0, [([(0, 0), (1, 0)], [1200, 1200], 1), ([(0, 0), (1, 0)], [4096, 4096], 0)], (0, 0))
-    big_b = P.Tensor.create(0, [([(0, 0), (1, 0)], [1200, 1200], 0), ([(0, 0), (1, 0)], [8, 8], 1)], (0, 0))
-    c = P.ftensordot(big_a, big_b, [0], [0])
+    # A's fused copy, 2 x 4096 x 1200 FP64 (two contracted sector combinations
+    # per charge, so its blocks cannot be read in place), exceeds the 64 MiB array
+    two = [(0, 0), (1, 0)]
+    big_a = P.Tensor.create(0, [(two, [4096, 4096], 0), (two, [600, 600], 1), (two, [1, 1], 1)], (0, 0))
+    big_b3 = P.Tensor.create(0, [(two, [600, 600], 0), (two, [1, 1], 0), (two, [8, 8], 1)], (0, 0))
+    c = P.ftensordot(big_a, big_b3, [1, 2], [0, 1])
     o2 = torch.zeros(c.size, device="cuda", dtype=torch.float64)
     with pytest.raises(P.FtnError) as e:
-        P.ftensordot_noalloc(big_a, big_b, [0], [0], o2)
+        P.ftensordot_noalloc(big_a, big_b3, [1, 2], [0, 1], o2)
     assert e.value.code == -1
+    big_b = P.Tensor.create(0, [(two, [1200, 1200], 0), (two, [8, 8], 1)], (0, 0))
     # with A's contracted leg last A's blocks are read in place: only B's fused
     # copy takes scratch space, so the same product at that size fits
     big_a2 = P.Tensor.create(0, [([(0, 0), (1, 0)], [4096, 4096], 0), ([(0, 0), (1, 0)], [1200, 1200], 1)], (0, 0))
@@ -91,3 +94,13 @@ def test_noalloc_errors(P):
     P.ftensordot_noalloc(big_a2, big_b, [1], [0], o3)
     torch.cuda.synchronize()
     assert torch.equal(o3, want) and want.abs().max().item() > 0
+    # the contracted leg first: A's blocks read in place as transposed matrices
+    big_a3 = P.Tensor.create(0, [(two, [1200, 1200], 1), (two, [4096, 4096], 0)], (0, 0))
+    big_a3.data_view().normal_(generator=g)
+    torch.cuda.synchronize()
+    c3 = P.ftensordot(big_a3, big_b, [0], [0])
+    want = c3.data()
+    o4 = torch.full((c3.size,), float("nan"), device="cuda", dtype=torch.float64)
+    P.ftensordot_noalloc(big_a3, big_b, [0], [0], o4)
+    torch.cuda.synchronize()
+    assert torch.equal(o4, want) and want.abs().max().item() > 0
