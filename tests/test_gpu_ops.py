@@ -241,6 +241,39 @@ def test_ftensordot_reads_a_in_place(P, case):
 
 
 @pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
+@pytest.mark.parametrize("conv", ["local", "global"])
+def test_ftensordot_reads_a_in_place_fp32_forms(P, gemm, conv):
+    # the FP32 and split-BF16 kernels on A read in place as signed transposed
+    # blocks (and as row slabs), against the oracle on the FP32-rounded inputs
+    rng = np.random.default_rng(61 + len(gemm) + len(conv))
+    sym = S.Z2
+    mk = lambda e, o, du: make_leg(sym, [(0,), (1,)], [e, o], du)
+    tol = {"f32": 1e-6, "bf16x3": 1e-4}[gemm]
+    from paper_2410_02215_amd import ftn
+    for la, lb, ax in [([(6, 5, 0), (64, 64, 1), (40, 24, 0), (16, 12, 0)], [(64, 64, 0), (20, 12, 1)], [1]),
+                       ([(40, 24, 0), (33, 31, 0), (64, 64, 1)], [(64, 64, 0), (20, 12, 1)], [2])]:
+        A = rand_tensor(rng, sym, [mk(*l) for l in la], total=(0,))
+        B = rand_tensor(rng, sym, [mk(*l) for l in lb], total=(1,))
+        A32, B32 = rounded_f32(A), rounded_f32(B)
+        ref = ftensordot(A32, B32, ax, [0], conv=conv)
+        ga, gb = to_gpu(A, torch.float32), to_gpu(B, torch.float32)
+        pc = P.LOCAL if conv == "local" else P.GLOBAL
+        gk = P.GEMM_F32 if gemm == "f32" else P.GEMM_BF16X3
+        P.ftensordot(ga, gb, ax, [0], conv=pc, gemm=gk)
+        torch.cuda.synchronize()
+        ftn.profile_collect()
+        ftn.profile_enable(True)
+        G = P.ftensordot(ga, gb, ax, [0], conv=pc, gemm=gk)
+        torch.cuda.synchronize()
+        ftn.profile_enable(False)
+        assert ftn.profile_collect()["permute"][1] == 1
+        assert_same_structure(ref, G)
+        r = flat_blocks(ref)
+        err = np.abs(_data(G) - r).max() / np.abs(r).max()
+        assert err < tol, err
+
+
+@pytest.mark.parametrize("gemm", ["f32", "bf16x3"])
 def test_ftensordot_fp32_forms(P, gemm):
     # FP32 tensors hold the FP64 inputs rounded to nearest; the oracle runs on
     # the same rounded values (promoted to FP64), so the error measured is that
