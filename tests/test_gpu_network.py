@@ -529,5 +529,8 @@ def test_precision_workload_on_a_16_site_cluster(P):
           "bf16x3 %.3g (%.2f s); %d compressions" % (err64, t64, errs["f32"], secs["f32"], errs["bf16x3"],
                                                      secs["bf16x3"], st["compressions"]))
     assert err64 <= 1e-10, err64
-    assert errs["f32"] <= 1e-5, errs
-    assert errs["bf16x3"] <= 1e-3, errs
+    # against the FP64 value of the unrounded inputs, so the FP32 input
+    # rounding is included (measured 9.4e-7; the arithmetic alone is held to
+    # 1e-6 on rounded inputs in test_precision_forms_on_a_u1u1_diamond_cluster)
+    assert errs["f32"] <= 2e-6, errs
+    assert errs["bf16x3"] <= 2e-4, errs
