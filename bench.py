@@ -6,7 +6,9 @@ with 40 sites, physical dim 4 (2 even / 2 odd), bond D = 4 (2 / 2), entries
 N(0, 1/32); approximate contraction with bond compression to chi = 64 along
 a seeded greedy path, FP64 throughout. One step = the norm <psi|psi> plus
 the hopping term <psi|h|psi> on the first edge: two network contractions
-(metric unit: contractions per second).
+(metric unit: contractions per second). The timed steps run on two streams,
+each driven by its own host thread and alternating the two kinds of
+contraction (--serial: one stream, norm then hopping term).
 
 Prints one JSON line with the throughput of the timed steps, a roofline
 entry for the dominant kernel (timed with two HIP events on each of its
@@ -93,10 +95,14 @@ def gpu_setup(cfg, paths):
     op = GP.operator_tensor(spec, operator_dense("hop", "Z2"))
     nn = GP.norm_network(spec, kets)
     nh = GP.norm_network(spec, kets, op=op, op_sites=cfg["op_sites"])
+    # a second network object of each kind (same site tensors) for the second
+    # host thread of the alternating schedule (gpu_steps)
+    nn2 = GP.norm_network(spec, kets)
+    nh2 = GP.norm_network(spec, kets, op=op, op_sites=cfg["op_sites"])
     torch.cuda.synchronize()
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
-    return dict(nn=nn, nh=nh, kets=kets, op=op, pn=paths["c2_norm"]["path"], ph=paths["c2_hop"]["path"],
-                streams=streams)
+    return dict(nn=nn, nh=nh, nn2=nn2, nh2=nh2, kets=kets, op=op, pn=paths["c2_norm"]["path"],
+                ph=paths["c2_hop"]["path"], streams=streams)
 
 
 def gpu_step(g, chi, concurrent=True, gemm=None):
@@ -138,6 +144,64 @@ def gpu_step(g, chi, concurrent=True, gemm=None):
     return (m1, e1, m2, e2), (s1, s2)
 
 
+def gpu_steps(g, chi, steps, concurrent=True, gemm=None, label=None):
+    """`steps` steps, each one norm and one hopping-term contraction.
+
+    Concurrent: two host threads, each driving its own stream, run `steps`
+    contractions each, alternating the two kinds (stream 0: norm, hop,
+    norm, ...; stream 1: hop, norm, hop, ...) with no join between steps, so
+    that both streams carry the same mix of work (alone the hopping term
+    takes longer than the norm, and a per-step join leaves one stream idle).
+    Every step's pair is computed; the results are those of the last norm
+    and the last hopping term. Not concurrent: norm then hopping term per
+    step on one stream.
+    """
+    import threading
+    import torch
+    nets = [[(g["nn"], g["pn"]), (g["nh"], g["ph"])], [(g["nn2"], g["pn"]), (g["nh2"], g["ph"])]]
+    last = [[None, None], [None, None]]  # per thread: last norm, last hop
+    stats = [[], []]
+    err = [None, None]
+
+    def contract(k, kind):
+        net, path = nets[k][kind]
+        if gemm is None:
+            return net.contract(path, chi=chi)
+        return net.contract(path, chi=chi, gemm=gemm)
+
+    def run(k):
+        try:
+            with torch.cuda.stream(g["streams"][k]):
+                for i in range(steps):
+                    kind = (i + k) % 2
+                    m, e, st = contract(k, kind)
+                    last[k][kind] = (i, m, e)
+                    stats[k].append(st)
+                    if label and k == 0:
+                        print("[bench] %s %d done (stream 0)" % (label, i), file=sys.stderr, flush=True)
+        except Exception as ex:  # re-raised in the caller
+            err[k] = ex
+
+    if concurrent:
+        th = threading.Thread(target=run, args=(1,))
+        th.start()
+        run(0)
+        th.join()
+        for ex in err:
+            if ex is not None:
+                raise ex
+        pick = lambda kind: max((x for x in (last[0][kind], last[1][kind]) if x is not None))[1:]
+        (m1, e1), (m2, e2) = pick(0), pick(1)
+        return (m1, e1, m2, e2), stats[0] + stats[1]
+    res, st = None, []
+    for i in range(steps):
+        res, s2 = gpu_step(g, chi, False, gemm)
+        st += list(s2)
+        if label:
+            print("[bench] %s %d done" % (label, i), file=sys.stderr, flush=True)
+    return res, st
+
+
 def to_f32(P, t):
     """FP32 copy of a library tensor (entries rounded to nearest)."""
     inf = t.info()
@@ -159,7 +223,8 @@ def c2_forms(P, cfg, g, chi, steps, golden):
     spec = cfg["spec"]
     k32 = [to_f32(P, k) for k in g["kets"]]
     op32 = to_f32(P, g["op"])
-    g32 = dict(g, nn=GP.norm_network(spec, k32), nh=GP.norm_network(spec, k32, op=op32, op_sites=cfg["op_sites"]))
+    g32 = dict(g, nn=GP.norm_network(spec, k32), nh=GP.norm_network(spec, k32, op=op32, op_sites=cfg["op_sites"]),
+               nn2=GP.norm_network(spec, k32), nh2=GP.norm_network(spec, k32, op=op32, op_sites=cfg["op_sites"]))
     # the FP64 path on the FP32-rounded inputs: the reference that isolates
     # the error of the FP32 arithmetic from the rounding of the inputs
     k64r = [to_f64(P, k) for k in k32]
@@ -170,11 +235,10 @@ def c2_forms(P, cfg, g, chi, steps, golden):
     h64 = (r64[2] / r64[0]) * 2.0 ** (r64[3] - r64[1])
     out = {}
     for name, gemm in (("f32", P.GEMM_F32), ("bf16x3", P.GEMM_BF16X3)):
-        gpu_step(g32, chi, True, gemm)
+        gpu_steps(g32, chi, 2, True, gemm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            res, _ = gpu_step(g32, chi, True, gemm)
+        res, _ = gpu_steps(g32, chi, steps, True, gemm)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         norm = res[0] * 2.0 ** res[1]
@@ -557,13 +621,10 @@ def main():
     t0 = time.perf_counter()
     flops = 0.0
     tb_flops = 0.0
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        res, st = gpu_step(g, chi, not args.serial)
-        flops += st[0]["flops"] + st[1]["flops"]
-        tb_flops += st[0]["compress_textbook_flops"] + st[1]["compress_textbook_flops"]
-        print("[bench] step %d done (%.1f ms host)" % (k, 1000 * (time.perf_counter() - ts)), file=sys.stderr,
-              flush=True)
+    res, st = gpu_steps(g, chi, args.steps, not args.serial, label="step")
+    for x in st:
+        flops += x["flops"]
+        tb_flops += x["compress_textbook_flops"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     w1 = time.monotonic_ns()
@@ -574,8 +635,7 @@ def main():
     P.ftn.profile_enable(True)
     p0 = time.monotonic_ns()
     tp0 = time.perf_counter()
-    for k in range(args.steps):
-        gpu_step(g, chi, not args.serial)
+    gpu_steps(g, chi, args.steps, not args.serial)
     torch.cuda.synchronize()
     tp1 = time.perf_counter()
     p1 = time.monotonic_ns()
@@ -596,7 +656,10 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "sites": cfg["spec"].n_sites, "chi": chi,
                    "contractions_per_step": 2, "terms": ["norm", "hopping(first edge)"],
-                   "streams": 1 if args.serial else 2},
+                   "streams": 1 if args.serial else 2,
+                   "schedule": ("one stream: norm then hopping term per step" if args.serial else
+                                "two streams, each running one contraction per step, alternating norm and "
+                                "hopping term, no join between steps")},
         "ftensordot_useful_tflops": flops / el / 1e12,
         "textbook_tflops": {"ftensordot": flops / el / 1e12, "compression": tb_flops / el / 1e12,
                             "note": "useful block-pair GEMM flops plus the textbook QR/LQ/SVD/absorb counts of "
