@@ -383,6 +383,10 @@ def main_amplitudes(args):
                    "amplitudes_per_step": B, "workers": args.workers},
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
+        # algorithmic work (flops or bytes, as the class's peak is priced) and
+        # algorithmic bytes per launch of every class
+        "kernel_work_per_launch": {c: prof[c][2] / prof[c][1] for c in prof if prof[c][1] > 0},
+        "kernel_bytes_per_launch": {c: prof[c][3] / prof[c][1] for c in prof if prof[c][1] > 0},
         # launches of the library's worker threads are not instrumented: with
         # more than one worker the line carries wall-clock rates only
         "roofline": roofline(prof, cfg["name"]) if any(prof[c][0] > 0 for c in prof) else None,
@@ -515,6 +519,10 @@ def main_gradient(args):
         "profiled_ms_per_step": 1000.0 * (tp1 - tp0) / args.steps,
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
+        # algorithmic work (flops or bytes, as the class's peak is priced) and
+        # algorithmic bytes per launch of every class
+        "kernel_work_per_launch": {c: prof[c][2] / prof[c][1] for c in prof if prof[c][1] > 0},
+        "kernel_bytes_per_launch": {c: prof[c][3] / prof[c][1] for c in prof if prof[c][1] > 0},
         "result": {"energy": E, "grad_norm": gnorm},
         "roofline": roofline(prof, cfg["name"]),
     }
@@ -667,6 +675,10 @@ def main():
         "autotune": dict(tune_stats, enabled=not args.no_autotune),
         "kernel_time_ms": {c: prof[c][0] / args.steps for c in prof if prof[c][0] > 0},
         "kernel_launches": {c: prof[c][1] / args.steps for c in prof if prof[c][0] > 0},
+        # algorithmic work (flops or bytes, as the class's peak is priced) and
+        # algorithmic bytes per launch of every class
+        "kernel_work_per_launch": {c: prof[c][2] / prof[c][1] for c in prof if prof[c][1] > 0},
+        "kernel_bytes_per_launch": {c: prof[c][3] / prof[c][1] for c in prof if prof[c][1] > 0},
         "kernel_rate": {c: "%.4g %s" % (prof[c][2 if PEAK[c][1] == "TFLOP/s" else 3] / (prof[c][0] * 1e-3) /
                                         (1e12 if PEAK[c][1] == "TFLOP/s" else 1e9),
                                         PEAK[c][1])
